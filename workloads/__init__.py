@@ -1,0 +1,18 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This package holds only input generation: grids, potentials, initial data and
+the time functions f_r(t), A(t) that define a problem. None of the solver's
+arithmetic lives here.
+"""
+from .synth import (  # noqa: F401
+    Problem,
+    periodic_grid,
+    free_grid,
+    c0_problem,
+    c1_problem,
+    c2_problem,
+    c3_problem,
+    c4_problems,
+    periodic_problem_from_seed,
+    free_problem_from_seed,
+)

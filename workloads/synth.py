@@ -1,0 +1,279 @@
+"""Seeded synthetic problems shaped like the paper's 1D and 2D examples.
+
+The paper's own examples start from Chebfun ground states that are not
+available here, so seeded random Gaussian wells, pulses and wave packets of
+the same form stand in for them (Section 6 uses Gaussian wells, the pulse of
+eq. (apulse) and Gaussian initial data).  Every draw goes through
+``numpy.random.default_rng(seed)`` (PCG64) in the order written below.
+
+Grids (problem statement, Sections 2.1 and 3.3):
+  periodic:   x_j = -pi + 2 pi j / M,  j = 0..M-1, on [-pi, pi)
+  free space: x_j = -1 + 2 j / M,      j = 0..M-1, on [-1, 1)
+
+A problem is V(x,t) = sum_r f_r(t) V_r(x) with real fields V_r, a vector
+potential A(t) and initial data u0, marched to time T with step dt.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+TWO_PI = 2.0 * np.pi
+
+
+def periodic_grid(M: int) -> np.ndarray:
+    return -np.pi + TWO_PI * np.arange(M, dtype=np.float64) / M
+
+
+def free_grid(M: int) -> np.ndarray:
+    return -1.0 + 2.0 * np.arange(M, dtype=np.float64) / M
+
+
+@dataclass
+class Problem:
+    """Plain description of one TDSE instance (no solver state)."""
+
+    name: str
+    dim: int
+    domain: str                      # "periodic" | "free"
+    M: Tuple[int, ...]
+    T: float
+    nsteps: int
+    order: int
+    u0: np.ndarray                   # complex128, shape M
+    V_fields: List[np.ndarray]       # real float64 arrays, shape M
+    f_kind: List[str]                # per field: "const" | "sin"
+    f_params: List[Tuple[float, float]]  # per field: (amp, omega) for 1 + amp sin(omega t)
+    A_kind: str = "none"             # "none" | "pulse_sin2" | "stepwise"
+    A_params: Tuple[float, ...] = ()  # pulse: (E0, omega, Tp, dir_0, dir_1)
+    A_steps: Optional[np.ndarray] = None  # stepwise: [nsteps, dim] values on each step
+    precision: str = "fp64"          # "fp64" | "fp32split"
+    n_start: Optional[int] = None    # default order - 2
+    # free-space quadrature parameters
+    eps: float = 1e-10
+    p: int = 8
+    q: int = 10
+    panels: int = 1
+    nu: Tuple[int, ...] = ()
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def dt(self) -> float:
+        return self.T / self.nsteps
+
+    @property
+    def start_steps(self) -> int:
+        return self.order - 2 if self.n_start is None else self.n_start
+
+    def f(self, r: int, t: float) -> float:
+        """Time factor f_r(t) of field r."""
+        if self.f_kind[r] == "const":
+            return 1.0
+        amp, om = self.f_params[r]
+        return 1.0 + amp * np.sin(om * t)
+
+    def A(self, t: float) -> np.ndarray:
+        """Vector potential A(t) in R^dim."""
+        out = np.zeros(self.dim)
+        if self.A_kind == "none":
+            return out
+        if self.A_kind == "pulse_sin2":
+            E0, om, Tp = self.A_params[:3]
+            d = np.asarray(self.A_params[3:3 + self.dim], dtype=np.float64)
+            return E0 * np.sin(np.pi * t / Tp) ** 2 * np.sin(om * t) * d
+        if self.A_kind == "stepwise":
+            dt = self.dt
+            m = int(np.floor(t / dt + 1e-12))
+            m = min(max(m, 0), self.nsteps - 1)
+            return np.asarray(self.A_steps[m], dtype=np.float64).copy()
+        raise ValueError(self.A_kind)
+
+    def grid(self, axis: int) -> np.ndarray:
+        g = periodic_grid if self.domain == "periodic" else free_grid
+        return g(self.M[axis])
+
+    def mesh(self) -> List[np.ndarray]:
+        axes = [self.grid(a) for a in range(self.dim)]
+        return list(np.meshgrid(*axes, indexing="ij"))
+
+
+# --------------------------------------------------------------------------
+# periodic workloads
+
+
+def _periodized_gauss(X: Sequence[np.ndarray], c: Sequence[float], s: float, images: int) -> np.ndarray:
+    """sum over image shifts m in {-images..images}^d of exp(-|x - c - 2 pi m|^2 / s^2)."""
+    d = len(X)
+    out = np.zeros(X[0].shape)
+    rng_m = range(-images, images + 1)
+    shifts = np.array(np.meshgrid(*([list(rng_m)] * d), indexing="ij")).reshape(d, -1).T
+    for m in shifts:
+        r2 = np.zeros(X[0].shape)
+        for a in range(d):
+            r2 += (X[a] - c[a] - TWO_PI * m[a]) ** 2
+        out += np.exp(-r2 / (s * s))
+    return out
+
+
+def _normalize(u: np.ndarray, cell: float) -> np.ndarray:
+    """Scale so that sum |u|^2 * cell = 1 (left-endpoint rule on the grid)."""
+    return u / np.sqrt(np.sum(np.abs(u) ** 2) * cell)
+
+
+def c0_problem(seed: int = 0, M: int = 256, T: float = 1.0, nsteps: int = 100, order: int = 8) -> Problem:
+    """1D periodic well V = -a cos x, A = 0, Gaussian u0 (seed 0)."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(1.0, 5.0)
+    x0 = rng.uniform(-1.0, 1.0)
+    sig = rng.uniform(0.3, 0.6)
+    x = periodic_grid(M)
+    V0 = -a * np.cos(x)
+    u0 = _periodized_gauss([x], [x0], sig, images=2).astype(np.complex128)
+    u0 = _normalize(u0, TWO_PI / M)
+    return Problem(name="C0", dim=1, domain="periodic", M=(M,), T=T, nsteps=nsteps, order=order,
+                   u0=u0, V_fields=[V0], f_kind=["const"], f_params=[(0.0, 0.0)],
+                   meta=dict(a=a, x0=x0, sigma=sig))
+
+
+def periodic_problem_from_seed(seed: int, dim: int, M: Sequence[int], T: float, nsteps: int,
+                               order: int = 8, precision: str = "fp64", name: str = "",
+                               A_kind: str = "pulse_sin2") -> Problem:
+    """The 2D (or 1D analogue) periodic recipe: four Gaussian wells with a
+    sinusoidal modulation, a sin^2-enveloped pulse along e1 and a Gaussian u0.
+
+    Draw order: c_j ~ U[2,8] (4), p_j ~ U[-2,2]^d (4), s_j ~ U[0.3,0.8] (4),
+    E0 ~ U[0.5,2], omega ~ U[5,15], x0 ~ U[-1,1]^d, sigma ~ U[0.3,0.6].
+    """
+    rng = np.random.default_rng(seed)
+    cj = rng.uniform(2.0, 8.0, size=4)
+    pj = rng.uniform(-2.0, 2.0, size=(4, dim))
+    sj = rng.uniform(0.3, 0.8, size=4)
+    E0 = rng.uniform(0.5, 2.0)
+    om = rng.uniform(5.0, 15.0)
+    x0 = rng.uniform(-1.0, 1.0, size=dim)
+    sig = rng.uniform(0.3, 0.6)
+    M = tuple(int(m) for m in M)
+    axes = [periodic_grid(m) for m in M]
+    X = list(np.meshgrid(*axes, indexing="ij"))
+    images = 1 if dim == 2 else 2
+    V0 = np.zeros(M)
+    for j in range(4):
+        V0 -= cj[j] * _periodized_gauss(X, pj[j], sj[j], images)
+    u0 = _periodized_gauss(X, x0, sig, images).astype(np.complex128)
+    u0 = _normalize(u0, (TWO_PI) ** dim / np.prod(M))
+    direction = (1.0, 0.0)
+    prob = Problem(name=name or f"periodic{dim}d_seed{seed}", dim=dim, domain="periodic", M=M, T=T,
+                   nsteps=nsteps, order=order, u0=u0, V_fields=[V0], f_kind=["sin"],
+                   f_params=[(0.1, om)], A_kind="pulse_sin2", A_params=(E0, om, T) + direction,
+                   precision=precision,
+                   meta=dict(c=cj, p=pj, s=sj, E0=E0, omega=om, x0=x0, sigma=sig))
+    if A_kind == "stepwise":
+        # piecewise-constant A on each step, sampled at the step midpoint
+        dt = T / nsteps
+        tm = (np.arange(nsteps) + 0.5) * dt
+        steps = np.zeros((nsteps, dim))
+        for m, t in enumerate(tm):
+            steps[m] = prob.A(t)
+        prob.A_kind = "stepwise"
+        prob.A_steps = steps
+        prob.A_params = ()
+    elif A_kind == "none":
+        prob.A_kind = "none"
+        prob.A_params = ()
+    return prob
+
+
+def c1_problem(seed: int = 1, M: int = 512, T: float = 2.0, nsteps: int = 2000, order: int = 8) -> Problem:
+    """2D periodic, 512 x 512, T = 2, 2000 steps, FP64 (seed 1)."""
+    return periodic_problem_from_seed(seed, 2, (M, M), T, nsteps, order, name="C1")
+
+
+def c3_problem(seed: int = 3, M: int = 1024, T: float = 2.0, nsteps: int = 2000, order: int = 8,
+               precision: str = "fp32split") -> Problem:
+    """The 2D periodic recipe at 1024 x 1024 (seed 3), FP32-split by default."""
+    return periodic_problem_from_seed(seed, 2, (M, M), T, nsteps, order, precision=precision, name="C3")
+
+
+def c4_problems(T: float = 2.0, nsteps: int = 500, order: int = 8, precision: str = "fp32split",
+                count: int = 64, scale: int = 1) -> List[Problem]:
+    """64 periodic instances of uneven sizes: i < 32 are 1D with M in
+    {256, 512, 1024, 2048}; i >= 32 are 2D with M in {128, 256, 384, 512}^2.
+    Instance i uses seed 4000 + i and a stepwise A (one sample per step).
+    ``scale`` divides every size (for quick tests)."""
+    out = []
+    for i in range(count):
+        if i < count // 2:
+            m = [256, 512, 1024, 2048][i % 4] // scale
+            prob = periodic_problem_from_seed(4000 + i, 1, (m,), T, nsteps, order, precision,
+                                              name=f"C4[{i}]", A_kind="stepwise")
+        else:
+            m = [128, 256, 384, 512][i % 4] // scale
+            prob = periodic_problem_from_seed(4000 + i, 2, (m, m), T, nsteps, order, precision,
+                                              name=f"C4[{i}]", A_kind="stepwise")
+        out.append(prob)
+    return out
+
+
+# --------------------------------------------------------------------------
+# free-space workloads
+
+
+def _bump(s: np.ndarray) -> np.ndarray:
+    """C-infinity bump b(s) = exp(1 - 1/(1 - s^2)) for |s| < 1, else 0."""
+    out = np.zeros_like(s)
+    inside = np.abs(s) < 1.0
+    out[inside] = np.exp(1.0 - 1.0 / (1.0 - s[inside] ** 2))
+    return out
+
+
+def free_problem_from_seed(seed: int, dim: int, M: Sequence[int], T: float, nsteps: int,
+                           order: int = 8, eps: float = 1e-10, q: int = 10, panels: int = 1,
+                           nu: Optional[Sequence[int]] = None, name: str = "",
+                           A_kind: str = "pulse_sin2", E0_scale: float = 1.0) -> Problem:
+    """Free-space recipe: the periodic draw order with the geometry rescaled
+    into [-1,1]^d and every field windowed by a C-infinity bump.
+
+    p_j ~ U[-0.5,0.5]^d, s_j ~ U[0.1,0.3], x0 ~ U[-0.3,0.3]^d, sigma ~ U[0.1,0.2].
+    """
+    rng = np.random.default_rng(seed)
+    cj = rng.uniform(2.0, 8.0, size=4)
+    pj = rng.uniform(-0.5, 0.5, size=(4, dim))
+    sj = rng.uniform(0.1, 0.3, size=4)
+    E0 = rng.uniform(0.5, 2.0) * E0_scale
+    om = rng.uniform(5.0, 15.0)
+    x0 = rng.uniform(-0.3, 0.3, size=dim)
+    sig = rng.uniform(0.1, 0.2)
+    M = tuple(int(m) for m in M)
+    axes = [free_grid(m) for m in M]
+    X = list(np.meshgrid(*axes, indexing="ij"))
+    win = np.ones(M)
+    for a in range(dim):
+        win = win * _bump(X[a])
+    V0 = np.zeros(M)
+    for j in range(4):
+        r2 = sum((X[a] - pj[j, a]) ** 2 for a in range(dim))
+        V0 -= cj[j] * np.exp(-r2 / sj[j] ** 2)
+    V0 = V0 * win
+    r2 = sum((X[a] - x0[a]) ** 2 for a in range(dim))
+    u0 = (win * np.exp(-r2 / sig ** 2)).astype(np.complex128)
+    u0 = _normalize(u0, 2.0 ** dim / np.prod(M))
+    if nu is None:
+        nu = tuple(4 * m for m in M)
+    prob = Problem(name=name or f"free{dim}d_seed{seed}", dim=dim, domain="free", M=M, T=T, nsteps=nsteps,
+                   order=order, u0=u0, V_fields=[V0], f_kind=["sin"], f_params=[(0.1, om)],
+                   A_kind="pulse_sin2", A_params=(E0, om, T, 1.0, 0.0), eps=eps, q=q, panels=panels,
+                   nu=tuple(int(v) for v in nu),
+                   meta=dict(c=cj, p=pj, s=sj, E0=E0, omega=om, x0=x0, sigma=sig))
+    if A_kind == "none":
+        prob.A_kind = "none"
+        prob.A_params = ()
+    return prob
+
+
+def c2_problem(seed: int = 2, M: int = 256, T: float = 1.0, nsteps: int = 1000, order: int = 8,
+               nu: int = 2048) -> Problem:
+    """2D free space, 256 x 256 physical points, eps = 1e-10, p = 8, q = 10,
+    one Gauss panel per side, FFT size nu = 2048 per axis (seed 2)."""
+    return free_problem_from_seed(seed, 2, (M, M), T, nsteps, order, nu=(nu, nu), name="C2")
