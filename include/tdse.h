@@ -1,0 +1,146 @@
+/* tdse.h -- C ABI of the MI355X (gfx950) Volterra-integral TDSE marcher.
+ *
+ * Method: Kaye, Barnett, Greengard, "A high-order integral equation-based
+ * solver for the time-dependent Schrodinger equation" (arXiv:2001.06113).
+ *
+ * The library solves, on one GPU,
+ *     i u_t = -Lap u + V(x,t) u + i A(t).grad u,   u(x,0) = u0(x)      (Section 1, eq. (schrodfree))
+ * on the periodic box [-pi,pi]^d (Section 2), for d = 1 or 2, with
+ *     V(x,t) = sum_r f_r(t) V_r(x)    (real fields V_r on the grid),
+ * by the Fourier-mode recurrence of Lemma 1 with the n-th order implicit
+ * Adams rule of eq. (uadamsk) (Section 2.2, Table 1 for n = 8) and the
+ * iterated-Richardson start-up of Section 2.2.  Each step is one inverse
+ * FFT, a pointwise diagonal solve, one forward FFT and a per-mode
+ * recurrence, all in HIP kernels.
+ *
+ * Conventions
+ *   - complex values are interleaved (re, im) doubles (complex128), arrays in
+ *     C order with the last axis fastest; a 1D problem has shape [M[0]].
+ *   - periodic grid x_j = -pi + 2 pi j / M, j = 0..M-1 (Section 2.1).
+ *   - dt = T / nsteps.
+ *
+ * Errors: every call returns TDSE_OK (0) or a negative status; no C++
+ * exception crosses this boundary.  tdse_status_string() names a status and
+ * tdse_last_error() gives the text of the most recent failure on the calling
+ * thread.
+ *
+ * Ownership: host inputs are copied during tdse_plan (callbacks are invoked
+ * only inside tdse_plan).  The device workspace belongs to the caller and
+ * must outlive every call that uses it; the plan owns only host metadata.
+ * Device work is asynchronous on the stream given to tdse_bind; calls that
+ * return data to host memory synchronize that stream.  A plan is not
+ * thread-safe.
+ */
+#ifndef TDSE_H
+#define TDSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define TDSE_OK            0
+#define TDSE_EINVAL       -1   /* bad sizes, non-integer T/dt, bad order, NULL */
+#define TDSE_EUNSUPPORTED -2   /* a valid request this build does not do      */
+#define TDSE_ENOMEM       -3   /* workspace missing or too small              */
+#define TDSE_EDEVICE      -4   /* a HIP runtime error                         */
+#define TDSE_ENONFINITE   -5   /* the state became NaN/Inf                    */
+#define TDSE_ESTATE       -6   /* calls made in the wrong order               */
+
+/* ---- enumerations ------------------------------------------------------- */
+#define TDSE_PERIODIC 0        /* D = [-pi,pi]^d, Section 2                    */
+#define TDSE_FREE     1        /* D = R^d, supp u0, V in [-1,1]^d, Section 3   */
+
+#define TDSE_FP64        0     /* every stage in double precision             */
+#define TDSE_FP32_SPLIT  1     /* complex64 transforms and history, FP64 state */
+
+#define TDSE_F_CONST     0     /* f_r(t) = 1                                   */
+#define TDSE_F_SIN       1     /* f_r(t) = 1 + f_params[2r] sin(f_params[2r+1] t) */
+#define TDSE_F_CALLBACK  2     /* f_r(t) = f_fn(r, t, f_ctx)                   */
+
+#define TDSE_A_NONE      0     /* A = 0                                        */
+#define TDSE_A_PULSE_SIN2 1    /* A = E0 sin^2(pi t/Tp) sin(w t) dir; A_params = {E0, w, Tp, dir[0..d-1]} */
+#define TDSE_A_CALLBACK  2     /* A(t) from A_fn; phi = int A by Gauss-Legendre per step */
+#define TDSE_A_STEPWISE  3     /* A constant on each step: A_steps[nsteps][d]  */
+
+typedef double (*tdse_scalar_fn)(int32_t r, double t, void* ctx);
+typedef void (*tdse_vector_fn)(double t, double* A_out, void* ctx);
+
+/* Problem statement (Section 1: domain, u0 via tdse_set_state, V(x,t), A(t),
+ * T, step size, order).  Unused fields may be zero. */
+typedef struct {
+  int32_t dim;             /* 1 or 2                                         */
+  int32_t domain;          /* TDSE_PERIODIC (TDSE_FREE: EUNSUPPORTED here)   */
+  int32_t M[2];            /* grid points per axis: even, 2^a 3^b, 2..4096   */
+  double  T;               /* final time > 0                                 */
+  int32_t nsteps;          /* number of steps, dt = T / nsteps               */
+  int32_t order;           /* implicit Adams order n in {2,4,6,8}            */
+  int32_t n_start;         /* Richardson start-up steps; < 0 means n - 2     */
+  int32_t precision;       /* TDSE_FP64 | TDSE_FP32_SPLIT                    */
+  int32_t nV;              /* number of spatial fields, 1..8                 */
+  const double* V_fields;  /* host [nV][prod M] real, last axis fastest      */
+  int32_t f_kind;          /* TDSE_F_*                                       */
+  const double* f_params;  /* TDSE_F_SIN: [nV][2] = (amp, omega)             */
+  tdse_scalar_fn f_fn; void* f_ctx;
+  int32_t A_kind;          /* TDSE_A_*                                       */
+  const double* A_params;  /* TDSE_A_PULSE_SIN2: {E0, omega, Tp, dir[d]}     */
+  const double* A_steps;   /* TDSE_A_STEPWISE: host [nsteps][d]              */
+  tdse_vector_fn A_fn; void* A_ctx;
+} tdse_problem_t;
+
+typedef struct tdse_plan_s* tdse_plan_t;   /* opaque, owned by the library  */
+
+/* Build a plan: validate the problem and precompute every time-dependent
+ * scalar (phi(t) = int_0^t A, eq. (phi); f_r(t)) at all step and sub-step
+ * times, the implicit Adams weights (Table 1 for n = 8) and the Richardson
+ * weights (Section 2.2).  Host only.  On success *out owns a new plan. */
+int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out);
+
+/* Bytes of device workspace the plan needs (alignment 256). */
+int tdse_workspace_size(tdse_plan_t plan, size_t* bytes);
+
+/* Attach a device workspace of `bytes` bytes (caller-owned, 256-aligned) and
+ * a HIP stream (NULL = default stream); uploads the static tables.  May be
+ * called again to move the plan to another buffer or stream. */
+int tdse_bind(tdse_plan_t plan, void* device_workspace, size_t bytes, void* hip_stream);
+
+/* Set u(.,0) = u0 (complex128, shape M) and reset the clock to t = 0.
+ * on_device != 0: u0 is a device pointer (copied asynchronously); otherwise
+ * host memory (copied before return). */
+int tdse_set_state(tdse_plan_t plan, const void* u0, int32_t on_device);
+
+/* Advance `nsteps` time steps (asynchronous on the bound stream).  The first
+ * n_start steps use Richardson extrapolation of the order-2 scheme of
+ * eq. (utrapk); later steps use eq. (uadamsk).  ESTATE past t = T. */
+int tdse_step(tdse_plan_t plan, int32_t nsteps);
+
+/* Copy u(., t_current) into `u` (complex128, shape M).  on_device != 0:
+ * device pointer, asynchronous; otherwise host memory, synchronizes. */
+int tdse_get_state(tdse_plan_t plan, void* u, int32_t on_device);
+
+/* set_state(u0) + step(all remaining) + get_state(uT). */
+int tdse_run(tdse_plan_t plan, const void* u0, void* uT, int32_t on_device);
+
+/* Scalar queries (keys below). */
+#define TDSE_Q_MODES          0   /* modes per instance (prod M)               */
+#define TDSE_Q_STEPS_DONE     1   /* steps taken since set_state               */
+#define TDSE_Q_DT             2
+#define TDSE_Q_BYTES_PER_STEP 3   /* algorithmic HBM bytes of one Adams step   */
+#define TDSE_Q_MU             16  /* + j: Adams weight mu_j                    */
+#define TDSE_Q_RICHARDSON     32  /* + l: weight of the 2^l-sub-step result    */
+#define TDSE_Q_PHI            64  /* + axis: phi_axis(T)                       */
+int tdse_query(tdse_plan_t plan, int32_t key, double* value);
+
+/* Release the plan (not the caller's workspace). */
+void tdse_destroy(tdse_plan_t plan);
+
+const char* tdse_status_string(int status);
+const char* tdse_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDSE_H */

@@ -1,0 +1,63 @@
+"""ctypes declarations of the C ABI in include/tdse.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtdse.so")
+
+SCALAR_FN = C.CFUNCTYPE(C.c_double, C.c_int32, C.c_double, C.c_void_p)
+VECTOR_FN = C.CFUNCTYPE(None, C.c_double, C.POINTER(C.c_double), C.c_void_p)
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("domain", C.c_int32), ("M", C.c_int32 * 2),
+        ("T", C.c_double), ("nsteps", C.c_int32), ("order", C.c_int32),
+        ("n_start", C.c_int32), ("precision", C.c_int32), ("nV", C.c_int32),
+        ("V_fields", C.POINTER(C.c_double)),
+        ("f_kind", C.c_int32), ("f_params", C.POINTER(C.c_double)),
+        ("f_fn", SCALAR_FN), ("f_ctx", C.c_void_p),
+        ("A_kind", C.c_int32), ("A_params", C.POINTER(C.c_double)),
+        ("A_steps", C.POINTER(C.c_double)),
+        ("A_fn", VECTOR_FN), ("A_ctx", C.c_void_p),
+    ]
+
+
+EXPORTS = [
+    "tdse_plan", "tdse_workspace_size", "tdse_bind", "tdse_set_state", "tdse_step",
+    "tdse_get_state", "tdse_run", "tdse_query", "tdse_destroy", "tdse_status_string",
+    "tdse_last_error",
+]
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libtdse.so; raise if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2001_06113_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    lib.tdse_plan.argtypes = [C.POINTER(Problem), C.POINTER(P)]
+    lib.tdse_workspace_size.argtypes = [P, C.POINTER(C.c_size_t)]
+    lib.tdse_bind.argtypes = [P, P, C.c_size_t, P]
+    lib.tdse_set_state.argtypes = [P, P, C.c_int32]
+    lib.tdse_step.argtypes = [P, C.c_int32]
+    lib.tdse_get_state.argtypes = [P, P, C.c_int32]
+    lib.tdse_run.argtypes = [P, P, P, C.c_int32]
+    lib.tdse_query.argtypes = [P, C.c_int32, C.POINTER(C.c_double)]
+    lib.tdse_destroy.argtypes = [P]
+    lib.tdse_destroy.restype = None
+    lib.tdse_status_string.argtypes = [C.c_int]
+    lib.tdse_status_string.restype = C.c_char_p
+    lib.tdse_last_error.argtypes = []
+    lib.tdse_last_error.restype = C.c_char_p
+    for name in ("tdse_plan", "tdse_workspace_size", "tdse_bind", "tdse_set_state", "tdse_step",
+                 "tdse_get_state", "tdse_run", "tdse_query"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib

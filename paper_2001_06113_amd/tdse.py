@@ -1,0 +1,149 @@
+"""Python binding of libtdse.so: a Plan owns a device workspace (torch) and
+forwards every call to the C ABI of include/tdse.h.  No arithmetic on the
+solution happens here; torch supplies device memory and the stream."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+PERIODIC, FREE = 0, 1
+FP64, FP32_SPLIT = 0, 1
+F_KINDS = {"const": 0, "sin": 1, "callback": 2}
+A_KINDS = {"none": 0, "pulse_sin2": 1, "callback": 2, "stepwise": 3}
+Q_MODES, Q_STEPS_DONE, Q_DT, Q_BYTES_PER_STEP = 0, 1, 2, 3
+Q_MU, Q_RICHARDSON, Q_PHI = 16, 32, 64
+
+
+class TDSEError(RuntimeError):
+    def __init__(self, status: int, call: str):
+        lib = _lib.load()
+        super().__init__(f"{call}: {lib.tdse_status_string(status).decode()} ({lib.tdse_last_error().decode()})")
+        self.status = status
+
+
+def _check(status: int, call: str) -> None:
+    if status != 0:
+        raise TDSEError(status, call)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Plan:
+    """One TDSE instance planned and bound to a device workspace.
+
+    Arguments follow the problem statement: grid M, final time T, number of
+    steps, implicit Adams order, potential fields V_r(x) with time factors
+    f_r(t) and the vector potential A(t).
+    """
+
+    def __init__(self, *, dim: int, M: Sequence[int], T: float, nsteps: int, V_fields,
+                 order: int = 8, n_start: int = -1, precision: str = "fp64",
+                 f_kind: str = "const", f_params=None, A_kind: str = "none", A_params=None,
+                 A_steps=None, domain: str = "periodic", device=None, stream=None):
+        self.lib = _lib.load()
+        self.dim = dim
+        self.M = tuple(int(m) for m in M)
+        self.shape = self.M
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        V = np.ascontiguousarray(np.asarray(V_fields, dtype=np.float64).reshape(-1, *self.M))
+        prob = _lib.Problem()
+        prob.dim = dim
+        prob.domain = PERIODIC if domain == "periodic" else FREE
+        for a in range(dim):
+            prob.M[a] = self.M[a]
+        prob.T = float(T)
+        prob.nsteps = int(nsteps)
+        prob.order = int(order)
+        prob.n_start = int(n_start)
+        prob.precision = FP64 if precision == "fp64" else FP32_SPLIT
+        prob.nV = V.shape[0]
+        keep = [V]
+        prob.V_fields = _dptr(V)
+        prob.f_kind = F_KINDS[f_kind]
+        if f_params is not None:
+            fp = np.ascontiguousarray(np.asarray(f_params, dtype=np.float64).ravel())
+            keep.append(fp)
+            prob.f_params = _dptr(fp)
+        prob.A_kind = A_KINDS[A_kind]
+        if A_params is not None:
+            ap = np.ascontiguousarray(np.asarray(A_params, dtype=np.float64).ravel())
+            keep.append(ap)
+            prob.A_params = _dptr(ap)
+        if A_steps is not None:
+            st = np.ascontiguousarray(np.asarray(A_steps, dtype=np.float64).ravel())
+            keep.append(st)
+            prob.A_steps = _dptr(st)
+        handle = C.c_void_p()
+        _check(self.lib.tdse_plan(C.byref(prob), C.byref(handle)), "tdse_plan")
+        self.handle = handle
+        size = C.c_size_t()
+        _check(self.lib.tdse_workspace_size(handle, C.byref(size)), "tdse_workspace_size")
+        self.ws_bytes = size.value
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        _check(self.lib.tdse_bind(handle, C.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                                  C.c_void_p(self.stream.cuda_stream)), "tdse_bind")
+
+    @classmethod
+    def from_problem(cls, prob, **kw) -> "Plan":
+        """Plan a workloads.Problem (duck-typed: the plain problem fields)."""
+        # one time-factor kind for all fields: constant fields get amplitude 0
+        sin = any(k == "sin" for k in prob.f_kind)
+        f_kind = "sin" if sin else "const"
+        f_params = None
+        if sin:
+            f_params = [tuple(fp) if k == "sin" else (0.0, 0.0) for fp, k in zip(prob.f_params, prob.f_kind)]
+        return cls(dim=prob.dim, M=prob.M, T=prob.T, nsteps=prob.nsteps, V_fields=np.stack(prob.V_fields),
+                   order=prob.order, n_start=-1 if prob.n_start is None else prob.n_start,
+                   precision=prob.precision, f_kind=f_kind, f_params=f_params, A_kind=prob.A_kind,
+                   A_params=prob.A_params if prob.A_kind == "pulse_sin2" else None,
+                   A_steps=prob.A_steps if prob.A_kind == "stepwise" else None,
+                   domain=prob.domain, **kw)
+
+    # -------------------------------------------------------------- calls
+    def _as_device(self, u) -> torch.Tensor:
+        t = torch.as_tensor(u)
+        return t.to(device=self.device, dtype=torch.complex128).contiguous().reshape(self.shape)
+
+    def set_state(self, u0) -> None:
+        self._u0 = self._as_device(u0)
+        _check(self.lib.tdse_set_state(self.handle, C.c_void_p(self._u0.data_ptr()), 1), "tdse_set_state")
+
+    def step(self, k: int) -> None:
+        _check(self.lib.tdse_step(self.handle, int(k)), "tdse_step")
+
+    def get_state(self) -> torch.Tensor:
+        out = torch.empty(self.shape, dtype=torch.complex128, device=self.device)
+        _check(self.lib.tdse_get_state(self.handle, C.c_void_p(out.data_ptr()), 1), "tdse_get_state")
+        return out
+
+    def run(self, u0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        u0d = self._as_device(u0)
+        self._u0 = u0d
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.complex128, device=self.device)
+        _check(self.lib.tdse_run(self.handle, C.c_void_p(u0d.data_ptr()), C.c_void_p(out.data_ptr()), 1), "tdse_run")
+        return out
+
+    def query(self, key: int) -> float:
+        v = C.c_double()
+        _check(self.lib.tdse_query(self.handle, int(key), C.byref(v)), "tdse_query")
+        return v.value
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self.lib.tdse_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

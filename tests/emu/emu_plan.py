@@ -1,0 +1,92 @@
+"""Run the emulated library (libtdse_emu.so) on host memory through the same
+C ABI as the GPU build."""
+import ctypes as C
+import os
+
+import numpy as np
+
+from paper_2001_06113_amd import _lib
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def load(rebuild: bool = False):
+    path = os.path.join(HERE, "libtdse_emu.so")
+    if rebuild or not os.path.exists(path):
+        from . import build_emu
+
+        build_emu.build()
+    saved = _lib.LIB_PATH, _lib._lib
+    try:
+        _lib.LIB_PATH, _lib._lib = path, None
+        lib = _lib.load()
+    finally:
+        _lib.LIB_PATH, _lib._lib = saved
+    return lib
+
+
+class EmuPlan:
+    """Plan of a workloads.Problem on the emulated library."""
+
+    def __init__(self, lib, prob):
+        self.lib = lib
+        p = _lib.Problem()
+        p.dim = prob.dim
+        p.domain = 0 if prob.domain == "periodic" else 1
+        for a in range(prob.dim):
+            p.M[a] = prob.M[a]
+        p.T = prob.T
+        p.nsteps = prob.nsteps
+        p.order = prob.order
+        p.n_start = -1 if prob.n_start is None else prob.n_start
+        p.precision = 0 if prob.precision == "fp64" else 1
+        V = np.ascontiguousarray(np.stack(prob.V_fields).astype(np.float64))
+        self._keep = [V]
+        p.nV = V.shape[0]
+        p.V_fields = V.ctypes.data_as(C.POINTER(C.c_double))
+        if any(k == "sin" for k in prob.f_kind):
+            fp = np.array([tuple(f) if k == "sin" else (0.0, 0.0) for f, k in zip(prob.f_params, prob.f_kind)],
+                          dtype=np.float64).ravel()
+            self._keep.append(fp)
+            p.f_kind = 1
+            p.f_params = fp.ctypes.data_as(C.POINTER(C.c_double))
+        kinds = {"none": 0, "pulse_sin2": 1, "stepwise": 3}
+        p.A_kind = kinds[prob.A_kind]
+        if prob.A_kind == "pulse_sin2":
+            ap = np.asarray(prob.A_params, dtype=np.float64)
+            self._keep.append(ap)
+            p.A_params = ap.ctypes.data_as(C.POINTER(C.c_double))
+        if prob.A_kind == "stepwise":
+            st = np.ascontiguousarray(np.asarray(prob.A_steps, dtype=np.float64).ravel())
+            self._keep.append(st)
+            p.A_steps = st.ctypes.data_as(C.POINTER(C.c_double))
+        self.prob = p
+        h = C.c_void_p()
+        st = lib.tdse_plan(C.byref(p), C.byref(h))
+        if st:
+            raise RuntimeError(lib.tdse_last_error().decode())
+        self.h = h
+        sz = C.c_size_t()
+        lib.tdse_workspace_size(h, C.byref(sz))
+        raw = np.zeros(sz.value + 512, dtype=np.uint8)
+        off = (-raw.ctypes.data) % 256
+        self.ws = raw[off:off + sz.value]
+        self._raw = raw
+        st = lib.tdse_bind(h, C.c_void_p(self.ws.ctypes.data), sz.value, None)
+        if st:
+            raise RuntimeError(lib.tdse_last_error().decode())
+        self.shape = tuple(prob.M)
+
+    def run(self, u0):
+        u0 = np.ascontiguousarray(np.asarray(u0, dtype=np.complex128))
+        out = np.zeros(self.shape, dtype=np.complex128)
+        st = self.lib.tdse_run(self.h, C.c_void_p(u0.ctypes.data), C.c_void_p(out.ctypes.data), 1)
+        if st:
+            raise RuntimeError(self.lib.tdse_last_error().decode())
+        return out
+
+    def __del__(self):
+        try:
+            self.lib.tdse_destroy(self.h)
+        except Exception:
+            pass

@@ -1,0 +1,137 @@
+// CPU emulation of the small part of HIP the kernels use, for tests only.
+//
+// The kernel sources are compiled with g++ after this header (which
+// pre-empts <hip/hip_runtime.h>).  A launch runs the blocks one after
+// another; the blockDim.x threads of a block are cooperative fibers on one OS
+// thread that switch at __syncthreads().  __shared__ arrays become function statics,
+// shared by the threads of the (single) running block.  "Device" memory is
+// host memory.  This exercises indexing, barriers and arithmetic of the
+// kernels on the CPU; it says nothing about timing.
+#pragma once
+#define HIP_INCLUDE_HIP_HIP_RUNTIME_H 1
+
+#include <algorithm>
+#include <cmath>
+#include <ucontext.h>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <vector>
+
+struct double2 { double x, y; };
+struct float2 { float x, y; };
+struct dim3 {
+  unsigned x = 1, y = 1, z = 1;
+  dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+struct uint3_ { unsigned x = 0, y = 0, z = 0; };
+
+extern thread_local uint3_ threadIdx;
+extern thread_local uint3_ blockIdx;
+extern dim3 blockDim, gridDim;
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+#define __restrict__
+
+typedef int hipError_t;
+typedef void* hipStream_t;
+enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
+enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyHostToHost };
+
+namespace emu {
+// Cooperative fibers: every emulated thread of a block runs on one OS thread
+// until it reaches __syncthreads(); when all have arrived (or finished) the
+// scheduler resumes them.  Kernels call __syncthreads() uniformly.
+struct Fiber {
+  ucontext_t ctx;
+  bool done = false;
+  unsigned tid = 0;
+};
+constexpr size_t kStack = 1 << 17;
+inline char* stack_for(unsigned t) {  // one uninitialised stack per fiber slot, reused
+  static std::vector<char*> pool;
+  while (pool.size() <= t) pool.push_back(new char[kStack]);
+  return pool[t];
+}
+struct Block {
+  ucontext_t sched;
+  std::vector<Fiber> fibers;
+  std::function<void()> body;
+  int current = -1;
+};
+extern Block* g_block;
+inline void fiber_entry() {
+  Block* b = g_block;
+  Fiber& f = b->fibers[b->current];
+  threadIdx.x = f.tid;
+  b->body();
+  f.done = true;
+  swapcontext(&f.ctx, &b->sched);
+}
+template <typename K, typename... Args>
+void launch(K kernel, dim3 grid, dim3 block, Args... args) {
+  gridDim = grid;
+  blockDim = block;
+  for (unsigned bi = 0; bi < grid.x; ++bi) {
+    Block b;
+    g_block = &b;
+    blockIdx.x = bi;
+    b.body = [&]() { kernel(args...); };
+    b.fibers.resize(block.x);
+    for (unsigned t = 0; t < block.x; ++t) {
+      Fiber& f = b.fibers[t];
+      f.tid = t;
+      getcontext(&f.ctx);
+      f.ctx.uc_stack.ss_sp = stack_for(t);
+      f.ctx.uc_stack.ss_size = kStack;
+      f.ctx.uc_link = nullptr;
+      makecontext(&f.ctx, (void (*)())fiber_entry, 0);
+    }
+    bool any = true;
+    while (any) {
+      any = false;
+      for (unsigned t = 0; t < block.x; ++t) {
+        if (b.fibers[t].done) continue;
+        b.current = (int)t;
+        threadIdx.x = t;
+        swapcontext(&b.sched, &b.fibers[t].ctx);
+        if (!b.fibers[t].done) any = true;
+      }
+    }
+    g_block = nullptr;
+  }
+}
+inline void barrier_wait() {
+  Block* b = g_block;
+  Fiber& f = b->fibers[b->current];
+  swapcontext(&f.ctx, &b->sched);
+  threadIdx.x = f.tid;
+}
+}  // namespace emu
+
+inline void __syncthreads() { emu::barrier_wait(); }
+inline void sincos(double x, double* s, double* c) { *s = std::sin(x); *c = std::cos(x); }
+inline void sincosf(float x, float* s, float* c) { *s = std::sin(x); *c = std::cos(x); }
+using std::min;
+using std::max;
+
+#define hipLaunchKernelGGL(K, G, B, SH, S, ...) emu::launch(K, G, B, __VA_ARGS__)
+inline hipError_t hipGetLastError() { return hipSuccess; }
+inline const char* hipGetErrorString(hipError_t) { return "emulated"; }
+inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) {
+  std::memcpy(d, s, n);
+  return hipSuccess;
+}
+inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t) {
+  std::memset(d, v, n);
+  return hipSuccess;
+}
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipDeviceSynchronize() { return hipSuccess; }

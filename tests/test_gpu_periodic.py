@@ -1,0 +1,122 @@
+"""GPU parity of the periodic FP64 path against the CPU oracle (through the C ABI).
+
+Bar: relative L2 <= 1e-11 on the grid (FP64 path vs FP64 oracle on the same
+seeded inputs)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.periodic import PeriodicOracle
+from workloads import Problem, c0_problem, periodic_grid, periodic_problem_from_seed
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2001_06113_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2001_06113_amd import build
+
+        build.build()
+    yield
+
+
+def gpu_run(prob):
+    from paper_2001_06113_amd.tdse import Plan
+
+    plan = Plan.from_problem(prob, device="cuda:0")
+    u = plan.run(prob.u0).cpu().numpy()
+    plan.close()
+    return u
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def check(prob, tol=TOL):
+    print(f"case {prob.name} M={prob.M} steps={prob.nsteps} order={prob.order}", flush=True)
+    u = gpu_run(prob)
+    ref, _ = PeriodicOracle(prob).run()
+    r = rel(u, ref)
+    print(f"  rel-L2 = {r:.3e}", flush=True)
+    assert np.all(np.isfinite(u))
+    assert r <= tol, r
+    return r
+
+
+def test_c0_1d_full():
+    check(c0_problem())
+
+
+@pytest.mark.parametrize("M", [(64, 96), (96, 8), (48, 384), (1024, 16), (16, 2048), (24, 24)])
+def test_2d_shapes(M):
+    check(periodic_problem_from_seed(31, 2, M, 0.2, 40))
+
+
+@pytest.mark.parametrize("M", [(256,), (384,), (2048,), (8,)])
+def test_1d_shapes(M):
+    check(periodic_problem_from_seed(32, 1, M, 0.3, 30))
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_lower_orders(order):
+    check(periodic_problem_from_seed(33, 2, (32, 64), 0.2, 25, order=order))
+    check(periodic_problem_from_seed(34, 1, (128,), 0.2, 25, order=order))
+
+
+def test_stepwise_field():
+    check(periodic_problem_from_seed(35, 2, (64, 64), 0.3, 60, A_kind="stepwise"))
+
+
+def test_no_field():
+    check(periodic_problem_from_seed(36, 2, (64, 32), 0.3, 30, A_kind="none"))
+
+
+@pytest.mark.parametrize("nsteps", [1, 2, 6, 7, 8])
+def test_runs_ending_in_startup(nsteps):
+    check(periodic_problem_from_seed(37, 2, (32, 32), 0.01 * nsteps, nsteps))
+
+
+def test_step_in_pieces_is_bitwise_run():
+    from paper_2001_06113_amd.tdse import Plan
+
+    prob = periodic_problem_from_seed(38, 2, (64, 64), 0.3, 30)
+    plan = Plan.from_problem(prob, device="cuda:0")
+    full = plan.run(prob.u0).cpu().numpy()
+    plan.set_state(prob.u0)
+    for k in (3, 4, 1, 10, 12):
+        plan.step(k)
+    pieces = plan.get_state().cpu().numpy()
+    assert np.array_equal(full, pieces)
+    assert plan.query(1) == 30.0
+
+
+def test_c1_size_200_steps():
+    # the 512 x 512 kernels and launch shapes timed by the benchmark, 200 steps at dt = 1e-3
+    check(periodic_problem_from_seed(1, 2, (512, 512), 0.2, 200))
+
+
+def test_trapezoid_invariant_full_c1():
+    # order 2: ||(1 + i dt/2 V(t_N)) u_N|| = ||(1 + i dt/2 V(0)) u_0|| exactly, at full size and length
+    from paper_2001_06113_amd.tdse import Plan
+
+    prob = periodic_problem_from_seed(1, 2, (512, 512), 2.0, 2000, order=2)
+    plan = Plan.from_problem(prob, device="cuda:0")
+    u = plan.run(prob.u0).cpu().numpy()
+    dt = prob.dt
+
+    def Vt(t):
+        return sum(prob.f(r, t) * V for r, V in enumerate(prob.V_fields))
+
+    a = np.linalg.norm((1 + 0.5j * dt * Vt(2.0)) * u)
+    b = np.linalg.norm((1 + 0.5j * dt * Vt(0.0)) * prob.u0)
+    assert abs(a - b) / b < 1e-11, (a, b)
