@@ -1,0 +1,178 @@
+"""Benchmark: mode-updates/s of the 2D periodic FP64 marcher on one MI355X.
+
+Workload: 2D periodic TDSE, 512 x 512 grid, T = 2, 2000 steps of the 8th-order
+implicit Adams scheme (6 Richardson start-up steps), four-well potential with
+sinusoidal modulation and a sin^2 pulse, seed 1, complex128 (synthetic inputs).
+One benchmark "step" is one whole run [0, T] on inputs already resident in
+device memory: start-up plus 1994 Adams steps.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--workload c1|c3fp64]
+
+Prints one JSON line.  value = modes x time steps / wall time of the K timed
+runs (whole job).  roofline: algorithmic bytes of the dominant kernel (the
+Adams row pass) per launch / its mean duration measured with HIP events on the
+library's stream during the timed runs.  cpu_baseline: the FP64 oracle on the
+host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=60, help="time steps in the oracle sample")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3fp64"])
+    ap.add_argument("--prof-runs", type=int, default=3, help="eager runs timed per kernel with HIP events")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run device copies of 256 MiB (to scale HBM byte counters) and exit")
+    return ap.parse_args()
+
+
+def calibrate_copy():
+    import torch
+
+    n = 256 * 1024 * 1024 // 16
+    a = torch.ones(n, dtype=torch.complex128, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 16, "copy_bytes_written": b.numel() * 16, "copies": 5}))
+
+
+def cpu_baseline(prob, nsteps: int) -> dict:
+    """Time the FP64 oracle (as written) on the first `nsteps` steps."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.periodic import PeriodicOracle
+
+    with threadpool_limits(limits=1):
+        orc = PeriodicOracle(prob)
+        t0 = time.perf_counter()
+        orc.run(nsteps=nsteps)
+        dt = time.perf_counter() - t0
+    modes = float(prob.u0.size)
+    return {
+        "value": modes * nsteps / dt,
+        "unit": "mode-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{prob.name} at full size ({'x'.join(map(str, prob.M))}), first {nsteps} of {prob.nsteps} "
+                  f"steps (6 Richardson start-up steps + {nsteps - prob.start_steps} Adams steps), "
+                  f"numpy/pocketfft single thread, {dt:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2001_06113_amd import _lib
+    from paper_2001_06113_amd.tdse import (Q_BYTES_COL, Q_BYTES_ROW, Q_PROF_MS_COL, Q_PROF_MS_ROW,
+                                           Q_PROF_N_COL, Q_PROF_N_ROW, Plan)
+    from workloads import c1_problem, periodic_problem_from_seed
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2001_06113_amd import build
+
+        build.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    if args.workload == "c1":
+        prob = c1_problem()
+        wname = "2D periodic TDSE 512x512, T=2, 2000 steps AM8 (config 1)"
+    else:
+        prob = periodic_problem_from_seed(3, 2, (1024, 1024), 2.0, 2000, name="C3-fp64")
+        wname = "2D periodic TDSE 1024x1024, T=2, 2000 steps AM8, FP64 (config 3 geometry)"
+    plan = Plan.from_problem(prob, device=dev)
+    u0 = torch.as_tensor(prob.u0).to(dev)
+    out = torch.empty_like(u0)
+    modes = float(u0.numel())
+
+    # timed region: whole runs replayed from one captured hipGraph
+    plan.use_graph(True)
+    for _ in range(max(args.warmup, 1)):
+        plan.run(u0, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run(u0, out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ok = bool(torch.isfinite(torch.view_as_real(out)).all().item())
+
+    # per-kernel durations: the same runs launched eagerly, every Adams
+    # column and row pass bracketed by HIP events on the library's stream
+    plan.profile(True)
+    for _ in range(args.prof_runs):
+        plan.run(u0, out)
+    row_ms, col_ms = plan.query(Q_PROF_MS_ROW), plan.query(Q_PROF_MS_COL)
+    n_row, n_col = plan.query(Q_PROF_N_ROW), plan.query(Q_PROF_N_COL)
+    plan.profile(False)
+
+    ms_per_run = wall * 1e3 / args.steps
+    value = modes * prob.nsteps * args.steps / wall
+    row_us, col_us = row_ms * 1e3 / max(n_row, 1), col_ms * 1e3 / max(n_col, 1)
+    row_b, col_b = plan.query(Q_BYTES_ROW), plan.query(Q_BYTES_COL)
+    dom_b, dom_us, dom = (row_b, row_us, "row") if row_us * 1 >= col_us else (col_b, col_us, "col")
+    achieved = dom_b / (dom_us * 1e-6) / 1e9 if dom_us > 0 else None
+    res = {
+        "metric": "mode-updates/s",
+        "value": value,
+        "unit": "mode-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_run,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wname, "grid": list(prob.M), "time_steps": prob.nsteps,
+                   "order": prob.order, "modes": int(modes), "seed": 1 if args.workload == "c1" else 3,
+                   "finite": ok},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": None,
+            "kernel": f"Adams {dom} pass (k_{dom})",
+            "bytes_per_launch": dom_b,
+            "mean_launch_us": dom_us,
+            "row_pass_us": row_us,
+            "col_pass_us": col_us,
+        },
+        "adams_step_us_eager": row_us + col_us,
+        "graph_us_per_time_step": wall * 1e6 / (args.steps * prob.nsteps),
+        "steady_mode_updates_per_s_eager": modes / ((row_us + col_us) * 1e-6) if row_us > 0 else None,
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

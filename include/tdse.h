@@ -74,7 +74,7 @@ typedef void (*tdse_vector_fn)(double t, double* A_out, void* ctx);
 typedef struct {
   int32_t dim;             /* 1 or 2                                         */
   int32_t domain;          /* TDSE_PERIODIC (TDSE_FREE: EUNSUPPORTED here)   */
-  int32_t M[2];            /* grid points per axis: even, 2^a 3^b, 2..4096   */
+  int32_t M[2];            /* grid points per axis: 2^a or 3*2^a, 8..3072    */
   double  T;               /* final time > 0                                 */
   int32_t nsteps;          /* number of steps, dt = T / nsteps               */
   int32_t order;           /* implicit Adams order n in {2,4,6,8}            */
@@ -129,10 +129,29 @@ int tdse_run(tdse_plan_t plan, const void* u0, void* uT, int32_t on_device);
 #define TDSE_Q_STEPS_DONE     1   /* steps taken since set_state               */
 #define TDSE_Q_DT             2
 #define TDSE_Q_BYTES_PER_STEP 3   /* algorithmic HBM bytes of one Adams step   */
+#define TDSE_Q_PROF_MS_COL    8   /* profiling: summed ms of Adams column passes */
+#define TDSE_Q_PROF_MS_ROW    9   /* profiling: summed ms of Adams row passes  */
+#define TDSE_Q_PROF_N_COL    10   /* profiling: number of timed column passes  */
+#define TDSE_Q_PROF_N_ROW    11   /* profiling: number of timed row passes     */
+#define TDSE_Q_BYTES_COL     12   /* algorithmic HBM bytes of one Adams column pass */
+#define TDSE_Q_BYTES_ROW     13   /* algorithmic HBM bytes of one Adams row pass    */
 #define TDSE_Q_MU             16  /* + j: Adams weight mu_j                    */
 #define TDSE_Q_RICHARDSON     32  /* + l: weight of the 2^l-sub-step result    */
 #define TDSE_Q_PHI            64  /* + axis: phi_axis(T)                       */
 int tdse_query(tdse_plan_t plan, int32_t key, double* value);
+
+/* Per-kernel timing: with enable != 0 every implicit Adams column and row
+ * pass is bracketed by HIP events on the bound stream; the TDSE_Q_PROF_*
+ * queries synchronize that stream and return the sums since the last call
+ * with enable != 0.  enable = 0 stops recording. */
+int tdse_profile(tdse_plan_t plan, int32_t enable);
+
+/* Whole-run graph replay: with enable != 0, tdse_run captures the complete
+ * step sequence of [0, T] into a hipGraph on its first call and replays it on
+ * later calls (the u0 and uT copies stay outside the graph).  Needs a
+ * non-default stream at tdse_bind; EINVAL otherwise.  Profiling
+ * (tdse_profile) runs eagerly.  tdse_bind drops a captured graph. */
+int tdse_graph(tdse_plan_t plan, int32_t enable);
 
 /* Release the plan (not the caller's workspace). */
 void tdse_destroy(tdse_plan_t plan);

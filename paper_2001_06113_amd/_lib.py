@@ -27,7 +27,7 @@ class Problem(C.Structure):
 EXPORTS = [
     "tdse_plan", "tdse_workspace_size", "tdse_bind", "tdse_set_state", "tdse_step",
     "tdse_get_state", "tdse_run", "tdse_query", "tdse_destroy", "tdse_status_string",
-    "tdse_last_error",
+    "tdse_last_error", "tdse_profile", "tdse_graph",
 ]
 
 _lib = None
@@ -50,6 +50,10 @@ def load() -> C.CDLL:
     lib.tdse_get_state.argtypes = [P, P, C.c_int32]
     lib.tdse_run.argtypes = [P, P, P, C.c_int32]
     lib.tdse_query.argtypes = [P, C.c_int32, C.POINTER(C.c_double)]
+    lib.tdse_graph.argtypes = [P, C.c_int32]
+    lib.tdse_graph.restype = C.c_int
+    lib.tdse_profile.argtypes = [P, C.c_int32]
+    lib.tdse_profile.restype = C.c_int
     lib.tdse_destroy.argtypes = [P]
     lib.tdse_destroy.restype = None
     lib.tdse_status_string.argtypes = [C.c_int]

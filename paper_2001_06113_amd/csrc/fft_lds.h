@@ -1,10 +1,15 @@
-// LDS-resident complex FFTs along one line, for gfx950 (64-wide wavefronts).
+// Register-resident line FFTs with LDS exchanges, for gfx950 (64-wide waves).
 //
-// A line of N complex values sits contiguously in LDS.  The transform is a
-// self-sorting (Stockham) sequence of radix-R passes: pass p reads butterfly
-// inputs j + r*N/R, twiddles them by W_{Ns R}^{r k} with k = j mod Ns, forms
-// the R-point DFT in registers and writes it to (j/Ns)*Ns*R + k + r*Ns.
-// Every pass is in place: all reads, one barrier, all writes, one barrier.
+// A line of N complex values is shared by TL threads; thread t keeps the EPT =
+// N/TL elements t + TL*m (m < EPT) in registers.  The transform is a
+// self-sorting (Stockham) sequence of radix-R passes, R dividing EPT: pass p
+// takes butterfly j = t + b*TL (b < EPT/R) from registers (inputs j + r*N/R,
+// i.e. v[b + r*EPT/R]), twiddles by W_{Ns R}^{r k} with k = j mod Ns, forms
+// the R-point DFT and writes it to (j/Ns)*Ns*R + k + r*Ns.  Between passes
+// the outputs go through LDS and come back in the t + TL*m layout; the last
+// pass writes its outputs straight back to registers, again in that layout.
+// A line therefore enters and leaves the transform in registers, in the same
+// element layout, which is also the layout of the fused pointwise work.
 //
 // Forward uses exp(-2 pi i jk/N), inverse exp(+2 pi i jk/N); neither scales.
 // Twiddles come from a table tw[m] = exp(-2 pi i m / N), m < N, built on the
@@ -14,21 +19,9 @@
 
 namespace tdse {
 
-template <typename R_>
-struct cplx_t;
-
-template <>
-struct cplx_t<double> { using type = double2; };
-template <>
-struct cplx_t<float> { using type = float2; };
-
 template <typename C>
 __device__ __forceinline__ C cmul(C a, C b) {
   return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-template <typename C>
-__device__ __forceinline__ C cmulc(C a, C b) {  // a * conj(b)
-  return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 template <typename C>
 __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
@@ -58,8 +51,7 @@ __device__ __forceinline__ void dft3(C* v) {
   C t1 = cadd(b, d);
   C t2 = csub(b, d);
   C m1 = C{a.x + c * t1.x, a.y + c * t1.y};
-  // s * i * t2
-  C m2 = C{-s * t2.y, s * t2.x};
+  C m2 = C{-s * t2.y, s * t2.x};  // s * i * t2
   v[0] = cadd(a, t1);
   v[1] = cadd(m1, m2);
   v[2] = csub(m1, m2);
@@ -81,14 +73,13 @@ template <bool INV, typename C>
 __device__ __forceinline__ void dft8(C* v) {
   using T = decltype(v[0].x);
   const T h = T(0.70710678118654752440);
-  // stage 1: radix-2 between halves
   C a[8];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     a[r] = cadd(v[r], v[r + 4]);
     a[r + 4] = csub(v[r], v[r + 4]);
   }
-  // twiddles W8^r on the odd half: 1, (1 -/+ i)/sqrt2, -/+i, (-1 -/+ i)/sqrt2
+  // W8^r on the difference half: 1, (1 -/+ i)/sqrt2, -/+ i, (-1 -/+ i)/sqrt2
   {
     C t = a[5];
     a[5] = INV ? C{h * (t.x - t.y), h * (t.x + t.y)} : C{h * (t.x + t.y), h * (t.y - t.x)};
@@ -100,7 +91,6 @@ __device__ __forceinline__ void dft8(C* v) {
   C o[4] = {a[4], a[5], a[6], a[7]};
   dft4<INV>(e);
   dft4<INV>(o);
-  // outputs: even frequencies from e, odd from o
   v[0] = e[0]; v[2] = e[1]; v[4] = e[2]; v[6] = e[3];
   v[1] = o[0]; v[3] = o[1]; v[5] = o[2]; v[7] = o[3];
 }
@@ -115,64 +105,87 @@ __device__ __forceinline__ void dft_small(C* v) {
 
 // ---------------------------------------------------------------- radix plan
 
-// next radix for a remaining length: 8 while possible, then 4, 2, 3
-__host__ __device__ constexpr int next_radix(int rem) {
-  return (rem % 8 == 0) ? 8 : (rem % 4 == 0 ? 4 : (rem % 2 == 0 ? 2 : (rem % 3 == 0 ? 3 : 1)));
+// Largest radix in {8, 4, 2} dividing both the remaining length and EPT;
+// 3 once the remaining length is odd.
+__host__ __device__ constexpr int pick_radix(int rem, int ept) {
+  return (rem % 8 == 0 && ept % 8 == 0) ? 8
+       : (rem % 4 == 0 && ept % 4 == 0) ? 4
+       : (rem % 2 == 0 && ept % 2 == 0) ? 2
+       : (rem % 3 == 0 && ept % 3 == 0) ? 3 : 1;
 }
 
-// One Stockham pass over a line in LDS.  Tl threads share the line; thread t
-// handles butterflies t, t + Tl, ...  All threads of the block must call it.
-template <int N, int R, int Ns, bool INV, int Tl, typename C>
-__device__ __forceinline__ void stockham_pass(C* line, int t, const C* __restrict__ tw) {
-  constexpr int NB = N / R;
-  constexpr int BPT = (NB + Tl - 1) / Tl;
-  constexpr int TWS = N / (Ns * R);
-  C v[BPT][R];
-#pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    const int j = t + b * Tl;
-    if (NB % Tl == 0 || j < NB) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = line[j + r * NB];
-    }
+__host__ __device__ constexpr bool plan_ok(int N, int ept) {
+  int ns = 1;
+  while (ns < N) {
+    const int r = pick_radix(N / ns, ept);
+    if (r == 1) return false;
+    ns *= r;
   }
-  __syncthreads();
+  return ns == N && N % ept == 0;
+}
+
+// LDS slot of line element p: one 16-byte pad after every 8 elements, so the
+// radix-8 scatter (lane stride 8 elements) and the contiguous gather both
+// spread over all banks.  A line needs lds_line_len(N) slots.
+__host__ __device__ constexpr int lds_slot(int p) { return p + (p >> 3); }
+__host__ __device__ constexpr int lds_line_len(int N) { return N + (N >> 3); }
+
+// Twiddle W_{Ns R}^{e} = tw[e * N / (Ns R)], conjugated for the inverse.
+template <bool INV, typename C>
+__device__ __forceinline__ C twiddle(const C* tw, int idx) {
+  C w = tw[idx];
+  if (INV) w.y = -w.y;
+  return w;
+}
+
+template <int N, int TL, int Ns, bool INV, typename C>
+__device__ __forceinline__ void fft_regs_rec(C* v, int t, C* line, const C* tw) {
+  constexpr int EPT = N / TL;
+  constexpr int R = pick_radix(N / Ns, EPT);
+  constexpr int B = EPT / R;   // butterflies per thread
+  constexpr int TWS = N / (Ns * R);
+  constexpr bool LAST = (Ns * R == N);
+  C x[B][R];
 #pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    const int j = t + b * Tl;
-    if (NB % Tl == 0 || j < NB) {
+  for (int b = 0; b < B; ++b) {
+    const int j = t + b * TL;
+    const int k = (Ns == 1) ? 0 : (j % Ns);
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[b][r] = v[b + r * B];
+    if constexpr (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) x[b][r] = cmul(x[b][r], twiddle<INV>(tw, r * k * TWS));
+    }
+    dft_small<R, INV>(x[b]);
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b + r * B] = x[b][r];
+  } else {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + b * TL;
       const int k = (Ns == 1) ? 0 : (j % Ns);
-      if constexpr (Ns > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          C w = tw[r * k * TWS];
-          if (INV) w.y = -w.y;
-          v[b][r] = cmul(v[b][r], w);
-        }
-      }
-      dft_small<R, INV>(v[b]);
       const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) line[base + r * Ns] = v[b][r];
+      for (int r = 0; r < R; ++r) line[lds_slot(base + r * Ns)] = x[b][r];
     }
-  }
-  __syncthreads();
-}
-
-template <int N, int Ns, bool INV, int Tl, typename C>
-__device__ __forceinline__ void fft_line_rec(C* line, int t, const C* __restrict__ tw) {
-  if constexpr (Ns < N) {
-    constexpr int R = next_radix(N / Ns);
-    static_assert(R > 1, "line length must be 2^a 3^b");
-    stockham_pass<N, R, Ns, INV, Tl>(line, t, tw);
-    fft_line_rec<N, Ns * R, INV, Tl>(line, t, tw);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = line[lds_slot(t + TL * m)];
+    __syncthreads();
+    fft_regs_rec<N, TL, Ns * R, INV>(v, t, line, tw);
   }
 }
 
-// Full FFT of one LDS line of length N by Tl cooperating threads.
-template <int N, bool INV, int Tl, typename C>
-__device__ __forceinline__ void fft_line(C* line, int t, const C* __restrict__ tw) {
-  if constexpr (N > 1) fft_line_rec<N, 1, INV, Tl>(line, t, tw);
+// FFT of one line held as v[m] = x[t + TL*m]; `line` is lds_line_len(N)
+// elements of LDS scratch for this line.  Every thread of the block must call it (barriers).
+template <int N, int TL, bool INV, typename C>
+__device__ __forceinline__ void fft_regs(C* v, int t, C* line, const C* tw) {
+  static_assert(plan_ok(N, N / TL), "line length must factor into radices dividing N/TL");
+  if constexpr (N > 1) fft_regs_rec<N, TL, 1, INV>(v, t, line, tw);
 }
 
 }  // namespace tdse

@@ -268,6 +268,28 @@ struct tdse_plan_s {
   bool bound = false;
   int cur = -1;   // steps taken since set_state; -1: no state
   int ucur = 0;   // which physical buffer holds u(t_cur)
+  // per-kernel event timing (tdse_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<size_t, int>> prof_marks;  // (first event index, 0 col / 1 row)
+
+  // whole-run graph (tdse_graph): captured on the first tdse_run, replayed after
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_ucur = 0;
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  }
+  ~tdse_plan_s() {
+    drop_graph();
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
 
   double2* B() const { return (double2*)(ws + o_B); }
   double2* ring() const { return (double2*)(ws + o_ring); }
@@ -348,6 +370,29 @@ void phase_req(const tdse_plan_s* p, LineArgs& a, int nj, double t_b, double tau
 int launch(const tdse_plan_s* p, bool col, const LineArgs& a) {
   hipError_t e = col ? launch_col_pass(p->M1, a, p->stream) : launch_row_pass(p->M2, a, p->stream);
   if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return TDSE_OK;
+}
+
+hipEvent_t next_event(tdse_plan_s* p) {
+  if (p->ev_used == p->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p->ev_pool.push_back(e);
+  }
+  return p->ev_pool[p->ev_used++];
+}
+
+// launch an implicit Adams pass, bracketed by events when profiling
+int launch_timed(tdse_plan_s* p, bool col, const LineArgs& a) {
+  if (!p->prof) return launch(p, col, a);
+  const size_t first = p->ev_used;
+  hipEvent_t e0 = next_event(p), e1 = next_event(p);
+  if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
+  HIP_TRY(hipEventRecord(e0, p->stream));
+  int s = launch(p, col, a);
+  if (s) return s;
+  HIP_TRY(hipEventRecord(e1, p->stream));
+  p->prof_marks.push_back({first, col ? 0 : 1});
   return TDSE_OK;
 }
 
@@ -471,7 +516,7 @@ int op_am_step(tdse_plan_s* p, int m, bool write_u) {
   c.csolve = p->mu[0] * p->dt;
   if (write_u) c.uout = p->u(p->ucur);
   if (m < p->nsteps) phase_req(p, c, n - 1, 0.0, p->dt, true, m + 1);
-  int s = launch(p, true, c);
+  int s = launch_timed(p, true, c);
   if (s) return s;
   if (m == p->nsteps) return TDSE_OK;
   LineArgs r = base_args(p);
@@ -486,10 +531,10 @@ int op_am_step(tdse_plan_s* p, int m, bool write_u) {
     r.ch[j] = p->dt * p->mu[j];
     r.slot_r[j] = ((m + 1 - j) % (n - 1) + (n - 1)) % (n - 1);
   }
-  return launch(p, false, r);
+  return launch_timed(p, false, r);
 }
 
-bool good_len(int M) { return M >= 8 && M <= 4096 && M % 2 == 0 && line_length_supported(M); }
+bool good_len(int M) { return M >= 8 && M <= 3072 && M % 2 == 0 && line_length_supported(M); }
 
 }  // namespace
 
@@ -519,7 +564,7 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   if (prob->domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "free-space domain is not available in this build");
   if (prob->precision != TDSE_FP64) return fail(TDSE_EUNSUPPORTED, "only TDSE_FP64 is available in this build");
   for (int a = 0; a < prob->dim; ++a)
-    if (!good_len(prob->M[a])) return fail(TDSE_EINVAL, "grid size must be even, 2^a 3^b, 8..4096");
+    if (!good_len(prob->M[a])) return fail(TDSE_EINVAL, "grid size must be 2^a or 3*2^a, 8..3072");
   if (!(prob->T > 0.0) || prob->nsteps < 1) return fail(TDSE_EINVAL, "need T > 0 and nsteps >= 1");
   if (prob->order < 2 || prob->order > 8 || prob->order % 2) return fail(TDSE_EINVAL, "order must be 2, 4, 6 or 8");
   if (prob->nV < 1 || prob->nV > MAXV || !prob->V_fields) return fail(TDSE_EINVAL, "need 1..8 potential fields");
@@ -598,6 +643,7 @@ int tdse_bind(tdse_plan_t p, void* ws, size_t bytes, void* stream) {
   if (!p || !ws) return fail(TDSE_EINVAL, "NULL argument");
   if (bytes < p->total) return fail(TDSE_ENOMEM, "workspace smaller than tdse_workspace_size");
   if (((uintptr_t)ws) & 255) return fail(TDSE_EINVAL, "workspace must be 256-byte aligned");
+  p->drop_graph();
   p->ws = (char*)ws;
   p->ws_bytes = bytes;
   p->stream = (hipStream_t)stream;
@@ -669,9 +715,44 @@ int tdse_get_state(tdse_plan_t p, void* u, int32_t on_device) {
 int tdse_run(tdse_plan_t p, const void* u0, void* uT, int32_t on_device) {
   int s = tdse_set_state(p, u0, on_device);
   if (s) return s;
-  s = tdse_step(p, p->nsteps);
-  if (s) return s;
+  if (!p->use_graph || p->prof) {
+    s = tdse_step(p, p->nsteps);
+    if (s) return s;
+    return tdse_get_state(p, uT, on_device);
+  }
+  if (!p->gexec) {
+    // capture the whole step sequence once; kernel arguments depend only on
+    // the plan and the bound workspace
+    HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    s = tdse_step(p, p->nsteps);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->stream, &g);
+    if (s) {
+      if (g) (void)hipGraphDestroy(g);
+      p->cur = -1;
+      return s;
+    }
+    if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    p->graph = g;
+    e = hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      p->drop_graph();
+      return fail(TDSE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    p->graph_ucur = p->ucur;
+  }
+  HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
+  p->cur = p->nsteps;
+  p->ucur = p->graph_ucur;
   return tdse_get_state(p, uT, on_device);
+}
+
+int tdse_graph(tdse_plan_t p, int32_t enable) {
+  if (!p) return fail(TDSE_EINVAL, "NULL plan");
+  if (enable && !p->stream) return fail(TDSE_EINVAL, "graph replay needs a non-default stream");
+  p->use_graph = enable != 0;
+  if (!p->use_graph) p->drop_graph();
+  return TDSE_OK;
 }
 
 int tdse_query(tdse_plan_t p, int32_t key, double* value) {
@@ -686,6 +767,29 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     *value = per * (double)p->P;
     return TDSE_OK;
   }
+  if (key >= TDSE_Q_PROF_MS_COL && key <= TDSE_Q_PROF_N_ROW) {
+    const int kind = (key == TDSE_Q_PROF_MS_COL || key == TDSE_Q_PROF_N_COL) ? 0 : 1;
+    const bool count = key >= TDSE_Q_PROF_N_COL;
+    if (!p->prof_marks.empty()) HIP_TRY(hipStreamSynchronize(p->stream));
+    double ms = 0.0, nk = 0.0;
+    for (auto& mk : p->prof_marks) {
+      if (mk.second != kind) continue;
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, p->ev_pool[mk.first], p->ev_pool[mk.first + 1]));
+      ms += t;
+      nk += 1.0;
+    }
+    *value = count ? nk : ms;
+    return TDSE_OK;
+  }
+  if (key == TDSE_Q_BYTES_COL || key == TDSE_Q_BYTES_ROW) {
+    // column pass: tile in and out (32) + the potential fields (8 nV);
+    // row pass: tile in and out (32), B in and out (32), n-2 history reads and
+    // one history write (16 (n-1))
+    const double per = key == TDSE_Q_BYTES_COL ? 32.0 + 8.0 * p->nV : 64.0 + 16.0 * (p->order - 1);
+    *value = per * (double)p->P;
+    return TDSE_OK;
+  }
   if (key >= TDSE_Q_MU && key < TDSE_Q_MU + p->order) { *value = p->mu[key - TDSE_Q_MU]; return TDSE_OK; }
   if (key >= TDSE_Q_RICHARDSON && key < TDSE_Q_RICHARDSON + p->L) { *value = p->rich[key - TDSE_Q_RICHARDSON]; return TDSE_OK; }
   if (key >= TDSE_Q_PHI && key < TDSE_Q_PHI + p->dim) {
@@ -695,6 +799,14 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     return TDSE_OK;
   }
   return fail(TDSE_EINVAL, "unknown query key");
+}
+
+int tdse_profile(tdse_plan_t p, int32_t enable) {
+  if (!p) return fail(TDSE_EINVAL, "NULL plan");
+  p->prof = enable != 0;
+  p->ev_used = 0;
+  p->prof_marks.clear();
+  return TDSE_OK;
 }
 
 void tdse_destroy(tdse_plan_t p) { delete p; }

@@ -16,6 +16,8 @@ FP64, FP32_SPLIT = 0, 1
 F_KINDS = {"const": 0, "sin": 1, "callback": 2}
 A_KINDS = {"none": 0, "pulse_sin2": 1, "callback": 2, "stepwise": 3}
 Q_MODES, Q_STEPS_DONE, Q_DT, Q_BYTES_PER_STEP = 0, 1, 2, 3
+Q_PROF_MS_COL, Q_PROF_MS_ROW, Q_PROF_N_COL, Q_PROF_N_ROW = 8, 9, 10, 11
+Q_BYTES_COL, Q_BYTES_ROW = 12, 13
 Q_MU, Q_RICHARDSON, Q_PHI = 16, 32, 64
 
 
@@ -87,9 +89,12 @@ class Plan:
         _check(self.lib.tdse_workspace_size(handle, C.byref(size)), "tdse_workspace_size")
         self.ws_bytes = size.value
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
-        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        # the plan's own stream (default priority); calls order it after the
+        # caller's current stream and the caller's stream after it
+        self.stream = torch.cuda.Stream(self.device) if stream is None else stream
         _check(self.lib.tdse_bind(handle, C.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
                                   C.c_void_p(self.stream.cuda_stream)), "tdse_bind")
+        self.graph = False
 
     @classmethod
     def from_problem(cls, prob, **kw) -> "Plan":
@@ -112,30 +117,51 @@ class Plan:
         t = torch.as_tensor(u)
         return t.to(device=self.device, dtype=torch.complex128).contiguous().reshape(self.shape)
 
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
     def set_state(self, u0) -> None:
         self._u0 = self._as_device(u0)
+        self._enter()
         _check(self.lib.tdse_set_state(self.handle, C.c_void_p(self._u0.data_ptr()), 1), "tdse_set_state")
 
     def step(self, k: int) -> None:
+        self._enter()
         _check(self.lib.tdse_step(self.handle, int(k)), "tdse_step")
+        self._leave()
 
     def get_state(self) -> torch.Tensor:
         out = torch.empty(self.shape, dtype=torch.complex128, device=self.device)
+        self._enter()
         _check(self.lib.tdse_get_state(self.handle, C.c_void_p(out.data_ptr()), 1), "tdse_get_state")
+        self._leave()
         return out
+
+    def use_graph(self, enable: bool = True) -> None:
+        """Replay the whole run from one captured hipGraph (tdse_graph)."""
+        _check(self.lib.tdse_graph(self.handle, 1 if enable else 0), "tdse_graph")
+        self.graph = bool(enable)
 
     def run(self, u0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         u0d = self._as_device(u0)
         self._u0 = u0d
         if out is None:
             out = torch.empty(self.shape, dtype=torch.complex128, device=self.device)
+        self._enter()
         _check(self.lib.tdse_run(self.handle, C.c_void_p(u0d.data_ptr()), C.c_void_p(out.data_ptr()), 1), "tdse_run")
+        self._leave()
         return out
 
     def query(self, key: int) -> float:
         v = C.c_double()
         _check(self.lib.tdse_query(self.handle, int(key), C.byref(v)), "tdse_query")
         return v.value
+
+    def profile(self, enable: bool) -> None:
+        _check(self.lib.tdse_profile(self.handle, 1 if enable else 0), "tdse_profile")
 
     def close(self) -> None:
         if getattr(self, "handle", None):

@@ -120,3 +120,24 @@ def test_trapezoid_invariant_full_c1():
     a = np.linalg.norm((1 + 0.5j * dt * Vt(2.0)) * u)
     b = np.linalg.norm((1 + 0.5j * dt * Vt(0.0)) * prob.u0)
     assert abs(a - b) / b < 1e-11, (a, b)
+
+
+def test_graph_replay_matches_eager():
+    # the captured whole-run graph, replayed several times with eager work in
+    # between, reproduces the eager run bit for bit every time
+    import torch
+
+    from paper_2001_06113_amd.tdse import Plan
+
+    prob = periodic_problem_from_seed(39, 2, (64, 128), 0.1, 40)
+    plan = Plan.from_problem(prob, device="cuda:0")
+    eager = plan.run(prob.u0).cpu().numpy()
+    plan.use_graph(True)
+    for rep in range(4):
+        got = plan.run(prob.u0).cpu().numpy()
+        assert np.array_equal(got, eager), rep
+        plan.use_graph(False)
+        again = plan.run(prob.u0).cpu().numpy()
+        assert np.array_equal(again, eager)
+        torch.cuda.synchronize()
+        plan.use_graph(True)
