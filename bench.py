@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=60, help="time steps in the oracle sample")
     ap.add_argument("--workload", default="c1", choices=["c1", "c3fp64"])
     ap.add_argument("--prof-runs", type=int, default=3, help="eager runs timed per kernel with HIP events")
+    ap.add_argument("--no-split", action="store_true", help="skip the FP32-split 1024x1024 leg")
+    ap.add_argument("--split-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run device copies of 256 MiB (to scale HBM byte counters) and exit")
     return ap.parse_args()
@@ -75,6 +77,40 @@ def cpu_baseline(prob, nsteps: int) -> dict:
                   f"steps (6 Richardson start-up steps + {nsteps - prob.start_steps} Adams steps), "
                   f"numpy/pocketfft single thread, {dt:.1f} s",
     }
+
+
+def split_leg(steps: int) -> dict:
+    """FP32-split form on the 1024 x 1024 workload (seed 3): throughput of
+    graph-replayed runs, and rel-L2 of u(T) against the FP64 GPU path."""
+    import torch
+
+    from paper_2001_06113_amd.tdse import Plan
+    from workloads import c3_problem
+
+    dev = torch.device("cuda:0")
+    res = {}
+    outs = {}
+    for prec in ("fp32split", "fp64"):
+        prob = c3_problem(precision=prec)
+        plan = Plan.from_problem(prob, device=dev)
+        plan.use_graph(True)
+        u0 = torch.as_tensor(prob.u0).to(dev)
+        out = torch.empty_like(u0)
+        plan.run(u0, out)
+        torch.cuda.synchronize()
+        n = steps if prec == "fp32split" else 1
+        t0 = time.perf_counter()
+        for _ in range(n):
+            plan.run(u0, out)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        outs[prec] = out.clone()
+        res[prec] = u0.numel() * prob.nsteps * n / wall
+        plan.close()
+    err = (torch.linalg.vector_norm(outs["fp32split"] - outs["fp64"]) / torch.linalg.vector_norm(outs["fp64"])).item()
+    return {"workload": "2D periodic TDSE 1024x1024, T=2, 2000 steps AM8 (config 3), FP32-split",
+            "value": res["fp32split"], "unit": "mode-updates/s", "fp64_value": res["fp64"],
+            "speedup_vs_fp64": res["fp32split"] / res["fp64"], "rel_l2_vs_fp64": err, "bar": 1e-6}
 
 
 def main():
@@ -169,6 +205,8 @@ def main():
         "graph_us_per_time_step": wall * 1e6 / (args.steps * prob.nsteps),
         "steady_mode_updates_per_s_eager": modes / ((row_us + col_us) * 1e-6) if row_us > 0 else None,
     }
+    if not args.no_split:
+        res["split"] = split_leg(args.split_steps)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     print(json.dumps(res), flush=True)

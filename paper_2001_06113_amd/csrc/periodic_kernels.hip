@@ -1,4 +1,4 @@
-// HIP kernels of the periodic marching scheme (FP64), gfx950.
+// HIP kernels of the periodic marching scheme, gfx950.
 //
 // One implicit step (Section 2.2, eq. (uadamsk)) on an M1 x M2 grid is two
 // passes over HBM, each a register-resident line FFT (fft_lds.h) with the
@@ -21,6 +21,12 @@
 // T_a,j[k] = exp(-i k^2 j dt + i k (phi_a(t_{n+1}) - phi_a(t_{n+1-j}))), the
 // factorised phase of Lemma 1.  A 1D problem is the case M1 = 1.
 //
+// Every kernel is a template on the transform type C: double2 (FP64) or
+// float2 (split precision).  In the split form the FFTs, the tile buffer,
+// the history ring, the diagonal solve and the history sum
+// sum_{j>=2} mu_j E^(j) What are complex64, while B, E^(1) uhat, the phase
+// factors, the Richardson accumulator and the physical solution stay FP64.
+//
 // Every global load a pass needs (tile, potential, B, history, phase factors)
 // is issued before its first FFT so their latencies overlap.
 #include "fft_lds.h"
@@ -28,13 +34,33 @@
 
 namespace tdse {
 
+template <typename C>
+struct real_of;
+template <>
+struct real_of<double2> { using type = double; };
+template <>
+struct real_of<float2> { using type = float; };
+
+template <typename C>
+__device__ __forceinline__ C from_d(double2 z) {
+  using R = typename real_of<C>::type;
+  return C{(R)z.x, (R)z.y};
+}
+template <typename C>
+__device__ __forceinline__ double2 to_d(C z) { return double2{(double)z.x, (double)z.y}; }
+
 // FFT index -> integer mode in [-M/2, M/2) (M even; M = 1 is the single mode 0)
 __device__ __forceinline__ int signed_mode(int idx, int M) { return idx < ((M + 1) >> 1) ? idx : idx - M; }
 
 // (-i c) * z
-__device__ __forceinline__ double2 mul_mi(double c, double2 z) { return double2{c * z.y, -c * z.x}; }
+template <typename C>
+__device__ __forceinline__ C mul_mi(double c, C z) {
+  using R = typename real_of<C>::type;
+  const R cc = (R)c;
+  return C{cc * z.y, -cc * z.x};
+}
 
-// Per-axis phase table of the next row pass (spread over all workgroups).
+// Per-axis phase table of the next row pass (spread over all workgroups), FP64.
 __device__ __forceinline__ void build_phase_table(const LineArgs& a, int nthreads) {
   const int per = a.M1 + a.M2;
   const int total = a.req.nj * per;
@@ -69,71 +95,77 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 // ------------------------------------------------------------- column pass
 
-template <int N, int LPW, int TL>
+template <typename C, int N, int LPW, int TL>
 __global__ __launch_bounds__(LPW * TL) void k_col(LineArgs a) {
+  using R = typename real_of<C>::type;
   constexpr int NT = LPW * TL;
   constexpr int EPT = N / TL;
   constexpr int PITCH = N > 1 ? lds_line_len(N) + 1 : 1;   // +1 spreads the LPW lines over banks
   constexpr bool TWL = (N > 1 && N <= 1024);
-  __shared__ double2 lds[LPW * PITCH];
-  __shared__ double2 twl[TWL ? N : 1];
+  __shared__ C lds[LPW * PITCH];
+  __shared__ C twl[TWL ? N : 1];
   const int tid = threadIdx.x;
   const int i = tid % LPW, t = tid / LPW;
-  // tiles sharing a 128-byte line of the potential (8-byte elements) share an XCD
+  // tiles sharing a 128-byte line of the potential share an XCD
   const int line = xcd_tile<(16 / LPW > 1 ? 16 / LPW : 1)>(blockIdx.x, gridDim.x) * LPW + i;
   const bool active = line < a.nlines;
   const int mode = a.mode;
+  const R* __restrict__ V = (const R*)a.V;
 
-  double2 v[EPT];
+  C v[EPT];
+  double2 u0[EPT];   // C_FWD reads the complex128 physical solution
   double vv[EPT];
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
-    v[m] = double2{0.0, 0.0};
+    v[m] = C{0, 0};
+    u0[m] = double2{0.0, 0.0};
     vv[m] = 0.0;
     if (active) {
       const int64_t g = (int64_t)line * a.line_stride + (int64_t)(t + TL * m) * a.elem_stride;
-      v[m] = a.src[g];
+      if (mode == C_FWD) u0[m] = ((const double2*)a.src)[g];
+      else v[m] = ((const C*)a.src)[g];
       double p = 0.0;
-      for (int r = 0; r < a.nV; ++r) p += a.fV[r] * a.V[r * a.vstride + g];
+      for (int r = 0; r < a.nV; ++r) p += a.fV[r] * (double)V[r * a.vstride + g];
       vv[m] = p;
     }
   }
   if constexpr (TWL) {
-    for (int q = tid; q < N; q += NT) twl[q] = a.tw[q];
+    for (int q = tid; q < N; q += NT) twl[q] = ((const C*)a.tw)[q];
   }
   if (a.req.nj > 0) build_phase_table(a, NT);
   if constexpr (TWL) __syncthreads();
-  const double2* tw = TWL ? twl : a.tw;
-  double2* myline = &lds[i * PITCH];
+  const C* tw = TWL ? twl : (const C*)a.tw;
+  C* myline = &lds[i * PITCH];
 
   if (mode == C_FWD) {
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
       const double cr = a.alpha_re + a.beta_re * vv[m], ci = a.alpha_im + a.beta_im * vv[m];
-      const double2 u = v[m];
-      v[m] = double2{(cr * u.x - ci * u.y) * a.scale, (cr * u.y + ci * u.x) * a.scale};
+      const double2 u = u0[m];
+      v[m] = from_d<C>(double2{(cr * u.x - ci * u.y) * a.scale, (cr * u.y + ci * u.x) * a.scale});
     }
   } else {  // C_SOLVE
     fft_regs<N, TL, true>(v, t, myline, tw);
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
-      const double2 w = v[m];
-      const double q = a.csolve * vv[m];
-      const double inv = 1.0 / (1.0 + q * q);
+      const C w = v[m];
+      const R q = (R)(a.csolve * vv[m]);
+      const R inv = R(1) / (R(1) + q * q);
       // u = w (1 - i q) / (1 + q^2)
-      const double2 u = double2{(w.x + q * w.y) * inv, (w.y - q * w.x) * inv};
+      const C u = C{(w.x + q * w.y) * inv, (w.y - q * w.x) * inv};
       if (active) {
         const int64_t g = (int64_t)line * a.line_stride + (int64_t)(t + TL * m) * a.elem_stride;
-        if (a.uout) a.uout[g] = u;
+        const double2 ud = to_d(u);
+        if (a.uout) a.uout[g] = ud;
         if (a.uacc) {
           double2 acc = a.acc_first ? double2{0.0, 0.0} : a.uacc[g];
-          acc.x += a.wacc * u.x;
-          acc.y += a.wacc * u.y;
+          acc.x += a.wacc * ud.x;
+          acc.y += a.wacc * ud.y;
           a.uacc[g] = acc;
         }
       }
-      const double s = vv[m] * a.scale;
-      v[m] = double2{s * u.x, s * u.y};
+      const R s = (R)(vv[m] * a.scale);
+      v[m] = C{s * u.x, s * u.y};
     }
   }
   fft_regs<N, TL, false>(v, t, myline, tw);
@@ -141,14 +173,14 @@ __global__ __launch_bounds__(LPW * TL) void k_col(LineArgs a) {
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
       const int64_t g = (int64_t)line * a.line_stride + (int64_t)(t + TL * m) * a.elem_stride;
-      a.dst[g] = v[m];
+      ((C*)a.dst)[g] = v[m];
     }
   }
 }
 
 // ---------------------------------------------------------------- row pass
 
-template <int N, int LPW, int TL>
+template <typename C, int N, int LPW, int TL>
 __global__ __launch_bounds__(LPW * TL) void k_row(LineArgs a) {
   constexpr int NT = LPW * TL;
   constexpr int EPT = N / TL;
@@ -156,8 +188,8 @@ __global__ __launch_bounds__(LPW * TL) void k_row(LineArgs a) {
   constexpr bool PF = EPT <= 4;   // prefetch history and phases into registers
   constexpr bool TWL = (N <= 1024);
   constexpr int PITCH = lds_line_len(N);
-  __shared__ double2 lds[LPW * PITCH];
-  __shared__ double2 twl[TWL ? N : 1];
+  __shared__ C lds[LPW * PITCH];
+  __shared__ C twl[TWL ? N : 1];
   const int tid = threadIdx.x;
   const int i = tid / TL, t = tid % TL;
   const int k1 = blockIdx.x * LPW + i;
@@ -166,16 +198,25 @@ __global__ __launch_bounds__(LPW * TL) void k_row(LineArgs a) {
   const int per = a.M1 + a.M2;
   const int nh = a.nh;
   const int64_t row0 = (int64_t)k1 * a.line_stride;
+  const C* __restrict__ src = (const C*)a.src;
+  const double2* __restrict__ ph = a.ph;
+  const C* __restrict__ ring = (const C*)a.ring;
+  const int64_t rstride = a.ring_stride;
+  const int M1 = a.M1;
+  int slot_r[MAXH + 1];
+#pragma unroll
+  for (int j = 0; j <= MAXH; ++j) slot_r[j] = a.slot_r[j];
 
-  double2 v[EPT];
+  C v[EPT];
   double2 Bp[EPT];
-  double2 Wr[PF ? NH - 1 : 1][EPT];
-  double2 T2[PF ? NH : 1][EPT];
+  C Wr[PF ? NH - 1 : 1][EPT];
+  double2 E1[EPT];               // E^(1) in FP64 (multiplies uhat)
+  C T2[PF ? NH - 1 : 1][EPT];    // axis-2 factors of E^(j), j >= 2, transform precision
   double2 T1[NH];
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
-    v[m] = double2{0.0, 0.0};
-    if (active) v[m] = a.src[row0 + (t + TL * m)];
+    v[m] = C{0, 0};
+    if (active) v[m] = (mode == R_INV) ? from_d<C>(a.Bm[row0 + (t + TL * m)]) : src[row0 + (t + TL * m)];
   }
   if (active && mode == R_AM) {
 #pragma unroll
@@ -185,55 +226,51 @@ __global__ __launch_bounds__(LPW * TL) void k_row(LineArgs a) {
       for (int j = 2; j <= NH; ++j) {
         if (j <= nh) {
 #pragma unroll
-          for (int m = 0; m < EPT; ++m) Wr[j - 2][m] = a.ring[a.slot_r[j] * a.ring_stride + row0 + (t + TL * m)];
+          for (int m = 0; m < EPT; ++m) Wr[j - 2][m] = ring[slot_r[j] * rstride + row0 + (t + TL * m)];
         }
       }
     }
   }
-  if (active && mode != R_FWD) {
+  if (active && mode != R_FWD && mode != R_INV) {
     const int nj = (mode == R_INIT) ? 1 : nh;
+    T1[0] = ph[k1];
 #pragma unroll
-    for (int j = 1; j <= NH; ++j) {
+    for (int m = 0; m < EPT; ++m) E1[m] = cmul(T1[0], ph[M1 + (t + TL * m)]);
+#pragma unroll
+    for (int j = 2; j <= NH; ++j) {
       if (j <= nj) {
-        T1[j - 1] = a.ph[(j - 1) * per + k1];
+        T1[j - 1] = ph[(j - 1) * per + k1];
         if constexpr (PF) {
 #pragma unroll
-          for (int m = 0; m < EPT; ++m) T2[j - 1][m] = a.ph[(j - 1) * per + a.M1 + (t + TL * m)];
+          for (int m = 0; m < EPT; ++m) T2[j - 2][m] = from_d<C>(ph[(j - 1) * per + M1 + (t + TL * m)]);
         }
       }
     }
   }
-  // Phase factor E^(j) and history term What_{n+1-j} at element m, from
-  // registers (PF) or from memory.  Only plain locals are captured: taking the
+  // E^(j), j >= 2, and the history term What_{n+1-j} at element m, from
+  // registers (PF) or memory.  Only plain locals are captured: taking the
   // address of the by-value kernel argument would copy it to scratch.
-  const double2* __restrict__ ph = a.ph;
-  const double2* __restrict__ ring = a.ring;
-  const int64_t rstride = a.ring_stride;
-  const int M1 = a.M1;
-  int slot_r[MAXH + 1];
-#pragma unroll
-  for (int j = 0; j <= MAXH; ++j) slot_r[j] = a.slot_r[j];
-  auto E = [&T1, &T2, ph, per, M1, t](int j, int m) -> double2 {
-    if constexpr (PF) return cmul(T1[j - 1], T2[j - 1][m]);
-    else return cmul(T1[j - 1], ph[(j - 1) * per + M1 + (t + TL * m)]);
+  auto Ej = [&T1, &T2, ph, per, M1, t](int j, int m) -> C {
+    if constexpr (PF) return cmul(from_d<C>(T1[j - 1]), T2[j - 2][m]);
+    else return from_d<C>(cmul(T1[j - 1], ph[(j - 1) * per + M1 + (t + TL * m)]));
   };
-  auto Wh = [&Wr, &slot_r, ring, rstride, row0, t](int j, int m) -> double2 {
+  auto Wh = [&Wr, &slot_r, ring, rstride, row0, t](int j, int m) -> C {
     if constexpr (PF) return Wr[j - 2][m];
     else return ring[slot_r[j] * rstride + row0 + (t + TL * m)];
   };
   if constexpr (TWL) {
-    for (int q = tid; q < N; q += NT) twl[q] = a.tw[q];
+    for (int q = tid; q < N; q += NT) twl[q] = ((const C*)a.tw)[q];
     __syncthreads();
   }
-  const double2* tw = TWL ? twl : a.tw;
-  double2* myline = &lds[i * PITCH];
+  const C* tw = TWL ? twl : (const C*)a.tw;
+  C* myline = &lds[i * PITCH];
 
-  fft_regs<N, TL, false>(v, t, myline, tw);
+  if (mode != R_INV) fft_regs<N, TL, false>(v, t, myline, tw);
 
   if (mode == R_FWD) {
     if (active) {
 #pragma unroll
-      for (int m = 0; m < EPT; ++m) a.fdst[row0 + (t + TL * m)] = v[m];
+      for (int m = 0; m < EPT; ++m) ((C*)a.fdst)[row0 + (t + TL * m)] = v[m];
     }
     return;
   }
@@ -241,58 +278,65 @@ __global__ __launch_bounds__(LPW * TL) void k_row(LineArgs a) {
   // FFT barriers company and touch no memory
   if (!active) {
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) v[m] = double2{0.0, 0.0};
+    for (int m = 0; m < EPT; ++m) v[m] = C{0, 0};
+  } else if (mode == R_INV) {
+    // v already holds the row of B
   } else if (mode == R_AM) {
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
-      const double2 W = v[m];
-      const double2 uh = cadd(Bp[m], mul_mi(a.c0, W));
-      double2 acc = cmul(E(1, m), cadd(uh, mul_mi(a.ch[1], W)));
+      const C W = v[m];
+      const double2 Wd = to_d(W);
+      const double2 uh = cadd(Bp[m], mul_mi(a.c0, Wd));
+      double2 acc = cmul(E1[m], cadd(uh, mul_mi(a.ch[1], Wd)));
+      C hist = C{0, 0};
 #pragma unroll
       for (int j = 2; j <= NH; ++j) {
-        if (j <= nh) acc = cadd(acc, cmul(E(j, m), mul_mi(a.ch[j], Wh(j, m))));
+        if (j <= nh) hist = cadd(hist, cmul(Ej(j, m), mul_mi(a.ch[j], Wh(j, m))));
       }
+      acc = cadd(acc, to_d(hist));
       const int64_t g = row0 + (t + TL * m);
-      if (a.slot_w >= 0) a.ring[a.slot_w * a.ring_stride + g] = W;
+      if (a.slot_w >= 0) ((C*)a.ring)[a.slot_w * rstride + g] = W;
       a.Bm[g] = acc;
-      v[m] = acc;
+      v[m] = from_d<C>(acc);
     }
   } else if (mode == R_INIT) {
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
-      const double2 acc = cmul(E(1, m), v[m]);
+      const double2 acc = cmul(E1[m], to_d(v[m]));
       a.Bm[row0 + (t + TL * m)] = acc;
-      v[m] = acc;
+      v[m] = from_d<C>(acc);
     }
   } else {  // R_FORM: B from uhat (this FFT) and nh history terms, all from the ring
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
-      double2 acc = cmul(E(1, m), v[m]);
+      double2 acc = cmul(E1[m], to_d(v[m]));
       const int64_t g = row0 + (t + TL * m);
+      acc = cadd(acc, cmul(E1[m], mul_mi(a.ch[1], to_d(ring[slot_r[1] * rstride + g]))));
+      C hist = C{0, 0};
 #pragma unroll
-      for (int j = 1; j <= NH; ++j) {  // static j: registers stay registers
-        if (j <= nh) {
-          const double2 Wj = ring[slot_r[j] * rstride + g];
-          acc = cadd(acc, cmul(E(j, m), mul_mi(a.ch[j], Wj)));
-        }
+      for (int j = 2; j <= NH; ++j) {  // static j: registers stay registers
+        if (j <= nh) hist = cadd(hist, cmul(Ej(j, m), mul_mi(a.ch[j], ring[slot_r[j] * rstride + g])));
       }
+      acc = cadd(acc, to_d(hist));
       a.Bm[g] = acc;
-      v[m] = acc;
+      v[m] = from_d<C>(acc);
     }
   }
   fft_regs<N, TL, true>(v, t, myline, tw);
   if (active) {
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) a.dst[row0 + (t + TL * m)] = v[m];
+    for (int m = 0; m < EPT; ++m) ((C*)a.dst)[row0 + (t + TL * m)] = v[m];
   }
 }
 
 // ---------------------------------------------------------------- dispatch
 
-// Column pass: EPT elements per thread (8, or 12 for lengths with a factor
-// 3), LPW columns per workgroup (2 from length 256: enough workgroups to fill
-// the chip at 512 columns), padded LDS lines.
-constexpr int col_ept(int N) { return N == 1 ? 1 : (N % 3 == 0 ? (N < 12 ? N : 12) : (N < 8 ? N : (N >= 256 && N <= 1024 ? 4 : 8))); }
+// Column pass: EPT elements per thread (4 for lengths 256..1024, 8 otherwise,
+// 12 with a factor 3), LPW columns per workgroup (2 from length 256: enough
+// workgroups to fill the chip at 512 columns), padded LDS lines.
+constexpr int col_ept(int N) {
+  return N == 1 ? 1 : (N % 3 == 0 ? (N < 12 ? N : 12) : (N < 8 ? N : (N >= 256 && N <= 1024 ? 4 : 8)));
+}
 constexpr int col_tl(int N) { return N / col_ept(N); }
 constexpr int col_lpw(int N) {
   return N == 1 ? 256 : (N > 1536 ? 1 : (N >= 256 ? 2 : (64 / col_tl(N) > 2 ? 64 / col_tl(N) : 2)));
@@ -301,9 +345,6 @@ constexpr int col_lpw(int N) {
 constexpr int row_ept(int N) { return N % 3 == 0 ? (N < 12 ? N : 12) : (N >= 2048 ? 8 : (N < 4 ? N : 4)); }
 constexpr int row_tl(int N) { return N / row_ept(N); }
 constexpr int row_lpw(int N) { return 128 / row_tl(N) > 1 ? 128 / row_tl(N) : 1; }
-
-int col_lines_per_block(int N) { return col_lpw(N); }
-int row_lines_per_block(int N) { return row_lpw(N); }
 
 #define TDSE_LINE_SIZES(X) \
   X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) \
@@ -320,13 +361,14 @@ bool line_length_supported(int N) {
   }
 }
 
-hipError_t launch_col_pass(int N, const LineArgs& a, hipStream_t s) {
+template <typename C>
+hipError_t col_pass(int N, const LineArgs& a, hipStream_t s) {
   switch (N) {
-#define X(n)                                                                                   \
-  case n: {                                                                                    \
-    constexpr int L = col_lpw(n), T = col_tl(n);                                               \
-    hipLaunchKernelGGL((k_col<n, L, T>), dim3((a.nlines + L - 1) / L), dim3(L * T), 0, s, a); \
-    break;                                                                                     \
+#define X(n)                                                                                      \
+  case n: {                                                                                       \
+    constexpr int L = col_lpw(n), T = col_tl(n);                                                  \
+    hipLaunchKernelGGL((k_col<C, n, L, T>), dim3((a.nlines + L - 1) / L), dim3(L * T), 0, s, a); \
+    break;                                                                                        \
   }
     X(1)
     TDSE_LINE_SIZES(X)
@@ -337,13 +379,14 @@ hipError_t launch_col_pass(int N, const LineArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_row_pass(int N, const LineArgs& a, hipStream_t s) {
+template <typename C>
+hipError_t row_pass(int N, const LineArgs& a, hipStream_t s) {
   switch (N) {
-#define X(n)                                                                                   \
-  case n: {                                                                                    \
-    constexpr int L = row_lpw(n), T = row_tl(n);                                               \
-    hipLaunchKernelGGL((k_row<n, L, T>), dim3((a.nlines + L - 1) / L), dim3(L * T), 0, s, a); \
-    break;                                                                                     \
+#define X(n)                                                                                      \
+  case n: {                                                                                       \
+    constexpr int L = row_lpw(n), T = row_tl(n);                                                  \
+    hipLaunchKernelGGL((k_row<C, n, L, T>), dim3((a.nlines + L - 1) / L), dim3(L * T), 0, s, a); \
+    break;                                                                                        \
   }
     TDSE_LINE_SIZES(X)
 #undef X
@@ -351,6 +394,24 @@ hipError_t launch_row_pass(int N, const LineArgs& a, hipStream_t s) {
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_narrow(const double2* __restrict__ src, float2* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = float2{(float)src[i].x, (float)src[i].y};
+}
+
+hipError_t launch_narrow(const double2* src, float2* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_narrow, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s) {
+  return prec == P_SPLIT ? col_pass<float2>(N, a, s) : col_pass<double2>(N, a, s);
+}
+hipError_t launch_row_pass(int prec, int N, const LineArgs& a, hipStream_t s) {
+  return prec == P_SPLIT ? row_pass<float2>(N, a, s) : row_pass<double2>(N, a, s);
 }
 
 }  // namespace tdse

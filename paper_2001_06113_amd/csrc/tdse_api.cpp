@@ -256,11 +256,18 @@ struct tdse_plan_s {
   int order = 8, ns = 6, L = 4, nsteps = 1, nV = 1, precision = TDSE_FP64;
   double T = 1.0, dt = 1.0;
   std::vector<double> mu, rich;
-  std::vector<double> Vhost;
   TimeFns tf;
-  std::vector<double2> tw1, tw2;
+  // Buffer sets of a "stage": the start-up always runs in FP64 (stage 0);
+  // the implicit Adams steps run in the plan's precision (stage 1, the same
+  // buffers as stage 0 for FP64 plans).
+  struct Stage {
+    int prec = P_FP64;
+    size_t cplx = 16, real = 8;          // bytes of a complex / real element
+    size_t o_ring = 0, o_tmp = 0, o_V = 0, o_tw1 = 0, o_tw2 = 0;
+    std::vector<char> Vhost, tw1, tw2;   // host copies uploaded at bind
+  } st[2];
   // workspace layout
-  size_t o_B = 0, o_ring = 0, o_tmp = 0, o_u[2] = {0, 0}, o_V = 0, o_tw1 = 0, o_tw2 = 0, o_ph = 0, total = 0;
+  size_t o_B = 0, o_u[2] = {0, 0}, o_ph = 0, total = 0;
   // binding and clock
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -292,12 +299,14 @@ struct tdse_plan_s {
   }
 
   double2* B() const { return (double2*)(ws + o_B); }
-  double2* ring() const { return (double2*)(ws + o_ring); }
-  double2* tmp() const { return (double2*)(ws + o_tmp); }
+  void* ring(int g) const { return ws + st[g].o_ring; }
+  void* ring_slot(int g, int s) const { return ws + st[g].o_ring + (size_t)s * P * st[g].cplx; }
+  void* tmp(int g) const { return ws + st[g].o_tmp; }
   double2* u(int i) const { return (double2*)(ws + o_u[i]); }
-  const double* V() const { return (const double*)(ws + o_V); }
+  const void* V(int g) const { return ws + st[g].o_V; }
   double2* ph() const { return (double2*)(ws + o_ph); }
-  const double2* tw(int axis) const { return (const double2*)(ws + (axis == 0 ? o_tw1 : o_tw2)); }
+  const void* tw(int g, int axis) const { return ws + (axis == 0 ? st[g].o_tw1 : st[g].o_tw2); }
+  bool split() const { return precision == TDSE_FP32_SPLIT; }
 
   double t_at(int m) const { return m * dt; }
   void fV_at(double t, double* f) const {
@@ -307,25 +316,29 @@ struct tdse_plan_s {
 
 namespace {
 
-std::vector<double2> twiddles(int N) {
-  std::vector<double2> tw(std::max(N, 1));
+// tw[m] = exp(-2 pi i m / N) from extended precision, rounded once to the
+// transform precision
+std::vector<char> twiddles(int N, bool split) {
+  const int n = std::max(N, 1);
+  std::vector<char> tw(n * (split ? sizeof(float2) : sizeof(double2)));
   for (int m = 0; m < N; ++m) {
     const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)N;
-    tw[m] = double2{(double)cosl(a), (double)sinl(a)};
+    if (split) ((float2*)tw.data())[m] = float2{(float)cosl(a), (float)sinl(a)};
+    else ((double2*)tw.data())[m] = double2{(double)cosl(a), (double)sinl(a)};
   }
   return tw;
 }
 
-LineArgs base_args(const tdse_plan_s* p) {
+LineArgs base_args(const tdse_plan_s* p, int g) {
   LineArgs a;
   std::memset(&a, 0, sizeof(a));
   a.M1 = p->M1;
   a.M2 = p->M2;
-  a.V = p->V();
+  a.V = p->V(g);
   a.nV = p->nV;
   a.vstride = p->P;
   a.scale = 1.0 / (double)p->P;
-  a.ring = p->ring();
+  a.ring = p->ring(g);
   a.ring_stride = p->P;
   a.Bm = p->B();
   a.ph = p->ph();
@@ -334,17 +347,17 @@ LineArgs base_args(const tdse_plan_s* p) {
 }
 
 // column-pass geometry: lines are the M2 columns, elements step by M2
-void col_geom(const tdse_plan_s* p, LineArgs& a) {
+void col_geom(const tdse_plan_s* p, int g, LineArgs& a) {
   a.line_stride = 1;
   a.elem_stride = p->M2;
   a.nlines = p->M2;
-  a.tw = p->tw(0);
+  a.tw = p->tw(g, 0);
 }
-void row_geom(const tdse_plan_s* p, LineArgs& a) {
+void row_geom(const tdse_plan_s* p, int g, LineArgs& a) {
   a.line_stride = p->M2;
   a.elem_stride = 1;
   a.nlines = p->M1;
-  a.tw = p->tw(1);
+  a.tw = p->tw(g, 1);
 }
 
 // phase request for E^(j) at t_b, j = 1..nj, over intervals of length j*tau
@@ -367,8 +380,9 @@ void phase_req(const tdse_plan_s* p, LineArgs& a, int nj, double t_b, double tau
   }
 }
 
-int launch(const tdse_plan_s* p, bool col, const LineArgs& a) {
-  hipError_t e = col ? launch_col_pass(p->M1, a, p->stream) : launch_row_pass(p->M2, a, p->stream);
+int launch(const tdse_plan_s* p, int g, bool col, const LineArgs& a) {
+  const int prec = p->st[g].prec;
+  hipError_t e = col ? launch_col_pass(prec, p->M1, a, p->stream) : launch_row_pass(prec, p->M2, a, p->stream);
   if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
   return TDSE_OK;
 }
@@ -383,72 +397,74 @@ hipEvent_t next_event(tdse_plan_s* p) {
 }
 
 // launch an implicit Adams pass, bracketed by events when profiling
-int launch_timed(tdse_plan_s* p, bool col, const LineArgs& a) {
-  if (!p->prof) return launch(p, col, a);
+int launch_timed(tdse_plan_s* p, int g, bool col, const LineArgs& a) {
+  if (!p->prof) return launch(p, g, col, a);
   const size_t first = p->ev_used;
   hipEvent_t e0 = next_event(p), e1 = next_event(p);
   if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
   HIP_TRY(hipEventRecord(e0, p->stream));
-  int s = launch(p, col, a);
+  int s = launch(p, g, col, a);
   if (s) return s;
   HIP_TRY(hipEventRecord(e1, p->stream));
   p->prof_marks.push_back({first, col ? 0 : 1});
   return TDSE_OK;
 }
 
-// What_m = F(V(t_m) u_m) into ring slot m mod (n-1)
+// What_m = F(V(t_m) u_m) into ring slot m mod (n-1) (start-up stage, FP64)
 int op_history(tdse_plan_s* p, int m) {
-  LineArgs a = base_args(p);
-  col_geom(p, a);
+  const int g = 0;
+  LineArgs a = base_args(p, g);
+  col_geom(p, g, a);
   a.mode = C_FWD;
   a.src = p->u(p->ucur);
-  a.dst = p->tmp();
+  a.dst = p->tmp(g);
   p->fV_at(p->t_at(m), a.fV);
   a.alpha_re = 0.0; a.alpha_im = 0.0; a.beta_re = 1.0; a.beta_im = 0.0;
-  int s = launch(p, true, a);
+  int s = launch(p, g, true, a);
   if (s) return s;
-  LineArgs r = base_args(p);
-  row_geom(p, r);
+  LineArgs r = base_args(p, g);
+  row_geom(p, g, r);
   r.mode = R_FWD;
-  r.src = p->tmp();
-  r.fdst = p->ring() + (int64_t)(m % (p->order - 1)) * p->P;
-  return launch(p, false, r);
+  r.src = p->tmp(g);
+  r.fdst = p->ring_slot(g, m % (p->order - 1));
+  return launch(p, g, false, r);
 }
 
-// One iterated-Richardson start-up step from t_{m-1} to t_m.
+// One iterated-Richardson start-up step from t_{m-1} to t_m (FP64).
 int op_richardson(tdse_plan_s* p, int m) {
+  const int g = 0;
   const double t = p->t_at(m - 1);
   const int src = p->ucur, acc = 1 - p->ucur;
   for (int l = 0; l < p->L; ++l) {
     const int nsub = 1 << l;
     const double delta = p->dt / nsub;
     // B = P F((1 - i delta/2 V(t)) u)
-    LineArgs a = base_args(p);
-    col_geom(p, a);
+    LineArgs a = base_args(p, g);
+    col_geom(p, g, a);
     a.mode = C_FWD;
     a.src = p->u(src);
-    a.dst = p->tmp();
+    a.dst = p->tmp(g);
     p->fV_at(t, a.fV);
     a.alpha_re = 1.0; a.alpha_im = 0.0; a.beta_re = 0.0; a.beta_im = -0.5 * delta;
     phase_req(p, a, 1, t + delta, delta, false, 0);
-    int s = launch(p, true, a);
+    int s = launch(p, g, true, a);
     if (s) return s;
-    LineArgs r = base_args(p);
-    row_geom(p, r);
+    LineArgs r = base_args(p, g);
+    row_geom(p, g, r);
     r.mode = R_INIT;
-    r.src = p->tmp();
-    r.dst = p->tmp();
-    s = launch(p, false, r);
+    r.src = p->tmp(g);
+    r.dst = p->tmp(g);
+    s = launch(p, g, false, r);
     if (s) return s;
     for (int k = 0; k < nsub; ++k) {
       const double ts = t + k * delta;
       const double ts1 = ts + delta;
       const bool last = (k == nsub - 1);
-      LineArgs c = base_args(p);
-      col_geom(p, c);
+      LineArgs c = base_args(p, g);
+      col_geom(p, g, c);
       c.mode = C_SOLVE;
-      c.src = p->tmp();
-      c.dst = p->tmp();
+      c.src = p->tmp(g);
+      c.dst = p->tmp(g);
       p->fV_at(ts1, c.fV);
       c.csolve = 0.5 * delta;
       if (last) {
@@ -458,19 +474,19 @@ int op_richardson(tdse_plan_s* p, int m) {
       } else {
         phase_req(p, c, 1, ts1 + delta, delta, false, 0);
       }
-      s = launch(p, true, c);
+      s = launch(p, g, true, c);
       if (s) return s;
       if (!last) {
-        LineArgs rr = base_args(p);
-        row_geom(p, rr);
+        LineArgs rr = base_args(p, g);
+        row_geom(p, g, rr);
         rr.mode = R_AM;
-        rr.src = p->tmp();
-        rr.dst = p->tmp();
+        rr.src = p->tmp(g);
+        rr.dst = p->tmp(g);
         rr.nh = 1;
         rr.c0 = 0.5 * delta;
         rr.ch[1] = 0.5 * delta;
         rr.slot_w = -1;
-        s = launch(p, false, rr);
+        s = launch(p, g, false, rr);
         if (s) return s;
       }
     }
@@ -479,51 +495,86 @@ int op_richardson(tdse_plan_s* p, int m) {
   return TDSE_OK;
 }
 
-// B_{ns+1} from uhat_ns = F u_ns and the history What_0..What_ns.
+// B_{ns+1} from uhat_ns = F u_ns and the history What_0..What_ns (FP64); a
+// split plan then narrows the history ring and the tile buffer to complex64.
 int op_am_init(tdse_plan_s* p) {
-  const int n = p->order, m = p->ns;
-  LineArgs a = base_args(p);
-  col_geom(p, a);
+  const int n = p->order, m = p->ns, g = 0;
+  LineArgs a = base_args(p, g);
+  col_geom(p, g, a);
   a.mode = C_FWD;
   a.src = p->u(p->ucur);
-  a.dst = p->tmp();
+  a.dst = p->tmp(g);
   a.alpha_re = 1.0; a.alpha_im = 0.0; a.beta_re = 0.0; a.beta_im = 0.0;
   phase_req(p, a, n - 1, 0.0, p->dt, true, m + 1);
-  int s = launch(p, true, a);
+  int s = launch(p, g, true, a);
   if (s) return s;
-  LineArgs r = base_args(p);
-  row_geom(p, r);
+  LineArgs r = base_args(p, g);
+  row_geom(p, g, r);
   r.mode = R_FORM;
-  r.src = p->tmp();
-  r.dst = p->tmp();
+  r.src = p->tmp(g);
+  r.dst = p->tmp(g);
   r.nh = n - 1;
   for (int j = 1; j <= n - 1; ++j) {
     r.slot_r[j] = (m + 1 - j) % (n - 1);
     r.ch[j] = p->dt * p->mu[j];
   }
-  return launch(p, false, r);
+  s = launch(p, g, false, r);
+  if (s) return s;
+  if (p->split()) {
+    hipError_t e = launch_narrow((const double2*)p->ring(0), (float2*)p->ring(1), (int64_t)(n - 1) * p->P, p->stream);
+    if (e == hipSuccess) e = launch_narrow((const double2*)p->tmp(0), (float2*)p->tmp(1), p->P, p->stream);
+    if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("narrow: ") + hipGetErrorString(e));
+  }
+  return TDSE_OK;
 }
 
-// Implicit Adams step m (eq. (uadamsk)).
-int op_am_step(tdse_plan_s* p, int m, bool write_u) {
-  const int n = p->order;
-  LineArgs c = base_args(p);
-  col_geom(p, c);
+// u_m = F^-1 B_m / (1 + i mu_0 dt V(t_m)) in FP64 from the FP64 state B
+// (output of a split plan).
+int op_fp64_output(tdse_plan_s* p, int m) {
+  const int g = 0;
+  LineArgs r = base_args(p, g);
+  row_geom(p, g, r);
+  r.mode = R_INV;
+  r.dst = p->tmp(g);
+  int s = launch(p, g, false, r);
+  if (s) return s;
+  LineArgs c = base_args(p, g);
+  col_geom(p, g, c);
   c.mode = C_SOLVE;
-  c.src = p->tmp();
-  c.dst = p->tmp();
+  c.src = p->tmp(g);
+  c.dst = p->tmp(g);
+  p->fV_at(p->t_at(m), c.fV);
+  c.csolve = p->mu[0] * p->dt;
+  c.uout = p->u(p->ucur);
+  return launch(p, g, true, c);
+}
+
+// Implicit Adams step m (eq. (uadamsk)), stage 1.
+int op_am_step(tdse_plan_s* p, int m, bool write_u) {
+  const int n = p->order, g = 1;
+  if (write_u && p->split()) {
+    int s = op_fp64_output(p, m);
+    if (s) return s;
+    write_u = false;
+  }
+  if (m == p->nsteps && !write_u && p->split()) return TDSE_OK;
+  LineArgs c = base_args(p, g);
+  col_geom(p, g, c);
+  c.mode = C_SOLVE;
+  c.src = p->tmp(g);
+  c.dst = p->tmp(g);
   p->fV_at(p->t_at(m), c.fV);
   c.csolve = p->mu[0] * p->dt;
   if (write_u) c.uout = p->u(p->ucur);
   if (m < p->nsteps) phase_req(p, c, n - 1, 0.0, p->dt, true, m + 1);
-  int s = launch_timed(p, true, c);
+  int s = launch_timed(p, g, true, c);
   if (s) return s;
   if (m == p->nsteps) return TDSE_OK;
-  LineArgs r = base_args(p);
-  row_geom(p, r);
+  LineArgs r = base_args(p, g);
+  row_geom(p, g, r);
   r.mode = R_AM;
-  r.src = p->tmp();
-  r.dst = p->tmp();
+  r.src = p->tmp(g);
+  r.dst = p->tmp(g);
   r.nh = n - 1;
   r.c0 = p->mu[0] * p->dt;
   r.slot_w = m % (n - 1);
@@ -531,7 +582,7 @@ int op_am_step(tdse_plan_s* p, int m, bool write_u) {
     r.ch[j] = p->dt * p->mu[j];
     r.slot_r[j] = ((m + 1 - j) % (n - 1) + (n - 1)) % (n - 1);
   }
-  return launch_timed(p, false, r);
+  return launch_timed(p, g, false, r);
 }
 
 bool good_len(int M) { return M >= 8 && M <= 3072 && M % 2 == 0 && line_length_supported(M); }
@@ -562,7 +613,7 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   *out = nullptr;
   if (prob->dim != 1 && prob->dim != 2) return fail(prob->dim == 3 ? TDSE_EUNSUPPORTED : TDSE_EINVAL, "dim must be 1 or 2");
   if (prob->domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "free-space domain is not available in this build");
-  if (prob->precision != TDSE_FP64) return fail(TDSE_EUNSUPPORTED, "only TDSE_FP64 is available in this build");
+  if (prob->precision != TDSE_FP64 && prob->precision != TDSE_FP32_SPLIT) return fail(TDSE_EINVAL, "unknown precision");
   for (int a = 0; a < prob->dim; ++a)
     if (!good_len(prob->M[a])) return fail(TDSE_EINVAL, "grid size must be 2^a or 3*2^a, 8..3072");
   if (!(prob->T > 0.0) || prob->nsteps < 1) return fail(TDSE_EINVAL, "need T > 0 and nsteps >= 1");
@@ -596,7 +647,20 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   p->precision = prob->precision;
   p->mu = adams_weights(p->order);
   p->rich = richardson_weights(p->L);
-  p->Vhost.assign(prob->V_fields, prob->V_fields + (size_t)p->nV * p->P);
+  const bool split = p->precision == TDSE_FP32_SPLIT;
+  for (int g = 0; g < 2; ++g) {
+    tdse_plan_s::Stage& S = p->st[g];
+    const bool sp = split && g == 1;
+    S.prec = sp ? P_SPLIT : P_FP64;
+    S.cplx = sp ? 8 : 16;
+    S.real = sp ? 4 : 8;
+    const size_t n = (size_t)p->nV * p->P;
+    S.Vhost.resize(n * S.real);
+    for (size_t q = 0; q < n; ++q) {
+      if (sp) ((float*)S.Vhost.data())[q] = (float)prob->V_fields[q];
+      else ((double*)S.Vhost.data())[q] = prob->V_fields[q];
+    }
+  }
 
   TimeFns& tf = p->tf;
   tf.dim = p->dim;
@@ -614,19 +678,31 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   tf.A_ctx = prob->A_ctx;
   tf.prepare();
 
-  p->tw1 = twiddles(p->M1);
-  p->tw2 = twiddles(p->M2);
+  for (int g = 0; g < 2; ++g) {
+    p->st[g].tw1 = twiddles(p->M1, p->st[g].prec == P_SPLIT);
+    p->st[g].tw2 = twiddles(p->M2, p->st[g].prec == P_SPLIT);
+  }
 
   size_t off = 0;
-  const size_t cbytes = (size_t)p->P * sizeof(double2);
+  const size_t cbytes = (size_t)p->P * sizeof(double2);   // complex128 buffers
   p->o_B = off; off = align256(off + cbytes);
-  p->o_ring = off; off = align256(off + (size_t)(p->order - 1) * cbytes);
-  p->o_tmp = off; off = align256(off + cbytes);
   p->o_u[0] = off; off = align256(off + cbytes);
   p->o_u[1] = off; off = align256(off + cbytes);
-  p->o_V = off; off = align256(off + (size_t)p->nV * p->P * sizeof(double));
-  p->o_tw1 = off; off = align256(off + p->tw1.size() * sizeof(double2));
-  p->o_tw2 = off; off = align256(off + p->tw2.size() * sizeof(double2));
+  for (int g = 0; g < (split ? 2 : 1); ++g) {
+    tdse_plan_s::Stage& S = p->st[g];
+    const size_t tbytes = (size_t)p->P * S.cplx;
+    S.o_ring = off; off = align256(off + (size_t)(p->order - 1) * tbytes);
+    S.o_tmp = off; off = align256(off + tbytes);
+    S.o_V = off; off = align256(off + S.Vhost.size());
+    S.o_tw1 = off; off = align256(off + S.tw1.size());
+    S.o_tw2 = off; off = align256(off + S.tw2.size());
+  }
+  if (!split) {
+    p->st[1] = p->st[0];
+    p->st[1].Vhost.clear();   // no second upload
+    p->st[1].tw1.clear();
+    p->st[1].tw2.clear();
+  }
   p->o_ph = off; off = align256(off + (size_t)(p->order - 1) * (p->M1 + p->M2) * sizeof(double2));
   p->total = off;
   *out = p;
@@ -647,9 +723,13 @@ int tdse_bind(tdse_plan_t p, void* ws, size_t bytes, void* stream) {
   p->ws = (char*)ws;
   p->ws_bytes = bytes;
   p->stream = (hipStream_t)stream;
-  HIP_TRY(hipMemcpyAsync(p->ws + p->o_V, p->Vhost.data(), p->Vhost.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->ws + p->o_tw1, p->tw1.data(), p->tw1.size() * sizeof(double2), hipMemcpyHostToDevice, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->ws + p->o_tw2, p->tw2.data(), p->tw2.size() * sizeof(double2), hipMemcpyHostToDevice, p->stream));
+  for (int g = 0; g < 2; ++g) {
+    const tdse_plan_s::Stage& S = p->st[g];
+    if (S.Vhost.empty()) continue;
+    HIP_TRY(hipMemcpyAsync(p->ws + S.o_V, S.Vhost.data(), S.Vhost.size(), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw1, S.tw1.data(), S.tw1.size(), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw2, S.tw2.data(), S.tw2.size(), hipMemcpyHostToDevice, p->stream));
+  }
   HIP_TRY(hipStreamSynchronize(p->stream));
   p->bound = true;
   p->cur = -1;
@@ -763,7 +843,8 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
   if (key == TDSE_Q_BYTES_PER_STEP) {
     // per mode: B in/out (32), history ring n-2 reads + 1 write (16 (n-1)),
     // two tile round trips (64), the potential fields (8 nV)
-    const double per = 32.0 + 16.0 * (p->order - 1) + (p->dim == 2 ? 64.0 : 32.0) + 8.0 * p->nV;
+    const double c = (double)p->st[1].cplx, r = (double)p->st[1].real;
+    const double per = 32.0 + c * (p->order - 1) + (p->dim == 2 ? 4 * c : 2 * c) + r * p->nV;
     *value = per * (double)p->P;
     return TDSE_OK;
   }
@@ -786,7 +867,8 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     // column pass: tile in and out (32) + the potential fields (8 nV);
     // row pass: tile in and out (32), B in and out (32), n-2 history reads and
     // one history write (16 (n-1))
-    const double per = key == TDSE_Q_BYTES_COL ? 32.0 + 8.0 * p->nV : 64.0 + 16.0 * (p->order - 1);
+    const double c = (double)p->st[1].cplx, r = (double)p->st[1].real;
+    const double per = key == TDSE_Q_BYTES_COL ? 2 * c + r * p->nV : 32.0 + 2 * c + c * (p->order - 1);
     *value = per * (double)p->P;
     return TDSE_OK;
   }

@@ -83,7 +83,7 @@ def _plan(lib, p):
     (dict(nsteps=0), -1),
     (dict(nV=0), -1),
     (dict(domain=1), -2),
-    (dict(precision=1), -2),
+    (dict(precision=7), -1),
 ])
 def test_plan_rejects(lib, kw, status):
     st, h = _plan(lib, _problem(**kw))

@@ -41,3 +41,24 @@ def test_emulated_kernels_match_oracle(emu, case):
     u = EmuPlan(emu, prob).run(prob.u0)
     ref, _ = PeriodicOracle(prob).run()
     assert _rel(u, ref) < 1e-12
+
+
+SPLIT_CASES = [
+    dict(seed=11, dim=2, M=(16, 32), T=0.05, N=12),
+    dict(seed=12, dim=1, M=(128,), T=0.05, N=10),
+    dict(seed=13, dim=2, M=(24, 8), T=0.05, N=8, order=4),
+]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=[f"split-{c['M']}-{c['N']}" for c in SPLIT_CASES])
+def test_emulated_split_precision_within_bar(emu, case):
+    # complex64 transforms and history with FP64 carried state: within 1e-6
+    from emu.emu_plan import EmuPlan
+
+    prob = periodic_problem_from_seed(case["seed"], case["dim"], case["M"], case["T"], case["N"],
+                                      order=case.get("order", 8), precision="fp32split")
+    u = EmuPlan(emu, prob).run(prob.u0)
+    ref, _ = PeriodicOracle(prob).run()
+    r = _rel(u, ref)
+    assert r < 1e-6, r
+    assert r > 1e-12   # really ran in reduced precision

@@ -1,0 +1,69 @@
+"""FP32-split form on the GPU: complex64 transforms, history and history sum,
+FP64 carried state and phases.  Bar: rel-L2 <= 1e-6 against FP64."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.periodic import PeriodicOracle
+from workloads import c3_problem, periodic_problem_from_seed
+
+pytestmark = pytest.mark.gpu
+BAR = 1e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2001_06113_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2001_06113_amd import build
+
+        build.build()
+    yield
+
+
+def run(prob):
+    from paper_2001_06113_amd.tdse import Plan
+
+    plan = Plan.from_problem(prob, device="cuda:0")
+    u = plan.run(prob.u0).cpu().numpy()
+    plan.close()
+    return u
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("M,N", [((64, 96), 60), ((256,), 50), ((384, 48), 30)])
+def test_split_vs_oracle(M, N):
+    prob = periodic_problem_from_seed(41, len(M), M, 0.001 * N, N, precision="fp32split")
+    print(f"case split M={M} steps={N}", flush=True)
+    u = run(prob)
+    ref, _ = PeriodicOracle(prob).run()
+    r = rel(u, ref)
+    print(f"  rel-L2 vs FP64 oracle = {r:.3e}", flush=True)
+    assert 1e-12 < r <= BAR
+
+
+def test_split_c3_size_vs_oracle_short():
+    prob = c3_problem(nsteps=20, T=0.02)
+    u = run(prob)
+    ref, _ = PeriodicOracle(prob).run()
+    r = rel(u, ref)
+    print(f"C3 1024^2, 20 steps: rel-L2 vs oracle = {r:.3e}", flush=True)
+    assert r <= BAR
+
+
+def test_split_c3_full_vs_fp64_gpu():
+    # full C3: 1024 x 1024, T = 2, 2000 steps; reference = the FP64 GPU path
+    split = run(c3_problem())
+    fp64 = run(c3_problem(precision="fp64"))
+    r = rel(split, fp64)
+    print(f"C3 full: rel-L2 split vs FP64 = {r:.3e}", flush=True)
+    assert np.all(np.isfinite(split))
+    assert r <= BAR
