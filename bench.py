@@ -79,6 +79,28 @@ def cpu_baseline(prob, nsteps: int) -> dict:
     }
 
 
+KERNEL_SOURCES = ("paper_2001_06113_amd/csrc/periodic_kernels.hip", "paper_2001_06113_amd/csrc/fft_lds.h",
+                  "paper_2001_06113_amd/csrc/tdse_internal.h")
+
+
+def measured_traffic(name: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    FETCH_SIZE/WRITE_SIZE summary, or None if the kernel sources changed
+    since those counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith("#"))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if kv.get("source_sha256", "").strip() != h.hexdigest():
+        return None
+    return float(kv["traffic_bytes"])
+
+
 def split_leg(steps: int) -> dict:
     """FP32-split form on the 1024 x 1024 workload (seed 3): throughput of
     graph-replayed runs, and rel-L2 of u(T) against the FP64 GPU path."""
@@ -194,7 +216,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": None,
+            "traffic": measured_traffic("k_row_512_fp64_traffic.txt") if dom == "row" else None,
             "kernel": f"Adams {dom} pass (k_{dom})",
             "bytes_per_launch": dom_b,
             "mean_launch_us": dom_us,

@@ -29,6 +29,8 @@
 //
 // Every global load a pass needs (tile, potential, B, history, phase factors)
 // is issued before its first FFT so their latencies overlap.
+#include <hip/hip_ext.h>
+
 #include "fft_lds.h"
 #include "tdse_internal.h"
 
@@ -361,13 +363,21 @@ bool line_length_supported(int N) {
   }
 }
 
+// With events e0/e1 the launch records them at the kernel's own start and
+// end (hipExtLaunchKernelGGL), which times the kernel without launch gaps.
+#define TDSE_LAUNCH(K, G, B, S, E0, E1, A)                        \
+  do {                                                            \
+    if (E0) hipExtLaunchKernelGGL(K, G, B, 0, S, E0, E1, 0, A);   \
+    else hipLaunchKernelGGL(K, G, B, 0, S, A);                    \
+  } while (0)
+
 template <typename C>
-hipError_t col_pass(int N, const LineArgs& a, hipStream_t s) {
+hipError_t col_pass(int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (N) {
 #define X(n)                                                                                      \
   case n: {                                                                                       \
     constexpr int L = col_lpw(n), T = col_tl(n);                                                  \
-    hipLaunchKernelGGL((k_col<C, n, L, T>), dim3((a.nlines + L - 1) / L), dim3(L * T), 0, s, a); \
+    TDSE_LAUNCH((k_col<C, n, L, T>), dim3((a.nlines + L - 1) / L), dim3(L * T), s, e0, e1, a);   \
     break;                                                                                        \
   }
     X(1)
@@ -380,12 +390,12 @@ hipError_t col_pass(int N, const LineArgs& a, hipStream_t s) {
 }
 
 template <typename C>
-hipError_t row_pass(int N, const LineArgs& a, hipStream_t s) {
+hipError_t row_pass(int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (N) {
 #define X(n)                                                                                      \
   case n: {                                                                                       \
     constexpr int L = row_lpw(n), T = row_tl(n);                                                  \
-    hipLaunchKernelGGL((k_row<C, n, L, T>), dim3((a.nlines + L - 1) / L), dim3(L * T), 0, s, a); \
+    TDSE_LAUNCH((k_row<C, n, L, T>), dim3((a.nlines + L - 1) / L), dim3(L * T), s, e0, e1, a);   \
     break;                                                                                        \
   }
     TDSE_LINE_SIZES(X)
@@ -407,11 +417,11 @@ hipError_t launch_narrow(const double2* src, float2* dst, int64_t n, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s) {
-  return prec == P_SPLIT ? col_pass<float2>(N, a, s) : col_pass<double2>(N, a, s);
+hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return prec == P_SPLIT ? col_pass<float2>(N, a, s, e0, e1) : col_pass<double2>(N, a, s, e0, e1);
 }
-hipError_t launch_row_pass(int prec, int N, const LineArgs& a, hipStream_t s) {
-  return prec == P_SPLIT ? row_pass<float2>(N, a, s) : row_pass<double2>(N, a, s);
+hipError_t launch_row_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return prec == P_SPLIT ? row_pass<float2>(N, a, s, e0, e1) : row_pass<double2>(N, a, s, e0, e1);
 }
 
 }  // namespace tdse

@@ -380,9 +380,11 @@ void phase_req(const tdse_plan_s* p, LineArgs& a, int nj, double t_b, double tau
   }
 }
 
-int launch(const tdse_plan_s* p, int g, bool col, const LineArgs& a) {
+int launch(const tdse_plan_s* p, int g, bool col, const LineArgs& a, hipEvent_t e0 = nullptr,
+           hipEvent_t e1 = nullptr) {
   const int prec = p->st[g].prec;
-  hipError_t e = col ? launch_col_pass(prec, p->M1, a, p->stream) : launch_row_pass(prec, p->M2, a, p->stream);
+  hipError_t e = col ? launch_col_pass(prec, p->M1, a, p->stream, e0, e1)
+                     : launch_row_pass(prec, p->M2, a, p->stream, e0, e1);
   if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
   return TDSE_OK;
 }
@@ -396,16 +398,15 @@ hipEvent_t next_event(tdse_plan_s* p) {
   return p->ev_pool[p->ev_used++];
 }
 
-// launch an implicit Adams pass, bracketed by events when profiling
+// launch an implicit Adams pass; when profiling, the dispatch itself records
+// events at the kernel's start and end
 int launch_timed(tdse_plan_s* p, int g, bool col, const LineArgs& a) {
   if (!p->prof) return launch(p, g, col, a);
   const size_t first = p->ev_used;
   hipEvent_t e0 = next_event(p), e1 = next_event(p);
   if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
-  HIP_TRY(hipEventRecord(e0, p->stream));
-  int s = launch(p, g, col, a);
+  int s = launch(p, g, col, a, e0, e1);
   if (s) return s;
-  HIP_TRY(hipEventRecord(e1, p->stream));
   p->prof_marks.push_back({first, col ? 0 : 1});
   return TDSE_OK;
 }

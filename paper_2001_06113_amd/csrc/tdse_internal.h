@@ -73,9 +73,12 @@ struct LineArgs {
   PhaseReq req;
 };
 
-// Launchers (periodic_kernels.hip).  Return a hipError_t.
-hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s);
-hipError_t launch_row_pass(int prec, int N, const LineArgs& a, hipStream_t s);
+// Launchers (periodic_kernels.hip).  Non-null events e0/e1 are recorded at
+// the kernel's own start and end.  Return a hipError_t.
+hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
+hipError_t launch_row_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 bool line_length_supported(int N);
 // dst[i] = (complex64) src[i], i < n (FP64 start-up state to split precision)
 hipError_t launch_narrow(const double2* src, float2* dst, int64_t n, hipStream_t s);

@@ -123,6 +123,7 @@ using std::min;
 using std::max;
 
 #define hipLaunchKernelGGL(K, G, B, SH, S, ...) emu::launch(K, G, B, __VA_ARGS__)
+#define hipExtLaunchKernelGGL(K, G, B, SH, S, E0, E1, FL, ...) emu::launch(K, G, B, __VA_ARGS__)
 inline hipError_t hipGetLastError() { return hipSuccess; }
 inline const char* hipGetErrorString(hipError_t) { return "emulated"; }
 inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) {
