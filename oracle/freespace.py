@@ -1,0 +1,149 @@
+"""FP64 oracle of the free-space complex-frequency scheme (Sections 3.3-3.4).
+
+Test infrastructure only (see the package docstring).
+
+Transforms are dense (no FFT), axis by axis:
+  forward  (eq. (fzdft)):     fhat(zeta_k) = (2/M) sum_j exp(-i zeta_k x_j) f(x_j)
+  inverse  (eq. (uciftdisc)): u(x_j) = (1/2pi) sum_k w_k exp(i zeta_k x_j) uhat(zeta_k)
+on the grid x_j = -1 + 2 j / M and the Gamma nodes of ``quadrature.gamma_rule``.
+Propagator over [t_a, t_b] (Lemma 3.1, eq. (uhatzinteq)):
+  P = exp(-i (zeta . zeta)(t_b - t_a) + i zeta . (phi(t_b) - phi(t_a))).
+Order-2 sub-step (eqs. (uhatzfd), (utrapzfd)) carries (u, uhat):
+  B = P (uhat - i d/2 What(t)),  u(t+d) = F^-1 B / (1 + i d/2 V(t+d)),
+  uhat(t+d) = B - i d/2 What(t+d),  What = F(V u).
+Start-up (Remark on high-order free-space schemes): iterated Richardson
+extrapolation of both u and uhat; What_n = F(V(t_n) u_n) from the
+extrapolated u_n.  Implicit Adams steps as in the periodic case with the
+complex-frequency transforms.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from .adams import adams_coefficients, richardson_extrapolate
+from .periodic import make_phi
+from .quadrature import choose_H, gamma_rule
+
+KAPPA = {8: 7}   # omitted regular nodes of the order-2p Alpert correction (Section 6, Example 2)
+
+
+def free_grid(M: int) -> np.ndarray:
+    return -1.0 + 2.0 * np.arange(M) / M
+
+
+@dataclass
+class FreeSpaceOracle:
+    prob: object
+    H: Optional[float] = None
+
+    def __post_init__(self):
+        p = self.prob
+        assert p.domain == "free"
+        self.d = p.dim
+        self.shape = tuple(p.M)
+        self.phi = make_phi(p)
+        self.mu = [float(m) for m in adams_coefficients(p.order)]
+        self.xs = [free_grid(m) for m in self.shape]
+        if self.H is None:
+            self.H = self.default_H()
+        kappa = KAPPA[p.p]
+        self.nodes = []
+        self.G, self.Ginv = [], []
+        for a in range(self.d):
+            zeta, w, info = gamma_rule(self.shape[a], self.H, p.nu[a], p.p, kappa, p.q, p.panels)
+            x = self.xs[a]
+            self.nodes.append((zeta, w, info))
+            self.G.append((2.0 / self.shape[a]) * np.exp(-1j * np.outer(zeta, x)))
+            self.Ginv.append((w[None, :] / (2 * np.pi)) * np.exp(1j * np.outer(x, zeta)))
+        Z = np.meshgrid(*[n[0] for n in self.nodes], indexing="ij")
+        self.Z = Z
+        self.Z2 = sum(z * z for z in Z)
+
+    # --- parameter choice (Remark on H, Section 3.2) -------------------------
+    def default_H(self) -> float:
+        p = self.prob
+        dt = p.dt
+        cell = np.prod([2.0 / m for m in self.shape])
+        normV, phimax = 0.0, 0.0
+        for n in range(p.nsteps + 1):
+            t = n * dt
+            normV = max(normV, float(np.sqrt(np.sum(self.V(t) ** 2) * cell)))
+            phimax = max(phimax, float(np.linalg.norm(self.phi(t))))
+        return choose_H(p.eps, normV, phimax, self.d)
+
+    # --- transforms ----------------------------------------------------------
+    def F(self, f: np.ndarray) -> np.ndarray:
+        out = f
+        for a in range(self.d):
+            out = np.moveaxis(np.tensordot(self.G[a], np.moveaxis(out, a, 0), axes=(1, 0)), 0, a)
+        return out
+
+    def Finv(self, g: np.ndarray) -> np.ndarray:
+        out = g
+        for a in range(self.d):
+            out = np.moveaxis(np.tensordot(self.Ginv[a], np.moveaxis(out, a, 0), axes=(1, 0)), 0, a)
+        return out
+
+    # --- problem data ----------------------------------------------------------
+    def V(self, t: float) -> np.ndarray:
+        p = self.prob
+        out = np.zeros(self.shape)
+        for r, Vr in enumerate(p.V_fields):
+            out = out + p.f(r, t) * Vr
+        return out
+
+    def prop(self, t_b: float, tau: float) -> np.ndarray:
+        dphi = np.asarray(self.phi(t_b)) - np.asarray(self.phi(t_b - tau))
+        arg = -self.Z2 * tau
+        for a in range(self.d):
+            arg = arg + self.Z[a] * dphi[a]
+        return np.exp(1j * arg)
+
+    # --- scheme --------------------------------------------------------------
+    def trap_substep(self, u, uh, t, delta):
+        W = self.F(self.V(t) * u)
+        B = self.prop(t + delta, delta) * (uh - 0.5j * delta * W)
+        un = self.Finv(B) / (1.0 + 0.5j * delta * self.V(t + delta))
+        Wn = self.F(self.V(t + delta) * un)
+        return un, B - 0.5j * delta * Wn
+
+    def richardson_step(self, u, uh, t, dt, levels):
+        Us, Uhs = [], []
+        for l in range(levels):
+            nsub = 2 ** l
+            v, vh = u, uh
+            for s in range(nsub):
+                v, vh = self.trap_substep(v, vh, t + s * dt / nsub, dt / nsub)
+            Us.append(v)
+            Uhs.append(vh)
+        return richardson_extrapolate(Us), richardson_extrapolate(Uhs)
+
+    def run(self, nsteps: Optional[int] = None):
+        p = self.prob
+        dt = p.dt
+        N = p.nsteps if nsteps is None else nsteps
+        n = p.order
+        ns = min(p.start_steps, N)
+        mu = self.mu
+        u = np.asarray(p.u0, dtype=np.complex128).copy()
+        uh = self.F(u)
+        us = [u]
+        for m in range(1, ns + 1):
+            u, uh = self.richardson_step(u, uh, (m - 1) * dt, dt, n // 2)
+            us.append(u)
+        if N <= ns:
+            return u, dict(uhat=uh)
+        W = {m: self.F(self.V(m * dt) * us[m]) for m in range(max(0, ns - (n - 2)), ns + 1)}
+        for step in range(ns + 1, N + 1):
+            tn = step * dt
+            B = self.prop(tn, dt) * uh
+            for j in range(1, n):
+                B = B - 1j * dt * mu[j] * self.prop(tn, j * dt) * W[step - j]
+            u = self.Finv(B) / (1.0 + 1j * mu[0] * dt * self.V(tn))
+            W[step] = self.F(self.V(tn) * u)
+            uh = B - 1j * mu[0] * dt * W[step]
+            W.pop(step - (n - 1), None)
+        return u, dict(uhat=uh)
