@@ -5,7 +5,9 @@
  *
  * The library solves, on one GPU,
  *     i u_t = -Lap u + V(x,t) u + i A(t).grad u,   u(x,0) = u0(x)      (Section 1, eq. (schrodfree))
- * on the periodic box [-pi,pi]^d (Section 2), for d = 1 or 2, with
+ * on the periodic box [-pi,pi]^d (Section 2) or in free space with u0, V
+ * supported in [-1,1]^d (Section 3, complex-frequency modes on the contour
+ * Gamma with the FFT-based transforms of Section 4), for d = 1 or 2, with
  *     V(x,t) = sum_r f_r(t) V_r(x)    (real fields V_r on the grid),
  * by the Fourier-mode recurrence of Lemma 1 with the n-th order implicit
  * Adams rule of eq. (uadamsk) (Section 2.2, Table 1 for n = 8) and the
@@ -16,7 +18,8 @@
  * Conventions
  *   - complex values are interleaved (re, im) doubles (complex128), arrays in
  *     C order with the last axis fastest; a 1D problem has shape [M[0]].
- *   - periodic grid x_j = -pi + 2 pi j / M, j = 0..M-1 (Section 2.1).
+ *   - periodic grid x_j = -pi + 2 pi j / M, j = 0..M-1 (Section 2.1);
+ *     free-space grid x_j = -1 + 2 j / M (Section 3.3).
  *   - dt = T / nsteps.
  *
  * Errors: every call returns TDSE_OK (0) or a negative status; no C++
@@ -73,7 +76,7 @@ typedef void (*tdse_vector_fn)(double t, double* A_out, void* ctx);
  * T, step size, order).  Unused fields may be zero. */
 typedef struct {
   int32_t dim;             /* 1 or 2                                         */
-  int32_t domain;          /* TDSE_PERIODIC (TDSE_FREE: EUNSUPPORTED here)   */
+  int32_t domain;          /* TDSE_PERIODIC | TDSE_FREE (FP64 only)          */
   int32_t M[2];            /* grid points per axis: 2^a or 3*2^a, 8..3072    */
   double  T;               /* final time > 0                                 */
   int32_t nsteps;          /* number of steps, dt = T / nsteps               */
@@ -89,6 +92,15 @@ typedef struct {
   const double* A_params;  /* TDSE_A_PULSE_SIN2: {E0, omega, Tp, dir[d]}     */
   const double* A_steps;   /* TDSE_A_STEPWISE: host [nsteps][d]              */
   tdse_vector_fn A_fn; void* A_ctx;
+  /* free space (Sections 3.4 and 4): tolerance eps for the choice of H
+   * (Remark on H), Alpert order p (8: 16th order, kappa = 7 omitted nodes),
+   * q Gauss nodes per panel and `panels` dyadic panels per side of Gamma_2,
+   * FFT size nu per axis (N_E = nu/2 - 2 kappa + 1 equispaced nodes per ray,
+   * h = pi M / nu); H > 0 overrides the rule for H. */
+  double  eps;
+  int32_t p, q, panels;
+  int32_t nu[2];
+  double  H;
 } tdse_problem_t;
 
 typedef struct tdse_plan_s* tdse_plan_t;   /* opaque, owned by the library  */
@@ -138,6 +150,11 @@ int tdse_run(tdse_plan_t plan, const void* u0, void* uT, int32_t on_device);
 #define TDSE_Q_MU             16  /* + j: Adams weight mu_j                    */
 #define TDSE_Q_RICHARDSON     32  /* + l: weight of the 2^l-sub-step result    */
 #define TDSE_Q_PHI            64  /* + axis: phi_axis(T)                       */
+#define TDSE_Q_FS_H           80  /* free space: contour parameter H          */
+#define TDSE_Q_FS_MODES       81  /* + axis: complex-frequency modes N_axis     */
+#define TDSE_Q_FS_NE          83  /* + axis: equispaced nodes per ray N_E      */
+#define TDSE_Q_ALPERT_X       96  /* + k: Alpert node x_k (units of h), k < p   */
+#define TDSE_Q_ALPERT_W      112  /* + k: Alpert weight w_k, k < p              */
 int tdse_query(tdse_plan_t plan, int32_t key, double* value);
 
 /* Per-kernel timing: with enable != 0 every implicit Adams column and row

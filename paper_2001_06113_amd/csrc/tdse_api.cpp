@@ -268,6 +268,23 @@ struct tdse_plan_s {
   } st[2];
   // workspace layout
   size_t o_B = 0, o_u[2] = {0, 0}, o_ph = 0, total = 0;
+
+  // ---- free space (Sections 3.4 and 4)
+  bool free_space = false;
+  double H = 0.0;
+  std::vector<double> alp_x, alp_w;   // Alpert end correction, units of h
+  struct FAxis {
+    int M = 1, N = 1, NE = 0, ND = 0, nu = 0;
+    double h = 0.0;
+    std::vector<double2> zeta, w;      // nodes and weights, order E1 A1 C A3 E3
+    std::vector<char> tables;          // pre3 pre1 ipost3 ipost1 [M], post3 post1 ipre3 ipre1 [NE],
+                                       // Dfwd [ND][M], Dinv [M][ND], tw [nu], zeta [N]
+    size_t o_tab = 0;                  // workspace offset of the tables
+  } fx[2];
+  int64_t NM = 1;                      // modes N1 N2
+  std::vector<double> Vsrc;            // potential fields (host copy, FP64)
+  size_t o_UH[2] = {0, 0}, o_tmpf = 0, o_ringf = 0, o_Vf = 0;
+  int uh_cur = 0;
   // binding and clock
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -299,6 +316,7 @@ struct tdse_plan_s {
   }
 
   double2* B() const { return (double2*)(ws + o_B); }
+  double2* UH(int i) const { return (double2*)(ws + o_UH[i]); }
   void* ring(int g) const { return ws + st[g].o_ring; }
   void* ring_slot(int g, int s) const { return ws + st[g].o_ring + (size_t)s * P * st[g].cplx; }
   void* tmp(int g) const { return ws + st[g].o_tmp; }
@@ -586,6 +604,514 @@ int op_am_step(tdse_plan_s* p, int m, bool write_u) {
   return launch_timed(p, g, false, r);
 }
 
+
+// ============================================================== free space
+
+// Alpert end correction (Section 3.4; the table itself is only cited there):
+// the p-point Gauss rule of the functional
+//   Lambda[f] = sum_{k<kappa} f(k) + sum_m (B_{m+1}/(m+1)) f^(m)(0)/m!,
+// whose moments Lambda[x^m] = B_{m+1}(kappa)/(m+1) make the corrected
+// trapezoid rule exact on x^m, m < 2p.  Recurrence coefficients by Gautschi's
+// modified Chebyshev algorithm on monic Legendre polynomials of [0, kappa],
+// nodes and weights from the Jacobi matrix (Golub-Welsch), all in long double.
+void alpert_rule(int p, int kappa, std::vector<double>& xo, std::vector<double>& wo) {
+  typedef long double LD;
+  const int n2 = 2 * p;
+  std::vector<LD> B(n2 + 2, 0.0L);
+  B[0] = 1.0L;
+  for (int m = 1; m <= n2 + 1; ++m) {
+    LD sum = 0.0L, binom = 1.0L;   // C(m+1, k)
+    for (int k = 0; k < m; ++k) {
+      sum += binom * B[k];
+      binom = binom * (LD)(m + 1 - k) / (LD)(k + 1);
+    }
+    B[m] = -sum / (LD)(m + 1);
+  }
+  const LD c = (LD)kappa;
+  std::vector<LD> a(n2 + 1), b(n2 + 1);
+  for (int l = 0; l <= n2; ++l) {
+    a[l] = c / 2;
+    b[l] = l == 0 ? 0.0L : (c / 2) * (c / 2) * (LD)l * l / (4.0L * l * l - 1.0L);
+  }
+  // pi_l: monomial coefficients d[l][m] and values at the integers k < kappa
+  std::vector<std::vector<LD>> d(n2 + 1, std::vector<LD>(n2 + 1, 0.0L));
+  std::vector<std::vector<LD>> val(n2 + 1, std::vector<LD>(kappa, 0.0L));
+  d[0][0] = 1.0L;
+  for (int k = 0; k < kappa; ++k) val[0][k] = 1.0L;
+  for (int l = 0; l + 1 <= n2; ++l) {
+    for (int m = 0; m <= l + 1; ++m) {
+      LD v = (m >= 1 ? d[l][m - 1] : 0.0L) - a[l] * d[l][m];
+      if (l >= 1) v -= b[l] * d[l - 1][m];
+      d[l + 1][m] = v;
+    }
+    for (int k = 0; k < kappa; ++k)
+      val[l + 1][k] = ((LD)k - a[l]) * val[l][k] - (l >= 1 ? b[l] * val[l - 1][k] : 0.0L);
+  }
+  std::vector<LD> nu(n2);
+  for (int l = 0; l < n2; ++l) {
+    LD s = 0.0L;
+    for (int k = 0; k < kappa; ++k) s += val[l][k];
+    for (int m = 0; m <= l; ++m) s += d[l][m] * B[m + 1] / (LD)(m + 1);
+    nu[l] = s;
+  }
+  // modified Chebyshev algorithm
+  std::vector<LD> alpha(p), beta(p);
+  std::vector<LD> sm1(n2, 0.0L), s0(nu), s1(n2, 0.0L);
+  alpha[0] = a[0] + nu[1] / nu[0];
+  beta[0] = nu[0];
+  for (int k = 1; k < p; ++k) {
+    for (int l = k; l <= n2 - k - 1; ++l)
+      s1[l] = s0[l + 1] - (alpha[k - 1] - a[l]) * s0[l] - beta[k - 1] * sm1[l] + b[l] * s0[l - 1];
+    alpha[k] = a[k] + s1[k + 1] / s1[k] - s0[k] / s0[k - 1];
+    beta[k] = s1[k] / s0[k - 1];
+    sm1 = s0;
+    s0 = s1;
+  }
+  // symmetric Jacobi matrix, cyclic Jacobi rotations with eigenvectors
+  std::vector<std::vector<LD>> J(p, std::vector<LD>(p, 0.0L)), Vv(p, std::vector<LD>(p, 0.0L));
+  for (int k = 0; k < p; ++k) {
+    J[k][k] = alpha[k];
+    if (k + 1 < p) J[k][k + 1] = J[k + 1][k] = std::sqrt(beta[k + 1]);
+    Vv[k][k] = 1.0L;
+  }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    LD off = 0.0L;
+    for (int i = 0; i < p; ++i)
+      for (int j = i + 1; j < p; ++j) off += J[i][j] * J[i][j];
+    if (off < 1e-36L) break;
+    for (int i = 0; i < p; ++i)
+      for (int j = i + 1; j < p; ++j) {
+        if (std::fabs(J[i][j]) < 1e-40L) continue;
+        const LD tau = (J[j][j] - J[i][i]) / (2.0L * J[i][j]);
+        const LD t = (tau >= 0 ? 1.0L : -1.0L) / (std::fabs(tau) + std::sqrt(1.0L + tau * tau));
+        const LD cs = 1.0L / std::sqrt(1.0L + t * t), sn = t * cs;
+        for (int k = 0; k < p; ++k) {
+          const LD jik = J[i][k], jjk = J[j][k];
+          J[i][k] = cs * jik - sn * jjk;
+          J[j][k] = sn * jik + cs * jjk;
+        }
+        for (int k = 0; k < p; ++k) {
+          const LD jki = J[k][i], jkj = J[k][j];
+          J[k][i] = cs * jki - sn * jkj;
+          J[k][j] = sn * jki + cs * jkj;
+        }
+        for (int k = 0; k < p; ++k) {
+          const LD vki = Vv[k][i], vkj = Vv[k][j];
+          Vv[k][i] = cs * vki - sn * vkj;
+          Vv[k][j] = sn * vki + cs * vkj;
+        }
+      }
+  }
+  std::vector<std::pair<LD, LD>> nw(p);
+  for (int k = 0; k < p; ++k) nw[k] = {J[k][k], beta[0] * Vv[0][k] * Vv[0][k]};
+  std::sort(nw.begin(), nw.end());
+  xo.resize(p);
+  wo.resize(p);
+  for (int k = 0; k < p; ++k) {
+    xo[k] = (double)nw[k].first;
+    wo[k] = (double)nw[k].second;
+  }
+}
+
+inline double2 cexp_ld(long double re, long double im) {
+  const long double m = std::exp(re);
+  return double2{(double)(m * std::cos(im)), (double)(m * std::sin(im))};
+}
+
+// Nodes, weights and transform tables of one axis (Sections 3.4 and 4.1).
+void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels) {
+  typedef long double LD;
+  tdse_plan_s::FAxis& F = p->fx[axis];
+  const int kappa = 7, pp = (int)p->alp_x.size();
+  const LD H = p->H;
+  const LD PI = 3.14159265358979323846264338327950288L;
+  F.M = M;
+  F.nu = nu;
+  F.NE = nu / 2 - 2 * kappa + 1;
+  F.h = (double)(PI * M / nu);
+  const LD h = PI * (LD)M / (LD)nu;
+  // Gamma_2 panels: dyadic toward 0, `panels` per side
+  std::vector<double> gx, gw;
+  gauss_legendre(q, gx, gw);
+  std::vector<LD> tc, wc;
+  for (int k = 1; k <= panels; ++k) {
+    const LD lo = k == 1 ? 0.0L : H / std::pow(2.0L, (LD)(panels - k + 1));
+    const LD hi = H / std::pow(2.0L, (LD)(panels - k));
+    for (int j = 0; j < q; ++j) {
+      // Gauss-Legendre nodes come in descending order from gauss_legendre
+      const int jj = q - 1 - j;
+      tc.push_back(0.5L * (hi - lo) * gx[jj] + 0.5L * (hi + lo));
+      wc.push_back(0.5L * (hi - lo) * gw[jj]);
+    }
+  }
+  const int half = (int)tc.size();
+  F.ND = 2 * pp + 2 * half;
+  F.N = 2 * F.NE + F.ND;
+  F.zeta.assign(F.N, double2{0, 0});
+  F.w.assign(F.N, double2{0, 0});
+  // E1 (mirror of E3), A1 (mirror of A3), C (-H..H), A3, E3
+  for (int e = 0; e < F.NE; ++e) {
+    const LD tau = H + kappa * h + e * h;
+    F.zeta[F.N - F.NE + e] = double2{(double)tau, (double)-H};
+    F.w[F.N - F.NE + e] = double2{(double)h, 0.0};
+    F.zeta[F.NE - 1 - e] = double2{(double)-tau, (double)H};
+    F.w[F.NE - 1 - e] = double2{(double)h, 0.0};
+  }
+  for (int k = 0; k < pp; ++k) {
+    const LD tau = H + (LD)p->alp_x[k] * h;
+    const int i3 = F.NE + pp + 2 * half + k, i1 = F.NE + pp - 1 - k;
+    F.zeta[i3] = double2{(double)tau, (double)-H};
+    F.w[i3] = double2{(double)(h * (LD)p->alp_w[k]), 0.0};
+    F.zeta[i1] = double2{(double)-tau, (double)H};
+    F.w[i1] = double2{(double)(h * (LD)p->alp_w[k]), 0.0};
+  }
+  for (int k = 0; k < half; ++k) {
+    // zeta = (1 - i) tau, weight (1 - i) w
+    const int ip = F.NE + pp + half + k, im = F.NE + pp + half - 1 - k;
+    F.zeta[ip] = double2{(double)tc[k], (double)-tc[k]};
+    F.w[ip] = double2{(double)wc[k], (double)-wc[k]};
+    F.zeta[im] = double2{(double)-tc[k], (double)tc[k]};
+    F.w[im] = double2{(double)wc[k], (double)-wc[k]};
+  }
+  // transform tables
+  const int NE = F.NE, ND = F.ND, N = F.N;
+  const LD alpha = H + kappa * h;
+  const LD s2M = 2.0L / (LD)M;
+  std::vector<double2> pre3(M), pre1(M), ipost3(M), ipost1(M), post3(NE), post1(NE), ipre3(NE), ipre1(NE);
+  std::vector<double2> Dfwd((size_t)ND * M), Dinv((size_t)M * ND), twt(nu), z(F.zeta);
+  for (int j = 0; j < M; ++j) {
+    const LD x = -1.0L + 2.0L * j / (LD)M;
+    const LD ph = 2.0L * alpha * j / (LD)M;
+    pre3[j] = cexp_ld(-H * x, -ph);
+    pre1[j] = cexp_ld(H * x, ph);
+    ipost3[j] = cexp_ld(H * x, -alpha + ph);
+    ipost1[j] = cexp_ld(-H * x, alpha - ph);
+  }
+  for (int e = 0; e < NE; ++e) {
+    const LD eh = e * h;
+    const double2 a3 = cexp_ld(0.0L, alpha + eh), a1 = cexp_ld(0.0L, -alpha - eh);
+    post3[e] = double2{(double)(s2M * a3.x), (double)(s2M * a3.y)};
+    post1[e] = double2{(double)(s2M * a1.x), (double)(s2M * a1.y)};
+    const LD wf = h / (2.0L * PI);
+    const double2 b3 = cexp_ld(0.0L, -eh), b1 = cexp_ld(0.0L, eh);
+    ipre3[e] = double2{(double)(wf * b3.x), (double)(wf * b3.y)};
+    ipre1[e] = double2{(double)(wf * b1.x), (double)(wf * b1.y)};
+  }
+  for (int q2 = 0; q2 < ND; ++q2) {
+    const double2 zz = F.zeta[NE + q2], ww = F.w[NE + q2];
+    for (int j = 0; j < M; ++j) {
+      const LD x = -1.0L + 2.0L * j / (LD)M;
+      // exp(-i zeta x) = exp(Im(zeta) x) exp(-i Re(zeta) x)
+      const double2 ef = cexp_ld((LD)zz.y * x, -(LD)zz.x * x);
+      Dfwd[(size_t)q2 * M + j] = double2{(double)(s2M * ef.x), (double)(s2M * ef.y)};
+      const double2 eb = cexp_ld(-(LD)zz.y * x, (LD)zz.x * x);
+      const LD wr = (LD)ww.x / (2.0L * PI), wi = (LD)ww.y / (2.0L * PI);
+      Dinv[(size_t)j * ND + q2] = double2{(double)(wr * eb.x - wi * eb.y), (double)(wr * eb.y + wi * eb.x)};
+    }
+  }
+  for (int m = 0; m < nu; ++m) {
+    const LD a = -2.0L * PI * (LD)m / (LD)nu;
+    twt[m] = double2{(double)std::cos(a), (double)std::sin(a)};
+  }
+  std::vector<std::vector<double2>*> parts = {&pre3, &pre1, &ipost3, &ipost1, &post3, &post1, &ipre3,
+                                              &ipre1, &Dfwd, &Dinv, &twt, &z};
+  size_t bytes = 0;
+  for (auto* v : parts) bytes = align256(bytes + v->size() * sizeof(double2));
+  F.tables.assign(bytes, 0);
+  size_t off = 0;
+  for (auto* v : parts) {
+    std::memcpy(F.tables.data() + off, v->data(), v->size() * sizeof(double2));
+    off = align256(off + v->size() * sizeof(double2));
+  }
+}
+
+// device view of axis a's tables
+CFAxis cf_axis(const tdse_plan_s* p, int axis) {
+  const tdse_plan_s::FAxis& F = p->fx[axis];
+  CFAxis c;
+  std::memset(&c, 0, sizeof(c));
+  c.M = F.M;
+  c.N = F.N;
+  c.NE = F.NE;
+  c.ND = F.ND;
+  if (F.nu == 0) {   // axis without transform (1D problem): one mode at zeta = 0
+    c.zeta = (const double2*)(p->ws + F.o_tab);
+    return c;
+  }
+  const double2* base = (const double2*)(p->ws + F.o_tab);
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    const double2* q = (const double2*)((const char*)base + off);
+    off = align256(off + n * sizeof(double2));
+    return q;
+  };
+  c.pre3 = take(F.M);
+  c.pre1 = take(F.M);
+  c.ipost3 = take(F.M);
+  c.ipost1 = take(F.M);
+  c.post3 = take(F.NE);
+  c.post1 = take(F.NE);
+  c.ipre3 = take(F.NE);
+  c.ipre1 = take(F.NE);
+  c.Dfwd = take((size_t)F.ND * F.M);
+  c.Dinv = take((size_t)F.M * F.ND);
+  c.tw = take(F.nu);
+  c.zeta = take(F.N);
+  return c;
+}
+
+FSArgs fs_args(const tdse_plan_s* p) {
+  FSArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.N1 = p->fx[0].N;
+  a.N2 = p->fx[1].N;
+  a.ax1 = cf_axis(p, 0);
+  a.ax2 = cf_axis(p, 1);
+  a.Bm = p->B();
+  a.ring = (double2*)(p->ws + p->o_ringf);
+  a.ring_stride = p->NM;
+  a.V = (const double*)(p->ws + p->o_Vf);
+  a.nV = p->nV;
+  a.vstride = p->P;
+  a.ph = p->ph();
+  a.slot_w = -1;
+  a.src = (const double2*)(p->ws + p->o_tmpf);
+  a.dst = (double2*)(p->ws + p->o_tmpf);
+  a.UH = p->UH(p->uh_cur);
+  a.UHacc = p->UH(1 - p->uh_cur);
+  return a;
+}
+
+int fs_launch(tdse_plan_s* p, bool col, const FSArgs& a, bool timed = false) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const size_t first = p->ev_used;
+  if (timed && p->prof) {
+    e0 = next_event(p);
+    e1 = next_event(p);
+    if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
+  }
+  hipError_t e = col ? launch_fs_col(p->dim == 2 ? p->fx[0].nu : 0, a, p->stream, e0, e1)
+                     : launch_fs_row(p->fx[1].nu, a, p->stream, e0, e1);
+  if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  if (e0) p->prof_marks.push_back({first, col ? 0 : 1});
+  return TDSE_OK;
+}
+
+void fs_phase_req(const tdse_plan_s* p, FSArgs& a, int nj, double t_b, double tau, bool stepgrid, int m_b) {
+  LineArgs tmp;
+  std::memset(&tmp, 0, sizeof(tmp));
+  phase_req(p, tmp, nj, t_b, tau, stepgrid, m_b);
+  a.req = tmp.req;
+}
+
+int fs_phase_only(const tdse_plan_s* p, const FSArgs& a) {
+  hipError_t e = launch_fs_phase(a, p->stream);
+  if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("phase kernel: ") + hipGetErrorString(e));
+  return TDSE_OK;
+}
+
+// modes dst = F((alpha + beta V(t)) u)
+int fs_forward(tdse_plan_s* p, double t, double ar, double ai, double br, double bi, double2* dst) {
+  FSArgs a = fs_args(p);
+  a.mode = C_FWD;
+  a.usrc = p->u(p->ucur);
+  p->fV_at(t, a.fV);
+  a.alpha_re = ar; a.alpha_im = ai; a.beta_re = br; a.beta_im = bi;
+  int s = fs_launch(p, true, a);
+  if (s) return s;
+  FSArgs r = fs_args(p);
+  r.mode = R_FWD;
+  r.fdst = dst;
+  return fs_launch(p, false, r);
+}
+
+double2* fs_ring_slot(const tdse_plan_s* p, int s) { return (double2*)(p->ws + p->o_ringf) + (int64_t)s * p->NM; }
+
+int fs_history(tdse_plan_s* p, int m) {
+  return fs_forward(p, p->t_at(m), 0.0, 0.0, 1.0, 0.0, fs_ring_slot(p, m % (p->order - 1)));
+}
+
+// Iterated Richardson step from t_{m-1} on both u and uhat (Remark on
+// high-order free-space schemes).
+int fs_richardson(tdse_plan_s* p, int m) {
+  const int n = p->order;
+  const double t = p->t_at(m - 1);
+  const int acc = 1 - p->ucur;
+  for (int l = 0; l < p->L; ++l) {
+    const int nsub = 1 << l;
+    const double delta = p->dt / nsub;
+    FSArgs ph = fs_args(p);
+    fs_phase_req(p, ph, 1, t + delta, delta, false, 0);
+    int s = fs_phase_only(p, ph);
+    if (s) return s;
+    FSArgs r = fs_args(p);
+    r.mode = R_BINIT;
+    r.slot_r[1] = (m - 1) % (n - 1);
+    r.c0 = 0.5 * delta;
+    s = fs_launch(p, false, r);
+    if (s) return s;
+    for (int k = 0; k < nsub; ++k) {
+      const double ts1 = t + k * delta + delta;
+      const bool last = (k == nsub - 1);
+      FSArgs c = fs_args(p);
+      c.mode = C_SOLVE;
+      p->fV_at(ts1, c.fV);
+      c.csolve = 0.5 * delta;
+      if (last) {
+        c.uacc = p->u(acc);
+        c.wacc = p->rich[l];
+        c.acc_first = (l == 0);
+      } else {
+        fs_phase_req(p, c, 1, ts1 + delta, delta, false, 0);
+      }
+      s = fs_launch(p, true, c);
+      if (s) return s;
+      FSArgs rr = fs_args(p);
+      if (!last) {
+        rr.mode = R_AM;
+        rr.nh = 1;
+        rr.c0 = 0.5 * delta;
+        rr.ch[1] = 0.5 * delta;
+      } else {
+        rr.mode = R_UHACC;
+        rr.c0 = 0.5 * delta;
+        rr.wacc = p->rich[l];
+        rr.acc_first = (l == 0);
+      }
+      s = fs_launch(p, false, rr);
+      if (s) return s;
+    }
+  }
+  p->ucur = acc;
+  p->uh_cur = 1 - p->uh_cur;
+  return TDSE_OK;
+}
+
+int fs_am_init(tdse_plan_s* p) {
+  const int n = p->order, m = p->ns;
+  FSArgs ph = fs_args(p);
+  fs_phase_req(p, ph, n - 1, 0.0, p->dt, true, m + 1);
+  int s = fs_phase_only(p, ph);
+  if (s) return s;
+  FSArgs r = fs_args(p);
+  r.mode = R_FORM;
+  r.nh = n - 1;
+  for (int j = 1; j <= n - 1; ++j) {
+    r.slot_r[j] = (m + 1 - j) % (n - 1);
+    r.ch[j] = p->dt * p->mu[j];
+  }
+  return fs_launch(p, false, r);
+}
+
+int fs_am_step(tdse_plan_s* p, int m, bool write_u) {
+  const int n = p->order;
+  FSArgs c = fs_args(p);
+  c.mode = C_SOLVE;
+  p->fV_at(p->t_at(m), c.fV);
+  c.csolve = p->mu[0] * p->dt;
+  if (write_u) c.uout = p->u(p->ucur);
+  if (m < p->nsteps) fs_phase_req(p, c, n - 1, 0.0, p->dt, true, m + 1);
+  int s = fs_launch(p, true, c, true);
+  if (s) return s;
+  if (m == p->nsteps) return TDSE_OK;
+  FSArgs r = fs_args(p);
+  r.mode = R_AM;
+  r.nh = n - 1;
+  r.c0 = p->mu[0] * p->dt;
+  r.slot_w = m % (n - 1);
+  for (int j = 1; j <= n - 1; ++j) {
+    r.ch[j] = p->dt * p->mu[j];
+    r.slot_r[j] = ((m + 1 - j) % (n - 1) + (n - 1)) % (n - 1);
+  }
+  return fs_launch(p, false, r, true);
+}
+
+int fs_step(tdse_plan_s* p, int m, bool write_u) {
+  int s = TDSE_OK;
+  if (m == 1) {
+    // uhat_0 = F u0 and What_0 = F(V(0) u0) (Section 3.3)
+    s = fs_forward(p, 0.0, 1.0, 0.0, 0.0, 0.0, p->UH(p->uh_cur));
+    if (!s) s = fs_history(p, 0);
+  }
+  if (s) return s;
+  if (m <= p->ns) {
+    s = fs_richardson(p, m);
+    if (!s) s = fs_history(p, m);
+    return s;
+  }
+  if (m == p->ns + 1) s = fs_am_init(p);
+  if (!s) s = fs_am_step(p, m, write_u);
+  return s;
+}
+
+// Plan the free-space tables and workspace (after the common planning).
+int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
+  if (prob->p != 8) return fail(TDSE_EUNSUPPORTED, "free space supports the order-16 Alpert rule only (p = 8)");
+  if (prob->q < 2 || prob->q > 32 || prob->panels < 1 || prob->panels > 8) return fail(TDSE_EINVAL, "need 2 <= q <= 32, 1 <= panels <= 8");
+  if (!(prob->eps > 0.0 && prob->eps < 1.0) && !(prob->H > 0.0)) return fail(TDSE_EINVAL, "need 0 < eps < 1 or H > 0");
+  p->free_space = true;
+  alpert_rule(8, 7, p->alp_x, p->alp_w);
+  // H from the Remark on its choice: log(eps / ((1 + ||V||_{2,inf}) eps_m)) / (2 d (1 + phi_max)),
+  // maxima over the step times
+  if (prob->H > 0.0) {
+    p->H = prob->H;
+  } else {
+    const double cell = (p->dim == 2 ? 4.0 / ((double)p->M1 * p->M2) : 2.0 / p->M2);
+    double normV = 0.0, phimax = 0.0;
+    std::vector<double> f(MAXV);
+    for (int n = 0; n <= p->nsteps; ++n) {
+      const double t = p->t_at(n);
+      p->fV_at(t, f.data());
+      double s2 = 0.0;
+      for (int64_t g = 0; g < p->P; ++g) {
+        double v = 0.0;
+        for (int r = 0; r < p->nV; ++r) v += f[r] * p->Vsrc[(size_t)r * p->P + g];
+        s2 += v * v;
+      }
+      normV = std::max(normV, std::sqrt(s2 * cell));
+      double ph[2];
+      p->tf.phi(t, ph);
+      phimax = std::max(phimax, std::sqrt(ph[0] * ph[0] + (p->dim == 2 ? ph[1] * ph[1] : 0.0)));
+    }
+    p->H = std::log(prob->eps / ((1.0 + normV) * std::ldexp(1.0, -52))) / (2.0 * p->dim * (1.0 + phimax));
+  }
+  if (!(p->H > 0.0)) return fail(TDSE_EINVAL, "the rule for H gives H <= 0 (eps too small)");
+  const int axes[2] = {p->dim == 2 ? prob->M[0] : 1, p->dim == 2 ? prob->M[1] : prob->M[0]};
+  const int nus[2] = {p->dim == 2 ? prob->nu[0] : 0, p->dim == 2 ? prob->nu[1] : prob->nu[0]};
+  for (int a = 0; a < 2; ++a) {
+    if (a == 0 && p->dim == 1) {
+      tdse_plan_s::FAxis& F = p->fx[0];
+      F = tdse_plan_s::FAxis();
+      F.tables.assign(256, 0);   // zeta = {0}
+      continue;
+    }
+    const int M = axes[a], nu = nus[a];
+    if (!fs_nu_supported(nu)) return fail(TDSE_EINVAL, "nu must be 256, 512, 1024 or 2048");
+    const int NE = nu / 2 - 13;
+    if (M < 8 || M % 2 || M > nu || NE <= M / 2) return fail(TDSE_EINVAL, "free space needs even M, M <= nu and N_E > M/2");
+    plan_free_axis(p, a, M, nu, prob->q, prob->panels);
+    if (p->fx[a].N > fs_max_modes(nu)) return fail(TDSE_EINVAL, "too many Gauss nodes for this nu (2p + 2 q panels > 90)");
+  }
+  p->NM = (int64_t)p->fx[0].N * p->fx[1].N;
+  size_t off = 0;
+  const size_t mb = (size_t)p->NM * sizeof(double2);
+  p->o_B = off; off = align256(off + mb);
+  p->o_ringf = off; off = align256(off + (size_t)(p->order - 1) * mb);
+  p->o_UH[0] = off; off = align256(off + mb);
+  p->o_UH[1] = off; off = align256(off + mb);
+  p->o_tmpf = off; off = align256(off + (size_t)p->fx[0].N * p->fx[1].M * sizeof(double2));
+  p->o_u[0] = off; off = align256(off + (size_t)p->P * sizeof(double2));
+  p->o_u[1] = off; off = align256(off + (size_t)p->P * sizeof(double2));
+  p->o_Vf = off; off = align256(off + (size_t)p->nV * p->P * sizeof(double));
+  p->o_ph = off; off = align256(off + (size_t)(p->order - 1) * (p->fx[0].N + p->fx[1].N) * sizeof(double2));
+  for (int a = 0; a < 2; ++a) {
+    p->fx[a].o_tab = off;
+    off = align256(off + p->fx[a].tables.size());
+  }
+  p->total = off;
+  return TDSE_OK;
+}
+
 bool good_len(int M) { return M >= 8 && M <= 3072 && M % 2 == 0 && line_length_supported(M); }
 
 }  // namespace
@@ -613,9 +1139,11 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   if (!prob || !out) return fail(TDSE_EINVAL, "NULL argument");
   *out = nullptr;
   if (prob->dim != 1 && prob->dim != 2) return fail(prob->dim == 3 ? TDSE_EUNSUPPORTED : TDSE_EINVAL, "dim must be 1 or 2");
-  if (prob->domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "free-space domain is not available in this build");
+  if (prob->domain != TDSE_PERIODIC && prob->domain != TDSE_FREE) return fail(TDSE_EINVAL, "unknown domain");
   if (prob->precision != TDSE_FP64 && prob->precision != TDSE_FP32_SPLIT) return fail(TDSE_EINVAL, "unknown precision");
-  for (int a = 0; a < prob->dim; ++a)
+  const bool free_dom = prob->domain == TDSE_FREE;
+  if (free_dom && prob->precision != TDSE_FP64) return fail(TDSE_EUNSUPPORTED, "the free-space scheme runs in FP64 only");
+  for (int a = 0; a < prob->dim && !free_dom; ++a)
     if (!good_len(prob->M[a])) return fail(TDSE_EINVAL, "grid size must be 2^a or 3*2^a, 8..3072");
   if (!(prob->T > 0.0) || prob->nsteps < 1) return fail(TDSE_EINVAL, "need T > 0 and nsteps >= 1");
   if (prob->order < 2 || prob->order > 8 || prob->order % 2) return fail(TDSE_EINVAL, "order must be 2, 4, 6 or 8");
@@ -679,6 +1207,19 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   tf.A_ctx = prob->A_ctx;
   tf.prepare();
 
+  if (free_dom) {
+    p->Vsrc.assign(prob->V_fields, prob->V_fields + (size_t)p->nV * p->P);
+    p->st[0].Vhost.clear();
+    p->st[1].Vhost.clear();
+    const int s = plan_free(p, prob);
+    if (s) {
+      delete p;
+      return s;
+    }
+    *out = p;
+    return TDSE_OK;
+  }
+
   for (int g = 0; g < 2; ++g) {
     p->st[g].tw1 = twiddles(p->M1, p->st[g].prec == P_SPLIT);
     p->st[g].tw2 = twiddles(p->M2, p->st[g].prec == P_SPLIT);
@@ -731,6 +1272,13 @@ int tdse_bind(tdse_plan_t p, void* ws, size_t bytes, void* stream) {
     HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw1, S.tw1.data(), S.tw1.size(), hipMemcpyHostToDevice, p->stream));
     HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw2, S.tw2.data(), S.tw2.size(), hipMemcpyHostToDevice, p->stream));
   }
+  if (p->free_space) {
+    HIP_TRY(hipMemcpyAsync(p->ws + p->o_Vf, p->Vsrc.data(), p->Vsrc.size() * sizeof(double), hipMemcpyHostToDevice,
+                           p->stream));
+    for (int a = 0; a < 2; ++a)
+      HIP_TRY(hipMemcpyAsync(p->ws + p->fx[a].o_tab, p->fx[a].tables.data(), p->fx[a].tables.size(),
+                             hipMemcpyHostToDevice, p->stream));
+  }
   HIP_TRY(hipStreamSynchronize(p->stream));
   p->bound = true;
   p->cur = -1;
@@ -741,6 +1289,7 @@ int tdse_set_state(tdse_plan_t p, const void* u0, int32_t on_device) {
   if (!p || !u0) return fail(TDSE_EINVAL, "NULL argument");
   if (!p->bound) return fail(TDSE_ESTATE, "tdse_bind must come first");
   p->ucur = 0;
+  p->uh_cur = 0;
   const size_t bytes = (size_t)p->P * sizeof(double2);
   if (on_device) {
     HIP_TRY(hipMemcpyAsync(p->u(0), u0, bytes, hipMemcpyDeviceToDevice, p->stream));
@@ -760,6 +1309,12 @@ int tdse_step(tdse_plan_t p, int32_t k) {
   const int end = p->cur + k;
   for (int m = p->cur + 1; m <= end; ++m) {
     int s = TDSE_OK;
+    if (p->free_space) {
+      s = fs_step(p, m, m == end);
+      if (s) return s;
+      p->cur = m;
+      continue;
+    }
     if (m <= p->ns) {
       if (m == 1) s = op_history(p, 0);
       if (!s) s = op_richardson(p, m);
@@ -841,6 +1396,38 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
   if (key == TDSE_Q_MODES) { *value = (double)p->P; return TDSE_OK; }
   if (key == TDSE_Q_STEPS_DONE) { *value = (double)p->cur; return TDSE_OK; }
   if (key == TDSE_Q_DT) { *value = p->dt; return TDSE_OK; }
+  if (p->free_space && (key == TDSE_Q_BYTES_PER_STEP || key == TDSE_Q_BYTES_COL || key == TDSE_Q_BYTES_ROW)) {
+    // column pass: tile (N1 x M2) in and out (32 per element) and the
+    // potential fields (8 nV per grid point); row pass: tile in and out,
+    // B in and out (32 per mode), n-2 history reads and one write (16 (n-1))
+    const double tile = (double)p->fx[0].N * p->fx[1].M;
+    const double col = 32.0 * tile + 8.0 * p->nV * (double)p->P;
+    const double row = 32.0 * tile + (32.0 + 16.0 * (p->order - 1)) * (double)p->NM;
+    *value = key == TDSE_Q_BYTES_COL ? col : key == TDSE_Q_BYTES_ROW ? row : col + row;
+    return TDSE_OK;
+  }
+  if (key == TDSE_Q_FS_H) {
+    if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");
+    *value = p->H;
+    return TDSE_OK;
+  }
+  if ((key >= TDSE_Q_FS_MODES && key < TDSE_Q_FS_MODES + 2) || (key >= TDSE_Q_FS_NE && key < TDSE_Q_FS_NE + 2)) {
+    if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");
+    const bool modes = key < TDSE_Q_FS_NE;
+    const int axis = key - (modes ? TDSE_Q_FS_MODES : TDSE_Q_FS_NE);
+    if (axis >= p->dim) return fail(TDSE_EINVAL, "axis out of range");
+    const tdse_plan_s::FAxis& F = p->fx[p->dim == 2 ? axis : 1];
+    *value = modes ? (double)F.N : (double)F.NE;
+    return TDSE_OK;
+  }
+  if ((key >= TDSE_Q_ALPERT_X && key < TDSE_Q_ALPERT_X + 16) || (key >= TDSE_Q_ALPERT_W && key < TDSE_Q_ALPERT_W + 16)) {
+    if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");
+    const bool xs = key < TDSE_Q_ALPERT_W;
+    const int k = key - (xs ? TDSE_Q_ALPERT_X : TDSE_Q_ALPERT_W);
+    if (k >= (int)p->alp_x.size()) return fail(TDSE_EINVAL, "Alpert index out of range");
+    *value = xs ? p->alp_x[k] : p->alp_w[k];
+    return TDSE_OK;
+  }
   if (key == TDSE_Q_BYTES_PER_STEP) {
     // per mode: B in/out (32), history ring n-2 reads + 1 write (16 (n-1)),
     // two tile round trips (64), the potential fields (8 nV)

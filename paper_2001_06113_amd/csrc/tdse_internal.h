@@ -18,6 +18,8 @@ enum PassMode : int {
   R_FWD = 4,    // forward FFT, store modes
   R_FORM = 5,   // forward FFT = uhat, B from uhat and history, inverse FFT
   R_INV = 6,    // inverse FFT of the FP64 state B (rows) into the tile buffer
+  R_BINIT = 7,  // free space: B = P (uhat - i c What), inverse transform
+  R_UHACC = 8,  // free space: forward transform, uhat^(l) = B - i c What accumulated
 };
 
 // Transform precision: FP64 everywhere, or complex64 transforms, tile
@@ -72,6 +74,60 @@ struct LineArgs {
   double2* ph;
   PhaseReq req;
 };
+
+// One axis of the free-space complex-frequency transform (freespace_kernels.hip):
+// modes ordered E1 | A1 C A3 | E3 with N = 2 NE + ND.  All tables complex128,
+// device pointers into the plan's workspace.
+struct CFAxis {
+  int M, N, NE, ND;             // grid points, modes, E-nodes per side, dense modes
+  const double2 *pre3, *pre1;   // [M] forward pre-multipliers (E3, E1)
+  const double2 *post3, *post1; // [NE] forward post-multipliers incl. 2/M
+  const double2 *ipre3, *ipre1; // [NE] inverse pre-multipliers incl. w/(2 pi)
+  const double2 *ipost3, *ipost1; // [M] inverse post-multipliers
+  const double2* Dfwd;          // [ND][M] (2/M) exp(-i zeta_q x_j)
+  const double2* Dinv;          // [M][ND] (w_q/2pi) exp(i zeta_q x_j)
+  const double2* tw;            // nu-point twiddles
+  const double2* zeta;          // [N] nodes (for the phase factors)
+};
+
+struct FSArgs {
+  int mode;
+  int N1, N2;                   // modes per axis (N1 = 1 for a 1D problem)
+  const double2* src;           // tile source
+  double2* dst;                 // tile destination
+  const double2* usrc;          // physical solution (C_FWD)
+  double2* fdst;                // R_FWD destination (modes)
+  double2* Bm;
+  double2* ring;
+  int64_t ring_stride;
+  double2* UH;                  // carried uhat (start-up)
+  double2* UHacc;               // Richardson accumulator of uhat
+  double2* uout;
+  double2* uacc;
+  double wacc;
+  int acc_first;
+  const double* V;
+  int nV;
+  int64_t vstride;
+  double fV[MAXV];
+  double csolve;
+  double alpha_re, alpha_im, beta_re, beta_im;
+  int nh, slot_w;
+  int slot_r[MAXH + 1];
+  double c0;
+  double ch[MAXH + 1];
+  double2* ph;
+  PhaseReq req;
+  CFAxis ax1, ax2;
+};
+
+// Free-space launchers (freespace_kernels.hip); events as for the periodic passes.
+hipError_t launch_fs_row(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// nu = 0: the pointwise pass of a 1D problem
+hipError_t launch_fs_col(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_fs_phase(const FSArgs& a, hipStream_t s);
+bool fs_nu_supported(int nu);
+int fs_max_modes(int nu);
 
 // Launchers (periodic_kernels.hip).  Non-null events e0/e1 are recorded at
 // the kernel's own start and end.  Return a hipError_t.

@@ -48,7 +48,8 @@ class Plan:
     def __init__(self, *, dim: int, M: Sequence[int], T: float, nsteps: int, V_fields,
                  order: int = 8, n_start: int = -1, precision: str = "fp64",
                  f_kind: str = "const", f_params=None, A_kind: str = "none", A_params=None,
-                 A_steps=None, domain: str = "periodic", device=None, stream=None):
+                 A_steps=None, domain: str = "periodic", eps: float = 1e-10, p: int = 8, q: int = 10,
+                 panels: int = 1, nu: Sequence[int] = (), H: float = 0.0, device=None, stream=None):
         self.lib = _lib.load()
         self.dim = dim
         self.M = tuple(int(m) for m in M)
@@ -82,6 +83,14 @@ class Plan:
             st = np.ascontiguousarray(np.asarray(A_steps, dtype=np.float64).ravel())
             keep.append(st)
             prob.A_steps = _dptr(st)
+        # free space: contour tolerance, Alpert order, Gauss panels, FFT sizes
+        prob.eps = float(eps)
+        prob.p = int(p)
+        prob.q = int(q)
+        prob.panels = int(panels)
+        for a, n in enumerate(nu):
+            prob.nu[a] = int(n)
+        prob.H = float(H)
         handle = C.c_void_p()
         _check(self.lib.tdse_plan(C.byref(prob), C.byref(handle)), "tdse_plan")
         self.handle = handle
@@ -110,7 +119,7 @@ class Plan:
                    precision=prob.precision, f_kind=f_kind, f_params=f_params, A_kind=prob.A_kind,
                    A_params=prob.A_params if prob.A_kind == "pulse_sin2" else None,
                    A_steps=prob.A_steps if prob.A_kind == "stepwise" else None,
-                   domain=prob.domain, **kw)
+                   domain=prob.domain, eps=prob.eps, p=prob.p, q=prob.q, panels=prob.panels, nu=prob.nu, **kw)
 
     # -------------------------------------------------------------- calls
     def _as_device(self, u) -> torch.Tensor:

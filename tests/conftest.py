@@ -11,3 +11,11 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture(scope="session")
+def emu():
+    """The library's kernels and C ABI compiled for the host (tests/emu), built once per session."""
+    from emu.emu_plan import load
+
+    return load(rebuild=True)

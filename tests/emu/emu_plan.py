@@ -28,7 +28,7 @@ def load(rebuild: bool = False):
 class EmuPlan:
     """Plan of a workloads.Problem on the emulated library."""
 
-    def __init__(self, lib, prob):
+    def __init__(self, lib, prob, H: float = 0.0):
         self.lib = lib
         p = _lib.Problem()
         p.dim = prob.dim
@@ -60,6 +60,13 @@ class EmuPlan:
             st = np.ascontiguousarray(np.asarray(prob.A_steps, dtype=np.float64).ravel())
             self._keep.append(st)
             p.A_steps = st.ctypes.data_as(C.POINTER(C.c_double))
+        p.eps = prob.eps
+        p.p = prob.p
+        p.q = prob.q
+        p.panels = prob.panels
+        for a, n in enumerate(prob.nu):
+            p.nu[a] = n
+        p.H = H
         self.prob = p
         h = C.c_void_p()
         st = lib.tdse_plan(C.byref(p), C.byref(h))
@@ -76,6 +83,13 @@ class EmuPlan:
         if st:
             raise RuntimeError(lib.tdse_last_error().decode())
         self.shape = tuple(prob.M)
+
+    def query(self, key: int) -> float:
+        v = C.c_double()
+        st = self.lib.tdse_query(self.h, key, C.byref(v))
+        if st:
+            raise RuntimeError(self.lib.tdse_last_error().decode())
+        return v.value
 
     def run(self, u0):
         u0 = np.ascontiguousarray(np.asarray(u0, dtype=np.complex128))

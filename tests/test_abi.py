@@ -35,12 +35,15 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, n), n
 
 
-def _problem(dim=2, M=(32, 64), T=1.0, nsteps=100, order=8, A=None, nV=1, f=None, domain=0, precision=0):
+def _problem(dim=2, M=(32, 64), T=1.0, nsteps=100, order=8, A=None, nV=1, f=None, domain=0, precision=0,
+             nu=(256, 256), fs_p=8, q=10, panels=1, eps=1e-10, H=0.0):
     from paper_2001_06113_amd import _lib
 
     p = _lib.Problem()
     p.dim = dim
     p.domain = domain
+    p.nu[0], p.nu[1] = nu
+    p.p, p.q, p.panels, p.eps, p.H = fs_p, q, panels, eps, H
     p.M[0], p.M[1] = M[0], (M[1] if len(M) > 1 else 0)
     p.T = T
     p.nsteps = nsteps
@@ -82,8 +85,19 @@ def _plan(lib, p):
     (dict(T=0.0), -1),
     (dict(nsteps=0), -1),
     (dict(nV=0), -1),
-    (dict(domain=1), -2),
+    (dict(domain=2), -1),
     (dict(precision=7), -1),
+    # free space
+    (dict(domain=1, precision=1), -2),          # FP64 only
+    (dict(domain=1, fs_p=6), -2),               # order-16 Alpert rule only
+    (dict(domain=1, nu=(300, 256)), -1),        # FFT size not built
+    (dict(domain=1, M=(32, 300)), -1),          # M > nu
+    (dict(domain=1, M=(32, 63)), -1),           # odd M
+    (dict(domain=1, nu=(64, 256)), -1),         # N_E <= M/2
+    (dict(domain=1, eps=0.0), -1),              # no tolerance and no H
+    (dict(domain=1, q=1), -1),
+    (dict(domain=1, panels=0), -1),
+    (dict(domain=1, q=32, panels=8, nu=(256, 256)), -1),   # more Gauss nodes than the kernels hold
 ])
 def test_plan_rejects(lib, kw, status):
     st, h = _plan(lib, _problem(**kw))
@@ -144,6 +158,69 @@ def test_planner_phi_closed_form(lib):
     assert lib.tdse_query(h, 64, C.byref(v)) == 0
     assert abs(v.value - tot) < 1e-13
     assert lib.tdse_query(h, 65, C.byref(v)) == 0 and v.value == 0.0
+    lib.tdse_destroy(h)
+
+
+def test_free_space_planner_alpert_rule_matches_oracle(lib):
+    # the planner's long-double modified-Chebyshev/Golub-Welsch construction
+    # against the oracle's exact Hankel solve and mpmath roots
+    from oracle.quadrature import alpert_float
+
+    st, h = _plan(lib, _problem(domain=1))
+    assert st == 0, lib.tdse_last_error()
+    x, w = alpert_float(8, 7)
+    v = C.c_double()
+    for k in range(8):
+        assert lib.tdse_query(h, 96 + k, C.byref(v)) == 0
+        assert abs(v.value - x[k]) < 2e-14
+        assert lib.tdse_query(h, 112 + k, C.byref(v)) == 0
+        assert abs(v.value - w[k]) < 2e-14
+    assert lib.tdse_query(h, 96 + 8, C.byref(v)) == -1
+    lib.tdse_destroy(h)
+
+
+@pytest.mark.parametrize("dim,M,nu", [(1, (64,), (512,)), (2, (48, 32), (256, 512))])
+def test_free_space_planner_contour_matches_oracle(lib, dim, M, nu):
+    # H from the rule of Section 3.2 with ||V|| and phi over the step times,
+    # mode counts N = 2 N_E + 2p + N_C of Section 3.4
+    from oracle.freespace import FreeSpaceOracle
+    from paper_2001_06113_amd import _lib
+    from workloads import free_problem_from_seed
+
+    prob = free_problem_from_seed(11, dim, M, 0.2, 40, nu=nu, eps=1e-11, q=7, panels=2)
+    orc = FreeSpaceOracle(prob)
+    p = _lib.Problem()
+    p.dim, p.domain, p.T, p.nsteps, p.order, p.n_start = dim, 1, prob.T, prob.nsteps, 8, -1
+    for a in range(dim):
+        p.M[a], p.nu[a] = M[a], nu[a]
+    p.eps, p.p, p.q, p.panels = prob.eps, 8, 7, 2
+    V = np.ascontiguousarray(prob.V_fields[0].ravel())
+    fp = np.asarray(prob.f_params[0], dtype=np.float64)
+    ap = np.asarray(prob.A_params, dtype=np.float64)
+    p._keep = [V, fp, ap]
+    p.nV = 1
+    p.V_fields = V.ctypes.data_as(C.POINTER(C.c_double))
+    p.f_kind, p.f_params = 1, fp.ctypes.data_as(C.POINTER(C.c_double))
+    p.A_kind, p.A_params = 1, ap.ctypes.data_as(C.POINTER(C.c_double))
+    st, h = _plan(lib, p)
+    assert st == 0, lib.tdse_last_error()
+    v = C.c_double()
+    assert lib.tdse_query(h, 80, C.byref(v)) == 0
+    assert abs(v.value - orc.H) < 1e-12 * orc.H
+    for a in range(dim):
+        assert lib.tdse_query(h, 81 + a, C.byref(v)) == 0
+        assert v.value == orc.nodes[a][2]["N"]
+        assert lib.tdse_query(h, 83 + a, C.byref(v)) == 0
+        assert v.value == orc.nodes[a][2]["NE"]
+    if dim == 1:
+        assert lib.tdse_query(h, 82, C.byref(v)) == -1   # no second axis
+    lib.tdse_destroy(h)
+
+
+def test_periodic_plan_has_no_contour(lib):
+    st, h = _plan(lib, _problem())
+    v = C.c_double()
+    assert lib.tdse_query(h, 80, C.byref(v)) == -1
     lib.tdse_destroy(h)
 
 

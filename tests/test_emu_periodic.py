@@ -8,13 +8,6 @@ from oracle.periodic import PeriodicOracle
 from workloads import periodic_problem_from_seed
 
 
-@pytest.fixture(scope="module")
-def emu():
-    from emu.emu_plan import load
-
-    return load(rebuild=True)
-
-
 def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
