@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--prof-runs", type=int, default=3, help="eager runs timed per kernel with HIP events")
     ap.add_argument("--no-split", action="store_true", help="skip the FP32-split 1024x1024 leg")
     ap.add_argument("--split-steps", type=int, default=3)
+    ap.add_argument("--no-free", action="store_true", help="skip the free-space 256x256 leg")
+    ap.add_argument("--free-runs", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run device copies of 256 MiB (to scale HBM byte counters) and exit")
     return ap.parse_args()
@@ -135,6 +137,50 @@ def split_leg(steps: int) -> dict:
             "speedup_vs_fp64": res["fp32split"] / res["fp64"], "rel_l2_vs_fp64": err, "bar": 1e-6}
 
 
+def free_space_leg(runs: int) -> dict:
+    """Free-space FP64 form on the 256 x 256 workload (seed 2, nu = 2048 per
+    axis, eps = 1e-10, 1000 steps): graph-replayed whole runs, and the
+    per-pass durations of one eager run from dispatch-recorded HIP events."""
+    import torch
+
+    from paper_2001_06113_amd.tdse import (Q_BYTES_COL, Q_BYTES_ROW, Q_PROF_MS_COL, Q_PROF_MS_ROW,
+                                           Q_PROF_N_COL, Q_PROF_N_ROW, Plan)
+    from workloads import c2_problem
+
+    dev = torch.device("cuda:0")
+    prob = c2_problem()
+    plan = Plan.from_problem(prob, device=dev)
+    u0 = torch.as_tensor(prob.u0).to(dev)
+    out = torch.empty_like(u0)
+    plan.use_graph(True)
+    plan.run(u0, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        plan.run(u0, out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / runs
+    plan.use_graph(False)
+    plan.profile(True)
+    plan.run(u0, out)
+    row_us = plan.query(Q_PROF_MS_ROW) * 1e3 / max(plan.query(Q_PROF_N_ROW), 1)
+    col_us = plan.query(Q_PROF_MS_COL) * 1e3 / max(plan.query(Q_PROF_N_COL), 1)
+    plan.profile(False)
+    n_modes = plan.query(81) * plan.query(82)
+    row_b, col_b = plan.query(Q_BYTES_ROW), plan.query(Q_BYTES_COL)
+    ach = row_b / (row_us * 1e-6) / 1e9
+    plan.close()
+    return {"workload": "2D free-space TDSE 256x256, nu=2048 per axis, eps=1e-10, p=8, q=10, 1 panel, "
+                        "T=1, 1000 steps AM8 (config 2)",
+            "value": n_modes * prob.nsteps / wall, "unit": "mode-updates/s",
+            "modes": int(n_modes), "grid_points": int(u0.numel()),
+            "grid_point_updates_per_s": u0.numel() * prob.nsteps / wall, "ms_per_run": wall * 1e3,
+            "roofline": {"bound": "hbm", "kernel": "free-space Adams row pass (k_fs_row)", "achieved": ach,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                         "bytes_per_launch": row_b, "mean_launch_us": row_us, "row_pass_us": row_us,
+                         "col_pass_us": col_us, "col_bytes_per_launch": col_b}}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -229,6 +275,8 @@ def main():
     }
     if not args.no_split:
         res["split"] = split_leg(args.split_steps)
+    if not args.no_free:
+        res["free_space"] = free_space_leg(args.free_runs)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     print(json.dumps(res), flush=True)

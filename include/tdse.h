@@ -155,6 +155,10 @@ int tdse_run(tdse_plan_t plan, const void* u0, void* uT, int32_t on_device);
 #define TDSE_Q_FS_NE          83  /* + axis: equispaced nodes per ray N_E      */
 #define TDSE_Q_ALPERT_X       96  /* + k: Alpert node x_k (units of h), k < p   */
 #define TDSE_Q_ALPERT_W      112  /* + k: Alpert weight w_k, k < p              */
+#define TDSE_Q_INSTANCES       4  /* batch: number of instances                 */
+#define TDSE_Q_INST_OFFSET  4096  /* batch, + i: element offset of instance i in packed states */
+#define TDSE_Q_INST_EPT_COL 8192  /* batch, + i: elements per thread of i's Adams column pass */
+#define TDSE_Q_INST_EPT_ROW 12288 /* batch, + i: elements per thread of i's Adams row pass    */
 int tdse_query(tdse_plan_t plan, int32_t key, double* value);
 
 /* Per-kernel timing: with enable != 0 every implicit Adams column and row
@@ -169,6 +173,39 @@ int tdse_profile(tdse_plan_t plan, int32_t enable);
  * non-default stream at tdse_bind; EINVAL otherwise.  Profiling
  * (tdse_profile) runs eagerly.  tdse_bind drops a captured graph. */
 int tdse_graph(tdse_plan_t plan, int32_t enable);
+
+/* ---- batches of independent instances ----------------------------------
+ *
+ * A batch plan marches `count` independent periodic problems together: at
+ * every pass of the scheme (the column and row passes of Section 2.2's steps
+ * and of the start-up) one launch per transform-schedule family covers the
+ * lines of every instance, so a time step of the whole batch is two or a few
+ * launches however many instances it holds.  The instances may differ in
+ * dimension, grid, potential, field and T, but share order, nsteps,
+ * n_start and precision (EINVAL otherwise); line lengths must be 2^a in
+ * 64..2048 or 3 * 2^a in 192..1536 (EUNSUPPORTED otherwise).
+ *
+ * The batch handle takes every call above: tdse_workspace_size / tdse_bind
+ * (one workspace for all instances; bind records the launch arguments of the
+ * whole run into it), tdse_set_state / tdse_get_state / tdse_run with packed
+ * states (instance i at element offset TDSE_Q_INST_OFFSET + i, in instance
+ * order), tdse_step, tdse_graph (tdse_run replays the whole batched run),
+ * tdse_profile and tdse_query (TDSE_Q_MODES: all instances' modes; keys
+ * that describe one problem answer for instance 0). */
+int tdse_plan_batch(const tdse_problem_t* probs, int32_t count, tdse_plan_t* out);
+
+/* Schedule search of a bound batch plan: for each pass kind and line length,
+ * every compiled schedule (elements per thread, hence lines per workgroup)
+ * is timed over `reps` launches of a recorded Adams step and the fastest is
+ * kept for the Adams passes.  The timing launches overwrite the state: call
+ * tdse_set_state (or tdse_run) afterwards.  EUNSUPPORTED for a single plan. */
+int tdse_autotune(tdse_plan_t plan, int32_t reps);
+
+/* Set or read one instance's state (complex128, that instance's shape); a
+ * batch steps once every instance has been set since its last step.  For a
+ * single plan instance 0 is the plan itself. */
+int tdse_set_instance_state(tdse_plan_t plan, int32_t instance, const void* u0, int32_t on_device);
+int tdse_get_instance_state(tdse_plan_t plan, int32_t instance, void* u, int32_t on_device);
 
 /* Release the plan (not the caller's workspace). */
 void tdse_destroy(tdse_plan_t plan);

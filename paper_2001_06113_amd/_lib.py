@@ -29,7 +29,8 @@ class Problem(C.Structure):
 EXPORTS = [
     "tdse_plan", "tdse_workspace_size", "tdse_bind", "tdse_set_state", "tdse_step",
     "tdse_get_state", "tdse_run", "tdse_query", "tdse_destroy", "tdse_status_string",
-    "tdse_last_error", "tdse_profile", "tdse_graph",
+    "tdse_last_error", "tdse_profile", "tdse_graph", "tdse_plan_batch", "tdse_autotune",
+    "tdse_set_instance_state", "tdse_get_instance_state",
 ]
 
 _lib = None
@@ -56,6 +57,10 @@ def load() -> C.CDLL:
     lib.tdse_graph.restype = C.c_int
     lib.tdse_profile.argtypes = [P, C.c_int32]
     lib.tdse_profile.restype = C.c_int
+    lib.tdse_plan_batch.argtypes = [C.POINTER(Problem), C.c_int32, C.POINTER(P)]
+    lib.tdse_autotune.argtypes = [P, C.c_int32]
+    lib.tdse_set_instance_state.argtypes = [P, C.c_int32, P, C.c_int32]
+    lib.tdse_get_instance_state.argtypes = [P, C.c_int32, P, C.c_int32]
     lib.tdse_destroy.argtypes = [P]
     lib.tdse_destroy.restype = None
     lib.tdse_status_string.argtypes = [C.c_int]
@@ -63,7 +68,8 @@ def load() -> C.CDLL:
     lib.tdse_last_error.argtypes = []
     lib.tdse_last_error.restype = C.c_char_p
     for name in ("tdse_plan", "tdse_workspace_size", "tdse_bind", "tdse_set_state", "tdse_step",
-                 "tdse_get_state", "tdse_run", "tdse_query"):
+                 "tdse_get_state", "tdse_run", "tdse_query", "tdse_plan_batch", "tdse_autotune",
+                 "tdse_set_instance_state", "tdse_get_instance_state"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtdse.so")
 
-HIP_SOURCES = ["periodic_kernels.hip", "freespace_kernels.hip"]
+HIP_SOURCES = ["periodic_kernels.hip", "freespace_kernels.hip", "batch_fp64.hip", "batch_split.hip"]
 HOST_SOURCES = ["tdse_api.cpp"]
 ARCH = os.environ.get("TDSE_OFFLOAD_ARCH", "gfx950")
 
@@ -34,7 +34,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
     cc = hipcc()
-    common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+    common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-lambda-capture",
               f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
     dev = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-ffp-contract=fast", "-munsafe-fp-atomics"]
@@ -47,17 +47,21 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         obj = os.path.join(objdir, src + ".o")
         cmds.append([cc, *common, *dev, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    # each compiler writes to its own log file (a pipe could fill up and stall it)
     procs = []
-    for cmd in cmds:
+    for cmd, obj in zip(cmds, objs):
         if verbose:
             print(" ".join(cmd), flush=True)
-        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
-        while sum(p.poll() is None for _, p in procs) >= jobs:
-            procs[0][1].wait()
-    for cmd, p in procs:
-        out, _ = p.communicate()
+        while sum(p.poll() is None for _, p, _ in procs) >= jobs:
+            next(p for _, p, _ in procs if p.poll() is None).wait()
+        log = open(obj + ".log", "w")
+        procs.append((cmd, subprocess.Popen(cmd, stdout=log, stderr=subprocess.STDOUT), log))
+    for cmd, p, log in procs:
+        p.wait()
+        log.close()
+        out = open(log.name).read()
         if p.returncode != 0:
-            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{out}")
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{out[-8000:]}")
         if verbose and out.strip():
             print(out)
     tmp = LIB + ".tmp"

@@ -1,0 +1,356 @@
+// Pass bodies of the periodic marching scheme, shared by the per-instance
+// kernels (periodic_kernels.hip) and the batched kernels (batch_kernels.h).
+//
+// One implicit step (Section 2.2, eq. (uadamsk)) on an M1 x M2 grid is two
+// passes over HBM, each a register-resident line FFT (fft_lds.h) with the
+// pointwise work of the step fused in:
+//
+//  column pass (axis 0; LPW columns per workgroup, lanes run across columns
+//  so each row segment is one coalesced access):
+//     inverse FFT along axis 0                      -> w = F^-1 B on the grid
+//     u = w / (1 + i mu_0 dt V(x,t_n))                 (diagonal solve, Section 2.1 remark)
+//     g = V(x,t_n) u / (M1 M2)
+//     forward FFT along axis 0
+//     (the block also writes the per-axis phase factors of the next row pass)
+//  row pass (axis 1, contiguous rows):
+//     forward FFT along axis 1                      -> What_n = F(V u_n)
+//     uhat_n = B_n - i mu_0 dt What_n, What_n into the history ring,
+//     B_{n+1} = E^(1) uhat_n - i dt sum_{j>=1} mu_j E^(j) What_{n+1-j}
+//     inverse FFT along axis 1
+//
+// with E^(j)(k1,k2) = T1_j[k1] T2_j[k2] and
+// T_a,j[k] = exp(-i k^2 j dt + i k (phi_a(t_{n+1}) - phi_a(t_{n+1-j}))), the
+// factorised phase of Lemma 1.  A 1D problem is the case M1 = 1.
+//
+// Every kernel is a template on the transform type C: double2 (FP64) or
+// float2 (split precision).  In the split form the FFTs, the tile buffer,
+// the history ring, the diagonal solve and the history sum
+// sum_{j>=2} mu_j E^(j) What are complex64, while B, E^(1) uhat, the phase
+// factors, the Richardson accumulator and the physical solution stay FP64.
+//
+// Every global load a pass needs (tile, potential, B, history, phase factors)
+// is issued before its first FFT so their latencies overlap.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+#include "tdse_internal.h"
+
+namespace tdse {
+
+
+template <typename C>
+struct real_of;
+template <>
+struct real_of<double2> { using type = double; };
+template <>
+struct real_of<float2> { using type = float; };
+
+template <typename C>
+__device__ __forceinline__ C from_d(double2 z) {
+  using R = typename real_of<C>::type;
+  return C{(R)z.x, (R)z.y};
+}
+template <typename C>
+__device__ __forceinline__ double2 to_d(C z) { return double2{(double)z.x, (double)z.y}; }
+
+// FFT index -> integer mode in [-M/2, M/2) (M even; M = 1 is the single mode 0)
+__device__ __forceinline__ int signed_mode(int idx, int M) { return idx < ((M + 1) >> 1) ? idx : idx - M; }
+
+// (-i c) * z
+template <typename C>
+__device__ __forceinline__ C mul_mi(double c, C z) {
+  using R = typename real_of<C>::type;
+  const R cc = (R)c;
+  return C{cc * z.y, -cc * z.x};
+}
+
+// Per-axis phase table of the next row pass, spread over the nblk workgroups
+// of the instance's column pass (blk = this workgroup's index), FP64.
+__device__ __forceinline__ void build_phase_table(const LineArgs& a, int nthreads, int blk, int nblk) {
+  const int per = a.M1 + a.M2;
+  const int total = a.req.nj * per;
+  for (int idx = blk * nthreads + threadIdx.x; idx < total; idx += nblk * nthreads) {
+    const int j = idx / per;
+    const int kk = idx - j * per;
+    double k, dphi;
+    if (kk < a.M1) {
+      k = (double)signed_mode(kk, a.M1);
+      dphi = a.req.dphi1[j];
+    } else {
+      k = (double)signed_mode(kk - a.M1, a.M2);
+      dphi = a.req.dphi2[j];
+    }
+    const double th = -(k * k) * a.req.tau[j] + k * dphi;
+    double s, c;
+    sincos(th, &s, &c);
+    a.ph[idx] = double2{c, s};
+  }
+}
+
+// Workgroups are dealt to the eight XCDs round-robin.  Neighbouring column
+// tiles share 128-byte lines (of the tile data and of the potential), so the
+// G tiles Gq..Gq+G-1 go to workgroups b, b+8, ..., b+8(G-1), which sit on the
+// same XCD and L2.
+template <int G>
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  if (nb % (8 * G)) return b;
+  const int x = b & 7, s = b >> 3;
+  return G * ((s / G) * 8 + x) + (s % G);
+}
+
+// ------------------------------------------------------------- column pass
+
+template <typename C, int N, int LPW>
+struct col_lds {
+  static constexpr int PITCH = N > 1 ? lds_line_len(N) + 1 : 1;   // +1 spreads the LPW lines over banks
+  static constexpr bool TWL = (N > 1 && N <= 1024);
+  static constexpr int elems = LPW * PITCH + (TWL ? N : 0);      // line buffers, then the twiddles
+};
+
+// Column pass over lines line0 .. line0+LPW-1 of one instance; blk/nblk
+// place this workgroup among the instance's column-pass workgroups (for the
+// phase table).  lds holds col_lds<C,N,LPW>::elems elements.
+template <typename C, int N, int LPW, int TL>
+__device__ __forceinline__ void col_body(const LineArgs& a, int line0, int blk, int nblk, C* lds) {
+  using R = typename real_of<C>::type;
+  constexpr int NT = LPW * TL;
+  constexpr int EPT = N / TL;
+  constexpr int PITCH = col_lds<C, N, LPW>::PITCH;
+  constexpr bool TWL = col_lds<C, N, LPW>::TWL;
+  C* twl = lds + LPW * PITCH;
+  const int tid = threadIdx.x;
+  const int i = tid % LPW, t = tid / LPW;
+  const int line = line0 + i;
+  const bool active = line < a.nlines;
+  const int mode = a.mode;
+  const R* __restrict__ V = (const R*)a.V;
+
+  C v[EPT];
+  double2 u0[EPT];   // C_FWD reads the complex128 physical solution
+  double vv[EPT];
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) {
+    v[m] = C{0, 0};
+    u0[m] = double2{0.0, 0.0};
+    vv[m] = 0.0;
+    if (active) {
+      const int64_t g = (int64_t)line * a.line_stride + (int64_t)(t + TL * m) * a.elem_stride;
+      if (mode == C_FWD) u0[m] = ((const double2*)a.src)[g];
+      else v[m] = ((const C*)a.src)[g];
+      double p = 0.0;
+      for (int r = 0; r < a.nV; ++r) p += a.fV[r] * (double)V[r * a.vstride + g];
+      vv[m] = p;
+    }
+  }
+  if constexpr (TWL) {
+    for (int q = tid; q < N; q += NT) twl[q] = ((const C*)a.tw)[q];
+  }
+  if (a.req.nj > 0) build_phase_table(a, NT, blk, nblk);
+  if constexpr (TWL) __syncthreads();
+  const C* tw = TWL ? twl : (const C*)a.tw;
+  C* myline = &lds[i * PITCH];
+
+  if (mode == C_FWD) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const double cr = a.alpha_re + a.beta_re * vv[m], ci = a.alpha_im + a.beta_im * vv[m];
+      const double2 u = u0[m];
+      v[m] = from_d<C>(double2{(cr * u.x - ci * u.y) * a.scale, (cr * u.y + ci * u.x) * a.scale});
+    }
+  } else {  // C_SOLVE
+    fft_regs<N, TL, true>(v, t, myline, tw);
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const C w = v[m];
+      const R q = (R)(a.csolve * vv[m]);
+      const R inv = R(1) / (R(1) + q * q);
+      // u = w (1 - i q) / (1 + q^2)
+      const C u = C{(w.x + q * w.y) * inv, (w.y - q * w.x) * inv};
+      if (active) {
+        const int64_t g = (int64_t)line * a.line_stride + (int64_t)(t + TL * m) * a.elem_stride;
+        const double2 ud = to_d(u);
+        if (a.uout) a.uout[g] = ud;
+        if (a.uacc) {
+          double2 acc = a.acc_first ? double2{0.0, 0.0} : a.uacc[g];
+          acc.x += a.wacc * ud.x;
+          acc.y += a.wacc * ud.y;
+          a.uacc[g] = acc;
+        }
+      }
+      const R s = (R)(vv[m] * a.scale);
+      v[m] = C{s * u.x, s * u.y};
+    }
+  }
+  fft_regs<N, TL, false>(v, t, myline, tw);
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int64_t g = (int64_t)line * a.line_stride + (int64_t)(t + TL * m) * a.elem_stride;
+      ((C*)a.dst)[g] = v[m];
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------- row pass
+
+template <typename C, int N, int LPW>
+struct row_lds {
+  static constexpr int PITCH = lds_line_len(N);
+  static constexpr bool TWL = (N <= 1024);
+  static constexpr int elems = LPW * PITCH + (TWL ? N : 0);
+};
+
+// Row pass over rows k1 = line0 .. line0+LPW-1 of one instance; lds holds
+// row_lds<C,N,LPW>::elems elements.
+template <typename C, int N, int LPW, int TL>
+__device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
+  constexpr int NT = LPW * TL;
+  constexpr int EPT = N / TL;
+  constexpr int NH = MAXH - 1;    // history terms of the order-8 rule (j = 1..7)
+  constexpr bool PF = EPT <= 4;   // prefetch history and phases into registers
+  constexpr bool TWL = row_lds<C, N, LPW>::TWL;
+  constexpr int PITCH = row_lds<C, N, LPW>::PITCH;
+  C* twl = lds + LPW * PITCH;
+  const int tid = threadIdx.x;
+  const int i = tid / TL, t = tid % TL;
+  const int k1 = line0 + i;
+  const bool active = k1 < a.nlines;
+  const int mode = a.mode;
+  const int per = a.M1 + a.M2;
+  const int nh = a.nh;
+  const int64_t row0 = (int64_t)k1 * a.line_stride;
+  const C* __restrict__ src = (const C*)a.src;
+  const double2* __restrict__ ph = a.ph;
+  const C* __restrict__ ring = (const C*)a.ring;
+  const int64_t rstride = a.ring_stride;
+  const int M1 = a.M1;
+  int slot_r[MAXH + 1];
+#pragma unroll
+  for (int j = 0; j <= MAXH; ++j) slot_r[j] = a.slot_r[j];
+
+  C v[EPT];
+  double2 Bp[EPT];
+  C Wr[PF ? NH - 1 : 1][EPT];
+  double2 E1[EPT];               // E^(1) in FP64 (multiplies uhat)
+  C T2[PF ? NH - 1 : 1][EPT];    // axis-2 factors of E^(j), j >= 2, transform precision
+  double2 T1[NH];
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) {
+    v[m] = C{0, 0};
+    if (active) v[m] = (mode == R_INV) ? from_d<C>(a.Bm[row0 + (t + TL * m)]) : src[row0 + (t + TL * m)];
+  }
+  if (active && mode == R_AM) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) Bp[m] = a.Bm[row0 + (t + TL * m)];
+    if constexpr (PF) {
+#pragma unroll
+      for (int j = 2; j <= NH; ++j) {
+        if (j <= nh) {
+#pragma unroll
+          for (int m = 0; m < EPT; ++m) Wr[j - 2][m] = ring[slot_r[j] * rstride + row0 + (t + TL * m)];
+        }
+      }
+    }
+  }
+  if (active && mode != R_FWD && mode != R_INV) {
+    const int nj = (mode == R_INIT) ? 1 : nh;
+    T1[0] = ph[k1];
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) E1[m] = cmul(T1[0], ph[M1 + (t + TL * m)]);
+#pragma unroll
+    for (int j = 2; j <= NH; ++j) {
+      if (j <= nj) {
+        T1[j - 1] = ph[(j - 1) * per + k1];
+        if constexpr (PF) {
+#pragma unroll
+          for (int m = 0; m < EPT; ++m) T2[j - 2][m] = from_d<C>(ph[(j - 1) * per + M1 + (t + TL * m)]);
+        }
+      }
+    }
+  }
+  // E^(j), j >= 2, and the history term What_{n+1-j} at element m, from
+  // registers (PF) or memory.  Only plain locals are captured: taking the
+  // address of the by-value kernel argument would copy it to scratch.
+  auto Ej = [&T1, &T2, ph, per, M1, t](int j, int m) -> C {
+    if constexpr (PF) return cmul(from_d<C>(T1[j - 1]), T2[j - 2][m]);
+    else return from_d<C>(cmul(T1[j - 1], ph[(j - 1) * per + M1 + (t + TL * m)]));
+  };
+  auto Wh = [&Wr, &slot_r, ring, rstride, row0, t](int j, int m) -> C {
+    if constexpr (PF) return Wr[j - 2][m];
+    else return ring[slot_r[j] * rstride + row0 + (t + TL * m)];
+  };
+  if constexpr (TWL) {
+    for (int q = tid; q < N; q += NT) twl[q] = ((const C*)a.tw)[q];
+    __syncthreads();
+  }
+  const C* tw = TWL ? twl : (const C*)a.tw;
+  C* myline = &lds[i * PITCH];
+
+  if (mode != R_INV) fft_regs<N, TL, false>(v, t, myline, tw);
+
+  if (mode == R_FWD) {
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) ((C*)a.fdst)[row0 + (t + TL * m)] = v[m];
+    }
+    return;
+  }
+  // fused recurrence; lanes past the last line (ragged tile) only keep the
+  // FFT barriers company and touch no memory
+  if (!active) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = C{0, 0};
+  } else if (mode == R_INV) {
+    // v already holds the row of B
+  } else if (mode == R_AM) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const C W = v[m];
+      const double2 Wd = to_d(W);
+      const double2 uh = cadd(Bp[m], mul_mi(a.c0, Wd));
+      double2 acc = cmul(E1[m], cadd(uh, mul_mi(a.ch[1], Wd)));
+      C hist = C{0, 0};
+#pragma unroll
+      for (int j = 2; j <= NH; ++j) {
+        if (j <= nh) hist = cadd(hist, cmul(Ej(j, m), mul_mi(a.ch[j], Wh(j, m))));
+      }
+      acc = cadd(acc, to_d(hist));
+      const int64_t g = row0 + (t + TL * m);
+      if (a.slot_w >= 0) ((C*)a.ring)[a.slot_w * rstride + g] = W;
+      a.Bm[g] = acc;
+      v[m] = from_d<C>(acc);
+    }
+  } else if (mode == R_INIT) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const double2 acc = cmul(E1[m], to_d(v[m]));
+      a.Bm[row0 + (t + TL * m)] = acc;
+      v[m] = from_d<C>(acc);
+    }
+  } else {  // R_FORM: B from uhat (this FFT) and nh history terms, all from the ring
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      double2 acc = cmul(E1[m], to_d(v[m]));
+      const int64_t g = row0 + (t + TL * m);
+      acc = cadd(acc, cmul(E1[m], mul_mi(a.ch[1], to_d(ring[slot_r[1] * rstride + g]))));
+      C hist = C{0, 0};
+#pragma unroll
+      for (int j = 2; j <= NH; ++j) {  // static j: registers stay registers
+        if (j <= nh) hist = cadd(hist, cmul(Ej(j, m), mul_mi(a.ch[j], ring[slot_r[j] * rstride + g])));
+      }
+      acc = cadd(acc, to_d(hist));
+      a.Bm[g] = acc;
+      v[m] = from_d<C>(acc);
+    }
+  }
+  fft_regs<N, TL, true>(v, t, myline, tw);
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) ((C*)a.dst)[row0 + (t + TL * m)] = v[m];
+  }
+}
+
+
+}  // namespace tdse

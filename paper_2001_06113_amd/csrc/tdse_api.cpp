@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -250,6 +251,17 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------------ plan object
 
+// A launch recorded instead of issued (batched execution, see tdse_plan_batch).
+struct RecLaunch {
+  int kind;          // 0 column pass, 1 row pass, 2 complex128 -> complex64 narrowing
+  int g;             // buffer stage
+  bool timed;        // an implicit Adams pass (profiled)
+  LineArgs a;        // passes
+  const void* nsrc;  // narrowing
+  void* ndst;
+  int64_t nn;
+};
+
 struct tdse_plan_s {
   int dim = 1, M1 = 1, M2 = 1;
   int64_t P = 1;
@@ -298,6 +310,41 @@ struct tdse_plan_s {
   size_t ev_used = 0;
   std::vector<std::pair<size_t, int>> prof_marks;  // (first event index, 0 col / 1 row)
 
+  // when set, passes are appended here instead of launched
+  std::vector<RecLaunch>* rec = nullptr;
+
+  // ---- batch of independent periodic instances (tdse_plan_batch)
+  std::vector<tdse_plan_s*> sub;                // owned
+  std::vector<size_t> sub_off;                  // workspace offset of each instance
+  std::vector<int64_t> sub_elem;                // element offset of each instance in packed states
+  struct GLaunch {
+    int kind, g;
+    bool timed;
+    int64_t arg0;    // first of count entries in the args table (kind 0/1) or the narrowing list (kind 2)
+  };
+  std::vector<std::vector<GLaunch>> seg;        // [m]: step m without output (m = 1..nsteps)
+  std::vector<GLaunch> seg_last;                // step nsteps with output
+  std::vector<int> ucur_after;                  // [m]: physical buffer of u after step m
+  std::vector<LineArgs> bargs;                  // host copy of the args table
+  struct Narrow {
+    const void* src;
+    void* dst;
+    int64_t n;
+  };
+  std::vector<Narrow> narrows;
+  size_t o_args = 0, cap_args = 0, o_targs = 0, cap_targs = 0, o_tiles = 0;
+  int64_t cap_tiles[2] = {0, 0};                // tile capacity per pass kind
+  struct TileSet {
+    int64_t off = 0;                            // element offset in the tile region
+    int first[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
+    size_t lds[3] = {0, 0, 0};
+  };
+  TileSet tiles[2][2];                          // [column/row][stage]
+  std::vector<int> ept[2];                      // [column/row][instance]: schedule of the Adams stage
+  bool batch_ready = false;                     // program recorded for the bound workspace
+  size_t lds_max = 65536;                       // device limit of LDS per workgroup
+  bool is_batch() const { return !sub.empty(); }
+
   // whole-run graph (tdse_graph): captured on the first tdse_run, replayed after
   bool use_graph = false;
   hipGraph_t graph = nullptr;
@@ -313,6 +360,7 @@ struct tdse_plan_s {
   ~tdse_plan_s() {
     drop_graph();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (tdse_plan_s* q : sub) delete q;
   }
 
   double2* B() const { return (double2*)(ws + o_B); }
@@ -400,6 +448,10 @@ void phase_req(const tdse_plan_s* p, LineArgs& a, int nj, double t_b, double tau
 
 int launch(const tdse_plan_s* p, int g, bool col, const LineArgs& a, hipEvent_t e0 = nullptr,
            hipEvent_t e1 = nullptr) {
+  if (p->rec) {
+    p->rec->push_back(RecLaunch{col ? 0 : 1, g, e0 != nullptr, a, nullptr, nullptr, 0});
+    return TDSE_OK;
+  }
   const int prec = p->st[g].prec;
   hipError_t e = col ? launch_col_pass(prec, p->M1, a, p->stream, e0, e1)
                      : launch_row_pass(prec, p->M2, a, p->stream, e0, e1);
@@ -419,6 +471,10 @@ hipEvent_t next_event(tdse_plan_s* p) {
 // launch an implicit Adams pass; when profiling, the dispatch itself records
 // events at the kernel's start and end
 int launch_timed(tdse_plan_s* p, int g, bool col, const LineArgs& a) {
+  if (p->rec) {
+    p->rec->push_back(RecLaunch{col ? 0 : 1, g, true, a, nullptr, nullptr, 0});
+    return TDSE_OK;
+  }
   if (!p->prof) return launch(p, g, col, a);
   const size_t first = p->ev_used;
   hipEvent_t e0 = next_event(p), e1 = next_event(p);
@@ -539,7 +595,10 @@ int op_am_init(tdse_plan_s* p) {
   }
   s = launch(p, g, false, r);
   if (s) return s;
-  if (p->split()) {
+  if (p->split() && p->rec) {
+    p->rec->push_back(RecLaunch{2, 0, false, LineArgs{}, p->ring(0), p->ring(1), (int64_t)(n - 1) * p->P});
+    p->rec->push_back(RecLaunch{2, 0, false, LineArgs{}, p->tmp(0), p->tmp(1), p->P});
+  } else if (p->split()) {
     hipError_t e = launch_narrow((const double2*)p->ring(0), (float2*)p->ring(1), (int64_t)(n - 1) * p->P, p->stream);
     if (e == hipSuccess) e = launch_narrow((const double2*)p->tmp(0), (float2*)p->tmp(1), p->P, p->stream);
     if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("narrow: ") + hipGetErrorString(e));
@@ -1112,6 +1171,384 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
   return TDSE_OK;
 }
 
+
+// Step m of one instance (write_u: leave u(t_m) in the physical buffer).
+int do_step(tdse_plan_s* p, int m, bool write_u) {
+  if (p->free_space) return fs_step(p, m, write_u);
+  int s = TDSE_OK;
+  if (m <= p->ns) {
+    if (m == 1) s = op_history(p, 0);
+    if (!s) s = op_richardson(p, m);
+    if (!s) s = op_history(p, m);
+    return s;
+  }
+  if (m == p->ns + 1) {
+    if (p->ns == 0) s = op_history(p, 0);
+    if (!s) s = op_am_init(p);
+  }
+  if (!s) s = op_am_step(p, m, write_u);
+  return s;
+}
+
+// ================================================================ batches
+//
+// A batch runs independent periodic instances that share the order, the
+// number of steps, the start-up length and the precision, so that every
+// instance takes the same sequence of passes.  At bind, the sequence of each
+// instance is recorded once (the launch arguments of every pass of the run),
+// the i-th passes of all instances are grouped, and their arguments are
+// stored in a device table; a step is then one batched launch per pass (and
+// per schedule family present), each workgroup taking one tile of one
+// instance.
+
+int batch_default_ept(bool col, int N) {
+  if (N == 1) return 1;
+  if (N % 3 == 0) return 6;
+  if (col) return (N >= 256 && N <= 1024) ? 4 : 8;
+  return N >= 2048 ? 8 : 4;
+}
+
+bool batch_len_ok(int N) {
+  for (int e : {1, 4, 6, 8, 12})
+    if (batch_schedule_ok(N, e)) return true;
+  return false;
+}
+
+int batch_len(const tdse_plan_s* q, int kind) { return kind == 0 ? q->M1 : q->M2; }
+int batch_lines(const tdse_plan_s* q, int kind) { return kind == 0 ? q->M2 : q->M1; }
+
+int64_t tile_base(const tdse_plan_s* p, int kind, int g) {
+  return kind == 0 ? g * p->cap_tiles[0] : 2 * p->cap_tiles[0] + g * p->cap_tiles[1];
+}
+
+// Tile table of one pass kind and buffer stage from per-instance schedules,
+// ordered by schedule family; uploaded synchronously.
+int batch_tiles(tdse_plan_s* p, int kind, int g, const std::vector<int>& ept) {
+  const int prec = p->sub[0]->st[g].prec;
+  std::vector<BatchTile> fam[3];
+  tdse_plan_s::TileSet& ts = p->tiles[kind][g];
+  ts.off = tile_base(p, kind, g);
+  for (int f = 0; f < 3; ++f) ts.lds[f] = 0;
+  for (size_t i = 0; i < p->sub.size(); ++i) {
+    const tdse_plan_s* q = p->sub[i];
+    const int N = batch_len(q, kind), e = ept[i];
+    const int f = batch_family(N, e);
+    if (f < 0) return fail(TDSE_EINVAL, "no batched schedule for this line length");
+    const int LPW = BATCH_THREADS / (N / e);
+    const int nl = batch_lines(q, kind);
+    const int nt = (nl + LPW - 1) / LPW;
+    for (int b = 0; b < nt; ++b) fam[f].push_back(BatchTile{(int32_t)i, b * LPW, b, nt, N * 64 + e, 0});
+    ts.lds[f] = std::max(ts.lds[f], batch_lds_bytes(prec, kind == 0, N, e));
+  }
+  std::vector<BatchTile> all;
+  for (int f = 0; f < 3; ++f) {
+    ts.first[f] = (int)all.size();
+    ts.cnt[f] = (int)fam[f].size();
+    if (ts.lds[f] > p->lds_max) return fail(TDSE_EINVAL, "batched schedule exceeds the LDS of a workgroup");
+    all.insert(all.end(), fam[f].begin(), fam[f].end());
+  }
+  if ((int64_t)all.size() > p->cap_tiles[kind]) return fail(TDSE_EINVAL, "tile table overflow");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  HIP_TRY(hipMemcpy(p->ws + p->o_tiles + ts.off * sizeof(BatchTile), all.data(), all.size() * sizeof(BatchTile),
+                    hipMemcpyHostToDevice));
+  return TDSE_OK;
+}
+
+// Group the i-th recorded launches of all instances.
+int batch_group(tdse_plan_s* p, std::vector<std::vector<RecLaunch>>& rl, std::vector<tdse_plan_s::GLaunch>& out,
+                std::vector<LineArgs>& args, std::vector<tdse_plan_s::Narrow>& nar) {
+  const size_t n = rl.size(), L = rl[0].size();
+  for (size_t i = 1; i < n; ++i)
+    if (rl[i].size() != L) return fail(TDSE_EINVAL, "batch instances take different pass sequences");
+  for (size_t k = 0; k < L; ++k) {
+    const RecLaunch& r0 = rl[0][k];
+    for (size_t i = 1; i < n; ++i)
+      if (rl[i][k].kind != r0.kind || rl[i][k].g != r0.g)
+        return fail(TDSE_EINVAL, "batch instances take different pass sequences");
+    tdse_plan_s::GLaunch gl{r0.kind, r0.g, r0.timed, 0};
+    if (r0.kind == 2) {
+      gl.arg0 = (int64_t)nar.size();
+      for (size_t i = 0; i < n; ++i) nar.push_back({rl[i][k].nsrc, rl[i][k].ndst, rl[i][k].nn});
+    } else {
+      gl.arg0 = (int64_t)args.size();
+      for (size_t i = 0; i < n; ++i) args.push_back(rl[i][k].a);
+    }
+    out.push_back(gl);
+  }
+  return TDSE_OK;
+}
+
+// record step m of every instance (instances' clocks at m - 1)
+int batch_record_step(tdse_plan_s* p, int m, bool write_u, std::vector<tdse_plan_s::GLaunch>& out,
+                      std::vector<LineArgs>& args, std::vector<tdse_plan_s::Narrow>& nar) {
+  std::vector<std::vector<RecLaunch>> rl(p->sub.size());
+  for (size_t i = 0; i < p->sub.size(); ++i) {
+    tdse_plan_s* q = p->sub[i];
+    q->rec = &rl[i];
+    const int s = do_step(q, m, write_u);
+    q->rec = nullptr;
+    if (s) return s;
+  }
+  return batch_group(p, rl, out, args, nar);
+}
+
+// Record the whole run: seg[m] for m = 1..nsteps, seg_last (step nsteps with
+// output), the args table and the narrowings.  Workspace pointers come from
+// the instances' current bindings.
+int batch_record(tdse_plan_s* p) {
+  const int N = p->nsteps;
+  p->seg.assign(N + 1, {});
+  p->seg_last.clear();
+  p->ucur_after.assign(N + 1, 0);
+  p->bargs.clear();
+  p->narrows.clear();
+  for (tdse_plan_s* q : p->sub) q->ucur = 0;
+  for (int m = 1; m <= N; ++m) {
+    const int s = batch_record_step(p, m, false, p->seg[m], p->bargs, p->narrows);
+    if (s) return s;
+    p->ucur_after[m] = p->sub[0]->ucur;
+  }
+  if (N > p->sub[0]->ns) {
+    const int s = batch_record_step(p, N, true, p->seg_last, p->bargs, p->narrows);
+    if (s) return s;
+  } else {
+    p->seg_last = p->seg[N];
+  }
+  for (tdse_plan_s* q : p->sub) q->ucur = 0;
+  return TDSE_OK;
+}
+
+int batch_exec(tdse_plan_s* p, const std::vector<tdse_plan_s::GLaunch>& L, const char* args_dev,
+               const std::vector<tdse_plan_s::Narrow>& nar) {
+  const size_t n = p->sub.size();
+  for (const tdse_plan_s::GLaunch& gl : L) {
+    if (gl.kind == 2) {
+      for (size_t i = 0; i < n; ++i) {
+        const tdse_plan_s::Narrow& w = nar[gl.arg0 + i];
+        const hipError_t e = launch_narrow((const double2*)w.src, (float2*)w.dst, w.n, p->stream);
+        if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("narrow: ") + hipGetErrorString(e));
+      }
+      continue;
+    }
+    const tdse_plan_s::TileSet& ts = p->tiles[gl.kind][gl.g];
+    const int prec = p->sub[0]->st[gl.g].prec;
+    const LineArgs* args = (const LineArgs*)args_dev + gl.arg0;
+    const BatchTile* tiles = (const BatchTile*)(p->ws + p->o_tiles) + ts.off;
+    for (int f = 0; f < 3; ++f) {
+      if (!ts.cnt[f]) continue;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      const size_t first = p->ev_used;
+      if (p->prof && gl.timed) {
+        e0 = next_event(p);
+        e1 = next_event(p);
+        if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
+      }
+      const hipError_t e = launch_batch_pass(prec, gl.kind == 0, f, args, tiles + ts.first[f], ts.cnt[f], ts.lds[f],
+                                             p->stream, e0, e1);
+      if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+      if (e0) p->prof_marks.push_back({first, gl.kind});
+    }
+  }
+  return TDSE_OK;
+}
+
+int batch_step(tdse_plan_s* p, int k) {
+  if (!p->batch_ready) return fail(TDSE_ESTATE, "tdse_bind must come first");
+  const int end = p->cur + k;
+  const char* args = p->ws + p->o_args;
+  for (int m = p->cur + 1; m <= end; ++m) {
+    int s;
+    if (m < end || m <= p->sub[0]->ns) {
+      s = batch_exec(p, p->seg[m], args, p->narrows);
+    } else if (m == p->nsteps) {
+      s = batch_exec(p, p->seg_last, args, p->narrows);
+    } else {
+      // a run that stops inside the Adams phase: step m with output,
+      // recorded now into the table of such steps
+      std::vector<tdse_plan_s::GLaunch> L;
+      std::vector<LineArgs> a;
+      std::vector<tdse_plan_s::Narrow> nar;
+      for (tdse_plan_s* q : p->sub) q->ucur = p->ucur_after[m - 1];
+      s = batch_record_step(p, m, true, L, a, nar);
+      if (s) return s;
+      if (a.size() > p->cap_targs) return fail(TDSE_EINVAL, "output step table overflow");
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      HIP_TRY(hipMemcpy(p->ws + p->o_targs, a.data(), a.size() * sizeof(LineArgs), hipMemcpyHostToDevice));
+      s = batch_exec(p, L, p->ws + p->o_targs, nar);
+    }
+    if (s) return s;
+    p->cur = m;
+  }
+  for (tdse_plan_s* q : p->sub) {
+    q->ucur = p->ucur_after[end];
+    q->cur = end;
+  }
+  return TDSE_OK;
+}
+
+// Plan a batch: instances planned one by one, then a dry recording of the
+// run (no device memory touched) to size the argument tables.
+int plan_batch(const tdse_problem_t* probs, int count, tdse_plan_s** out) {
+  std::unique_ptr<tdse_plan_s> p(new (std::nothrow) tdse_plan_s());
+  if (!p) return fail(TDSE_ENOMEM, "host allocation failed");
+  size_t off = 0;
+  int64_t elem = 0;
+  for (int i = 0; i < count; ++i) {
+    if (probs[i].domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "batches hold periodic instances");
+    tdse_plan_s* q = nullptr;
+    const int s = tdse_plan(&probs[i], &q);
+    if (s) return s;
+    p->sub.push_back(q);
+    const tdse_plan_s* q0 = p->sub[0];
+    if (q->order != q0->order || q->nsteps != q0->nsteps || q->ns != q0->ns || q->precision != q0->precision)
+      return fail(TDSE_EINVAL, "batch instances must share order, nsteps, n_start and precision");
+    for (int kind = 0; kind < 2; ++kind)
+      if (!batch_len_ok(batch_len(q, kind)))
+        return fail(TDSE_EUNSUPPORTED, "batched line lengths: 64..2048 (2^a) or 192..1536 (3 * 2^a)");
+    p->sub_off.push_back(off);
+    p->sub_elem.push_back(elem);
+    off = align256(off + q->total);
+    elem += q->P;
+  }
+  tdse_plan_s* q0 = p->sub[0];
+  p->dim = q0->dim;
+  p->order = q0->order;
+  p->ns = q0->ns;
+  p->nsteps = q0->nsteps;
+  p->precision = q0->precision;
+  p->P = elem;
+  p->dt = q0->dt;
+  p->T = q0->T;
+  // dry recording with placeholder workspaces
+  for (size_t i = 0; i < p->sub.size(); ++i) p->sub[i]->ws = (char*)(uintptr_t)(4096 + p->sub_off[i]);
+  int s = batch_record(p.get());
+  if (s) return s;
+  p->cap_args = p->bargs.size();
+  size_t tcap = 0;
+  for (int m = q0->ns + 1; m <= std::min(q0->ns + 2, p->nsteps); ++m) {
+    std::vector<tdse_plan_s::GLaunch> L;
+    std::vector<LineArgs> a;
+    std::vector<tdse_plan_s::Narrow> nar;
+    for (tdse_plan_s* q : p->sub) q->ucur = p->ucur_after[m - 1];
+    s = batch_record_step(p.get(), m, true, L, a, nar);
+    if (s) return s;
+    tcap = std::max(tcap, a.size());
+  }
+  for (tdse_plan_s* q : p->sub) {
+    q->ws = nullptr;
+    q->ucur = 0;
+  }
+  p->cap_targs = tcap;
+  p->bargs.clear();
+  p->bargs.shrink_to_fit();
+  p->narrows.clear();
+  p->seg.clear();
+  p->seg_last.clear();
+  for (int kind = 0; kind < 2; ++kind) {
+    p->cap_tiles[kind] = 0;
+    for (tdse_plan_s* q : p->sub) p->cap_tiles[kind] += batch_lines(q, kind);
+    p->ept[kind].resize(p->sub.size());
+    for (size_t i = 0; i < p->sub.size(); ++i) p->ept[kind][i] = batch_default_ept(kind == 0, batch_len(p->sub[i], kind));
+  }
+  p->o_args = off;
+  off = align256(off + p->cap_args * sizeof(LineArgs));
+  p->o_targs = off;
+  off = align256(off + std::max<size_t>(p->cap_targs, 1) * sizeof(LineArgs));
+  p->o_tiles = off;
+  off = align256(off + (size_t)(2 * p->cap_tiles[0] + 2 * p->cap_tiles[1]) * sizeof(BatchTile));
+  p->total = off;
+  *out = p.release();
+  return TDSE_OK;
+}
+
+int bind_batch(tdse_plan_s* p) {
+  int dev = 0, v = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  p->lds_max = (size_t)v;
+  for (size_t i = 0; i < p->sub.size(); ++i) {
+    const int s = tdse_bind(p->sub[i], p->ws + p->sub_off[i], p->sub[i]->total, p->stream);
+    if (s) return s;
+  }
+  int s = batch_record(p);
+  if (s) return s;
+  if (p->bargs.size() > p->cap_args) return fail(TDSE_EINVAL, "argument table overflow");
+  HIP_TRY(hipMemcpy(p->ws + p->o_args, p->bargs.data(), p->bargs.size() * sizeof(LineArgs), hipMemcpyHostToDevice));
+  for (int kind = 0; kind < 2; ++kind) {
+    std::vector<int> def(p->sub.size());
+    for (size_t i = 0; i < p->sub.size(); ++i) def[i] = batch_default_ept(kind == 0, batch_len(p->sub[i], kind));
+    s = batch_tiles(p, kind, 0, def);
+    if (!s) s = batch_tiles(p, kind, 1, p->ept[kind]);
+    if (s) return s;
+  }
+  p->batch_ready = true;
+  return TDSE_OK;
+}
+
+// Per-length schedule search on the Adams passes: for each pass kind and
+// each distinct line length, every compiled schedule that fits the LDS is
+// timed over `reps` launches of a recorded Adams step and the fastest kept.
+int autotune_batch(tdse_plan_s* p, int reps) {
+  const int ns = p->sub[0]->ns;
+  const int m = std::min(p->nsteps - 1, ns + 2);
+  if (m <= ns) return TDSE_OK;   // no Adams step to time
+  hipEvent_t t0 = next_event(p), t1 = next_event(p);
+  if (!t0 || !t1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
+  const bool prof = p->prof;
+  p->prof = false;
+  int status = TDSE_OK;
+  for (int kind = 0; kind < 2 && !status; ++kind) {
+    std::vector<tdse_plan_s::GLaunch> one;
+    for (const tdse_plan_s::GLaunch& gl : p->seg[m])
+      if (gl.kind == kind && gl.timed) one.push_back(gl);
+    if (one.empty()) continue;
+    one.resize(1);
+    std::vector<int> lens;
+    for (tdse_plan_s* q : p->sub) lens.push_back(batch_len(q, kind));
+    std::vector<int> uniq(lens);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    for (int N : uniq) {
+      int best = -1;
+      float best_ms = 0.f;
+      for (int e : {1, 4, 6, 8, 12}) {
+        if (!batch_schedule_ok(N, e)) continue;
+        const int prec = p->sub[0]->st[1].prec;
+        if (batch_lds_bytes(prec, kind == 0, N, e) > p->lds_max) continue;
+        std::vector<int> trial(p->ept[kind]);
+        for (size_t i = 0; i < lens.size(); ++i)
+          if (lens[i] == N) trial[i] = e;
+        status = batch_tiles(p, kind, 1, trial);
+        if (!status) status = batch_exec(p, one, p->ws + p->o_args, p->narrows);   // warm-up
+        if (status) break;
+        if (hipEventRecord(t0, p->stream) != hipSuccess) { status = fail(TDSE_EDEVICE, "hipEventRecord"); break; }
+        for (int r = 0; r < reps && !status; ++r) status = batch_exec(p, one, p->ws + p->o_args, p->narrows);
+        if (status) break;
+        float ms = 0.f;
+        if (hipEventRecord(t1, p->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+            hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+          status = fail(TDSE_EDEVICE, "autotune timing failed");
+          break;
+        }
+        if (best < 0 || ms < best_ms) {
+          best = e;
+          best_ms = ms;
+        }
+      }
+      if (status) break;
+      for (size_t i = 0; i < lens.size(); ++i)
+        if (lens[i] == N) p->ept[kind][i] = best;
+    }
+    if (!status) status = batch_tiles(p, kind, 1, p->ept[kind]);
+  }
+  p->prof = prof;
+  p->ev_used = 0;
+  p->prof_marks.clear();
+  p->drop_graph();
+  p->cur = -1;   // the timing runs overwrote the state
+  return status;
+}
+
 bool good_len(int M) { return M >= 8 && M <= 3072 && M % 2 == 0 && line_length_supported(M); }
 
 }  // namespace
@@ -1265,6 +1702,14 @@ int tdse_bind(tdse_plan_t p, void* ws, size_t bytes, void* stream) {
   p->ws = (char*)ws;
   p->ws_bytes = bytes;
   p->stream = (hipStream_t)stream;
+  if (p->is_batch()) {
+    p->batch_ready = false;
+    const int s = bind_batch(p);
+    if (s) return s;
+    p->bound = true;
+    p->cur = -1;
+    return TDSE_OK;
+  }
   for (int g = 0; g < 2; ++g) {
     const tdse_plan_s::Stage& S = p->st[g];
     if (S.Vhost.empty()) continue;
@@ -1288,6 +1733,14 @@ int tdse_bind(tdse_plan_t p, void* ws, size_t bytes, void* stream) {
 int tdse_set_state(tdse_plan_t p, const void* u0, int32_t on_device) {
   if (!p || !u0) return fail(TDSE_EINVAL, "NULL argument");
   if (!p->bound) return fail(TDSE_ESTATE, "tdse_bind must come first");
+  if (p->is_batch()) {
+    for (size_t i = 0; i < p->sub.size(); ++i) {
+      const int s = tdse_set_state(p->sub[i], (const double2*)u0 + p->sub_elem[i], on_device);
+      if (s) return s;
+    }
+    p->cur = 0;
+    return TDSE_OK;
+  }
   p->ucur = 0;
   p->uh_cur = 0;
   const size_t bytes = (size_t)p->P * sizeof(double2);
@@ -1306,26 +1759,10 @@ int tdse_step(tdse_plan_t p, int32_t k) {
   if (!p->bound || p->cur < 0) return fail(TDSE_ESTATE, "tdse_set_state must come first");
   if (k < 0) return fail(TDSE_EINVAL, "negative step count");
   if (p->cur + k > p->nsteps) return fail(TDSE_ESTATE, "stepping past T");
+  if (p->is_batch()) return batch_step(p, k);
   const int end = p->cur + k;
   for (int m = p->cur + 1; m <= end; ++m) {
-    int s = TDSE_OK;
-    if (p->free_space) {
-      s = fs_step(p, m, m == end);
-      if (s) return s;
-      p->cur = m;
-      continue;
-    }
-    if (m <= p->ns) {
-      if (m == 1) s = op_history(p, 0);
-      if (!s) s = op_richardson(p, m);
-      if (!s) s = op_history(p, m);
-    } else {
-      if (m == p->ns + 1) {
-        if (p->ns == 0) s = op_history(p, 0);
-        if (!s) s = op_am_init(p);
-      }
-      if (!s) s = op_am_step(p, m, m == end);
-    }
+    const int s = do_step(p, m, m == end);
     if (s) return s;
     p->cur = m;
   }
@@ -1335,6 +1772,13 @@ int tdse_step(tdse_plan_t p, int32_t k) {
 int tdse_get_state(tdse_plan_t p, void* u, int32_t on_device) {
   if (!p || !u) return fail(TDSE_EINVAL, "NULL argument");
   if (!p->bound || p->cur < 0) return fail(TDSE_ESTATE, "no state");
+  if (p->is_batch()) {
+    for (size_t i = 0; i < p->sub.size(); ++i) {
+      const int s = tdse_get_state(p->sub[i], (double2*)u + p->sub_elem[i], on_device);
+      if (s) return s;
+    }
+    return TDSE_OK;
+  }
   const size_t bytes = (size_t)p->P * sizeof(double2);
   if (on_device) {
     HIP_TRY(hipMemcpyAsync(u, p->u(p->ucur), bytes, hipMemcpyDeviceToDevice, p->stream));
@@ -1380,6 +1824,10 @@ int tdse_run(tdse_plan_t p, const void* u0, void* uT, int32_t on_device) {
   HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
   p->cur = p->nsteps;
   p->ucur = p->graph_ucur;
+  for (tdse_plan_s* q : p->sub) {
+    q->ucur = p->ucur_after[p->nsteps];
+    q->cur = p->nsteps;
+  }
   return tdse_get_state(p, uT, on_device);
 }
 
@@ -1393,6 +1841,36 @@ int tdse_graph(tdse_plan_t p, int32_t enable) {
 
 int tdse_query(tdse_plan_t p, int32_t key, double* value) {
   if (!p || !value) return fail(TDSE_EINVAL, "NULL argument");
+  if (p->is_batch()) {
+    const int n = (int)p->sub.size();
+    if (key == TDSE_Q_INSTANCES) { *value = n; return TDSE_OK; }
+    if (key == TDSE_Q_MODES) { *value = (double)p->P; return TDSE_OK; }
+    if (key == TDSE_Q_STEPS_DONE) { *value = (double)p->cur; return TDSE_OK; }
+    if (key >= TDSE_Q_INST_OFFSET && key < TDSE_Q_INST_OFFSET + n) {
+      *value = (double)p->sub_elem[key - TDSE_Q_INST_OFFSET];
+      return TDSE_OK;
+    }
+    if (key >= TDSE_Q_INST_EPT_COL && key < TDSE_Q_INST_EPT_COL + n) {
+      *value = p->ept[0][key - TDSE_Q_INST_EPT_COL];
+      return TDSE_OK;
+    }
+    if (key >= TDSE_Q_INST_EPT_ROW && key < TDSE_Q_INST_EPT_ROW + n) {
+      *value = p->ept[1][key - TDSE_Q_INST_EPT_ROW];
+      return TDSE_OK;
+    }
+    if (key == TDSE_Q_BYTES_PER_STEP || key == TDSE_Q_BYTES_COL || key == TDSE_Q_BYTES_ROW) {
+      double sum = 0.0;
+      for (tdse_plan_s* q : p->sub) {
+        double v = 0.0;
+        const int s = tdse_query(q, key, &v);
+        if (s) return s;
+        sum += v;
+      }
+      *value = sum;
+      return TDSE_OK;
+    }
+    if (key < TDSE_Q_PROF_MS_COL || key > TDSE_Q_PROF_N_ROW) return tdse_query(p->sub[0], key, value);
+  }
   if (key == TDSE_Q_MODES) { *value = (double)p->P; return TDSE_OK; }
   if (key == TDSE_Q_STEPS_DONE) { *value = (double)p->cur; return TDSE_OK; }
   if (key == TDSE_Q_DT) { *value = p->dt; return TDSE_OK; }
@@ -1477,6 +1955,42 @@ int tdse_profile(tdse_plan_t p, int32_t enable) {
   p->ev_used = 0;
   p->prof_marks.clear();
   return TDSE_OK;
+}
+
+int tdse_plan_batch(const tdse_problem_t* probs, int32_t count, tdse_plan_t* out) {
+  if (!probs || !out) return fail(TDSE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (count < 1 || count > 4096) return fail(TDSE_EINVAL, "count must be 1..4096");
+  return plan_batch(probs, count, out);
+}
+
+int tdse_autotune(tdse_plan_t p, int32_t reps) {
+  if (!p) return fail(TDSE_EINVAL, "NULL plan");
+  if (!p->is_batch()) return fail(TDSE_EUNSUPPORTED, "autotuning applies to batch plans");
+  if (!p->bound) return fail(TDSE_ESTATE, "tdse_bind must come first");
+  if (reps < 1 || reps > 1000) return fail(TDSE_EINVAL, "reps must be 1..1000");
+  return autotune_batch(p, reps);
+}
+
+int tdse_set_instance_state(tdse_plan_t p, int32_t instance, const void* u0, int32_t on_device) {
+  if (!p || !u0) return fail(TDSE_EINVAL, "NULL argument");
+  if (!p->is_batch()) return instance == 0 ? tdse_set_state(p, u0, on_device) : fail(TDSE_EINVAL, "instance out of range");
+  if (instance < 0 || instance >= (int)p->sub.size()) return fail(TDSE_EINVAL, "instance out of range");
+  if (!p->bound) return fail(TDSE_ESTATE, "tdse_bind must come first");
+  const int s = tdse_set_state(p->sub[instance], u0, on_device);
+  if (s) return s;
+  bool all = true;
+  for (tdse_plan_s* q : p->sub) all = all && q->cur == 0;
+  p->cur = all ? 0 : -1;
+  return TDSE_OK;
+}
+
+int tdse_get_instance_state(tdse_plan_t p, int32_t instance, void* u, int32_t on_device) {
+  if (!p || !u) return fail(TDSE_EINVAL, "NULL argument");
+  if (!p->is_batch()) return instance == 0 ? tdse_get_state(p, u, on_device) : fail(TDSE_EINVAL, "instance out of range");
+  if (instance < 0 || instance >= (int)p->sub.size()) return fail(TDSE_EINVAL, "instance out of range");
+  if (!p->bound || p->cur < 0) return fail(TDSE_ESTATE, "no state");
+  return tdse_get_state(p->sub[instance], u, on_device);
 }
 
 void tdse_destroy(tdse_plan_t p) { delete p; }

@@ -121,6 +121,22 @@ struct FSArgs {
   CFAxis ax1, ax2;
 };
 
+// Batched passes (batch_fp64.hip, batch_split.hip): one launch per schedule
+// family over the tiles of many instances.  A tile is one workgroup's lines
+// of one instance, transformed with the schedule sched = N * 64 + EPT (line
+// length N, EPT elements per thread); blk/nblk number the tile among the
+// instance's tiles of the pass.
+constexpr int BATCH_THREADS = 256;
+struct BatchTile {
+  int32_t inst, line0, blk, nblk, sched, pad;
+};
+bool batch_schedule_ok(int N, int ept);
+int batch_family(int N, int ept);                               // -1 if no such schedule
+size_t batch_lds_bytes(int prec, bool col, int N, int ept);   // 0 if no such schedule
+hipError_t launch_batch_pass(int prec, bool col, int family, const LineArgs* args, const BatchTile* tiles,
+                             int ntiles, size_t lds_bytes, hipStream_t s, hipEvent_t e0 = nullptr,
+                             hipEvent_t e1 = nullptr);
+
 // Free-space launchers (freespace_kernels.hip); events as for the periodic passes.
 hipError_t launch_fs_row(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // nu = 0: the pointwise pass of a 1D problem

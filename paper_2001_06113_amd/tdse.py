@@ -19,6 +19,7 @@ Q_MODES, Q_STEPS_DONE, Q_DT, Q_BYTES_PER_STEP = 0, 1, 2, 3
 Q_PROF_MS_COL, Q_PROF_MS_ROW, Q_PROF_N_COL, Q_PROF_N_ROW = 8, 9, 10, 11
 Q_BYTES_COL, Q_BYTES_ROW = 12, 13
 Q_MU, Q_RICHARDSON, Q_PHI = 16, 32, 64
+Q_INSTANCES, Q_INST_OFFSET, Q_INST_EPT_COL, Q_INST_EPT_ROW = 4, 4096, 8192, 12288
 
 
 class TDSEError(RuntimeError):
@@ -37,6 +38,68 @@ def _dptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+def problem_struct(*, dim: int, M: Sequence[int], T: float, nsteps: int, V_fields, order: int = 8,
+                   n_start: int = -1, precision: str = "fp64", f_kind: str = "const", f_params=None,
+                   A_kind: str = "none", A_params=None, A_steps=None, domain: str = "periodic",
+                   eps: float = 1e-10, p: int = 8, q: int = 10, panels: int = 1, nu: Sequence[int] = (),
+                   H: float = 0.0):
+    """Fill a tdse_problem_t; returns it with the arrays it points into (keep them alive)."""
+    M = tuple(int(m) for m in M)
+    V = np.ascontiguousarray(np.asarray(V_fields, dtype=np.float64).reshape(-1, *M))
+    prob = _lib.Problem()
+    prob.dim = dim
+    prob.domain = PERIODIC if domain == "periodic" else FREE
+    for a in range(dim):
+        prob.M[a] = M[a]
+    prob.T = float(T)
+    prob.nsteps = int(nsteps)
+    prob.order = int(order)
+    prob.n_start = int(n_start)
+    prob.precision = FP64 if precision == "fp64" else FP32_SPLIT
+    prob.nV = V.shape[0]
+    keep = [V]
+    prob.V_fields = _dptr(V)
+    prob.f_kind = F_KINDS[f_kind]
+    if f_params is not None:
+        fp = np.ascontiguousarray(np.asarray(f_params, dtype=np.float64).ravel())
+        keep.append(fp)
+        prob.f_params = _dptr(fp)
+    prob.A_kind = A_KINDS[A_kind]
+    if A_params is not None:
+        ap = np.ascontiguousarray(np.asarray(A_params, dtype=np.float64).ravel())
+        keep.append(ap)
+        prob.A_params = _dptr(ap)
+    if A_steps is not None:
+        st = np.ascontiguousarray(np.asarray(A_steps, dtype=np.float64).ravel())
+        keep.append(st)
+        prob.A_steps = _dptr(st)
+    # free space: contour tolerance, Alpert order, Gauss panels, FFT sizes
+    prob.eps = float(eps)
+    prob.p = int(p)
+    prob.q = int(q)
+    prob.panels = int(panels)
+    for a, n in enumerate(nu):
+        prob.nu[a] = int(n)
+    prob.H = float(H)
+    return prob, keep
+
+
+def problem_kwargs(prob) -> dict:
+    """Keyword arguments of problem_struct / Plan for a workloads.Problem
+    (duck-typed: the plain problem fields)."""
+    # one time-factor kind for all fields: constant fields get amplitude 0
+    sin = any(k == "sin" for k in prob.f_kind)
+    f_params = None
+    if sin:
+        f_params = [tuple(fp) if k == "sin" else (0.0, 0.0) for fp, k in zip(prob.f_params, prob.f_kind)]
+    return dict(dim=prob.dim, M=prob.M, T=prob.T, nsteps=prob.nsteps, V_fields=np.stack(prob.V_fields),
+                order=prob.order, n_start=-1 if prob.n_start is None else prob.n_start,
+                precision=prob.precision, f_kind="sin" if sin else "const", f_params=f_params,
+                A_kind=prob.A_kind, A_params=prob.A_params if prob.A_kind == "pulse_sin2" else None,
+                A_steps=prob.A_steps if prob.A_kind == "stepwise" else None,
+                domain=prob.domain, eps=prob.eps, p=prob.p, q=prob.q, panels=prob.panels, nu=prob.nu)
+
+
 class Plan:
     """One TDSE instance planned and bound to a device workspace.
 
@@ -45,52 +108,13 @@ class Plan:
     f_r(t) and the vector potential A(t).
     """
 
-    def __init__(self, *, dim: int, M: Sequence[int], T: float, nsteps: int, V_fields,
-                 order: int = 8, n_start: int = -1, precision: str = "fp64",
-                 f_kind: str = "const", f_params=None, A_kind: str = "none", A_params=None,
-                 A_steps=None, domain: str = "periodic", eps: float = 1e-10, p: int = 8, q: int = 10,
-                 panels: int = 1, nu: Sequence[int] = (), H: float = 0.0, device=None, stream=None):
+    def __init__(self, *, device=None, stream=None, **problem):
         self.lib = _lib.load()
-        self.dim = dim
-        self.M = tuple(int(m) for m in M)
+        self.dim = problem["dim"]
+        self.M = tuple(int(m) for m in problem["M"])
         self.shape = self.M
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
-        V = np.ascontiguousarray(np.asarray(V_fields, dtype=np.float64).reshape(-1, *self.M))
-        prob = _lib.Problem()
-        prob.dim = dim
-        prob.domain = PERIODIC if domain == "periodic" else FREE
-        for a in range(dim):
-            prob.M[a] = self.M[a]
-        prob.T = float(T)
-        prob.nsteps = int(nsteps)
-        prob.order = int(order)
-        prob.n_start = int(n_start)
-        prob.precision = FP64 if precision == "fp64" else FP32_SPLIT
-        prob.nV = V.shape[0]
-        keep = [V]
-        prob.V_fields = _dptr(V)
-        prob.f_kind = F_KINDS[f_kind]
-        if f_params is not None:
-            fp = np.ascontiguousarray(np.asarray(f_params, dtype=np.float64).ravel())
-            keep.append(fp)
-            prob.f_params = _dptr(fp)
-        prob.A_kind = A_KINDS[A_kind]
-        if A_params is not None:
-            ap = np.ascontiguousarray(np.asarray(A_params, dtype=np.float64).ravel())
-            keep.append(ap)
-            prob.A_params = _dptr(ap)
-        if A_steps is not None:
-            st = np.ascontiguousarray(np.asarray(A_steps, dtype=np.float64).ravel())
-            keep.append(st)
-            prob.A_steps = _dptr(st)
-        # free space: contour tolerance, Alpert order, Gauss panels, FFT sizes
-        prob.eps = float(eps)
-        prob.p = int(p)
-        prob.q = int(q)
-        prob.panels = int(panels)
-        for a, n in enumerate(nu):
-            prob.nu[a] = int(n)
-        prob.H = float(H)
+        prob, keep = problem_struct(**problem)
         handle = C.c_void_p()
         _check(self.lib.tdse_plan(C.byref(prob), C.byref(handle)), "tdse_plan")
         self.handle = handle
@@ -108,18 +132,7 @@ class Plan:
     @classmethod
     def from_problem(cls, prob, **kw) -> "Plan":
         """Plan a workloads.Problem (duck-typed: the plain problem fields)."""
-        # one time-factor kind for all fields: constant fields get amplitude 0
-        sin = any(k == "sin" for k in prob.f_kind)
-        f_kind = "sin" if sin else "const"
-        f_params = None
-        if sin:
-            f_params = [tuple(fp) if k == "sin" else (0.0, 0.0) for fp, k in zip(prob.f_params, prob.f_kind)]
-        return cls(dim=prob.dim, M=prob.M, T=prob.T, nsteps=prob.nsteps, V_fields=np.stack(prob.V_fields),
-                   order=prob.order, n_start=-1 if prob.n_start is None else prob.n_start,
-                   precision=prob.precision, f_kind=f_kind, f_params=f_params, A_kind=prob.A_kind,
-                   A_params=prob.A_params if prob.A_kind == "pulse_sin2" else None,
-                   A_steps=prob.A_steps if prob.A_kind == "stepwise" else None,
-                   domain=prob.domain, eps=prob.eps, p=prob.p, q=prob.q, panels=prob.panels, nu=prob.nu, **kw)
+        return cls(**{**problem_kwargs(prob), **kw})
 
     # -------------------------------------------------------------- calls
     def _as_device(self, u) -> torch.Tensor:
@@ -182,3 +195,78 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class BatchPlan(Plan):
+    """Many independent periodic instances marched together (tdse_plan_batch):
+    one workspace, one stream, batched launches per pass.  States are lists of
+    per-instance arrays (or one packed complex128 tensor)."""
+
+    def __init__(self, problems: Sequence[dict], *, device=None, stream=None):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        structs, keep = [], []
+        for kw in problems:
+            pr, k = problem_struct(**kw)
+            structs.append(pr)
+            keep += k
+        arr = (_lib.Problem * len(structs))(*structs)
+        self.shapes = [tuple(int(m) for m in kw["M"]) for kw in problems]
+        self.count = len(structs)
+        handle = C.c_void_p()
+        _check(self.lib.tdse_plan_batch(arr, len(structs), C.byref(handle)), "tdse_plan_batch")
+        self.handle = handle
+        size = C.c_size_t()
+        _check(self.lib.tdse_workspace_size(handle, C.byref(size)), "tdse_workspace_size")
+        self.ws_bytes = size.value
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(self.device) if stream is None else stream
+        _check(self.lib.tdse_bind(handle, C.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                                  C.c_void_p(self.stream.cuda_stream)), "tdse_bind")
+        self.graph = False
+        self.offsets = [int(self.query(Q_INST_OFFSET + i)) for i in range(self.count)]
+        self.total = int(self.query(Q_MODES))
+        self.shape = (self.total,)
+
+    @classmethod
+    def from_problems(cls, probs, **kw) -> "BatchPlan":
+        return cls([problem_kwargs(p) for p in probs], **kw)
+
+    def pack(self, states) -> torch.Tensor:
+        if isinstance(states, torch.Tensor) and states.dim() == 1:
+            return states.to(device=self.device, dtype=torch.complex128).contiguous()
+        parts = [torch.as_tensor(u).to(device=self.device, dtype=torch.complex128).reshape(-1) for u in states]
+        return torch.cat(parts).contiguous()
+
+    def unpack(self, packed: torch.Tensor):
+        return [packed[o:o + int(np.prod(s))].reshape(s) for o, s in zip(self.offsets, self.shapes)]
+
+    def _as_device(self, u) -> torch.Tensor:
+        return self.pack(u)
+
+    def autotune(self, reps: int = 20) -> list:
+        """Time the compiled schedules per line length (tdse_autotune); the
+        state is lost.  Returns the chosen (column, row) elements per thread."""
+        self._enter()
+        _check(self.lib.tdse_autotune(self.handle, int(reps)), "tdse_autotune")
+        self._leave()
+        return [(int(self.query(Q_INST_EPT_COL + i)), int(self.query(Q_INST_EPT_ROW + i))) for i in range(self.count)]
+
+    def set_instance_state(self, i: int, u0) -> None:
+        u = torch.as_tensor(u0).to(device=self.device, dtype=torch.complex128).contiguous()
+        self._keep_states = getattr(self, "_keep_states", {})
+        self._keep_states[i] = u
+        self._enter()
+        _check(self.lib.tdse_set_instance_state(self.handle, int(i), C.c_void_p(u.data_ptr()), 1),
+               "tdse_set_instance_state")
+
+    def get_instance_state(self, i: int) -> torch.Tensor:
+        out = torch.empty(self.shapes[i], dtype=torch.complex128, device=self.device)
+        self._enter()
+        _check(self.lib.tdse_get_instance_state(self.handle, int(i), C.c_void_p(out.data_ptr()), 1),
+               "tdse_get_instance_state")
+        self._leave()
+        return out
+
+    def run_list(self, u0s):
+        return self.unpack(self.run(u0s))

@@ -104,3 +104,58 @@ class EmuPlan:
             self.lib.tdse_destroy(self.h)
         except Exception:
             pass
+
+
+class EmuBatchPlan:
+    """Batch plan of several workloads.Problem on the emulated library; states packed in instance order."""
+
+    def __init__(self, lib, probs):
+        from paper_2001_06113_amd.tdse import problem_kwargs, problem_struct
+
+        self.lib = lib
+        structs, self._keep = [], []
+        for pr in probs:
+            s, k = problem_struct(**problem_kwargs(pr))
+            structs.append(s)
+            self._keep += k
+        arr = (_lib.Problem * len(structs))(*structs)
+        h = C.c_void_p()
+        st = lib.tdse_plan_batch(arr, len(structs), C.byref(h))
+        if st:
+            raise RuntimeError(lib.tdse_last_error().decode())
+        self.h = h
+        sz = C.c_size_t()
+        lib.tdse_workspace_size(h, C.byref(sz))
+        raw = np.zeros(sz.value + 512, dtype=np.uint8)
+        off = (-raw.ctypes.data) % 256
+        self.ws = raw[off:off + sz.value]
+        self._raw = raw
+        st = lib.tdse_bind(h, C.c_void_p(self.ws.ctypes.data), sz.value, None)
+        if st:
+            raise RuntimeError(lib.tdse_last_error().decode())
+        self.shapes = [tuple(pr.M) for pr in probs]
+        self.offsets = [int(self.query(4096 + i)) for i in range(len(probs))]
+
+    def query(self, key: int) -> float:
+        v = C.c_double()
+        st = self.lib.tdse_query(self.h, key, C.byref(v))
+        if st:
+            raise RuntimeError(self.lib.tdse_last_error().decode())
+        return v.value
+
+    def call(self, name, *args):
+        st = getattr(self.lib, name)(self.h, *args)
+        if st:
+            raise RuntimeError(f"{name}: {self.lib.tdse_last_error().decode()}")
+
+    def run(self, u0s):
+        packed = np.ascontiguousarray(np.concatenate([np.asarray(u, dtype=np.complex128).ravel() for u in u0s]))
+        out = np.zeros_like(packed)
+        self.call("tdse_run", C.c_void_p(packed.ctypes.data), C.c_void_p(out.ctypes.data), 1)
+        return [out[o:o + int(np.prod(s))].reshape(s) for o, s in zip(self.offsets, self.shapes)]
+
+    def __del__(self):
+        try:
+            self.lib.tdse_destroy(self.h)
+        except Exception:
+            pass

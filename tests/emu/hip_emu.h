@@ -149,4 +149,14 @@ inline hipError_t hipEventCreate(hipEvent_t* e) { *e = (hipEvent_t)new char[1]; 
 inline hipError_t hipEventDestroy(hipEvent_t e) { delete[] (char*)e; return hipSuccess; }
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
 inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 0.f; return hipSuccess; }
+inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 inline hipError_t hipDeviceSynchronize() { return hipSuccess; }
+inline hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) {
+  std::memcpy(d, s, n);
+  return hipSuccess;
+}
+enum hipDeviceAttribute_t { hipDeviceAttributeMaxSharedMemoryPerBlock };
+inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 160 * 1024; return hipSuccess; }
+// dynamic LDS: one static buffer per kernel and element type, as large as a CU's LDS
+#define HIP_DYNAMIC_SHARED(type, var) static type var[160 * 1024 / sizeof(type)];
