@@ -24,9 +24,13 @@
 //
 // Every kernel is a template on the transform type C: double2 (FP64) or
 // float2 (split precision).  In the split form the FFTs, the tile buffer,
-// the history ring, the diagonal solve and the history sum
-// sum_{j>=2} mu_j E^(j) What are complex64, while B, E^(1) uhat, the phase
-// factors, the Richardson accumulator and the physical solution stay FP64.
+// the history ring, the diagonal solve and the products E^(j) What (j >= 2)
+// are complex64, while B, E^(1) uhat, the dt mu_j weighting and sum of the
+// history products, the phase factors, the potential, the Richardson
+// accumulator and the physical solution stay FP64.  (A weight or a
+// potential rounded to FP32 is the same perturbation of the scheme at every
+// step, so its error would grow linearly in time rather than as a random
+// walk.)
 //
 // Every global load a pass needs (tile, potential, B, history, phase factors)
 // is issued before its first FFT so their latencies overlap.
@@ -124,7 +128,7 @@ __device__ __forceinline__ void col_body(const LineArgs& a, int line0, int blk, 
   const int line = line0 + i;
   const bool active = line < a.nlines;
   const int mode = a.mode;
-  const R* __restrict__ V = (const R*)a.V;
+  const double* __restrict__ V = (const double*)a.V;
 
   C v[EPT];
   double2 u0[EPT];   // C_FWD reads the complex128 physical solution
@@ -139,7 +143,7 @@ __device__ __forceinline__ void col_body(const LineArgs& a, int line0, int blk, 
       if (mode == C_FWD) u0[m] = ((const double2*)a.src)[g];
       else v[m] = ((const C*)a.src)[g];
       double p = 0.0;
-      for (int r = 0; r < a.nV; ++r) p += a.fV[r] * (double)V[r * a.vstride + g];
+      for (int r = 0; r < a.nV; ++r) p += a.fV[r] * V[r * a.vstride + g];
       vv[m] = p;
     }
   }
@@ -311,12 +315,14 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
       const double2 Wd = to_d(W);
       const double2 uh = cadd(Bp[m], mul_mi(a.c0, Wd));
       double2 acc = cmul(E1[m], cadd(uh, mul_mi(a.ch[1], Wd)));
-      C hist = C{0, 0};
+      // products E^(j) What in the transform precision, weighted by dt mu_j
+      // and summed in FP64
+      double2 hist = double2{0.0, 0.0};
 #pragma unroll
       for (int j = 2; j <= NH; ++j) {
-        if (j <= nh) hist = cadd(hist, cmul(Ej(j, m), mul_mi(a.ch[j], Wh(j, m))));
+        if (j <= nh) hist = cadd(hist, mul_mi(a.ch[j], to_d(cmul(Ej(j, m), Wh(j, m)))));
       }
-      acc = cadd(acc, to_d(hist));
+      acc = cadd(acc, hist);
       const int64_t g = row0 + (t + TL * m);
       if (a.slot_w >= 0) ((C*)a.ring)[a.slot_w * rstride + g] = W;
       a.Bm[g] = acc;
@@ -335,12 +341,12 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
       double2 acc = cmul(E1[m], to_d(v[m]));
       const int64_t g = row0 + (t + TL * m);
       acc = cadd(acc, cmul(E1[m], mul_mi(a.ch[1], to_d(ring[slot_r[1] * rstride + g]))));
-      C hist = C{0, 0};
+      double2 hist = double2{0.0, 0.0};
 #pragma unroll
       for (int j = 2; j <= NH; ++j) {  // static j: registers stay registers
-        if (j <= nh) hist = cadd(hist, cmul(Ej(j, m), mul_mi(a.ch[j], ring[slot_r[j] * rstride + g])));
+        if (j <= nh) hist = cadd(hist, mul_mi(a.ch[j], to_d(cmul(Ej(j, m), ring[slot_r[j] * rstride + g]))));
       }
-      acc = cadd(acc, to_d(hist));
+      acc = cadd(acc, hist);
       a.Bm[g] = acc;
       v[m] = from_d<C>(acc);
     }

@@ -1619,13 +1619,10 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
     const bool sp = split && g == 1;
     S.prec = sp ? P_SPLIT : P_FP64;
     S.cplx = sp ? 8 : 16;
-    S.real = sp ? 4 : 8;
-    const size_t n = (size_t)p->nV * p->P;
-    S.Vhost.resize(n * S.real);
-    for (size_t q = 0; q < n; ++q) {
-      if (sp) ((float*)S.Vhost.data())[q] = (float)prob->V_fields[q];
-      else ((double*)S.Vhost.data())[q] = prob->V_fields[q];
-    }
+    // the potential stays FP64 in both forms: rounded to FP32 it would be a
+    // fixed perturbation of the Hamiltonian whose error grows linearly in time
+    S.real = 8;
+    if (g == 0) S.Vhost.assign((const char*)prob->V_fields, (const char*)(prob->V_fields + (size_t)p->nV * p->P));
   }
 
   TimeFns& tf = p->tf;
@@ -1672,7 +1669,12 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
     const size_t tbytes = (size_t)p->P * S.cplx;
     S.o_ring = off; off = align256(off + (size_t)(p->order - 1) * tbytes);
     S.o_tmp = off; off = align256(off + tbytes);
-    S.o_V = off; off = align256(off + S.Vhost.size());
+    if (g == 0) {
+      S.o_V = off;
+      off = align256(off + S.Vhost.size());
+    } else {
+      S.o_V = p->st[0].o_V;   // one FP64 copy of the potential serves both stages
+    }
     S.o_tw1 = off; off = align256(off + S.tw1.size());
     S.o_tw2 = off; off = align256(off + S.tw2.size());
   }
@@ -1712,10 +1714,12 @@ int tdse_bind(tdse_plan_t p, void* ws, size_t bytes, void* stream) {
   }
   for (int g = 0; g < 2; ++g) {
     const tdse_plan_s::Stage& S = p->st[g];
-    if (S.Vhost.empty()) continue;
-    HIP_TRY(hipMemcpyAsync(p->ws + S.o_V, S.Vhost.data(), S.Vhost.size(), hipMemcpyHostToDevice, p->stream));
-    HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw1, S.tw1.data(), S.tw1.size(), hipMemcpyHostToDevice, p->stream));
-    HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw2, S.tw2.data(), S.tw2.size(), hipMemcpyHostToDevice, p->stream));
+    if (!S.Vhost.empty())
+      HIP_TRY(hipMemcpyAsync(p->ws + S.o_V, S.Vhost.data(), S.Vhost.size(), hipMemcpyHostToDevice, p->stream));
+    if (!S.tw1.empty())
+      HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw1, S.tw1.data(), S.tw1.size(), hipMemcpyHostToDevice, p->stream));
+    if (!S.tw2.empty())
+      HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw2, S.tw2.data(), S.tw2.size(), hipMemcpyHostToDevice, p->stream));
   }
   if (p->free_space) {
     HIP_TRY(hipMemcpyAsync(p->ws + p->o_Vf, p->Vsrc.data(), p->Vsrc.size() * sizeof(double), hipMemcpyHostToDevice,

@@ -38,7 +38,7 @@ struct PhaseReq {
 // Arguments of one line pass.  Buffers whose element type follows the
 // transform precision (complex128 or complex64) are untyped here; the
 // carried state B, the physical solution and the phase tables are always
-// complex128; the potential is double (FP64) or float (split).
+// complex128; the potential is double in both forms.
 struct LineArgs {
   const void* src;     // tile source: transform-precision tile, or complex128 physical u (C_FWD)
   void* dst;           // tile destination (transform precision)

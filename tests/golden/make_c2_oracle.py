@@ -41,7 +41,7 @@ def main():
         lines.append(f"# case {steps} norm {float(np.linalg.norm(u))!r}")
         for i in range(0, u.shape[0], STRIDE):
             for j in range(0, u.shape[1], STRIDE):
-                lines.append(f"{steps} {i} {j} {u[i, j].real!r} {u[i, j].imag!r}")
+                lines.append(f"{steps} {i} {j} {float(u[i, j].real)!r} {float(u[i, j].imag)!r}")
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(OUT)

@@ -55,3 +55,16 @@ def test_emulated_split_precision_within_bar(emu, case):
     r = _rel(u, ref)
     assert r < 1e-6, r
     assert r > 1e-12   # really ran in reduced precision
+
+
+def test_emulated_split_long_run_high_potential(emu):
+    # the 1D instance of the 64-instance workload with the largest |V| (about
+    # 19) over its 500 steps: rounded history weights or a rounded potential
+    # would perturb every step alike and push the error past 2e-6
+    from emu.emu_plan import EmuPlan
+    from workloads import c4_problems
+
+    prob = c4_problems()[12]
+    u = EmuPlan(emu, prob).run(prob.u0)
+    ref, _ = PeriodicOracle(prob).run()
+    assert _rel(u, ref) < 1e-6
