@@ -59,3 +59,9 @@ def richardson_extrapolate(U: Sequence, ratio: int = 2):
         col = [(f * col[l + 1] - col[l]) / (f - 1) for l in range(len(col) - 1)]
         m += 1
     return col[0]
+
+
+def richardson_weights_exact(L: int, ratio: int = 2) -> List[Fraction]:
+    """Weights r_l with richardson_extrapolate(U) = sum_l r_l U[l] (the tableau
+    is linear in its inputs), from unit inputs in exact arithmetic."""
+    return [richardson_extrapolate([Fraction(int(i == l)) for i in range(L)], ratio) for l in range(L)]
