@@ -207,6 +207,36 @@ int tdse_autotune(tdse_plan_t plan, int32_t reps);
 int tdse_set_instance_state(tdse_plan_t plan, int32_t instance, const void* u0, int32_t on_device);
 int tdse_get_instance_state(tdse_plan_t plan, int32_t instance, void* u, int32_t on_device);
 
+/* ---- field updates and the adjoint -------------------------------------
+ *
+ * Replace the stepwise field samples of a TDSE_A_STEPWISE plan: A_steps is
+ * [nsteps][dim] (batch: every instance's block in instance order).  EINVAL
+ * for other field kinds.  A captured graph is dropped; a batch re-records its
+ * launch arguments. */
+int tdse_set_field(tdse_plan_t plan, const double* A_steps);
+
+/* Device bytes the adjoint needs with checkpoints every `checkpoint_every`
+ * Adams steps (<= 0: about the square root of the step count). */
+int tdse_adjoint_workspace_size(tdse_plan_t plan, int32_t checkpoint_every, size_t* bytes);
+
+/* Reverse-mode derivative of a real objective J(u(T)) of the periodic scheme
+ * with a stepwise field, for the FP64 form of the scheme (a split plan's
+ * Adams passes are recomputed in FP64).  lambda_T is the adjoint seed:
+ * dJ = Re sum_j conj(lambda_T,j) du_j(T) (for <x_a> = w sum x_a |u|^2 with
+ * cell volume w, lambda_T = 2 w x_a u(T)).  The forward run from u0 is
+ * recomputed with checkpoints every `checkpoint_every` Adams steps and the
+ * scheme is then reversed step by step: every phase factor of Lemma 1
+ * contributes sum_k k_a Re(conj(adjoint of its output) i E x) to
+ * dJ/d(phi_a(t_b) - phi_a(t_a)), which the interval's overlap with step m
+ * carries to dJ/dA_m.  Outputs: dF_dA (host, [nsteps][dim]; batch: instance
+ * blocks in order) and, unless NULL, dF_du0 (dJ = Re <dF_du0, du0>; same
+ * memory kind as u0).  u0, lambda_T and dF_du0 are device pointers when
+ * on_device != 0, else host.  Synchronizes the bound stream; overwrites the
+ * plan's state (call tdse_set_state again before stepping).  EUNSUPPORTED for
+ * free-space plans or other field kinds. */
+int tdse_adjoint(tdse_plan_t plan, void* adj_workspace, size_t bytes, int32_t checkpoint_every, const void* u0,
+                 const void* lambda_T, int32_t on_device, double* dF_dA, void* dF_du0);
+
 /* Release the plan (not the caller's workspace). */
 void tdse_destroy(tdse_plan_t plan);
 

@@ -30,7 +30,8 @@ EXPORTS = [
     "tdse_plan", "tdse_workspace_size", "tdse_bind", "tdse_set_state", "tdse_step",
     "tdse_get_state", "tdse_run", "tdse_query", "tdse_destroy", "tdse_status_string",
     "tdse_last_error", "tdse_profile", "tdse_graph", "tdse_plan_batch", "tdse_autotune",
-    "tdse_set_instance_state", "tdse_get_instance_state",
+    "tdse_set_instance_state", "tdse_get_instance_state", "tdse_set_field", "tdse_adjoint_workspace_size",
+    "tdse_adjoint",
 ]
 
 _lib = None
@@ -61,6 +62,9 @@ def load() -> C.CDLL:
     lib.tdse_autotune.argtypes = [P, C.c_int32]
     lib.tdse_set_instance_state.argtypes = [P, C.c_int32, P, C.c_int32]
     lib.tdse_get_instance_state.argtypes = [P, C.c_int32, P, C.c_int32]
+    lib.tdse_set_field.argtypes = [P, C.POINTER(C.c_double)]
+    lib.tdse_adjoint_workspace_size.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
+    lib.tdse_adjoint.argtypes = [P, P, C.c_size_t, C.c_int32, P, P, C.c_int32, C.POINTER(C.c_double), P]
     lib.tdse_destroy.argtypes = [P]
     lib.tdse_destroy.restype = None
     lib.tdse_status_string.argtypes = [C.c_int]
@@ -69,7 +73,8 @@ def load() -> C.CDLL:
     lib.tdse_last_error.restype = C.c_char_p
     for name in ("tdse_plan", "tdse_workspace_size", "tdse_bind", "tdse_set_state", "tdse_step",
                  "tdse_get_state", "tdse_run", "tdse_query", "tdse_plan_batch", "tdse_autotune",
-                 "tdse_set_instance_state", "tdse_get_instance_state"):
+                 "tdse_set_instance_state", "tdse_get_instance_state", "tdse_set_field",
+                 "tdse_adjoint_workspace_size", "tdse_adjoint"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -372,7 +372,8 @@ struct tdse_plan_s {
   const void* V(int g) const { return ws + st[g].o_V; }
   double2* ph() const { return (double2*)(ws + o_ph); }
   const void* tw(int g, int axis) const { return ws + (axis == 0 ? st[g].o_tw1 : st[g].o_tw2); }
-  bool split() const { return precision == TDSE_FP32_SPLIT; }
+  bool force_fp64 = false;   // run the Adams passes of a split plan in FP64 (adjoint recomputation)
+  bool split() const { return precision == TDSE_FP32_SPLIT && !force_fp64; }
 
   double t_at(int m) const { return m * dt; }
   void fV_at(double t, double* f) const {
@@ -629,7 +630,7 @@ int op_fp64_output(tdse_plan_s* p, int m) {
 
 // Implicit Adams step m (eq. (uadamsk)), stage 1.
 int op_am_step(tdse_plan_s* p, int m, bool write_u) {
-  const int n = p->order, g = 1;
+  const int n = p->order, g = p->split() ? 1 : 0;
   if (write_u && p->split()) {
     int s = op_fp64_output(p, m);
     if (s) return s;
@@ -1549,6 +1550,478 @@ int autotune_batch(tdse_plan_s* p, int reps) {
   return status;
 }
 
+
+// ================================================================ adjoint
+//
+// Reverse-mode derivative of J(u_N) (dJ = Re <lam, du_N>) with respect to the
+// stepwise field samples A_m and to u0, for the FP64 scheme.  Forward: the
+// start-up states u_0..u_ns are kept and the Adams state (B and the history
+// ring) is checkpointed every K steps.  Reverse: per segment of K Adams steps
+// the forward is recomputed from its checkpoint, keeping B_n and What_n, and
+// the adjoint recurrence runs backwards (adjoint_kernels.hip):
+//   beta_N = F^-H conj(S_N) lam,
+//   beta_n = conj(E^(1)_{n+1}) beta_{n+1} + G_n^H omega_n,   G_n^H = F conj(S_n) V_n F^-1,
+//   omega_m = i dt sum_j c_{m,j} conj(E^(j)_{m+j}) beta_{m+j},
+// then the start-up sub-steps are reversed one by one.  Every phase factor
+// contributes sum_k k_a Re(conj(adjoint of its output) i E x) to dJ/d(dphi_a)
+// of its interval, and dJ/dA_m adds these with the interval's overlap with
+// step m.
+
+struct AdjLayout {
+  int K = 1, C = 0, H = 1, nblk = 1, L = 1, nsub_max = 1;
+  int64_t P = 1, rows = 0;
+  size_t o_ustore = 0, o_ck = 0, o_bseg = 0, o_wwin = 0, o_beta = 0, o_omega = 0, o_omsu = 0, o_Z = 0;
+  size_t o_phys[3] = {0, 0, 0}, o_modes[2] = {0, 0}, o_bvirt = 0, o_subv = 0, o_subg = 0, o_ph = 0;
+  size_t o_part = 0, o_red = 0, o_csr = 0, o_gA = 0, csr_bytes = 0, total = 0;
+  size_t ck_bytes = 0;
+};
+
+AdjLayout adj_layout(const tdse_plan_s* p, int K) {
+  AdjLayout L;
+  const int N = p->nsteps, ns = std::min(p->ns, N);
+  L.H = p->order - 1;
+  L.L = p->order / 2;
+  L.nsub_max = 1 << (L.L - 1);
+  L.P = p->P;
+  L.nblk = (int)((p->P + 255) / 256);
+  const int iters = N - 1 - ns;   // Adams iterations n = ns+1 .. N-1
+  if (K <= 0) K = std::max(1, (int)std::ceil(std::sqrt((double)std::max(iters, 1))));
+  L.K = K;
+  L.C = N > ns ? std::max(1, (iters + K - 1) / K) : 0;
+  const size_t a = (size_t)p->P * sizeof(double2);
+  L.ck_bytes = (size_t)(1 + L.H) * a;
+  L.rows = (N > ns ? (int64_t)(N - ns) * 2 * MAXH : 0) + (int64_t)ns * ((1 << L.L) - 1) * 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  L.o_ustore = take((size_t)(ns + 1) * a);
+  L.o_ck = take((size_t)L.C * L.ck_bytes);
+  L.o_bseg = take((size_t)K * a);
+  L.o_wwin = take((size_t)(K + L.H) * a);
+  L.o_beta = take(8 * a);
+  L.o_omega = take(a);
+  L.o_omsu = take((size_t)L.H * a);
+  L.o_Z = take(a);
+  for (int i = 0; i < 3; ++i) L.o_phys[i] = take(a);
+  for (int i = 0; i < 2; ++i) L.o_modes[i] = take(a);
+  L.o_bvirt = take(a);
+  L.o_subv = take((size_t)L.nsub_max * a);
+  L.o_subg = take((size_t)L.nsub_max * a);
+  L.o_ph = take((size_t)ADJ_PH * (p->M1 + p->M2) * sizeof(double2));
+  L.o_part = take((size_t)L.rows * L.nblk * sizeof(double));
+  L.o_red = take((size_t)L.rows * sizeof(double));
+  // field-gradient map: per sample (m, component) the rows that overlap it
+  const int64_t nA = (int64_t)N * p->dim;
+  const int64_t nnz = ((int64_t)(N - ns) * (L.H * (L.H + 1) / 2) + (int64_t)ns * ((1 << L.L) - 1)) * p->dim;
+  // rowptr, then the row indices and the weights, each 256-byte aligned (as laid out below)
+  L.csr_bytes = align256((size_t)(nA + 1) * sizeof(int)) + align256((size_t)nnz * sizeof(int)) +
+                (size_t)nnz * sizeof(double) + 8;
+  L.o_csr = take(L.csr_bytes);
+  L.o_gA = take((size_t)nA * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+struct AdjRun {
+  tdse_plan_s* p;
+  char* w;
+  AdjLayout L;
+  struct Row {
+    double ta, tb;
+    int axis;
+  };
+  std::vector<Row> rows;   // partial-sum row -> interval and internal axis
+  double2* at(size_t off, int64_t i = 0) const { return (double2*)(w + off) + i * L.P; }
+};
+
+int adj_err(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return TDSE_OK;
+}
+
+// dst = fft2((alpha + beta V(t)) src) * scale   (physical -> modes, unnormalized FFT)
+int adj_fft2(tdse_plan_s* p, const double2* src, double2* dst, double scale, double ar, double ai, double br, double bi,
+             double t) {
+  LineArgs a = base_args(p, 0);
+  col_geom(p, 0, a);
+  a.mode = C_FWD;
+  a.src = src;
+  a.dst = p->tmp(0);
+  p->fV_at(t, a.fV);
+  a.alpha_re = ar; a.alpha_im = ai; a.beta_re = br; a.beta_im = bi;
+  a.scale = scale;
+  int s = launch(p, 0, true, a);
+  if (s) return s;
+  LineArgs r = base_args(p, 0);
+  row_geom(p, 0, r);
+  r.mode = R_FWD;
+  r.src = p->tmp(0);
+  r.fdst = dst;
+  return launch(p, 0, false, r);
+}
+
+// unnormalized inverse FFT of modes src, then / (1 + i csolve V(t)) into dst (physical);
+// with zdst, the column pass's forward transform of V u / P lands in tmp and a
+// row FFT of it in zdst (G^H when csolve = -mu_0 dt)
+int adj_ifft2(tdse_plan_s* p, const double2* src, double2* dst, double csolve, double t, double2* zdst = nullptr) {
+  LineArgs r = base_args(p, 0);
+  row_geom(p, 0, r);
+  r.mode = R_INV;
+  r.Bm = (double2*)src;
+  r.dst = p->tmp(0);
+  int s = launch(p, 0, false, r);
+  if (s) return s;
+  LineArgs c = base_args(p, 0);
+  col_geom(p, 0, c);
+  c.mode = C_SOLVE;
+  c.src = p->tmp(0);
+  c.dst = p->tmp(0);
+  c.csolve = csolve;
+  p->fV_at(t, c.fV);
+  c.uout = dst;   // may be null
+  s = launch(p, 0, true, c);
+  if (s || !zdst) return s;
+  LineArgs f = base_args(p, 0);
+  row_geom(p, 0, f);
+  f.mode = R_FWD;
+  f.src = p->tmp(0);
+  f.fdst = zdst;
+  return launch(p, 0, false, f);
+}
+
+int adj_point(tdse_plan_s* p, const double2* in, double2* out, double t, double ar, double ai, double br, double bi,
+              double sc, bool divide, bool acc) {
+  AdjPoint a;
+  std::memset(&a, 0, sizeof(a));
+  a.P = p->P;
+  a.in = in;
+  a.out = out;
+  a.V = (const double*)p->V(0);
+  a.nV = p->nV;
+  a.vstride = p->P;
+  p->fV_at(t, a.fV);
+  a.ar = ar; a.ai = ai; a.br = br; a.bi = bi; a.s = sc;
+  a.divide = divide;
+  a.accumulate = acc;
+  return adj_err(launch_adj_point(a, p->stream), "adjoint pointwise");
+}
+
+// phase entries e: E over [tb - tau, tb]
+struct AdjPh {
+  AdjPhase q;
+  explicit AdjPh(const tdse_plan_s* p, double2* ph) {
+    std::memset(&q, 0, sizeof(q));
+    q.M1 = p->M1;
+    q.M2 = p->M2;
+    q.ph = ph;
+  }
+  void set(const tdse_plan_s* p, int e, double tb, double tau) {
+    double pb[2], pa[2];
+    p->tf.phi(tb, pb);
+    p->tf.phi(tb - tau, pa);
+    q.tau[e] = tau;
+    if (p->dim == 2) {
+      q.dphi1[e] = pb[0] - pa[0];
+      q.dphi2[e] = pb[1] - pa[1];
+    } else {
+      q.dphi1[e] = 0.0;
+      q.dphi2[e] = pb[0] - pa[0];
+    }
+    q.nj = std::max(q.nj, e + 1);
+  }
+};
+
+int adj_copy(tdse_plan_s* p, void* dst, const void* src, size_t bytes) {
+  return adj_err(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, p->stream), "adjoint copy");
+}
+
+int adjoint_single(tdse_plan_s* p, char* w, size_t wbytes, int K, const void* u0, const void* lam, int on_device,
+                   double* dF_dA, void* dF_du0) {
+  if (p->free_space) return fail(TDSE_EUNSUPPORTED, "the adjoint covers the periodic scheme");
+  if (p->tf.A_kind != TDSE_A_STEPWISE) return fail(TDSE_EUNSUPPORTED, "the adjoint differentiates stepwise field samples");
+  AdjRun R;
+  R.p = p;
+  R.w = w;
+  R.L = adj_layout(p, K);
+  const AdjLayout& L = R.L;
+  if (wbytes < L.total) return fail(TDSE_ENOMEM, "adjoint workspace smaller than tdse_adjoint_workspace_size");
+  if (((uintptr_t)w) & 255) return fail(TDSE_EINVAL, "adjoint workspace must be 256-byte aligned");
+  const int N = p->nsteps, ns = std::min(p->ns, N), H = L.H, n_ord = p->order;
+  const double dt = p->dt;
+  const std::vector<double>& mu = p->mu;
+  const size_t a = (size_t)p->P * sizeof(double2);
+  const double invP = 1.0 / (double)p->P;
+  const hipStream_t st = p->stream;
+  p->drop_graph();
+  const bool prof = p->prof;
+  p->prof = false;
+  p->force_fp64 = true;
+  int s = TDSE_OK;
+  auto done = [&](int status) {
+    p->force_fp64 = false;
+    p->prof = prof;
+    p->cur = -1;   // the recomputation overwrote the state
+    return status;
+  };
+  // ---- forward with storage
+  s = tdse_set_state(p, u0, on_device);
+  if (s) return done(s);
+  p->force_fp64 = true;
+  if (on_device) s = adj_copy(p, R.at(L.o_phys[2]), lam, a);
+  else s = adj_err(hipMemcpyAsync(R.at(L.o_phys[2]), lam, a, hipMemcpyHostToDevice, st), "adjoint seed");
+  if (!s) s = adj_copy(p, R.at(L.o_ustore, 0), p->u(p->ucur), a);
+  for (int m = 1; m <= ns && !s; ++m) {
+    s = do_step(p, m, false);
+    if (!s) s = adj_copy(p, R.at(L.o_ustore, m), p->u(p->ucur), a);
+  }
+  if (s) return done(s);
+  auto ck = [&](int c) { return w + L.o_ck + (size_t)c * L.ck_bytes; };
+  if (N > ns) {
+    if (ns == 0) s = op_history(p, 0);
+    if (!s) s = op_am_init(p);
+    if (!s) s = adj_copy(p, ck(0), p->B(), a);
+    if (!s) s = adj_copy(p, ck(0) + a, p->ring(0), (size_t)H * a);
+    for (int m = ns + 1; m <= N - 1 && !s; ++m) {
+      s = op_am_step(p, m, false);
+      const int sidx = m + 1 - (ns + 1);
+      if (!s && sidx % L.K == 0 && sidx / L.K < L.C) {
+        s = adj_copy(p, ck(sidx / L.K), p->B(), a);
+        if (!s) s = adj_copy(p, ck(sidx / L.K) + a, p->ring(0), (size_t)H * a);
+      }
+    }
+  }
+  if (s) return done(s);
+  // ---- reverse sweep
+  s = adj_err(hipMemsetAsync(w + L.o_beta, 0, 8 * a, st), "adjoint clear");
+  if (!s && L.rows) s = adj_err(hipMemsetAsync(w + L.o_part, 0, (size_t)L.rows * L.nblk * sizeof(double), st), "clear");
+  if (s) return done(s);
+  R.rows.assign((size_t)L.rows, AdjRun::Row{0.0, 0.0, 0});
+  double2* beta = R.at(L.o_beta);
+  auto bslot = [&](int idx) { return (idx >= ns + 1 && idx <= N) ? idx % 8 : -1; };
+  auto cfac = [&](int m, int j) {   // coefficient of What_m in B_{m+j}
+    if (j == 1) return m >= ns + 1 ? mu[0] + mu[1] : mu[1];
+    return mu[j];
+  };
+  AdjPh PH(p, R.at(L.o_ph));
+  const double2* Bvirt = R.at(L.o_bvirt);
+  // one adjoint Adams iteration at n: beta_n, the partials of step n+1, omega_{n-1}
+  auto am_iter = [&](int n, int beta_mode, bool grad, const double2* Bn, const double2* const* Wx,
+                     double2* omega_out) -> int {
+    PH.q.nj = 0;
+    for (int j = 1; j <= H; ++j) {
+      PH.set(p, j - 1, (n + 1) * dt, j * dt);
+      PH.set(p, H + j - 1, (n - 1 + j) * dt, j * dt);
+    }
+    int e = adj_err(launch_adj_phase(PH.q, st), "adjoint phases");
+    if (e) return e;
+    AdjAm A;
+    std::memset(&A, 0, sizeof(A));
+    A.M1 = p->M1;
+    A.M2 = p->M2;
+    A.H = H;
+    A.P = p->P;
+    A.ph = PH.q.ph;
+    A.beta = beta;
+    A.slot_b1 = bslot(n + 1);
+    A.slot_bn = n % 8;
+    A.beta_mode = beta_mode;
+    A.Z = R.at(L.o_Z);
+    A.omega = omega_out;
+    for (int j = 2; j <= H; ++j) A.slot_bj[j] = bslot(n - 1 + j);
+    for (int j = 1; j <= H; ++j) A.wj[j] = (n - 1 + j >= ns + 1 && n - 1 + j <= N && n - 1 >= 0) ? dt * cfac(n - 1, j) : 0.0;
+    A.has_grad = grad;
+    A.nblk = L.nblk;
+    if (grad) {
+      const int64_t g0 = (int64_t)(n - ns) * 2 * MAXH;
+      A.part = (double*)(w + L.o_part) + g0 * L.nblk;
+      A.Bn = Bn;
+      for (int j = 1; j <= H; ++j) {
+        A.Wx[j] = Wx[j];
+        A.cx[j] = j == 1 ? dt * (mu[0] + mu[1]) : dt * mu[j];
+        for (int ax = 0; ax < 2; ++ax) R.rows[g0 + 2 * (j - 1) + ax] = AdjRun::Row{(n + 1 - j) * dt, (n + 1) * dt, ax};
+      }
+    }
+    return adj_err(launch_adj_am(A, st), "adjoint Adams step");
+  };
+  auto omsu = [&](int m) { return R.at(L.o_omsu, m - (ns + 1 - H)); };
+  if (N > ns) {
+    // beta_N = F^-H conj(S_N) lam = fft2(lam / (1 - i mu_0 dt V(t_N)))
+    s = adj_point(p, R.at(L.o_phys[2]), R.at(L.o_phys[0]), N * dt, 1.0, 0.0, 0.0, -mu[0] * dt, 1.0, true, false);
+    if (!s) s = adj_fft2(p, R.at(L.o_phys[0]), beta + (int64_t)(N % 8) * p->P, 1.0, 1.0, 0.0, 0.0, 0.0, N * dt);
+    if (!s) s = am_iter(N, 2, false, nullptr, nullptr, R.at(L.o_omega));
+    if (!s && N - 1 <= ns) s = adj_copy(p, omsu(N - 1), R.at(L.o_omega), a);
+    for (int c = L.C - 1; c >= 0 && !s; --c) {
+      const int sc = ns + 1 + c * L.K;
+      const int ec = std::min(sc + L.K - 1, N - 1);
+      const int w0 = sc - H;   // window slot 0 holds What_{sc-H}
+      s = adj_copy(p, p->B(), ck(c), a);
+      if (!s) s = adj_copy(p, p->ring(0), ck(c) + a, (size_t)H * a);
+      if (!s) {
+        LineArgs r = base_args(p, 0);
+        row_geom(p, 0, r);
+        r.mode = R_INV;
+        r.dst = p->tmp(0);
+        s = launch(p, 0, false, r);
+      }
+      for (int i = std::max(w0, 0); i < sc && !s; ++i) s = adj_copy(p, R.at(L.o_wwin, i - w0), (char*)p->ring(0) + (size_t)(i % H) * a, a);
+      for (int n = sc; n <= ec && !s; ++n) {
+        s = adj_copy(p, R.at(L.o_bseg, n - sc), p->B(), a);
+        if (!s) s = op_am_step(p, n, false);
+        if (!s) s = adj_copy(p, R.at(L.o_wwin, n - w0), (char*)p->ring(0) + (size_t)(n % H) * a, a);
+      }
+      for (int n = ec; n >= sc && !s; --n) {
+        // Z = G_n^H omega_n = F conj(S_n) V_n F^-1 omega_n
+        s = adj_ifft2(p, R.at(L.o_omega), nullptr, -mu[0] * dt, n * dt, R.at(L.o_Z));
+        const double2* Wx[MAXH + 1] = {nullptr};
+        for (int j = 1; j <= H; ++j) Wx[j] = R.at(L.o_wwin, (j == 1 ? n : n + 1 - j) - w0);
+        if (!s) s = am_iter(n, 1, true, R.at(L.o_bseg, n - sc), Wx, R.at(L.o_omega));
+        if (!s && n - 1 <= ns) s = adj_copy(p, omsu(n - 1), R.at(L.o_omega), a);
+      }
+    }
+    if (s) return done(s);
+    // step ns+1 formed B from F u_ns: B_virt = F u_ns + i mu_0 dt What_ns gives x_1
+    {
+      const int w0 = ns + 1 - H;
+      s = adj_fft2(p, R.at(L.o_ustore, ns), R.at(L.o_modes[0]), invP, 1.0, 0.0, 0.0, 0.0, ns * dt);
+      if (!s) s = adj_err(launch_adj_axpy(p->P, R.at(L.o_modes[0]), R.at(L.o_wwin, ns - w0), 0.0, mu[0] * dt,
+                                          R.at(L.o_bvirt), st), "adjoint axpy");
+      const double2* Wx[MAXH + 1] = {nullptr};
+      for (int j = 1; j <= H; ++j) Wx[j] = R.at(L.o_wwin, (j == 1 ? ns : ns + 1 - j) - w0);
+      if (!s) s = am_iter(ns, 0, true, Bvirt, Wx, ns >= 1 ? R.at(L.o_omega) : nullptr);
+      if (!s && ns >= 1 && ns - 1 >= ns + 1 - H) s = adj_copy(p, omsu(ns - 1), R.at(L.o_omega), a);
+      for (int n = ns - 1; n >= std::max(1, ns + 2 - H) && !s; --n) {
+        s = am_iter(n, 0, false, nullptr, nullptr, R.at(L.o_omega));
+        if (!s) s = adj_copy(p, omsu(n - 1), R.at(L.o_omega), a);
+      }
+    }
+    if (s) return done(s);
+    // g_u_ns = ifftn(conj(E^(1)_{ns+1}) beta_{ns+1}) + V_ns ifftn(omega_ns)
+    PH.q.nj = 0;
+    PH.set(p, 0, (ns + 1) * dt, dt);
+    s = adj_err(launch_adj_phase(PH.q, st), "adjoint phases");
+    if (!s) s = adj_copy(p, R.at(L.o_modes[0]), beta + (int64_t)((ns + 1) % 8) * p->P, a);
+    if (!s) {
+      AdjSub S;
+      std::memset(&S, 0, sizeof(S));
+      S.M1 = p->M1; S.M2 = p->M2; S.mode = 2; S.P = p->P; S.ph = PH.q.ph; S.y = R.at(L.o_modes[0]);
+      S.nblk = L.nblk;
+      s = adj_err(launch_adj_sub(S, st), "adjoint phase");
+    }
+    if (!s) s = adj_ifft2(p, R.at(L.o_modes[0]), R.at(L.o_phys[0]), 0.0, ns * dt);
+    if (!s) s = adj_point(p, R.at(L.o_phys[0]), R.at(L.o_phys[1]), ns * dt, invP, 0.0, 0.0, 0.0, 1.0, false, false);
+    if (!s) s = adj_ifft2(p, omsu(ns), R.at(L.o_phys[0]), 0.0, ns * dt);
+    if (!s) s = adj_point(p, R.at(L.o_phys[0]), R.at(L.o_phys[1]), ns * dt, 0.0, 0.0, invP, 0.0, 1.0, false, true);
+  } else {
+    s = adj_copy(p, R.at(L.o_phys[1]), R.at(L.o_phys[2]), a);
+  }
+  if (s) return done(s);
+  // ---- start-up sub-steps, newest first; g_u in phys[1], g_u_{m-1} built in phys[2]
+  int64_t row = (N > ns ? (int64_t)(N - ns) * 2 * MAXH : 0);
+  for (int m = ns; m >= 1 && !s; --m) {
+    const double t0 = (m - 1) * dt;
+    if (N > ns && m - 1 >= ns + 1 - H) {
+      s = adj_ifft2(p, omsu(m - 1), R.at(L.o_phys[0]), 0.0, t0);
+      if (!s) s = adj_point(p, R.at(L.o_phys[0]), R.at(L.o_phys[2]), t0, 0.0, 0.0, invP, 0.0, 1.0, false, false);
+    } else {
+      s = adj_err(hipMemsetAsync(R.at(L.o_phys[2]), 0, a, st), "adjoint clear");
+    }
+    for (int l = 0; l < L.L && !s; ++l) {
+      const int nsub = 1 << l;
+      const double d = dt / nsub;
+      // recompute the level's sub-step inputs v_s and g_s = F((1 - i d/2 V) v_s)
+      s = adj_copy(p, R.at(L.o_subv, 0), R.at(L.o_ustore, m - 1), a);
+      for (int k = 0; k < nsub && !s; ++k) {
+        const double tau = t0 + k * d;
+        s = adj_fft2(p, R.at(L.o_subv, k), R.at(L.o_subg, k), invP, 1.0, 0.0, 0.0, -0.5 * d, tau);
+        if (s || k == nsub - 1) continue;
+        PH.q.nj = 0;
+        PH.set(p, 0, tau + d, d);
+        s = adj_err(launch_adj_phase(PH.q, st), "adjoint phases");
+        if (s) break;
+        AdjSub S;
+        std::memset(&S, 0, sizeof(S));
+        S.M1 = p->M1; S.M2 = p->M2; S.mode = 1; S.P = p->P; S.ph = PH.q.ph; S.y = R.at(L.o_modes[1]);
+        S.g = R.at(L.o_subg, k); S.nblk = L.nblk;
+        s = adj_err(launch_adj_sub(S, st), "adjoint phase");
+        if (!s) s = adj_ifft2(p, R.at(L.o_modes[1]), R.at(L.o_subv, k + 1), 0.5 * d, tau + d);
+      }
+      // reverse the level: g_v = r_l g_u_m
+      if (!s) s = adj_point(p, R.at(L.o_phys[1]), R.at(L.o_phys[0]), t0, p->rich[l], 0.0, 0.0, 0.0, 1.0, false, false);
+      for (int k = nsub - 1; k >= 0 && !s; --k) {
+        const double tau = t0 + k * d;
+        s = adj_point(p, R.at(L.o_phys[0]), R.at(L.o_phys[0]), tau + d, 1.0, 0.0, 0.0, -0.5 * d, 1.0, true, false);
+        if (!s) s = adj_fft2(p, R.at(L.o_phys[0]), R.at(L.o_modes[1]), 1.0, 1.0, 0.0, 0.0, 0.0, tau);
+        if (s) break;
+        PH.q.nj = 0;
+        PH.set(p, 0, tau + d, d);
+        s = adj_err(launch_adj_phase(PH.q, st), "adjoint phases");
+        if (s) break;
+        AdjSub S;
+        std::memset(&S, 0, sizeof(S));
+        S.M1 = p->M1; S.M2 = p->M2; S.mode = 0; S.P = p->P; S.ph = PH.q.ph; S.y = R.at(L.o_modes[1]);
+        S.g = R.at(L.o_subg, k); S.nblk = L.nblk;
+        S.part = (double*)(w + L.o_part) + row * L.nblk;
+        for (int ax = 0; ax < 2; ++ax) R.rows[row + ax] = AdjRun::Row{tau, tau + d, ax};
+        row += 2;
+        s = adj_err(launch_adj_sub(S, st), "adjoint phase");
+        if (!s) s = adj_ifft2(p, R.at(L.o_modes[1]), R.at(L.o_phys[0]), 0.0, tau);
+        if (!s) s = adj_point(p, R.at(L.o_phys[0]), R.at(L.o_phys[0]), tau, 1.0, 0.0, 0.0, 0.5 * d, invP, false, false);
+      }
+      if (!s) s = adj_point(p, R.at(L.o_phys[0]), R.at(L.o_phys[2]), t0, 1.0, 0.0, 0.0, 0.0, 1.0, false, true);
+    }
+    if (!s) s = adj_copy(p, R.at(L.o_phys[1]), R.at(L.o_phys[2]), a);
+  }
+  if (s) return done(s);
+  // ---- dJ/dA: reduce the partials, then map rows to samples
+  const int64_t nA = (int64_t)N * p->dim;
+  std::vector<std::vector<std::pair<int, double>>> by(nA);
+  for (int64_t r = 0; r < row; ++r) {
+    const AdjRun::Row& q = R.rows[r];
+    if (q.tb <= q.ta) continue;
+    const int comp = p->dim == 2 ? q.axis : (q.axis == 1 ? 0 : -1);
+    if (comp < 0) continue;
+    const int m0 = std::max(0, (int)std::floor(q.ta / dt + 1e-9));
+    const int m1 = std::min(N, (int)std::ceil(q.tb / dt - 1e-9));
+    for (int mm = m0; mm < m1; ++mm) {
+      const double ov = std::min(q.tb, (mm + 1) * dt) - std::max(q.ta, mm * dt);
+      if (ov > 0) by[(int64_t)mm * p->dim + comp].push_back({(int)r, ov});
+    }
+  }
+  std::vector<int> rowptr(nA + 1, 0), src;
+  std::vector<double> wt;
+  for (int64_t o = 0; o < nA; ++o) {
+    for (auto& e : by[o]) {
+      src.push_back(e.first);
+      wt.push_back(e.second);
+    }
+    rowptr[o + 1] = (int)src.size();
+  }
+  const size_t b_rp = rowptr.size() * sizeof(int), b_src = src.size() * sizeof(int), b_wt = wt.size() * sizeof(double);
+  const size_t o_src = align256(b_rp), o_wt = align256(o_src + b_src);
+  if (o_wt + b_wt + 8 > L.csr_bytes) return done(fail(TDSE_EINVAL, "adjoint map overflow"));
+  std::vector<char> csr(o_wt + b_wt + 8, 0);
+  std::memcpy(csr.data(), rowptr.data(), b_rp);
+  if (b_src) std::memcpy(csr.data() + o_src, src.data(), b_src);
+  if (b_wt) std::memcpy(csr.data() + o_wt, wt.data(), b_wt);
+  s = adj_err(launch_adj_reduce((double*)(w + L.o_part), (double*)(w + L.o_red), (int)row, L.nblk, st), "adjoint reduce");
+  if (!s) s = adj_err(hipStreamSynchronize(st), "adjoint sync");
+  if (!s) s = adj_err(hipMemcpy(w + L.o_csr, csr.data(), csr.size(), hipMemcpyHostToDevice), "adjoint map upload");
+  if (!s) {
+    char* cb = w + L.o_csr;
+    s = adj_err(launch_adj_to_A((double*)(w + L.o_red), (const int*)cb, (const int*)(cb + o_src),
+                                (const double*)(cb + o_wt), (double*)(w + L.o_gA), (int)nA, st), "adjoint map");
+  }
+  if (!s && dF_dA) s = adj_err(hipMemcpyAsync(dF_dA, w + L.o_gA, nA * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+  if (!s && dF_du0)
+    s = adj_err(hipMemcpyAsync(dF_du0, R.at(L.o_phys[1]), a, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st),
+                "copy");
+  if (!s) s = adj_err(hipStreamSynchronize(st), "adjoint sync");
+  return done(s);
+}
+
 bool good_len(int M) { return M >= 8 && M <= 3072 && M % 2 == 0 && line_length_supported(M); }
 
 }  // namespace
@@ -1995,6 +2468,63 @@ int tdse_get_instance_state(tdse_plan_t p, int32_t instance, void* u, int32_t on
   if (instance < 0 || instance >= (int)p->sub.size()) return fail(TDSE_EINVAL, "instance out of range");
   if (!p->bound || p->cur < 0) return fail(TDSE_ESTATE, "no state");
   return tdse_get_state(p->sub[instance], u, on_device);
+}
+
+
+int tdse_set_field(tdse_plan_t p, const double* A_steps) {
+  if (!p || !A_steps) return fail(TDSE_EINVAL, "NULL argument");
+  if (p->is_batch()) {
+    size_t off = 0;
+    for (tdse_plan_s* q : p->sub) {
+      const int s = tdse_set_field(q, A_steps + off);
+      if (s) return s;
+      off += (size_t)q->nsteps * q->dim;
+    }
+    p->drop_graph();
+    if (p->batch_ready) {
+      const int s = batch_record(p);
+      if (s) return s;
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      HIP_TRY(hipMemcpy(p->ws + p->o_args, p->bargs.data(), p->bargs.size() * sizeof(LineArgs), hipMemcpyHostToDevice));
+    }
+    return TDSE_OK;
+  }
+  if (p->tf.A_kind != TDSE_A_STEPWISE) return fail(TDSE_EINVAL, "tdse_set_field needs a stepwise-field plan");
+  p->tf.A_steps.assign(A_steps, A_steps + (size_t)p->nsteps * p->dim);
+  p->tf.prepare();
+  p->drop_graph();
+  return TDSE_OK;
+}
+
+int tdse_adjoint_workspace_size(tdse_plan_t p, int32_t checkpoint_every, size_t* bytes) {
+  if (!p || !bytes) return fail(TDSE_EINVAL, "NULL argument");
+  size_t b = 0;
+  if (p->is_batch()) {
+    for (tdse_plan_s* q : p->sub) b = std::max(b, adj_layout(q, checkpoint_every).total);
+  } else {
+    b = adj_layout(p, checkpoint_every).total;
+  }
+  *bytes = b;
+  return TDSE_OK;
+}
+
+int tdse_adjoint(tdse_plan_t p, void* ws, size_t bytes, int32_t checkpoint_every, const void* u0, const void* lambda_T,
+                 int32_t on_device, double* dF_dA, void* dF_du0) {
+  if (!p || !ws || !u0 || !lambda_T) return fail(TDSE_EINVAL, "NULL argument");
+  if (!p->bound) return fail(TDSE_ESTATE, "tdse_bind must come first");
+  if (!p->is_batch()) return adjoint_single(p, (char*)ws, bytes, checkpoint_every, u0, lambda_T, on_device, dF_dA, dF_du0);
+  size_t aoff = 0;
+  for (size_t i = 0; i < p->sub.size(); ++i) {
+    tdse_plan_s* q = p->sub[i];
+    const int64_t e = p->sub_elem[i];
+    const int s = adjoint_single(q, (char*)ws, bytes, checkpoint_every, (const double2*)u0 + e,
+                                 (const double2*)lambda_T + e, on_device, dF_dA ? dF_dA + aoff : nullptr,
+                                 dF_du0 ? (void*)((double2*)dF_du0 + e) : nullptr);
+    if (s) return s;
+    aoff += (size_t)q->nsteps * q->dim;
+  }
+  p->cur = -1;
+  return TDSE_OK;
 }
 
 void tdse_destroy(tdse_plan_t p) { delete p; }

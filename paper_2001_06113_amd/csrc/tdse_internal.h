@@ -137,6 +137,62 @@ hipError_t launch_batch_pass(int prec, bool col, int family, const LineArgs* arg
                              int ntiles, size_t lds_bytes, hipStream_t s, hipEvent_t e0 = nullptr,
                              hipEvent_t e1 = nullptr);
 
+// Adjoint of the periodic scheme (adjoint_kernels.hip), FP64.
+constexpr int ADJ_PH = 2 * MAXH;   // phase entries of one adjoint Adams step
+struct AdjPhase {                  // per-axis table ph[e (M1+M2) + k], e < nj
+  int M1, M2, nj;
+  double tau[ADJ_PH], dphi1[ADJ_PH], dphi2[ADJ_PH];
+  double2* ph;
+};
+struct AdjAm {                     // one adjoint implicit Adams step (mode space, P modes)
+  int M1, M2, H;
+  int64_t P;
+  const double2* ph;               // entries j-1: E^(j)_{n+1}; H+j-1: E^(j)_{n-1+j}
+  double2* beta;                   // ring of adjoint states, slots of P modes
+  int slot_b1;                     // beta_{n+1} (-1: zero)
+  int slot_bn;                     // beta_n
+  int beta_mode;                   // 0: beta_n = 0; 1: beta_n = conj(E^(1)_{n+1}) beta_{n+1} + Z; 2: read
+  const double2* Z;                // G_n^H omega_n
+  double2* omega;                  // out: omega_{n-1} (null: none)
+  int slot_bj[MAXH + 1];           // beta_{n-1+j}, j >= 2 (-1: zero)
+  double wj[MAXH + 1];             // omega weights dt c_{n-1,j}
+  int has_grad;                    // dJ/d(dphi) partials of the phase factors of step n+1
+  const double2* Bn;               // x_1 = B_n - i cx[1] What_n
+  const double2* Wx[MAXH + 1];     // Wx[1] = What_n, Wx[j] = What_{n+1-j}
+  double cx[MAXH + 1];             // x_j = -i cx[j] What_{n+1-j}, j >= 2
+  double* part;                    // partial sums [2 (j-1) + axis][nblk]
+  int nblk;
+};
+struct AdjSub {                    // phase factor of an order-2 sub-step (entry 0 of ph)
+  int M1, M2, mode;                // 1: y = E g; 0: partials and y = conj(E) y; 2: y = conj(E) y
+  int64_t P;
+  const double2* ph;
+  double2* y;
+  const double2* g;
+  double* part;                    // partial sums [axis][nblk]
+  int nblk;
+};
+struct AdjPoint {                  // out (+)= s (alpha + beta V) in, or s in / (alpha + beta V)
+  int64_t P;
+  const double2* in;
+  double2* out;
+  const double* V;
+  int nV;
+  int64_t vstride;
+  double fV[MAXV];
+  double ar, ai, br, bi, s;
+  int divide, accumulate;
+};
+hipError_t launch_adj_phase(const AdjPhase& q, hipStream_t s);
+hipError_t launch_adj_am(const AdjAm& a, hipStream_t s);
+hipError_t launch_adj_sub(const AdjSub& a, hipStream_t s);
+hipError_t launch_adj_point(const AdjPoint& a, hipStream_t s);
+hipError_t launch_adj_axpy(int64_t P, const double2* x, const double2* y, double cr, double ci, double2* out,
+                           hipStream_t s);
+hipError_t launch_adj_reduce(const double* part, double* red, int nrows, int nblk, hipStream_t s);
+hipError_t launch_adj_to_A(const double* red, const int* rowptr, const int* src, const double* wt, double* out,
+                           int nout, hipStream_t s);
+
 // Free-space launchers (freespace_kernels.hip); events as for the periodic passes.
 hipError_t launch_fs_row(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // nu = 0: the pointwise pass of a 1D problem

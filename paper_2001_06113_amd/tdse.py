@@ -111,6 +111,7 @@ class Plan:
     def __init__(self, *, device=None, stream=None, **problem):
         self.lib = _lib.load()
         self.dim = problem["dim"]
+        self.nsteps = int(problem["nsteps"])
         self.M = tuple(int(m) for m in problem["M"])
         self.shape = self.M
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -182,6 +183,37 @@ class Plan:
         _check(self.lib.tdse_query(self.handle, int(key), C.byref(v)), "tdse_query")
         return v.value
 
+    def set_field(self, A_steps) -> None:
+        """New stepwise field samples [nsteps, dim] (tdse_set_field)."""
+        a = np.ascontiguousarray(np.asarray(A_steps, dtype=np.float64).ravel())
+        _check(self.lib.tdse_set_field(self.handle, _dptr(a)), "tdse_set_field")
+
+    def adjoint(self, u0, lam, checkpoint_every: int = 0):
+        """dJ/dA [nsteps, dim] (numpy) and dJ/du0 (device tensor) for dJ = Re <lam, du(T)>
+        (tdse_adjoint); the plan's state is overwritten."""
+        u0d = self._as_device(u0)
+        lamd = self._as_device(lam)
+        size = C.c_size_t()
+        _check(self.lib.tdse_adjoint_workspace_size(self.handle, int(checkpoint_every), C.byref(size)),
+               "tdse_adjoint_workspace_size")
+        if getattr(self, "_adj_ws", None) is None or self._adj_ws.numel() < size.value:
+            self._adj_ws = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        n_out = int(sum(self._field_shape()))
+        gA = np.zeros(n_out, dtype=np.float64)
+        g0 = torch.empty_like(u0d)
+        self._enter()
+        _check(self.lib.tdse_adjoint(self.handle, C.c_void_p(self._adj_ws.data_ptr()), size.value,
+                                     int(checkpoint_every), C.c_void_p(u0d.data_ptr()), C.c_void_p(lamd.data_ptr()),
+                                     1, _dptr(gA), C.c_void_p(g0.data_ptr())), "tdse_adjoint")
+        self._leave()
+        return self._split_field(gA), g0
+
+    def _field_shape(self):
+        return [self.nsteps * self.dim]
+
+    def _split_field(self, flat):
+        return flat.reshape(self.nsteps, self.dim)
+
     def profile(self, enable: bool) -> None:
         _check(self.lib.tdse_profile(self.handle, 1 if enable else 0), "tdse_profile")
 
@@ -212,6 +244,7 @@ class BatchPlan(Plan):
             keep += k
         arr = (_lib.Problem * len(structs))(*structs)
         self.shapes = [tuple(int(m) for m in kw["M"]) for kw in problems]
+        self.field_shapes = [(int(kw["nsteps"]), int(kw["dim"])) for kw in problems]
         self.count = len(structs)
         handle = C.c_void_p()
         _check(self.lib.tdse_plan_batch(arr, len(structs), C.byref(handle)), "tdse_plan_batch")
@@ -268,5 +301,42 @@ class BatchPlan(Plan):
         self._leave()
         return out
 
+    def _field_shape(self):
+        return [n * d for n, d in self.field_shapes]
+
+    def _split_field(self, flat):
+        out, o = [], 0
+        for n, d in self.field_shapes:
+            out.append(flat[o:o + n * d].reshape(n, d))
+            o += n * d
+        return out
+
     def run_list(self, u0s):
         return self.unpack(self.run(u0s))
+
+
+class TDSEFunction(torch.autograd.Function):
+    """u(T) as a differentiable function of the stepwise field samples (and of
+    u0) of a planned periodic problem: forward sets the samples and runs the
+    plan; backward is the library's adjoint (tdse_adjoint), seeded with the
+    incoming gradient of u(T) (torch's convention dJ = Re <grad, du>).
+
+        uT = TDSEFunction.apply(A_steps, plan, u0)        # A_steps [nsteps, dim] float64
+    """
+
+    @staticmethod
+    def forward(ctx, A_steps, plan, u0, checkpoint_every=0):
+        plan.set_field(A_steps.detach().cpu().numpy())
+        u0d = plan._as_device(u0.detach() if isinstance(u0, torch.Tensor) else u0).clone()
+        out = plan.run(u0d)
+        ctx.plan, ctx.u0, ctx.k = plan, u0d, int(checkpoint_every)
+        ctx.A_meta = (A_steps.dtype, A_steps.device)
+        ctx.u0_is_tensor = isinstance(u0, torch.Tensor)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_uT):
+        gA, g0 = ctx.plan.adjoint(ctx.u0, grad_uT.detach().contiguous(), ctx.k)
+        dtype, device = ctx.A_meta
+        gA_t = torch.as_tensor(np.asarray(gA), dtype=dtype, device=device)
+        return gA_t, None, (g0 if ctx.u0_is_tensor else None), None

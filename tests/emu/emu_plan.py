@@ -159,3 +159,24 @@ class EmuBatchPlan:
             self.lib.tdse_destroy(self.h)
         except Exception:
             pass
+
+
+def emu_adjoint(plan, u0, lam, checkpoint_every=0):
+    """tdse_adjoint on an EmuPlan: (dJ/dA [nsteps, dim], dJ/du0)."""
+    lib, h = plan.lib, plan.h
+    sz = C.c_size_t()
+    lib.tdse_adjoint_workspace_size(h, checkpoint_every, C.byref(sz))
+    raw = np.zeros(sz.value + 512, dtype=np.uint8)
+    off = (-raw.ctypes.data) % 256
+    ws = raw[off:off + sz.value]
+    u0 = np.ascontiguousarray(u0, dtype=np.complex128)
+    lam = np.ascontiguousarray(lam, dtype=np.complex128)
+    nsteps, dim = plan.prob.nsteps, plan.prob.dim
+    gA = np.zeros((nsteps, dim))
+    g0 = np.zeros_like(u0)
+    st = lib.tdse_adjoint(h, C.c_void_p(ws.ctypes.data), sz.value, checkpoint_every, C.c_void_p(u0.ctypes.data),
+                          C.c_void_p(lam.ctypes.data), 1, gA.ctypes.data_as(C.POINTER(C.c_double)),
+                          C.c_void_p(g0.ctypes.data))
+    if st:
+        raise RuntimeError(lib.tdse_last_error().decode())
+    return gA, g0
