@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-split", action="store_true", help="skip the FP32-split 1024x1024 leg")
     ap.add_argument("--split-steps", type=int, default=3)
     ap.add_argument("--no-free", action="store_true", help="skip the free-space 256x256 leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched leg")
+    ap.add_argument("--batch-runs", type=int, default=3)
     ap.add_argument("--free-runs", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run device copies of 256 MiB (to scale HBM byte counters) and exit")
@@ -81,14 +83,18 @@ def cpu_baseline(prob, nsteps: int) -> dict:
     }
 
 
-KERNEL_SOURCES = ("paper_2001_06113_amd/csrc/periodic_kernels.hip", "paper_2001_06113_amd/csrc/fft_lds.h",
-                  "paper_2001_06113_amd/csrc/tdse_internal.h")
+KERNEL_SOURCES = ("paper_2001_06113_amd/csrc/periodic_kernels.hip", "paper_2001_06113_amd/csrc/periodic_body.h",
+                  "paper_2001_06113_amd/csrc/fft_lds.h", "paper_2001_06113_amd/csrc/tdse_internal.h")
 
 
-def measured_traffic(name: str):
-    """HBM bytes per launch of the dominant kernel from the committed
-    FETCH_SIZE/WRITE_SIZE summary, or None if the kernel sources changed
-    since those counters were taken."""
+FS_KERNEL_SOURCES = ("paper_2001_06113_amd/csrc/freespace_kernels.hip", "paper_2001_06113_amd/csrc/fft_lds.h",
+                     "paper_2001_06113_amd/csrc/tdse_internal.h")
+
+
+def measured_traffic(name: str, sources=KERNEL_SOURCES):
+    """HBM bytes per launch of a kernel from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None if the kernel sources changed since those counters were
+    taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", name)
@@ -96,7 +102,7 @@ def measured_traffic(name: str):
         return None
     kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith("#"))
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if kv.get("source_sha256", "").strip() != h.hexdigest():
         return None
@@ -177,8 +183,72 @@ def free_space_leg(runs: int) -> dict:
             "grid_point_updates_per_s": u0.numel() * prob.nsteps / wall, "ms_per_run": wall * 1e3,
             "roofline": {"bound": "hbm", "kernel": "free-space Adams row pass (k_fs_row)", "achieved": ach,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                         "traffic": measured_traffic("k_fs_row_2048_traffic.txt", FS_KERNEL_SOURCES),
                          "bytes_per_launch": row_b, "mean_launch_us": row_us, "row_pass_us": row_us,
                          "col_pass_us": col_us, "col_bytes_per_launch": col_b}}
+
+
+def batch_leg(runs: int) -> dict:
+    """Batched form on the 64-instance workload (seed 4000 + i; 32 1D with
+    M in {256..2048}, 32 2D with M in {128..512}^2; 500 steps, FP32-split,
+    stepwise field): autotuned schedules, graph-replayed whole runs, against
+    the same instances run one plan at a time; and the adjoint of every
+    instance's <x_1>(T) with respect to its 500 field samples."""
+    import numpy as np
+    import torch
+
+    from paper_2001_06113_amd.tdse import Q_BYTES_PER_STEP, BatchPlan, Plan
+    from workloads import c4_problems
+
+    dev = torch.device("cuda:0")
+    probs = c4_problems()
+    b = BatchPlan.from_problems(probs, device=dev)
+    t0 = time.perf_counter()
+    chosen = b.autotune(5)
+    tune_s = time.perf_counter() - t0
+    b.use_graph(True)
+    u0 = b.pack([p.u0 for p in probs])
+    out = b.run(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        out = b.run(u0, out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / runs
+    nsteps = probs[0].nsteps
+    value = b.total * nsteps / wall
+    bytes_step = b.query(Q_BYTES_PER_STEP)
+    # the same work one plan after another (each replayed from its own graph)
+    seq = 0.0
+    for p in probs:
+        pl = Plan.from_problem(p, device=dev)
+        pl.use_graph(True)
+        ui = torch.as_tensor(p.u0).to(dev)
+        oi = pl.run(ui)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pl.run(ui, oi)
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t1
+        pl.close()
+    # adjoint of <x_1>(T) for every instance, seeded from the batch output
+    lams = []
+    for p, uT in zip(probs, b.unpack(out)):
+        x = torch.as_tensor(-np.pi + 2 * np.pi * np.arange(p.M[0]) / p.M[0], device=dev)
+        w = float(np.prod([2 * np.pi / m for m in p.M]))
+        lams.append(2.0 * w * (x.reshape(-1, *([1] * (p.dim - 1)))) * uT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gAs, _ = b.adjoint(u0, lams)
+    adj_s = time.perf_counter() - t0
+    b.close()
+    return {"workload": "64 periodic instances (32 1D M=256..2048, 32 2D M=128^2..512^2), T=2, 500 steps AM8, "
+                        "FP32-split, stepwise A (config 4)",
+            "value": value, "unit": "mode-updates/s", "ms_per_run": wall * 1e3, "modes": int(b.total),
+            "algorithmic_GBps": bytes_step * nsteps / wall / 1e9,
+            "one_plan_at_a_time_value": b.total * nsteps / seq, "speedup_vs_one_plan_at_a_time": seq / wall,
+            "autotune_s": tune_s, "schedules_col_row": sorted(set(chosen)),
+            "adjoint_s_all_instances": adj_s, "adjoint_samples": int(sum(g.size for g in gAs))}
 
 
 def main():
@@ -277,6 +347,8 @@ def main():
         res["split"] = split_leg(args.split_steps)
     if not args.no_free:
         res["free_space"] = free_space_leg(args.free_runs)
+    if not args.no_batch:
+        res["batch"] = batch_leg(args.batch_runs)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     print(json.dumps(res), flush=True)
