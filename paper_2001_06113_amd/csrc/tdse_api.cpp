@@ -290,7 +290,7 @@ struct tdse_plan_s {
     double h = 0.0;
     std::vector<double2> zeta, w;      // nodes and weights, order E1 A1 C A3 E3
     std::vector<char> tables;          // pre3 pre1 ipost3 ipost1 [M], post3 post1 ipre3 ipre1 [NE],
-                                       // Dfwd [ND][M], Dinv [M][ND], tw [nu], zeta [N]
+                                       // Dfwd [ND][M], Dinv [ND][M], tw [nu], zeta [N]
     size_t o_tab = 0;                  // workspace offset of the tables
   } fx[2];
   int64_t NM = 1;                      // modes N1 N2
@@ -866,7 +866,7 @@ void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels) 
       Dfwd[(size_t)q2 * M + j] = double2{(double)(s2M * ef.x), (double)(s2M * ef.y)};
       const double2 eb = cexp_ld(-(LD)zz.y * x, (LD)zz.x * x);
       const LD wr = (LD)ww.x / (2.0L * PI), wi = (LD)ww.y / (2.0L * PI);
-      Dinv[(size_t)j * ND + q2] = double2{(double)(wr * eb.x - wi * eb.y), (double)(wr * eb.y + wi * eb.x)};
+      Dinv[(size_t)q2 * M + j] = double2{(double)(wr * eb.x - wi * eb.y), (double)(wr * eb.y + wi * eb.x)};
     }
   }
   for (int m = 0; m < nu; ++m) {
@@ -1151,6 +1151,8 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
     if (M < 8 || M % 2 || M > nu || NE <= M / 2) return fail(TDSE_EINVAL, "free space needs even M, M <= nu and N_E > M/2");
     plan_free_axis(p, a, M, nu, prob->q, prob->panels);
     if (p->fx[a].N > fs_max_modes(nu)) return fail(TDSE_EINVAL, "too many Gauss nodes for this nu (2p + 2 q panels > 90)");
+    if (fs_line_lds_bytes(nu, M, p->fx[a].ND) > 65536)
+      return fail(TDSE_EINVAL, "free-space line needs more than 64 KiB of LDS (M too large for this nu)");
   }
   p->NM = (int64_t)p->fx[0].N * p->fx[1].N;
   size_t off = 0;

@@ -85,7 +85,7 @@ struct CFAxis {
   const double2 *ipre3, *ipre1; // [NE] inverse pre-multipliers incl. w/(2 pi)
   const double2 *ipost3, *ipost1; // [M] inverse post-multipliers
   const double2* Dfwd;          // [ND][M] (2/M) exp(-i zeta_q x_j)
-  const double2* Dinv;          // [M][ND] (w_q/2pi) exp(i zeta_q x_j)
+  const double2* Dinv;          // [ND][M] (w_q/2pi) exp(i zeta_q x_j)
   const double2* tw;            // nu-point twiddles
   const double2* zeta;          // [N] nodes (for the phase factors)
 };
@@ -200,6 +200,7 @@ hipError_t launch_fs_col(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0 =
 hipError_t launch_fs_phase(const FSArgs& a, hipStream_t s);
 bool fs_nu_supported(int nu);
 int fs_max_modes(int nu);
+size_t fs_line_lds_bytes(int nu, int M, int ND);   // dynamic LDS of a line workgroup
 
 // Launchers (periodic_kernels.hip).  Non-null events e0/e1 are recorded at
 // the kernel's own start and end.  Return a hipError_t.
