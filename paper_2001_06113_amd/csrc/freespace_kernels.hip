@@ -187,8 +187,11 @@ __device__ __forceinline__ double2 fs_mode_update(const FSArgs& a, int k1, int p
 
 // ---------------------------------------------------------------- row pass
 
+// Three workgroups per CU (a register budget of 168; the few values that
+// spill cost less than the latency a third wave per SIMD hides in the
+// per-mode updates).
 template <int NU>
-__global__ __launch_bounds__(NU / 8) void k_fs_row(FSArgs a) {
+__global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_fs_row(FSArgs a) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
   HIP_DYNAMIC_SHARED(double2, fs_lds)
