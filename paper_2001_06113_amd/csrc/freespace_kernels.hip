@@ -59,48 +59,70 @@ __device__ __forceinline__ void build_phase_table_fs(const FSArgs& a, int nthrea
 }
 
 // Line transforms with the ray modes in registers.  Thread t holds, for
-// e = t + TL m (m < EPT = 8): v3[m] = mode N - N_E + e (E3 ray) and
-// v1[m] = mode N_E - 1 - e (E1 ray), zero for e >= N_E, which is the layout
-// the nu-point FFT leaves them in; the N_D dense modes N_E + q live in LDS
-// (dm).  The dense block's forward sums are split over (mode, chunk) pairs
-// and reduced through LDS (part, N_D * max(1, TL / N_D) entries).
+// e = t + TL m: v3[m] = mode N - N_E + e (E3 ray) and v1[m] = mode N_E - 1 - e
+// (E1 ray), zero for e >= N_E, which is the layout the nu-point FFT leaves
+// them in.  N_E = nu/2 - 13 < nu/2 = 4 TL, so only m < RAY = 4 can hold a
+// ray mode: the rays are carried as four values per thread, and the other
+// four FFT slots are compile-time zeros going into the inverse FFTs.  The
+// N_D dense modes N_E + q live in LDS (dm).  The dense block's forward sums
+// are split over (mode, chunk) pairs and reduced through LDS (part,
+// N_D * max(1, TL / N_D) entries).
+constexpr int RAY = 4;
 
 // forward transform of f[0..M) (LDS); ends with dm complete (a barrier)
 template <int NU>
-__device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[8], double2 (&v1)[8], double2* dm,
+__device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY], double2 (&v1)[RAY], double2* dm,
                                            double2* part, double2* fline, const CFAxis& ax, int t) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
   const int M = ax.M, NE = ax.NE, ND = ax.ND;
+  // Table reads use an in-range twin index (min(e, n - 1)) and the result is
+  // selected afterwards, so they carry no branch and issue together.
+  double2 w[EPT];
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
-    const int e = t + TL * m;
-    v3[m] = e < M ? cmul(ax.pre3[e], f[e]) : double2{0.0, 0.0};
+    const int e = t + TL * m, ec = min(e, M - 1);
+    const double2 x = cmul(ax.pre3[ec], f[ec]);
+    w[m] = e < M ? x : double2{0.0, 0.0};
   }
-  fft_regs<NU, TL, false>(v3, t, fline, ax.tw);
+  fft_regs<NU, TL, false>(w, t, fline, ax.tw);
+#pragma unroll
+  for (int m = 0; m < RAY; ++m) {
+    const int e = t + TL * m;
+    const double2 x = cmul(ax.post3[min(e, NE - 1)], w[m]);
+    v3[m] = e < NE ? x : double2{0.0, 0.0};
+  }
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
-    const int e = t + TL * m;
-    v3[m] = e < NE ? cmul(ax.post3[e], v3[m]) : double2{0.0, 0.0};
+    const int e = t + TL * m, ec = min(e, M - 1);
+    const double2 x = cmul(ax.pre1[ec], f[ec]);
+    w[m] = e < M ? x : double2{0.0, 0.0};
   }
+  fft_regs<NU, TL, true>(w, t, fline, ax.tw);
 #pragma unroll
-  for (int m = 0; m < EPT; ++m) {
+  for (int m = 0; m < RAY; ++m) {
     const int e = t + TL * m;
-    v1[m] = e < M ? cmul(ax.pre1[e], f[e]) : double2{0.0, 0.0};
+    const double2 x = cmul(ax.post1[min(e, NE - 1)], w[m]);
+    v1[m] = e < NE ? x : double2{0.0, 0.0};
   }
-  fft_regs<NU, TL, true>(v1, t, fline, ax.tw);
-#pragma unroll
-  for (int m = 0; m < EPT; ++m) {
-    const int e = t + TL * m;
-    v1[m] = e < NE ? cmul(ax.post1[e], v1[m]) : double2{0.0, 0.0};
-  }
-  // dense modes: thread (q, c) sums j = c, c + C, ... (lanes of one q read consecutive j)
+  // dense modes: thread (q, c) sums j = c, c + C, ... (lanes of one q read
+  // consecutive j), DB matrix entries per batch of loads
+  constexpr int DB = 4;
   const int C = TL / ND > 1 ? TL / ND : 1;
   for (int i = t; i < ND * C; i += TL) {   // more dense modes than threads: several pairs per thread
     const int q = i / C, c = i - q * C;
     const double2* row = ax.Dfwd + (int64_t)q * M;
     double2 acc = {0.0, 0.0};
-    for (int j = c; j < M; j += C) acc = cadd(acc, cmul(row[j], f[j]));
+    for (int j0 = c; j0 < M; j0 += DB * C) {
+      double2 d[DB];
+#pragma unroll
+      for (int u = 0; u < DB; ++u) d[u] = row[min(j0 + u * C, M - 1)];
+#pragma unroll
+      for (int u = 0; u < DB; ++u) {
+        const int j = j0 + u * C;
+        if (j < M) acc = cadd(acc, cmul(d[u], f[j]));
+      }
+    }
     part[i] = acc;
   }
   __syncthreads();
@@ -112,34 +134,60 @@ __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[8], d
   __syncthreads();
 }
 
-// inverse transform of the modes (v3, v1 registers, dm LDS) into
-// out[m] = u(t + TL m) for t + TL m < M; v3 and v1 are overwritten
+// inverse transform of the modes (v3, v1 registers, dm LDS) into u[0..M)
+// (LDS); thread t writes u[t + TL m] only, so it may read those entries back
+// without a barrier
 template <int NU>
-__device__ __forceinline__ void cf_inverse(double2 (&v3)[8], double2 (&v1)[8], const double2* dm, double2* fline,
-                                           const CFAxis& ax, int t, double2 (&out)[8]) {
+__device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const double2 (&v1)[RAY], const double2* dm,
+                                           double2* fline, const CFAxis& ax, int t, double2* u) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
   const int M = ax.M, NE = ax.NE, ND = ax.ND;
+  double2 w[EPT];
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     const int e = t + TL * m;
-    v3[m] = e < NE ? cmul(ax.ipre3[e], v3[m]) : double2{0.0, 0.0};
+    if (m < RAY) {
+      const double2 x = cmul(ax.ipre3[min(e, NE - 1)], v3[m < RAY ? m : 0]);
+      w[m] = e < NE ? x : double2{0.0, 0.0};
+    } else {
+      w[m] = double2{0.0, 0.0};
+    }
   }
-  fft_regs<NU, TL, true>(v3, t, fline, ax.tw);
+  fft_regs<NU, TL, true>(w, t, fline, ax.tw);
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     const int e = t + TL * m;
-    out[m] = e < M ? cmul(ax.ipost3[e], v3[m]) : double2{0.0, 0.0};
-    v1[m] = e < NE ? cmul(ax.ipre1[e], v1[m]) : double2{0.0, 0.0};
+    if (e < M) u[e] = cmul(ax.ipost3[e], w[m]);
   }
-  fft_regs<NU, TL, false>(v1, t, fline, ax.tw);
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) {
+    const int e = t + TL * m;
+    if (m < RAY) {
+      const double2 x = cmul(ax.ipre1[min(e, NE - 1)], v1[m < RAY ? m : 0]);
+      w[m] = e < NE ? x : double2{0.0, 0.0};
+    } else {
+      w[m] = double2{0.0, 0.0};
+    }
+  }
+  fft_regs<NU, TL, false>(w, t, fline, ax.tw);
+  // E1 part, then the dense modes in batches of DB matrix entries
+  constexpr int DB = 8;
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     const int e = t + TL * m;
     if (e < M) {
-      double2 s = cadd(out[m], cmul(ax.ipost1[e], v1[m]));
-      for (int q = 0; q < ND; ++q) s = cadd(s, cmul(ax.Dinv[(int64_t)q * M + e], dm[q]));
-      out[m] = s;
+      double2 s = cadd(u[e], cmul(ax.ipost1[e], w[m]));
+      for (int q0 = 0; q0 < ND; q0 += DB) {
+        double2 d[DB];
+#pragma unroll
+        for (int u8 = 0; u8 < DB; ++u8) d[u8] = ax.Dinv[(int64_t)min(q0 + u8, ND - 1) * M + e];
+#pragma unroll
+        for (int u8 = 0; u8 < DB; ++u8) {
+          if (q0 + u8 < ND) s = cadd(s, cmul(d[u8], dm[q0 + u8]));
+        }
+      }
+      u[e] = s;
     }
   }
 }
@@ -152,22 +200,31 @@ size_t fs_lds_bytes(int M, int ND) {
 }
 
 // The per-mode step of the row pass for mode g = row_m + k; W is the mode of
-// the forward transform (R_AM, R_UHACC).  Returns the new B (R_UHACC: unused).
-__device__ __forceinline__ double2 fs_mode_update(const FSArgs& a, int k1, int per, int k, int64_t g, double2 W) {
+// the forward transform (R_AM, R_UHACC).  T1[j-1] is the row's axis-0 factor
+// of E^(j).  Returns the new B (R_UHACC: unused).  The history terms are
+// unrolled, so a mode's loads are issued together.
+__device__ __forceinline__ double2 fs_mode_update(const FSArgs& a, const double2 (&T1)[MAXH], int per, int k,
+                                                  int64_t g, double2 W) {
   const int mode = a.mode;
-  const double2* ph = a.ph;
+  const double2* __restrict__ ph = a.ph;
+  const double2* __restrict__ ring = a.ring;
   const int N1 = a.N1;
-  // E^(j) = T1_j[k1] T2_j[k]; the first factor is uniform over the workgroup
-  auto E = [ph, per, N1, k1, k](int j) { return cmul(ph[(j - 1) * per + k1], ph[(j - 1) * per + N1 + k]); };
+  const int nh = a.nh;
+  const int64_t rs = a.ring_stride;
+  // E^(j) = T1_j[k1] T2_j[k]
+  auto E = [ph, per, N1, k, &T1](int j) { return cmul(T1[j - 1], ph[(j - 1) * per + N1 + k]); };
   double2 acc;
   if (mode == R_AM) {
     const double2 uh = cadd(a.Bm[g], fs_mul_mi(a.c0, W));
     acc = cmul(E(1), cadd(uh, fs_mul_mi(a.ch[1], W)));
-    for (int j = 2; j <= a.nh; ++j) acc = cadd(acc, cmul(E(j), fs_mul_mi(a.ch[j], a.ring[a.slot_r[j] * a.ring_stride + g])));
-    if (a.slot_w >= 0) a.ring[a.slot_w * a.ring_stride + g] = W;
+#pragma unroll
+    for (int j = 2; j < MAXH; ++j) {
+      if (j <= nh) acc = cadd(acc, cmul(E(j), fs_mul_mi(a.ch[j], ring[a.slot_r[j] * rs + g])));
+    }
+    if (a.slot_w >= 0) a.ring[a.slot_w * rs + g] = W;
     a.Bm[g] = acc;
   } else if (mode == R_BINIT) {
-    const double2 Wr = a.ring[a.slot_r[1] * a.ring_stride + g];
+    const double2 Wr = ring[a.slot_r[1] * rs + g];
     acc = cmul(E(1), cadd(a.UH[g], fs_mul_mi(a.c0, Wr)));
     a.Bm[g] = acc;
   } else if (mode == R_UHACC) {
@@ -179,7 +236,10 @@ __device__ __forceinline__ double2 fs_mode_update(const FSArgs& a, int k1, int p
     acc = s;
   } else {  // R_FORM
     acc = cmul(E(1), a.UH[g]);
-    for (int j = 1; j <= a.nh; ++j) acc = cadd(acc, cmul(E(j), fs_mul_mi(a.ch[j], a.ring[a.slot_r[j] * a.ring_stride + g])));
+#pragma unroll
+    for (int j = 1; j < MAXH; ++j) {
+      if (j <= nh) acc = cadd(acc, cmul(E(j), fs_mul_mi(a.ch[j], ring[a.slot_r[j] * rs + g])));
+    }
     a.Bm[g] = acc;
   }
   return acc;
@@ -191,7 +251,7 @@ __device__ __forceinline__ double2 fs_mode_update(const FSArgs& a, int k1, int p
 // spill cost less than the latency a third wave per SIMD hides in the
 // per-mode updates).
 template <int NU>
-__global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_fs_row(FSArgs a) {
+__global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_fs_row(FSArgs a) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
   HIP_DYNAMIC_SHARED(double2, fs_lds)
@@ -208,7 +268,7 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(3, 8))) 
   const int64_t row_m = (int64_t)k1 * N2;   // mode row
   const int64_t row_p = (int64_t)k1 * M2;   // tile row (physical axis 1)
 
-  double2 v3[EPT], v1[EPT];
+  double2 v3[RAY], v1[RAY];
   const bool need_fwd = (mode == R_AM || mode == R_FWD || mode == R_UHACC);
   if (need_fwd) {
     for (int j = t; j < M2; j += TL) fin[j] = a.src[row_p + j];
@@ -216,11 +276,11 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     cf_forward<NU>(fin, v3, v1, dm, part, fline, ax, t);
   } else {
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) v3[m] = v1[m] = double2{0.0, 0.0};
+    for (int m = 0; m < RAY; ++m) v3[m] = v1[m] = double2{0.0, 0.0};
   }
   if (mode == R_FWD) {
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) {
+    for (int m = 0; m < RAY; ++m) {
       const int e = t + TL * m;
       if (e < NE) {
         a.fdst[row_m + N2 - NE + e] = v3[m];
@@ -230,25 +290,134 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(3, 8))) 
     for (int q = t; q < ND; q += TL) a.fdst[row_m + NE + q] = dm[q];
     return;
   }
+  // the row's axis-0 factors of E^(j) (uniform over the workgroup)
+  double2 T1[MAXH];
+  const int nj = (mode == R_AM || mode == R_FORM) ? a.nh : (mode == R_BINIT ? 1 : 0);
 #pragma unroll
-  for (int m = 0; m < EPT; ++m) {
-    const int e = t + TL * m;
-    if (e < NE) {
-      v3[m] = fs_mode_update(a, k1, per, N2 - NE + e, row_m + N2 - NE + e, v3[m]);
-      v1[m] = fs_mode_update(a, k1, per, NE - 1 - e, row_m + NE - 1 - e, v1[m]);
+  for (int j = 1; j <= MAXH; ++j) T1[j - 1] = j <= nj ? a.ph[(j - 1) * per + k1] : double2{0.0, 0.0};
+  if (mode == R_AM) {
+    // The ray modes' Adams step, history term by history term over all of
+    // the thread's modes.  The new history entry What_n goes to its ring slot
+    // first (no history term reads that slot); B is stored after the last
+    // load.  Lanes past the end of a ray load their ray's last mode and store
+    // nothing.
+    const double2* __restrict__ ph = a.ph;
+    const double2* __restrict__ ring = a.ring;
+    const int64_t rs = a.ring_stride;
+    const int nh = a.nh;
+    const int N1 = a.N1;
+    int k3[RAY], k1r[RAY];
+    double2 acc3[RAY], acc1[RAY];
+#pragma unroll
+    for (int m = 0; m < RAY; ++m) {
+      const int ec = min(t + TL * m, NE - 1);
+      k3[m] = N2 - NE + ec;
+      k1r[m] = NE - 1 - ec;
+      const double2 B3 = a.Bm[row_m + k3[m]], B1 = a.Bm[row_m + k1r[m]];
+      const double2 E3 = cmul(T1[0], ph[N1 + k3[m]]), E1 = cmul(T1[0], ph[N1 + k1r[m]]);
+      // E^(1) (uhat - i dt mu_1 W),  uhat = B - i dt mu_0 W
+      acc3[m] = cmul(E3, cadd(cadd(B3, fs_mul_mi(a.c0, v3[m])), fs_mul_mi(a.ch[1], v3[m])));
+      acc1[m] = cmul(E1, cadd(cadd(B1, fs_mul_mi(a.c0, v1[m])), fs_mul_mi(a.ch[1], v1[m])));
+      if (a.slot_w >= 0 && t + TL * m < NE) {
+        a.ring[a.slot_w * rs + row_m + k3[m]] = v3[m];
+        a.ring[a.slot_w * rs + row_m + k1r[m]] = v1[m];
+      }
+    }
+    // history terms j >= 2 in batches b = (j, ray): the history modes and
+    // phase factors of batch b+1 are loaded while batch b is summed
+    double2 w[2][RAY], pf[2][RAY];
+    auto load = [&](int b) {
+      const int j = 2 + (b >> 1);
+      const double2* __restrict__ rj = ring + a.slot_r[j] * rs + row_m;
+      const double2* __restrict__ pj = ph + (j - 1) * per + N1;
+#pragma unroll
+      for (int m = 0; m < RAY; ++m) {
+        const int kk = (b & 1) ? k1r[m] : k3[m];
+        w[b & 1][m] = rj[kk];
+        pf[b & 1][m] = pj[kk];
+      }
+    };
+    auto use = [&](int b) {
+      const int j = 2 + (b >> 1);
+#pragma unroll
+      for (int m = 0; m < RAY; ++m) {
+        const double2 x = fs_mul_mi(a.ch[j], cmul(cmul(T1[j - 1], pf[b & 1][m]), w[b & 1][m]));
+        if (b & 1) acc1[m] = cadd(acc1[m], x);
+        else acc3[m] = cadd(acc3[m], x);
+      }
+    };
+    if (nh == MAXH - 1) {   // the full order-8 history: straight-line, software-pipelined
+      constexpr int NB = 2 * (MAXH - 2);
+      load(0);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        if (b + 1 < NB) load(b + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        use(b);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < 2 * (MAXH - 2); ++b) {
+        if (2 + (b >> 1) <= nh) {
+          load(b);
+          __builtin_amdgcn_sched_barrier(0);
+          use(b);
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < RAY; ++m) {
+      const bool live = t + TL * m < NE;
+      if (live) {
+        a.Bm[row_m + k3[m]] = acc3[m];
+        a.Bm[row_m + k1r[m]] = acc1[m];
+      }
+      v3[m] = live ? acc3[m] : double2{0.0, 0.0};
+      v1[m] = live ? acc1[m] : double2{0.0, 0.0};
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < RAY; ++m) {
+      const int e = t + TL * m;
+      if (e < NE) {
+        v3[m] = fs_mode_update(a, T1, per, N2 - NE + e, row_m + N2 - NE + e, v3[m]);
+        v1[m] = fs_mode_update(a, T1, per, NE - 1 - e, row_m + NE - 1 - e, v1[m]);
+      }
     }
   }
-  for (int q = t; q < ND; q += TL)
-    dm[q] = fs_mode_update(a, k1, per, NE + q, row_m + NE + q, need_fwd ? dm[q] : double2{0.0, 0.0});
+  if (mode == R_AM && a.nh == MAXH - 1) {
+    // dense modes, one per thread: every load of the mode issued together
+    const double2* __restrict__ ph = a.ph;
+    const double2* __restrict__ ring = a.ring;
+    const int64_t rs = a.ring_stride;
+    const int N1 = a.N1;
+    for (int q = t; q < ND; q += TL) {
+      const int k = NE + q;
+      const int64_t g = row_m + k;
+      const double2 W = dm[q];
+      double2 pf[MAXH - 1], wh[MAXH - 2];
+      const double2 B = a.Bm[g];
+#pragma unroll
+      for (int j = 1; j < MAXH; ++j) pf[j - 1] = ph[(j - 1) * per + N1 + k];
+#pragma unroll
+      for (int j = 2; j < MAXH; ++j) wh[j - 2] = ring[a.slot_r[j] * rs + g];
+      __builtin_amdgcn_sched_barrier(0);
+      double2 acc = cmul(cmul(T1[0], pf[0]), cadd(cadd(B, fs_mul_mi(a.c0, W)), fs_mul_mi(a.ch[1], W)));
+#pragma unroll
+      for (int j = 2; j < MAXH; ++j) acc = cadd(acc, fs_mul_mi(a.ch[j], cmul(cmul(T1[j - 1], pf[j - 1]), wh[j - 2])));
+      if (a.slot_w >= 0) a.ring[a.slot_w * rs + g] = W;
+      a.Bm[g] = acc;
+      dm[q] = acc;
+    }
+  } else {
+    for (int q = t; q < ND; q += TL)
+      dm[q] = fs_mode_update(a, T1, per, NE + q, row_m + NE + q, need_fwd ? dm[q] : double2{0.0, 0.0});
+  }
   if (mode == R_UHACC) return;
   __syncthreads();
-  double2 out[EPT];
-  cf_inverse<NU>(v3, v1, dm, fline, ax, t, out);
-#pragma unroll
-  for (int m = 0; m < EPT; ++m) {
-    const int e = t + TL * m;
-    if (e < M2) a.dst[row_p + e] = out[m];
-  }
+  cf_inverse<NU>(v3, v1, dm, fline, ax, t, fin);   // the forward input is no longer needed
+  for (int e = t; e < M2; e += TL) a.dst[row_p + e] = fin[e];
 }
 
 // ------------------------------------------------------------- column pass
@@ -278,28 +447,28 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
   const int mode = a.mode;
 
   if (a.req.nj > 0) build_phase_table_fs(a, TL);
-  double2 v3[EPT], v1[EPT];
+  double2 v3[RAY], v1[RAY];
   if (mode == C_SOLVE) {
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) {
+    for (int m = 0; m < RAY; ++m) {
       const int e = t + TL * m;
       v3[m] = e < NE ? a.src[(int64_t)(N1 - NE + e) * M2 + y] : double2{0.0, 0.0};
       v1[m] = e < NE ? a.src[(int64_t)(NE - 1 - e) * M2 + y] : double2{0.0, 0.0};
     }
     for (int q = t; q < ND; q += TL) dm[q] = a.src[(int64_t)(NE + q) * M2 + y];
     __syncthreads();
-    double2 w[EPT];
-    cf_inverse<NU>(v3, v1, dm, fline, ax, t, w);
+    cf_inverse<NU>(v3, v1, dm, fline, ax, t, fin);   // w = F^-1 B on the column, in place of the forward input
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
       const int e = t + TL * m;
       if (e < M1) {
+        const double2 wv = fin[e];
         const int64_t g = (int64_t)e * M2 + y;
         double Vs = 0.0;
         for (int r = 0; r < a.nV; ++r) Vs += a.fV[r] * a.V[r * a.vstride + g];
         const double q = a.csolve * Vs;
         const double inv = 1.0 / (1.0 + q * q);
-        const double2 u = double2{(w[m].x + q * w[m].y) * inv, (w[m].y - q * w[m].x) * inv};
+        const double2 u = double2{(wv.x + q * wv.y) * inv, (wv.y - q * wv.x) * inv};
         if (a.uout) a.uout[g] = u;
         if (a.uacc) {
           double2 s = a.acc_first ? double2{0.0, 0.0} : a.uacc[g];
@@ -323,7 +492,7 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
   __syncthreads();
   cf_forward<NU>(fin, v3, v1, dm, part, fline, ax, t);
 #pragma unroll
-  for (int m = 0; m < EPT; ++m) {
+  for (int m = 0; m < RAY; ++m) {
     const int e = t + TL * m;
     if (e < NE) {
       a.dst[(int64_t)(N1 - NE + e) * M2 + y] = v3[m];

@@ -1150,6 +1150,8 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
     const int NE = nu / 2 - 13;
     if (M < 8 || M % 2 || M > nu || NE <= M / 2) return fail(TDSE_EINVAL, "free space needs even M, M <= nu and N_E > M/2");
     plan_free_axis(p, a, M, nu, prob->q, prob->panels);
+    // the line kernels carry each ray in the first half of the nu-point FFT
+    if (p->fx[a].NE >= nu / 2) return fail(TDSE_EINVAL, "ray modes must number fewer than nu/2");
     if (p->fx[a].N > fs_max_modes(nu)) return fail(TDSE_EINVAL, "too many Gauss nodes for this nu (2p + 2 q panels > 90)");
     if (fs_line_lds_bytes(nu, M, p->fx[a].ND) > 65536)
       return fail(TDSE_EINVAL, "free-space line needs more than 64 KiB of LDS (M too large for this nu)");

@@ -37,6 +37,8 @@ extern dim3 blockDim, gridDim;
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
+// scheduling hints of the GPU compiler have no meaning on the CPU
+inline void __builtin_amdgcn_sched_barrier(int) {}
 #define __shared__ static
 #define __restrict__
 
