@@ -70,7 +70,8 @@ __device__ __forceinline__ C mul_mi(double c, C z) {
 }
 
 // Per-axis phase table of the next row pass, spread over the nblk workgroups
-// of the instance's column pass (blk = this workgroup's index), FP64.
+// of the instance's column pass (blk = this workgroup's index), FP64, and
+// rounded to complex64 into ph32 for the split form.
 __device__ __forceinline__ void build_phase_table(const LineArgs& a, int nthreads, int blk, int nblk) {
   const int per = a.M1 + a.M2;
   const int total = a.req.nj * per;
@@ -89,6 +90,7 @@ __device__ __forceinline__ void build_phase_table(const LineArgs& a, int nthread
     double s, c;
     sincos(th, &s, &c);
     a.ph[idx] = double2{c, s};
+    if (a.ph32) a.ph32[idx] = float2{(float)c, (float)s};
   }
 }
 
@@ -133,41 +135,89 @@ __device__ __forceinline__ void col_body(const LineArgs& a, int line0, int blk, 
   C v[EPT];
   double2 u0[EPT];   // C_FWD reads the complex128 physical solution
   double vv[EPT];
+  // tile loads first, then one batch of EPT potential loads per field, so
+  // that each batch is a single round trip
+  const int64_t g0 = (int64_t)line * a.line_stride + (int64_t)t * a.elem_stride;
+  const int64_t gs = (int64_t)TL * a.elem_stride;
+  // loads in the order of first use (they complete in order): twiddles,
+  // tile, then the potential, which is needed only after the first FFT
+  constexpr int TWN = TWL ? (N + NT - 1) / NT : 1;
+  C twr[TWN];
+  if constexpr (TWL) {
+#pragma unroll
+    for (int k = 0; k < TWN; ++k) {
+      const int q = tid + k * NT;
+      if (N % NT == 0 || q < N) twr[k] = ((const C*)a.tw)[q];
+    }
+  }
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     v[m] = C{0, 0};
     u0[m] = double2{0.0, 0.0};
     vv[m] = 0.0;
-    if (active) {
-      const int64_t g = (int64_t)line * a.line_stride + (int64_t)(t + TL * m) * a.elem_stride;
-      if (mode == C_FWD) u0[m] = ((const double2*)a.src)[g];
-      else v[m] = ((const C*)a.src)[g];
-      double p = 0.0;
-      for (int r = 0; r < a.nV; ++r) p += a.fV[r] * V[r * a.vstride + g];
-      vv[m] = p;
+  }
+  // In FP64 the tile and the physical solution have one element type: one
+  // load serves both modes (a per-mode choice between two loaded copies
+  // would wait for the data at once)
+  constexpr bool F64 = sizeof(C) == sizeof(double2);
+  if (active) {
+    if (F64 || mode != C_FWD) {
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) v[m] = ((const C*)a.src)[g0 + m * gs];
+    } else {
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) u0[m] = ((const double2*)a.src)[g0 + m * gs];
     }
   }
   if constexpr (TWL) {
-    for (int q = tid; q < N; q += NT) twl[q] = ((const C*)a.tw)[q];
+#pragma unroll
+    for (int k = 0; k < TWN; ++k) {
+      const int q = tid + k * NT;
+      if (N % NT == 0 || q < N) twl[q] = twr[k];
+    }
   }
-  if (a.req.nj > 0) build_phase_table(a, NT, blk, nblk);
+  // potential: the first field's loads stay in flight through the first
+  // FFT (its product is formed at first use); further fields, if any, are
+  // summed into vv just before the pointwise step
+  double v0[EPT];
+  const double f0 = a.nV > 0 ? a.fV[0] : 0.0;
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) v0[m] = 0.0;
+  if (active && a.nV > 0) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v0[m] = V[g0 + m * gs];
+  }
+  auto more_fields = [&]() {
+    if (!active) return;
+    for (int r = 1; r < a.nV; ++r) {
+      double vr[EPT];
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) vr[m] = V[r * a.vstride + g0 + m * gs];
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) vv[m] += a.fV[r] * vr[m];
+    }
+  };
   if constexpr (TWL) __syncthreads();
   const C* tw = TWL ? twl : (const C*)a.tw;
   C* myline = &lds[i * PITCH];
 
   if (mode == C_FWD) {
+    more_fields();
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
-      const double cr = a.alpha_re + a.beta_re * vv[m], ci = a.alpha_im + a.beta_im * vv[m];
-      const double2 u = u0[m];
+      const double Vs = vv[m] + f0 * v0[m];
+      const double cr = a.alpha_re + a.beta_re * Vs, ci = a.alpha_im + a.beta_im * Vs;
+      const double2 u = F64 ? to_d(v[m]) : u0[m];
       v[m] = from_d<C>(double2{(cr * u.x - ci * u.y) * a.scale, (cr * u.y + ci * u.x) * a.scale});
     }
   } else {  // C_SOLVE
     fft_regs<N, TL, true>(v, t, myline, tw);
+    more_fields();
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
       const C w = v[m];
-      const R q = (R)(a.csolve * vv[m]);
+      const double Vs = vv[m] + f0 * v0[m];
+      const R q = (R)(a.csolve * Vs);
       const R inv = R(1) / (R(1) + q * q);
       // u = w (1 - i q) / (1 + q^2)
       const C u = C{(w.x + q * w.y) * inv, (w.y - q * w.x) * inv};
@@ -182,7 +232,7 @@ __device__ __forceinline__ void col_body(const LineArgs& a, int line0, int blk, 
           a.uacc[g] = acc;
         }
       }
-      const R s = (R)(vv[m] * a.scale);
+      const R s = (R)(Vs * a.scale);
       v[m] = C{s * u.x, s * u.y};
     }
   }
@@ -194,6 +244,8 @@ __device__ __forceinline__ void col_body(const LineArgs& a, int line0, int blk, 
       ((C*)a.dst)[g] = v[m];
     }
   }
+  // last, so that its loads and waits delay none of the pass's own
+  if (a.req.nj > 0) build_phase_table(a, NT, blk, nblk);
 }
 
 
@@ -237,13 +289,55 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
   C v[EPT];
   double2 Bp[EPT];
   C Wr[PF ? NH - 1 : 1][EPT];
-  double2 E1[EPT];               // E^(1) in FP64 (multiplies uhat)
+  // E^(1) = T1[0] P1 in FP64 (it multiplies uhat), formed only after the
+  // forward FFT: a product taken here would wait for its loads, and loads
+  // complete in order, so for every load issued before them
+  double2 P1[EPT];
   C T2[PF ? NH - 1 : 1][EPT];    // axis-2 factors of E^(j), j >= 2, transform precision
   double2 T1[NH];
+  constexpr bool F64 = sizeof(C) == sizeof(double2);
+  // Loads are issued in the order their values are first needed, since
+  // they complete in order: twiddles (staged into LDS), the row factors T1
+  // (uniform along the row), the tile, then B, the history and the axis-2
+  // factors, which are used only after the forward FFT.
+  constexpr int TWN = TWL ? (N + NT - 1) / NT : 1;
+  C twr[TWN];
+  if constexpr (TWL) {
 #pragma unroll
-  for (int m = 0; m < EPT; ++m) {
-    v[m] = C{0, 0};
-    if (active) v[m] = (mode == R_INV) ? from_d<C>(a.Bm[row0 + (t + TL * m)]) : src[row0 + (t + TL * m)];
+    for (int i = 0; i < TWN; ++i) {
+      const int q = tid + i * NT;
+      if (N % NT == 0 || q < N) twr[i] = ((const C*)a.tw)[q];
+    }
+  }
+  const bool phases = active && mode != R_FWD && mode != R_INV;
+  const int nj = (mode == R_INIT) ? 1 : nh;
+  if (phases) {
+    // unconditional (entries past nj repeat entry nj and go unused), so the
+    // loads share one block and one wait
+    const int njc = nj > 1 ? nj : 1;
+#pragma unroll
+    for (int j = 1; j <= NH; ++j) T1[j - 1] = ph[((j < njc ? j : njc) - 1) * per + k1];
+  }
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) v[m] = C{0, 0};
+  if (active) {
+    // one loop per source: a per-element choice would wait for the data
+    if (mode == R_INV) {
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) v[m] = from_d<C>(a.Bm[row0 + (t + TL * m)]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) v[m] = src[row0 + (t + TL * m)];
+    }
+  }
+  // twiddles into LDS before the later loads are issued: waiting for them
+  // then never waits for those
+  if constexpr (TWL) {
+#pragma unroll
+    for (int i = 0; i < TWN; ++i) {
+      const int q = tid + i * NT;
+      if (N % NT == 0 || q < N) twl[q] = twr[i];
+    }
   }
   if (active && mode == R_AM) {
 #pragma unroll
@@ -258,18 +352,17 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
       }
     }
   }
-  if (active && mode != R_FWD && mode != R_INV) {
-    const int nj = (mode == R_INIT) ? 1 : nh;
-    T1[0] = ph[k1];
+  if (phases) {
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) E1[m] = cmul(T1[0], ph[M1 + (t + TL * m)]);
+    for (int m = 0; m < EPT; ++m) P1[m] = ph[M1 + (t + TL * m)];
+    if constexpr (PF) {
+      // the split form reads the complex64 copy: no conversion waits here
+      const C* __restrict__ tpj = F64 ? (const C*)ph : (const C*)a.ph32;
 #pragma unroll
-    for (int j = 2; j <= NH; ++j) {
-      if (j <= nj) {
-        T1[j - 1] = ph[(j - 1) * per + k1];
-        if constexpr (PF) {
+      for (int j = 2; j <= NH; ++j) {
+        if (j <= nj) {
 #pragma unroll
-          for (int m = 0; m < EPT; ++m) T2[j - 2][m] = from_d<C>(ph[(j - 1) * per + M1 + (t + TL * m)]);
+          for (int m = 0; m < EPT; ++m) T2[j - 2][m] = tpj[(j - 1) * per + M1 + (t + TL * m)];
         }
       }
     }
@@ -285,10 +378,7 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
     if constexpr (PF) return Wr[j - 2][m];
     else return ring[slot_r[j] * rstride + row0 + (t + TL * m)];
   };
-  if constexpr (TWL) {
-    for (int q = tid; q < N; q += NT) twl[q] = ((const C*)a.tw)[q];
-    __syncthreads();
-  }
+  if constexpr (TWL) __syncthreads();
   const C* tw = TWL ? twl : (const C*)a.tw;
   C* myline = &lds[i * PITCH];
 
@@ -314,7 +404,7 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
       const C W = v[m];
       const double2 Wd = to_d(W);
       const double2 uh = cadd(Bp[m], mul_mi(a.c0, Wd));
-      double2 acc = cmul(E1[m], cadd(uh, mul_mi(a.ch[1], Wd)));
+      double2 acc = cmul(cmul(T1[0], P1[m]), cadd(uh, mul_mi(a.ch[1], Wd)));
       // products E^(j) What in the transform precision, weighted by dt mu_j
       // and summed in FP64
       double2 hist = double2{0.0, 0.0};
@@ -331,16 +421,17 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
   } else if (mode == R_INIT) {
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
-      const double2 acc = cmul(E1[m], to_d(v[m]));
+      const double2 acc = cmul(cmul(T1[0], P1[m]), to_d(v[m]));
       a.Bm[row0 + (t + TL * m)] = acc;
       v[m] = from_d<C>(acc);
     }
   } else {  // R_FORM: B from uhat (this FFT) and nh history terms, all from the ring
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
-      double2 acc = cmul(E1[m], to_d(v[m]));
+      const double2 E1 = cmul(T1[0], P1[m]);
+      double2 acc = cmul(E1, to_d(v[m]));
       const int64_t g = row0 + (t + TL * m);
-      acc = cadd(acc, cmul(E1[m], mul_mi(a.ch[1], to_d(ring[slot_r[1] * rstride + g]))));
+      acc = cadd(acc, cmul(E1, mul_mi(a.ch[1], to_d(ring[slot_r[1] * rstride + g]))));
       double2 hist = double2{0.0, 0.0};
 #pragma unroll
       for (int j = 2; j <= NH; ++j) {  // static j: registers stay registers

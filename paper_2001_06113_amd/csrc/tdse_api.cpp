@@ -279,7 +279,7 @@ struct tdse_plan_s {
     std::vector<char> Vhost, tw1, tw2;   // host copies uploaded at bind
   } st[2];
   // workspace layout
-  size_t o_B = 0, o_u[2] = {0, 0}, o_ph = 0, total = 0;
+  size_t o_B = 0, o_u[2] = {0, 0}, o_ph = 0, o_ph32 = 0, total = 0;
 
   // ---- free space (Sections 3.4 and 4)
   bool free_space = false;
@@ -371,6 +371,7 @@ struct tdse_plan_s {
   double2* u(int i) const { return (double2*)(ws + o_u[i]); }
   const void* V(int g) const { return ws + st[g].o_V; }
   double2* ph() const { return (double2*)(ws + o_ph); }
+  float2* ph32() const { return o_ph32 ? (float2*)(ws + o_ph32) : nullptr; }
   const void* tw(int g, int axis) const { return ws + (axis == 0 ? st[g].o_tw1 : st[g].o_tw2); }
   bool force_fp64 = false;   // run the Adams passes of a split plan in FP64 (adjoint recomputation)
   bool split() const { return precision == TDSE_FP32_SPLIT && !force_fp64; }
@@ -409,6 +410,7 @@ LineArgs base_args(const tdse_plan_s* p, int g) {
   a.ring_stride = p->P;
   a.Bm = p->B();
   a.ph = p->ph();
+  a.ph32 = p->ph32();
   a.slot_w = -1;
   return a;
 }
@@ -2162,6 +2164,10 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
     p->st[1].tw2.clear();
   }
   p->o_ph = off; off = align256(off + (size_t)(p->order - 1) * (p->M1 + p->M2) * sizeof(double2));
+  if (split) {   // the same table rounded to complex64, read by the split row pass
+    p->o_ph32 = off;
+    off = align256(off + (size_t)(p->order - 1) * (p->M1 + p->M2) * sizeof(float2));
+  }
   p->total = off;
   *out = p;
   return TDSE_OK;

@@ -72,6 +72,7 @@ struct LineArgs {
   void* fdst;          // R_FWD destination (transform precision)
   // phase table
   double2* ph;
+  float2* ph32;        // split form: the table rounded to complex64 (null in FP64 plans)
   PhaseReq req;
 };
 
