@@ -13,7 +13,8 @@
 //
 // Forward uses exp(-2 pi i jk/N), inverse exp(+2 pi i jk/N); neither scales.
 // Twiddles come from a table tw[m] = exp(-2 pi i m / N), m < N, built on the
-// host in extended precision; the inverse conjugates them.
+// host in extended precision (or from two small tables of its entries,
+// TwPair); the inverse conjugates them.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -138,8 +139,23 @@ __device__ __forceinline__ C twiddle(const C* tw, int idx) {
   return w;
 }
 
-template <int N, int TL, int Ns, bool INV, typename C>
-__device__ __forceinline__ void fft_regs_rec(C* v, int t, C* line, const C* tw) {
+// Two-level twiddle source for long lines: tw[idx] = coarse[idx / F] *
+// fine[idx % F] with F = 2^LF, both small tables (N/F + F entries, e.g. in
+// LDS) holding entries of the full table; one extra rounding per twiddle.
+template <typename C, int LF>
+struct TwPair {
+  const C* coarse;
+  const C* fine;
+};
+template <bool INV, typename C, int LF>
+__device__ __forceinline__ C twiddle(const TwPair<C, LF>& tw, int idx) {
+  C w = cmul(tw.coarse[idx >> LF], tw.fine[idx & ((1 << LF) - 1)]);
+  if (INV) w.y = -w.y;
+  return w;
+}
+
+template <int N, int TL, int Ns, bool INV, typename C, typename TW>
+__device__ __forceinline__ void fft_regs_rec(C* v, int t, C* line, const TW& tw) {
   constexpr int EPT = N / TL;
   constexpr int R = pick_radix(N / Ns, EPT);
   constexpr int B = EPT / R;   // butterflies per thread
@@ -182,8 +198,8 @@ __device__ __forceinline__ void fft_regs_rec(C* v, int t, C* line, const C* tw) 
 
 // FFT of one line held as v[m] = x[t + TL*m]; `line` is lds_line_len(N)
 // elements of LDS scratch for this line.  Every thread of the block must call it (barriers).
-template <int N, int TL, bool INV, typename C>
-__device__ __forceinline__ void fft_regs(C* v, int t, C* line, const C* tw) {
+template <int N, int TL, bool INV, typename C, typename TW>
+__device__ __forceinline__ void fft_regs(C* v, int t, C* line, const TW& tw) {
   static_assert(plan_ok(N, N / TL), "line length must factor into radices dividing N/TL");
   if constexpr (N > 1) fft_regs_rec<N, TL, 1, INV>(v, t, line, tw);
 }

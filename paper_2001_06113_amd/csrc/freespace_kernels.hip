@@ -69,10 +69,26 @@ __device__ __forceinline__ void build_phase_table_fs(const FSArgs& a, int nthrea
 // N_D * max(1, TL / N_D) entries).
 constexpr int RAY = 4;
 
+// nu-point twiddles from two small tables in LDS (TwPair): 2^LF fine and
+// nu / 2^LF coarse entries, staged from the full table at kernel start
+template <int NU>
+struct fs_tw {
+  static constexpr int LF = NU >= 2048 ? 6 : (NU >= 512 ? 5 : 4);
+  static constexpr int NF = 1 << LF, NC = NU >> LF;
+  using type = TwPair<double2, LF>;
+};
+template <int NU>
+__device__ __forceinline__ typename fs_tw<NU>::type stage_twiddles(const CFAxis& ax, double2* tws, int t) {
+  constexpr int NC = fs_tw<NU>::NC, NF = fs_tw<NU>::NF, LF = fs_tw<NU>::LF;
+  for (int i = t; i < NC + NF; i += NU / 8) tws[i] = i < NC ? ax.tw[i << LF] : ax.tw[i - NC];
+  return typename fs_tw<NU>::type{tws, tws + NC};
+}
+
 // forward transform of f[0..M) (LDS); ends with dm complete (a barrier)
 template <int NU>
 __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY], double2 (&v1)[RAY], double2* dm,
-                                           double2* part, double2* fline, const CFAxis& ax, int t) {
+                                           double2* part, double2* fline, const CFAxis& ax,
+                                           const typename fs_tw<NU>::type& tw, int t) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
   const int M = ax.M, NE = ax.NE, ND = ax.ND;
@@ -85,7 +101,7 @@ __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY],
     const double2 x = cmul(ax.pre3[ec], f[ec]);
     w[m] = e < M ? x : double2{0.0, 0.0};
   }
-  fft_regs<NU, TL, false>(w, t, fline, ax.tw);
+  fft_regs<NU, TL, false>(w, t, fline, tw);
 #pragma unroll
   for (int m = 0; m < RAY; ++m) {
     const int e = t + TL * m;
@@ -98,30 +114,28 @@ __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY],
     const double2 x = cmul(ax.pre1[ec], f[ec]);
     w[m] = e < M ? x : double2{0.0, 0.0};
   }
-  fft_regs<NU, TL, true>(w, t, fline, ax.tw);
+  fft_regs<NU, TL, true>(w, t, fline, tw);
 #pragma unroll
   for (int m = 0; m < RAY; ++m) {
     const int e = t + TL * m;
     const double2 x = cmul(ax.post1[min(e, NE - 1)], w[m]);
     v1[m] = e < NE ? x : double2{0.0, 0.0};
   }
-  // dense modes: thread (q, c) sums j = c, c + C, ... (lanes of one q read
-  // consecutive j), DB matrix entries per batch of loads
-  constexpr int DB = 4;
+  // dense modes: thread (q, c) sums the contiguous chunk j0 <= j < j0 + L of
+  // the row q of Dfwd.  Entries along a row form a geometric sequence
+  // (equispaced x_j), so the chunk is Dfwd[q][j0] times a Horner sum in the
+  // ratio rfwd[q]: two table reads per chunk, L LDS reads.
   const int C = TL / ND > 1 ? TL / ND : 1;
+  const int L = (M + C - 1) / C;
   for (int i = t; i < ND * C; i += TL) {   // more dense modes than threads: several pairs per thread
     const int q = i / C, c = i - q * C;
-    const double2* row = ax.Dfwd + (int64_t)q * M;
+    const int j0 = c * L, j1 = min(j0 + L, M);
     double2 acc = {0.0, 0.0};
-    for (int j0 = c; j0 < M; j0 += DB * C) {
-      double2 d[DB];
-#pragma unroll
-      for (int u = 0; u < DB; ++u) d[u] = row[min(j0 + u * C, M - 1)];
-#pragma unroll
-      for (int u = 0; u < DB; ++u) {
-        const int j = j0 + u * C;
-        if (j < M) acc = cadd(acc, cmul(d[u], f[j]));
-      }
+    if (j0 < M) {
+      const double2 r = ax.rfwd[q];
+      const double2 d0 = ax.Dfwd[(int64_t)q * M + j0];
+      for (int j = j1 - 1; j >= j0; --j) acc = cadd(cmul(acc, r), f[j]);
+      acc = cmul(d0, acc);
     }
     part[i] = acc;
   }
@@ -139,7 +153,8 @@ __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY],
 // without a barrier
 template <int NU>
 __device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const double2 (&v1)[RAY], const double2* dm,
-                                           double2* fline, const CFAxis& ax, int t, double2* u) {
+                                           double2* fline, const CFAxis& ax, const typename fs_tw<NU>::type& tw,
+                                           int t, double2* u) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
   const int M = ax.M, NE = ax.NE, ND = ax.ND;
@@ -154,7 +169,7 @@ __device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const doubl
       w[m] = double2{0.0, 0.0};
     }
   }
-  fft_regs<NU, TL, true>(w, t, fline, ax.tw);
+  fft_regs<NU, TL, true>(w, t, fline, tw);
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     const int e = t + TL * m;
@@ -170,7 +185,7 @@ __device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const doubl
       w[m] = double2{0.0, 0.0};
     }
   }
-  fft_regs<NU, TL, false>(w, t, fline, ax.tw);
+  fft_regs<NU, TL, false>(w, t, fline, tw);
   // E1 part, then the dense modes in batches of DB matrix entries
   constexpr int DB = 8;
 #pragma unroll
@@ -192,11 +207,12 @@ __device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const doubl
   }
 }
 
-// dynamic LDS of a line kernel: f[M] | FFT exchange line | dm[ND] | part[ND * C]
+// dynamic LDS of a line kernel: f[M] | FFT exchange line | dm[ND] | part[ND * C] | twiddles
 __host__ __device__ constexpr int fs_part_len(int TL, int ND) { return ND * (TL / ND > 1 ? TL / ND : 1); }
 template <int NU>
 size_t fs_lds_bytes(int M, int ND) {
-  return sizeof(double2) * (size_t)(M + lds_line_len(NU) + ND + fs_part_len(NU / 8, ND));
+  return sizeof(double2) *
+         (size_t)(M + lds_line_len(NU) + ND + fs_part_len(NU / 8, ND) + fs_tw<NU>::NC + fs_tw<NU>::NF);
 }
 
 // The per-mode step of the row pass for mode g = row_m + k; W is the mode of
@@ -247,11 +263,11 @@ __device__ __forceinline__ double2 fs_mode_update(const FSArgs& a, const double2
 
 // ---------------------------------------------------------------- row pass
 
-// Three workgroups per CU (a register budget of 168; the few values that
-// spill cost less than the latency a third wave per SIMD hides in the
-// per-mode updates).
+// Two workgroups per CU with the full register budget: with the history
+// loads batched, spill traffic at a budget of 168 (three per CU) costs more
+// than the latency a third wave per SIMD hides.
 template <int NU>
-__global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_fs_row(FSArgs a) {
+__global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fs_row(FSArgs a) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
   HIP_DYNAMIC_SHARED(double2, fs_lds)
@@ -261,8 +277,10 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(3, 3))) 
   double2* fline = fin + M2;
   double2* dm = fline + lds_line_len(NU);
   double2* part = dm + ND;
+  double2* tws = part + fs_part_len(TL, ND);
   const int t = threadIdx.x;
   const int k1 = blockIdx.x;
+  const auto tw = stage_twiddles<NU>(ax, tws, t);   // read after the first barrier below
   const int mode = a.mode;
   const int per = a.N1 + a.N2;
   const int64_t row_m = (int64_t)k1 * N2;   // mode row
@@ -273,7 +291,7 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(3, 3))) 
   if (need_fwd) {
     for (int j = t; j < M2; j += TL) fin[j] = a.src[row_p + j];
     __syncthreads();
-    cf_forward<NU>(fin, v3, v1, dm, part, fline, ax, t);
+    cf_forward<NU>(fin, v3, v1, dm, part, fline, ax, tw, t);
   } else {
 #pragma unroll
     for (int m = 0; m < RAY; ++m) v3[m] = v1[m] = double2{0.0, 0.0};
@@ -416,7 +434,7 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(3, 3))) 
   }
   if (mode == R_UHACC) return;
   __syncthreads();
-  cf_inverse<NU>(v3, v1, dm, fline, ax, t, fin);   // the forward input is no longer needed
+  cf_inverse<NU>(v3, v1, dm, fline, ax, tw, t, fin);   // the forward input is no longer needed
   for (int e = t; e < M2; e += TL) a.dst[row_p + e] = fin[e];
 }
 
@@ -442,8 +460,10 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
   double2* fline = fin + M1;
   double2* dm = fline + lds_line_len(NU);
   double2* part = dm + ND;
+  double2* tws = part + fs_part_len(TL, ND);
   const int t = threadIdx.x;
   const int y = fs_col_of(blockIdx.x, gridDim.x);   // physical column (axis 1)
+  const auto tw = stage_twiddles<NU>(ax, tws, t);   // read after the first barrier below
   const int mode = a.mode;
 
   if (a.req.nj > 0) build_phase_table_fs(a, TL);
@@ -457,7 +477,7 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
     }
     for (int q = t; q < ND; q += TL) dm[q] = a.src[(int64_t)(NE + q) * M2 + y];
     __syncthreads();
-    cf_inverse<NU>(v3, v1, dm, fline, ax, t, fin);   // w = F^-1 B on the column, in place of the forward input
+    cf_inverse<NU>(v3, v1, dm, fline, ax, tw, t, fin);   // w = F^-1 B on the column, in place of the forward input
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
       const int e = t + TL * m;
@@ -490,7 +510,7 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
     }
   }
   __syncthreads();
-  cf_forward<NU>(fin, v3, v1, dm, part, fline, ax, t);
+  cf_forward<NU>(fin, v3, v1, dm, part, fline, ax, tw, t);
 #pragma unroll
   for (int m = 0; m < RAY; ++m) {
     const int e = t + TL * m;

@@ -875,8 +875,14 @@ void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels) 
     const LD a = -2.0L * PI * (LD)m / (LD)nu;
     twt[m] = double2{(double)std::cos(a), (double)std::sin(a)};
   }
+  // ratio of consecutive forward dense entries: Dfwd[q][j+1] = Dfwd[q][j] exp(-i zeta_q 2/M)
+  std::vector<double2> rfwd(ND);
+  for (int q2 = 0; q2 < ND; ++q2) {
+    const double2 zz = F.zeta[NE + q2];
+    rfwd[q2] = cexp_ld((LD)zz.y * 2.0L / (LD)M, -(LD)zz.x * 2.0L / (LD)M);
+  }
   std::vector<std::vector<double2>*> parts = {&pre3, &pre1, &ipost3, &ipost1, &post3, &post1, &ipre3,
-                                              &ipre1, &Dfwd, &Dinv, &twt, &z};
+                                              &ipre1, &Dfwd, &Dinv, &twt, &z, &rfwd};
   size_t bytes = 0;
   for (auto* v : parts) bytes = align256(bytes + v->size() * sizeof(double2));
   F.tables.assign(bytes, 0);
@@ -919,6 +925,7 @@ CFAxis cf_axis(const tdse_plan_s* p, int axis) {
   c.Dinv = take((size_t)F.M * F.ND);
   c.tw = take(F.nu);
   c.zeta = take(F.N);
+  c.rfwd = take(F.ND);
   return c;
 }
 

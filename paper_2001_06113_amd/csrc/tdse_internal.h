@@ -89,6 +89,7 @@ struct CFAxis {
   const double2* Dinv;          // [ND][M] (w_q/2pi) exp(i zeta_q x_j)
   const double2* tw;            // nu-point twiddles
   const double2* zeta;          // [N] nodes (for the phase factors)
+  const double2* rfwd;          // [ND] exp(-i zeta_q 2/M): Dfwd[q][j+1] = Dfwd[q][j] rfwd[q]
 };
 
 struct FSArgs {
