@@ -187,7 +187,7 @@ __device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const doubl
   }
   fft_regs<NU, TL, false>(w, t, fline, tw);
   // E1 part, then the dense modes in batches of DB matrix entries
-  constexpr int DB = 8;
+  constexpr int DB = 18;
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     const int e = t + TL * m;
