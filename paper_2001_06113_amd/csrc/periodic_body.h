@@ -33,7 +33,9 @@
 // walk.)
 //
 // Every global load a pass needs (tile, potential, B, history, phase factors)
-// is issued before its first FFT so their latencies overlap.
+// is issued before its first FFT so their latencies overlap, in the order of
+// first use: a wave's loads complete in issue order, so waiting for one
+// waits for all loads issued before it.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -134,9 +136,7 @@ __device__ __forceinline__ void col_body(const LineArgs& a, int line0, int blk, 
 
   C v[EPT];
   double2 u0[EPT];   // C_FWD reads the complex128 physical solution
-  double vv[EPT];
-  // tile loads first, then one batch of EPT potential loads per field, so
-  // that each batch is a single round trip
+  double vv[EPT];   // potential fields after the first (summed at first use)
   const int64_t g0 = (int64_t)line * a.line_stride + (int64_t)t * a.elem_stride;
   const int64_t gs = (int64_t)TL * a.elem_stride;
   // loads in the order of first use (they complete in order): twiddles,
