@@ -215,6 +215,14 @@ int tdse_get_instance_state(tdse_plan_t plan, int32_t instance, void* u, int32_t
  * launch arguments. */
 int tdse_set_field(tdse_plan_t plan, const double* A_steps);
 
+/* Concurrency of a batch plan's adjoint: the instances' adjoints run from
+ * `streams` host threads (1..16, default 8), each on a stream of its own with
+ * a workspace slice of its own, since one instance's adjoint is a long chain
+ * of small launches.  1 runs them one after another on the bound stream.
+ * Call before tdse_adjoint_workspace_size (the size scales with it).  Single
+ * plans accept and ignore it. */
+int tdse_adjoint_streams(tdse_plan_t plan, int32_t streams);
+
 /* Device bytes the adjoint needs with checkpoints every `checkpoint_every`
  * Adams steps (<= 0: about the square root of the step count). */
 int tdse_adjoint_workspace_size(tdse_plan_t plan, int32_t checkpoint_every, size_t* bytes);

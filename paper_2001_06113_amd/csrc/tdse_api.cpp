@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/tdse.h"
@@ -315,6 +316,7 @@ struct tdse_plan_s {
 
   // ---- batch of independent periodic instances (tdse_plan_batch)
   std::vector<tdse_plan_s*> sub;                // owned
+  int adj_streams = 8;                          // batch adjoint: host threads / streams
   std::vector<size_t> sub_off;                  // workspace offset of each instance
   std::vector<int64_t> sub_elem;                // element offset of each instance in packed states
   struct GLaunch {
@@ -1751,6 +1753,9 @@ int adj_copy(tdse_plan_s* p, void* dst, const void* src, size_t bytes) {
   return adj_err(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, p->stream), "adjoint copy");
 }
 
+// host threads (and streams) of a batch plan's adjoint
+int adj_workers(const tdse_plan_s* p) { return std::max(1, std::min(p->adj_streams, (int)p->sub.size())); }
+
 int adjoint_single(tdse_plan_s* p, char* w, size_t wbytes, int K, const void* u0, const void* lam, int on_device,
                    double* dF_dA, void* dF_du0) {
   if (p->free_space) return fail(TDSE_EUNSUPPORTED, "the adjoint covers the periodic scheme");
@@ -2518,10 +2523,18 @@ int tdse_adjoint_workspace_size(tdse_plan_t p, int32_t checkpoint_every, size_t*
   size_t b = 0;
   if (p->is_batch()) {
     for (tdse_plan_s* q : p->sub) b = std::max(b, adj_layout(q, checkpoint_every).total);
+    b = align256(b) * (size_t)adj_workers(p);
   } else {
     b = adj_layout(p, checkpoint_every).total;
   }
   *bytes = b;
+  return TDSE_OK;
+}
+
+int tdse_adjoint_streams(tdse_plan_t p, int32_t streams) {
+  if (!p) return fail(TDSE_EINVAL, "NULL plan");
+  if (streams < 1 || streams > 16) return fail(TDSE_EINVAL, "streams must be 1..16");
+  p->adj_streams = streams;
   return TDSE_OK;
 }
 
@@ -2530,18 +2543,83 @@ int tdse_adjoint(tdse_plan_t p, void* ws, size_t bytes, int32_t checkpoint_every
   if (!p || !ws || !u0 || !lambda_T) return fail(TDSE_EINVAL, "NULL argument");
   if (!p->bound) return fail(TDSE_ESTATE, "tdse_bind must come first");
   if (!p->is_batch()) return adjoint_single(p, (char*)ws, bytes, checkpoint_every, u0, lambda_T, on_device, dF_dA, dF_du0);
-  size_t aoff = 0;
-  for (size_t i = 0; i < p->sub.size(); ++i) {
+  const int nsub = (int)p->sub.size();
+  std::vector<size_t> aoff(nsub + 1, 0);
+  size_t slice = 0;
+  for (int i = 0; i < nsub; ++i) {
+    aoff[i + 1] = aoff[i] + (size_t)p->sub[i]->nsteps * p->sub[i]->dim;
+    slice = std::max(slice, adj_layout(p->sub[i], checkpoint_every).total);
+  }
+  slice = align256(slice);
+  const int T = adj_workers(p);
+  if (bytes < slice * (size_t)T) return fail(TDSE_ENOMEM, "adjoint workspace smaller than tdse_adjoint_workspace_size");
+  auto one = [&](int i, char* w) {
     tdse_plan_s* q = p->sub[i];
     const int64_t e = p->sub_elem[i];
-    const int s = adjoint_single(q, (char*)ws, bytes, checkpoint_every, (const double2*)u0 + e,
-                                 (const double2*)lambda_T + e, on_device, dF_dA ? dF_dA + aoff : nullptr,
-                                 dF_du0 ? (void*)((double2*)dF_du0 + e) : nullptr);
-    if (s) return s;
-    aoff += (size_t)q->nsteps * q->dim;
+    return adjoint_single(q, w, slice, checkpoint_every, (const double2*)u0 + e, (const double2*)lambda_T + e,
+                          on_device, dF_dA ? dF_dA + aoff[i] : nullptr,
+                          dF_du0 ? (void*)((double2*)dF_du0 + e) : nullptr);
+  };
+  if (T == 1) {
+    for (int i = 0; i < nsub; ++i) {
+      const int s = one(i, (char*)ws);
+      if (s) return s;
+    }
+    p->cur = -1;
+    return TDSE_OK;
   }
+  // T workers, worker t takes instances t, t + T, ...: a stream each
+  // (non-blocking, default priority), ordered after the work already on the
+  // bound stream, and the bound stream ordered after all of them
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::vector<hipStream_t> streams(T, nullptr);
+  std::vector<hipEvent_t> evs(T + 1, nullptr);
+  int s = TDSE_OK;
+  auto cleanup = [&]() {
+    for (hipStream_t x : streams)
+      if (x) (void)hipStreamDestroy(x);
+    for (hipEvent_t x : evs)
+      if (x) (void)hipEventDestroy(x);
+  };
+  for (int k = 0; k <= T && !s; ++k) s = adj_err(hipEventCreateWithFlags(&evs[k], hipEventDisableTiming), "adjoint event");
+  for (int t = 0; t < T && !s; ++t) s = adj_err(hipStreamCreateWithFlags(&streams[t], hipStreamNonBlocking), "adjoint stream");
+  if (!s) s = adj_err(hipEventRecord(evs[T], p->stream), "adjoint event");
+  for (int t = 0; t < T && !s; ++t) s = adj_err(hipStreamWaitEvent(streams[t], evs[T], 0), "adjoint wait");
+  if (s) {
+    cleanup();
+    return s;
+  }
+  std::vector<int> st(T, TDSE_OK);
+  std::vector<std::string> msg(T);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < T; ++t) {
+    pool.emplace_back([&, t]() {
+      if (hipSetDevice(dev) != hipSuccess) {
+        st[t] = TDSE_EDEVICE;
+        msg[t] = "adjoint worker: hipSetDevice failed";
+        return;
+      }
+      char* w = (char*)ws + (size_t)t * slice;
+      for (int i = t; i < nsub && st[t] == TDSE_OK; i += T) {
+        tdse_plan_s* q = p->sub[i];
+        hipStream_t keep = q->stream;
+        q->stream = streams[t];
+        st[t] = one(i, w);
+        q->stream = keep;
+      }
+      if (st[t]) msg[t] = g_last_error;   // the error text is per thread
+    });
+  }
+  for (std::thread& th : pool) th.join();
+  for (int t = 0; t < T; ++t) {
+    if (!s && st[t]) s = fail(st[t], msg[t]);
+    if (hipEventRecord(evs[t], streams[t]) == hipSuccess) (void)hipStreamWaitEvent(p->stream, evs[t], 0);
+  }
+  for (hipStream_t x : streams) (void)hipStreamSynchronize(x);
+  cleanup();
   p->cur = -1;
-  return TDSE_OK;
+  return s;
 }
 
 void tdse_destroy(tdse_plan_t p) { delete p; }

@@ -208,6 +208,10 @@ class Plan:
         self._leave()
         return self._split_field(gA), g0
 
+    def adjoint_streams(self, streams: int) -> None:
+        """Host threads / streams of a batch adjoint (tdse_adjoint_streams; 1 = one instance at a time)."""
+        _check(self.lib.tdse_adjoint_streams(self.handle, int(streams)), "tdse_adjoint_streams")
+
     def _field_shape(self):
         return [self.nsteps * self.dim]
 

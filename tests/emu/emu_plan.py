@@ -134,6 +134,7 @@ class EmuBatchPlan:
         if st:
             raise RuntimeError(lib.tdse_last_error().decode())
         self.shapes = [tuple(pr.M) for pr in probs]
+        self.fields = [(pr.nsteps, pr.dim) for pr in probs]
         self.offsets = [int(self.query(4096 + i)) for i in range(len(probs))]
 
     def query(self, key: int) -> float:
@@ -180,3 +181,32 @@ def emu_adjoint(plan, u0, lam, checkpoint_every=0):
     if st:
         raise RuntimeError(lib.tdse_last_error().decode())
     return gA, g0
+
+
+def emu_batch_adjoint(bplan, u0s, lams, checkpoint_every=0):
+    """tdse_adjoint on an EmuBatchPlan: per-instance (dJ/dA [nsteps, dim], dJ/du0) lists."""
+    lib, h = bplan.lib, bplan.h
+    sz = C.c_size_t()
+    st = lib.tdse_adjoint_workspace_size(h, checkpoint_every, C.byref(sz))
+    if st:
+        raise RuntimeError(lib.tdse_last_error().decode())
+    raw = np.zeros(sz.value + 512, dtype=np.uint8)
+    off = (-raw.ctypes.data) % 256
+    ws = raw[off:off + sz.value]
+    pack = lambda xs: np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.complex128).ravel() for x in xs]))
+    u0 = pack(u0s)
+    lam = pack(lams)
+    sizes = [(nsteps, dim) for nsteps, dim in bplan.fields]
+    gA = np.zeros(sum(n * d for n, d in sizes))
+    g0 = np.zeros_like(u0)
+    st = lib.tdse_adjoint(h, C.c_void_p(ws.ctypes.data), sz.value, checkpoint_every, C.c_void_p(u0.ctypes.data),
+                          C.c_void_p(lam.ctypes.data), 1, gA.ctypes.data_as(C.POINTER(C.c_double)),
+                          C.c_void_p(g0.ctypes.data))
+    if st:
+        raise RuntimeError(lib.tdse_last_error().decode())
+    gAs, a = [], 0
+    for n, d in sizes:
+        gAs.append(gA[a:a + n * d].reshape(n, d))
+        a += n * d
+    g0s = [g0[o:o + int(np.prod(s))].reshape(s) for o, s in zip(bplan.offsets, bplan.shapes)]
+    return gAs, g0s

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <vector>
 
 struct double2 { double x, y; };
@@ -77,8 +78,15 @@ inline void fiber_entry() {
   f.done = true;
   swapcontext(&f.ctx, &b->sched);
 }
+// kernels run one at a time, whichever host thread launches them (the
+// emulated grid state, fiber stacks and __shared__ arrays are process-wide)
+inline std::mutex& launch_mutex() {
+  static std::mutex m;
+  return m;
+}
 template <typename K, typename... Args>
 void launch(K kernel, dim3 grid, dim3 block, Args... args) {
+  std::lock_guard<std::mutex> hold(launch_mutex());
   gridDim = grid;
   blockDim = block;
   for (unsigned bi = 0; bi < grid.x; ++bi) {
@@ -159,6 +167,12 @@ inline hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) {
 }
 enum hipDeviceAttribute_t { hipDeviceAttributeMaxSharedMemoryPerBlock };
 inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+inline hipError_t hipSetDevice(int) { return hipSuccess; }
+constexpr unsigned hipStreamNonBlocking = 1, hipEventDisableTiming = 2;
+inline hipError_t hipStreamCreateWithFlags(hipStream_t* st, unsigned) { *st = (hipStream_t)new char[1]; return hipSuccess; }
+inline hipError_t hipStreamDestroy(hipStream_t st) { delete[] (char*)st; return hipSuccess; }
+inline hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = (hipEvent_t)new char[1]; return hipSuccess; }
+inline hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
 inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 160 * 1024; return hipSuccess; }
 // dynamic LDS: one static buffer per kernel and element type, as large as a CU's LDS
 #define HIP_DYNAMIC_SHARED(type, var) static type var[160 * 1024 / sizeof(type)];

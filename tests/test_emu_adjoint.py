@@ -51,3 +51,33 @@ def test_adjoint_rejects_other_fields(emu):
     prob = periodic_problem_from_seed(74, 1, (32,), 0.1, 8)        # smooth pulse, not stepwise
     with pytest.raises(RuntimeError, match="stepwise"):
         emu_adjoint(EmuPlan(emu, prob), prob.u0, prob.u0)
+
+
+def test_emulated_batch_adjoint_on_several_streams(emu):
+    # a batch's adjoints run from several host threads, each on a stream and a
+    # workspace slice of its own: every instance's result is the same whichever
+    # worker computed it, and matches the oracle's reverse sweep
+    from emu.emu_plan import EmuBatchPlan, emu_batch_adjoint
+
+    shapes = [(1, (64,)), (2, (64, 64)), (1, (128,)), (1, (256,))]
+    probs = [periodic_problem_from_seed(80 + i, d, M, 0.1, 10, A_kind="stepwise") for i, (d, M) in enumerate(shapes)]
+    lams = [dipole_seed(p, PeriodicOracle(p).run()[0], axis=p.dim - 1) for p in probs]
+    b = EmuBatchPlan(emu, probs)
+    res, sizes = {}, {}
+    for streams in (1, 3, 4):
+        assert emu.tdse_adjoint_streams(b.h, streams) == 0
+        res[streams] = emu_batch_adjoint(b, [p.u0 for p in probs], lams)
+        import ctypes as C
+        sz = C.c_size_t()
+        assert emu.tdse_adjoint_workspace_size(b.h, 0, C.byref(sz)) == 0
+        sizes[streams] = sz.value
+    assert sizes[3] == 3 * sizes[1] and sizes[4] == 4 * sizes[1]
+    for streams in (3, 4):
+        for x, y in zip(res[1][0] + res[1][1], res[streams][0] + res[streams][1]):
+            assert np.array_equal(x, y)
+    for i, p in enumerate(probs):
+        gA, g0 = adjoint(p, lams[i])
+        assert np.max(np.abs(res[4][0][i] - gA)) <= 1e-12 * np.max(np.abs(gA))
+        assert np.linalg.norm(res[4][1][i] - g0) <= 1e-12 * np.linalg.norm(g0)
+    assert emu.tdse_adjoint_streams(b.h, 0) != 0
+    assert emu.tdse_adjoint_streams(b.h, 17) != 0
