@@ -257,7 +257,7 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU (no sharding across GPUs); --gpus must be 1"}))
         sys.exit(2)
     import torch
 

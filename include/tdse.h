@@ -47,7 +47,7 @@ extern "C" {
 /* ---- status codes ---------------------------------------------------- */
 #define TDSE_OK            0
 #define TDSE_EINVAL       -1   /* bad sizes, non-integer T/dt, bad order, NULL */
-#define TDSE_EUNSUPPORTED -2   /* a valid request this build does not do      */
+#define TDSE_EUNSUPPORTED -2   /* a valid request the library does not do    */
 #define TDSE_ENOMEM       -3   /* workspace missing or too small              */
 #define TDSE_EDEVICE      -4   /* a HIP runtime error                         */
 #define TDSE_ENONFINITE   -5   /* the state became NaN/Inf                    */

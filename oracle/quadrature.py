@@ -13,9 +13,9 @@ Test infrastructure only (see the package docstring).
   refined in mpmath; the w_k solve the first p moment equations.
 * ``gauss_legendre(q)``: numpy's Gauss-Legendre rule (a library primitive).
 * ``gamma_rule(...)``: the five node sets E1, A1, C, A3, E3 of Section 3.4 in
-  that order, with the readings listed in the design doc (E-nodes
+  that order, with these readings of the section: E-nodes
   H + kappa h + (k-1) h - iH, k = 1..N_E; panels per side given directly;
-  Gamma_2 nodes (1 - i) tau).
+  Gamma_2 nodes (1 - i) tau.
 * ``choose_H``: the rule of the Remark on the choice of H (Section 3.2),
   H = log(eps / ((1 + ||V||_{2,inf}) eps_m)) / (2 d (1 + phi_max)).
 """

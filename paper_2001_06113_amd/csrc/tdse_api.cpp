@@ -2052,7 +2052,7 @@ const char* tdse_status_string(int status) {
   switch (status) {
     case TDSE_OK: return "TDSE_OK";
     case TDSE_EINVAL: return "TDSE_EINVAL: invalid argument";
-    case TDSE_EUNSUPPORTED: return "TDSE_EUNSUPPORTED: not supported by this build";
+    case TDSE_EUNSUPPORTED: return "TDSE_EUNSUPPORTED: not supported by the library";
     case TDSE_ENOMEM: return "TDSE_ENOMEM: workspace missing or too small";
     case TDSE_EDEVICE: return "TDSE_EDEVICE: HIP runtime error";
     case TDSE_ENONFINITE: return "TDSE_ENONFINITE: non-finite state";
