@@ -67,6 +67,13 @@ def test_1d_shapes(M):
     check(periodic_problem_from_seed(32, 1, M, 0.3, 30))
 
 
+@pytest.mark.parametrize("M", [(3072,), (8, 3072), (3072, 8), (1536, 24)])
+def test_longest_lines(M):
+    # the longest supported line (3 * 1024) along each axis, and a 1536-point
+    # column pass over a ragged set of 24 columns
+    check(periodic_problem_from_seed(35, len(M), M, 0.2, 20))
+
+
 @pytest.mark.parametrize("order", [2, 4, 6])
 def test_lower_orders(order):
     check(periodic_problem_from_seed(33, 2, (32, 64), 0.2, 25, order=order))

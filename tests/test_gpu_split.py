@@ -39,7 +39,7 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("M,N", [((64, 96), 60), ((256,), 50), ((384, 48), 30)])
+@pytest.mark.parametrize("M,N", [((64, 96), 60), ((256,), 50), ((384, 48), 30), ((3072,), 30), ((3072, 8), 20), ((8, 3072), 20)])
 def test_split_vs_oracle(M, N):
     prob = periodic_problem_from_seed(41, len(M), M, 0.001 * N, N, precision="fp32split")
     print(f"case split M={M} steps={N}", flush=True)
