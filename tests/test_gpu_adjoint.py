@@ -75,6 +75,34 @@ def test_autograd_function_dipole_gradient():
     plan.close()
 
 
+def test_batch_adjoint_streams_agree():
+    # a batch's adjoints from 8 host threads on 8 streams (more instances than
+    # workers) equal the one-stream run bit for bit: each instance's arithmetic
+    # is the same on any stream and workspace slice
+    from paper_2001_06113_amd.tdse import BatchPlan
+
+    shapes = [(1, (64,)), (2, (64, 64)), (1, (256,)), (2, (128, 64)), (1, (2048,)), (2, (192, 256)),
+              (1, (384,)), (2, (64, 128)), (1, (128,))]
+    probs = [periodic_problem_from_seed(90 + i, d, M, 0.1, 30, A_kind="stepwise") for i, (d, M) in enumerate(shapes)]
+    lams = [dipole_seed(p, PeriodicOracle(p).run()[0], axis=p.dim - 1) for p in probs]
+    print("case batch adjoint on 1 and 8 streams", flush=True)
+    b = BatchPlan.from_problems(probs, device="cuda:0")
+    b.adjoint_streams(1)
+    gA1, g01 = b.adjoint([p.u0 for p in probs], lams)
+    g01 = g01.cpu().numpy()
+    b.adjoint_streams(8)
+    gA8, g08 = b.adjoint([p.u0 for p in probs], lams)
+    g08 = g08.cpu().numpy()
+    b.close()
+    for x, y in zip(gA1, gA8):
+        assert np.array_equal(x, y)
+    assert np.array_equal(g01, g08)
+    gA, _ = adjoint(probs[1], lams[1])
+    r = np.max(np.abs(gA8[1] - gA)) / np.max(np.abs(gA))
+    print(f"  instance 1 {probs[1].M}: vs oracle {r:.2e}", flush=True)
+    assert r <= 1e-10
+
+
 def test_c4_batch_adjoint():
     # the 64-instance batch (FP32-split forward plans, 500 steps): the FP64
     # derivative of each instance's <x_1>(T) with respect to its 500 samples
