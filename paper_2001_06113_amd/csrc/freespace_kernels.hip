@@ -269,7 +269,6 @@ __device__ __forceinline__ double2 fs_mode_update(const FSArgs& a, const double2
 template <int NU>
 __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fs_row(FSArgs a) {
   constexpr int TL = NU / 8;
-  constexpr int EPT = 8;
   HIP_DYNAMIC_SHARED(double2, fs_lds)
   const CFAxis& ax = a.ax2;
   const int M2 = ax.M, N2 = ax.N, NE = ax.NE, ND = ax.ND;

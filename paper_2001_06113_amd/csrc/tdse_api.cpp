@@ -838,7 +838,7 @@ void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels) 
     F.w[im] = double2{(double)wc[k], (double)-wc[k]};
   }
   // transform tables
-  const int NE = F.NE, ND = F.ND, N = F.N;
+  const int NE = F.NE, ND = F.ND;
   const LD alpha = H + kappa * h;
   const LD s2M = 2.0L / (LD)M;
   std::vector<double2> pre3(M), pre1(M), ipost3(M), ipost1(M), post3(NE), post1(NE), ipre3(NE), ipre1(NE);
@@ -1271,7 +1271,7 @@ int batch_tiles(tdse_plan_s* p, int kind, int g, const std::vector<int>& ept) {
 }
 
 // Group the i-th recorded launches of all instances.
-int batch_group(tdse_plan_s* p, std::vector<std::vector<RecLaunch>>& rl, std::vector<tdse_plan_s::GLaunch>& out,
+int batch_group(std::vector<std::vector<RecLaunch>>& rl, std::vector<tdse_plan_s::GLaunch>& out,
                 std::vector<LineArgs>& args, std::vector<tdse_plan_s::Narrow>& nar) {
   const size_t n = rl.size(), L = rl[0].size();
   for (size_t i = 1; i < n; ++i)
@@ -1305,7 +1305,7 @@ int batch_record_step(tdse_plan_s* p, int m, bool write_u, std::vector<tdse_plan
     q->rec = nullptr;
     if (s) return s;
   }
-  return batch_group(p, rl, out, args, nar);
+  return batch_group(rl, out, args, nar);
 }
 
 // Record the whole run: seg[m] for m = 1..nsteps, seg_last (step nsteps with
@@ -1767,7 +1767,7 @@ int adjoint_single(tdse_plan_s* p, char* w, size_t wbytes, int K, const void* u0
   const AdjLayout& L = R.L;
   if (wbytes < L.total) return fail(TDSE_ENOMEM, "adjoint workspace smaller than tdse_adjoint_workspace_size");
   if (((uintptr_t)w) & 255) return fail(TDSE_EINVAL, "adjoint workspace must be 256-byte aligned");
-  const int N = p->nsteps, ns = std::min(p->ns, N), H = L.H, n_ord = p->order;
+  const int N = p->nsteps, ns = std::min(p->ns, N), H = L.H;
   const double dt = p->dt;
   const std::vector<double>& mu = p->mu;
   const size_t a = (size_t)p->P * sizeof(double2);
