@@ -6,7 +6,7 @@ sinusoidal modulation and a sin^2 pulse, seed 1, complex128 (synthetic inputs).
 One benchmark "step" is one whole run [0, T] on inputs already resident in
 device memory: start-up plus 1994 Adams steps.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--workload c1|c3fp64]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--workload periodic-2d-512|periodic-2d-1024-fp64]
 
 Prints one JSON line.  value = modes x time steps / wall time of the K timed
 runs (whole job).  roofline: algorithmic bytes of the dominant kernel (the
@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60, help="time steps in the oracle sample")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3fp64"])
+    ap.add_argument("--workload", default="periodic-2d-512", choices=["periodic-2d-512", "periodic-2d-1024-fp64"])
     ap.add_argument("--prof-runs", type=int, default=3, help="eager runs timed per kernel with HIP events")
     ap.add_argument("--no-split", action="store_true", help="skip the FP32-split 1024x1024 leg")
     ap.add_argument("--split-steps", type=int, default=3)
@@ -115,13 +115,13 @@ def split_leg(steps: int) -> dict:
     import torch
 
     from paper_2001_06113_amd.tdse import Plan
-    from workloads import c3_problem
+    from workloads import periodic_2d_1024_problem
 
     dev = torch.device("cuda:0")
     res = {}
     outs = {}
     for prec in ("fp32split", "fp64"):
-        prob = c3_problem(precision=prec)
+        prob = periodic_2d_1024_problem(precision=prec)
         plan = Plan.from_problem(prob, device=dev)
         plan.use_graph(True)
         u0 = torch.as_tensor(prob.u0).to(dev)
@@ -138,7 +138,7 @@ def split_leg(steps: int) -> dict:
         res[prec] = u0.numel() * prob.nsteps * n / wall
         plan.close()
     err = (torch.linalg.vector_norm(outs["fp32split"] - outs["fp64"]) / torch.linalg.vector_norm(outs["fp64"])).item()
-    return {"workload": "2D periodic TDSE 1024x1024, T=2, 2000 steps AM8 (config 3), FP32-split",
+    return {"workload": "2D periodic TDSE 1024x1024, T=2, 2000 steps AM8, FP32-split",
             "value": res["fp32split"], "unit": "mode-updates/s", "fp64_value": res["fp64"],
             "speedup_vs_fp64": res["fp32split"] / res["fp64"], "rel_l2_vs_fp64": err, "bar": 1e-6}
 
@@ -151,10 +151,10 @@ def free_space_leg(runs: int) -> dict:
 
     from paper_2001_06113_amd.tdse import (Q_BYTES_COL, Q_BYTES_ROW, Q_PROF_MS_COL, Q_PROF_MS_ROW,
                                            Q_PROF_N_COL, Q_PROF_N_ROW, Plan)
-    from workloads import c2_problem
+    from workloads import free_2d_256_problem
 
     dev = torch.device("cuda:0")
-    prob = c2_problem()
+    prob = free_2d_256_problem()
     plan = Plan.from_problem(prob, device=dev)
     u0 = torch.as_tensor(prob.u0).to(dev)
     out = torch.empty_like(u0)
@@ -177,7 +177,7 @@ def free_space_leg(runs: int) -> dict:
     ach = row_b / (row_us * 1e-6) / 1e9
     plan.close()
     return {"workload": "2D free-space TDSE 256x256, nu=2048 per axis, eps=1e-10, p=8, q=10, 1 panel, "
-                        "T=1, 1000 steps AM8 (config 2)",
+                        "T=1, 1000 steps AM8",
             "value": n_modes * prob.nsteps / wall, "unit": "mode-updates/s",
             "modes": int(n_modes), "grid_points": int(u0.numel()),
             "grid_point_updates_per_s": u0.numel() * prob.nsteps / wall, "ms_per_run": wall * 1e3,
@@ -198,10 +198,10 @@ def batch_leg(runs: int) -> dict:
     import torch
 
     from paper_2001_06113_amd.tdse import Q_BYTES_PER_STEP, BatchPlan, Plan
-    from workloads import c4_problems
+    from workloads import batch_64_problems
 
     dev = torch.device("cuda:0")
-    probs = c4_problems()
+    probs = batch_64_problems()
     b = BatchPlan.from_problems(probs, device=dev)
     t0 = time.perf_counter()
     chosen = b.autotune(5)
@@ -243,7 +243,7 @@ def batch_leg(runs: int) -> dict:
     adj_s = time.perf_counter() - t0
     b.close()
     return {"workload": "64 periodic instances (32 1D M=256..2048, 32 2D M=128^2..512^2), T=2, 500 steps AM8, "
-                        "FP32-split, stepwise A (config 4)",
+                        "FP32-split, stepwise A",
             "value": value, "unit": "mode-updates/s", "ms_per_run": wall * 1e3, "modes": int(b.total),
             "algorithmic_GBps": bytes_step * nsteps / wall / 1e9,
             "one_plan_at_a_time_value": b.total * nsteps / seq, "speedup_vs_one_plan_at_a_time": seq / wall,
@@ -264,7 +264,7 @@ def main():
     from paper_2001_06113_amd import _lib
     from paper_2001_06113_amd.tdse import (Q_BYTES_COL, Q_BYTES_ROW, Q_PROF_MS_COL, Q_PROF_MS_ROW,
                                            Q_PROF_N_COL, Q_PROF_N_ROW, Plan)
-    from workloads import c1_problem, periodic_problem_from_seed
+    from workloads import periodic_2d_512_problem, periodic_problem_from_seed
 
     if not os.path.exists(_lib.LIB_PATH):
         from paper_2001_06113_amd import build
@@ -272,12 +272,12 @@ def main():
         build.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    if args.workload == "c1":
-        prob = c1_problem()
-        wname = "2D periodic TDSE 512x512, T=2, 2000 steps AM8 (config 1)"
+    if args.workload == "periodic-2d-512":
+        prob = periodic_2d_512_problem()
+        wname = "2D periodic TDSE 512x512, T=2, 2000 steps AM8, FP64"
     else:
-        prob = periodic_problem_from_seed(3, 2, (1024, 1024), 2.0, 2000, name="C3-fp64")
-        wname = "2D periodic TDSE 1024x1024, T=2, 2000 steps AM8, FP64 (config 3 geometry)"
+        prob = periodic_problem_from_seed(3, 2, (1024, 1024), 2.0, 2000, name="periodic-2d-1024-fp64")
+        wname = "2D periodic TDSE 1024x1024, T=2, 2000 steps AM8, FP64"
     plan = Plan.from_problem(prob, device=dev)
     u0 = torch.as_tensor(prob.u0).to(dev)
     out = torch.empty_like(u0)
@@ -324,7 +324,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wname, "grid": list(prob.M), "time_steps": prob.nsteps,
-                   "order": prob.order, "modes": int(modes), "seed": 1 if args.workload == "c1" else 3,
+                   "order": prob.order, "modes": int(modes), "seed": 1 if args.workload == "periodic-2d-512" else 3,
                    "finite": ok},
         "roofline": {
             "bound": "hbm",

@@ -1,4 +1,4 @@
-"""Write c2_oracle_sample.txt: sampled values of the free-space oracle on the
+"""Write free_2d_256_oracle_sample.txt: sampled values of the free-space oracle on the
 2D free-space workload (seed 2, 256 x 256 points on [-1,1)^2, FFT size 2048
 per axis, eps = 1e-10, p = 8, q = 10, one Gauss panel per side, 1000 steps to
 T = 1; Sections 3.3-3.4).
@@ -8,7 +8,7 @@ steps (six Richardson start-up steps and two Adams steps) and all 1000 steps.
 Every 8th grid point per axis is written, as "case i j Re(u) Im(u)", with the
 grid 2-norm of each result.  Calls only oracle/ and workloads/.
 
-    python tests/golden/make_c2_oracle.py      (about 20-40 min on 8 cores)
+    python tests/golden/make_free_2d_256_oracle.py      (about 20-40 min on 8 cores)
 """
 import os
 import sys
@@ -20,19 +20,19 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from oracle.freespace import FreeSpaceOracle  # noqa: E402
-from workloads import c2_problem  # noqa: E402
+from workloads import free_2d_256_problem  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_oracle_sample.txt")
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "free_2d_256_oracle_sample.txt")
 STRIDE = 8
 
 
 def main():
-    full = c2_problem()
+    full = free_2d_256_problem()
     H = FreeSpaceOracle(full).H
     lines = [f"# free-space oracle on the 2D free-space workload (seed 2, 256^2, nu 2048, eps 1e-10, p 8, q 10, 1 panel)",
              f"# H {H!r}", f"# stride {STRIDE}"]
     for steps in (8, 1000):
-        prob = c2_problem()
+        prob = free_2d_256_problem()
         prob.nsteps = steps
         prob.T = full.dt * steps
         t = time.time()

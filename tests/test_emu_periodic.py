@@ -62,9 +62,9 @@ def test_emulated_split_long_run_high_potential(emu):
     # 19) over its 500 steps: rounded history weights or a rounded potential
     # would perturb every step alike and push the error past 2e-6
     from emu.emu_plan import EmuPlan
-    from workloads import c4_problems
+    from workloads import batch_64_problems
 
-    prob = c4_problems()[12]
+    prob = batch_64_problems()[12]
     u = EmuPlan(emu, prob).run(prob.u0)
     ref, _ = PeriodicOracle(prob).run()
     assert _rel(u, ref) < 1e-6

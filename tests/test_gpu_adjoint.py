@@ -8,7 +8,7 @@ import pytest
 
 from oracle.adjoint import adjoint, dipole, dipole_seed
 from oracle.periodic import PeriodicOracle
-from workloads import c4_problems, periodic_problem_from_seed
+from workloads import batch_64_problems, periodic_problem_from_seed
 
 pytestmark = pytest.mark.gpu
 
@@ -103,16 +103,16 @@ def test_batch_adjoint_streams_agree():
     assert r <= 1e-10
 
 
-def test_c4_batch_adjoint():
+def test_batch_64_adjoint():
     # the 64-instance batch (FP32-split forward plans, 500 steps): the FP64
     # derivative of each instance's <x_1>(T) with respect to its 500 samples
     import torch
 
     from paper_2001_06113_amd.tdse import BatchPlan, Plan
 
-    probs = c4_problems()
-    p64s = c4_problems(precision="fp64")
-    print("case C4 batch adjoint", flush=True)
+    probs = batch_64_problems()
+    p64s = batch_64_problems(precision="fp64")
+    print("case 64-instance batch adjoint", flush=True)
     # seeds from the FP64 forward of every instance
     lams, uTs = [], []
     for p in p64s:

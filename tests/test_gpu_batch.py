@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle.periodic import PeriodicOracle
-from workloads import c4_problems, periodic_problem_from_seed
+from workloads import batch_64_problems, periodic_problem_from_seed
 
 pytestmark = pytest.mark.gpu
 
@@ -59,11 +59,11 @@ def test_mixed_batch_matches_oracle(prec, tol):
         assert r <= tol, (p.M, r)
 
 
-def test_c4_geometry_fp64_against_oracle():
+def test_batch_64_fp64_against_oracle():
     # all 64 instances of the uneven batch in FP64 for 10 steps; one instance
     # of each size against the oracle
-    probs = c4_problems(T=0.04, nsteps=10, precision="fp64")
-    print("case C4 geometry FP64, 10 steps", flush=True)
+    probs = batch_64_problems(T=0.04, nsteps=10, precision="fp64")
+    print("case 64-instance batch geometry, FP64, 10 steps", flush=True)
     b = batch(probs)
     outs = b.run_list([p.u0 for p in probs])
     for i in (0, 1, 2, 3, 32, 33, 34, 35):
@@ -73,7 +73,7 @@ def test_c4_geometry_fp64_against_oracle():
     b.close()
 
 
-def test_c4_full_split_autotuned():
+def test_batch_64_split_autotuned():
     # the benchmarked configuration: 64 instances, 500 steps, FP32-split,
     # autotuned schedules, whole-run graph replay; every instance within 1e-6
     # of the FP64 GPU path, the smallest 1D and 2D ones against the oracle
@@ -81,8 +81,8 @@ def test_c4_full_split_autotuned():
 
     from paper_2001_06113_amd.tdse import Plan
 
-    probs = c4_problems()
-    print("case C4 full split", flush=True)
+    probs = batch_64_problems()
+    print("case 64-instance batch, full split run", flush=True)
     b = batch(probs)
     chosen = b.autotune(5)
     print(f"  schedules {sorted(set(chosen))}", flush=True)
@@ -95,7 +95,7 @@ def test_c4_full_split_autotuned():
     outs = [u.cpu().numpy() for u in b.unpack(first)]
     b.close()
     worst = 0.0
-    for i, p64 in enumerate(c4_problems(precision="fp64")):
+    for i, p64 in enumerate(batch_64_problems(precision="fp64")):
         pl = Plan.from_problem(p64, device="cuda:0")
         ref = pl.run(p64.u0).cpu().numpy()
         pl.close()

@@ -12,12 +12,12 @@ import numpy as np
 import pytest
 
 from oracle.freespace import FreeSpaceOracle
-from workloads import Problem, c2_problem, free_grid, free_problem_from_seed
+from workloads import Problem, free_2d_256_problem, free_grid, free_problem_from_seed
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-11
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_oracle_sample.txt")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "free_2d_256_oracle_sample.txt")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -85,13 +85,13 @@ def _golden():
 
 
 @pytest.mark.parametrize("steps", [8, 1000])
-def test_c2_full_size_against_stored_oracle_samples(steps):
+def test_free_2d_256_full_size_against_stored_oracle_samples(steps):
     # the 256 x 256, nu = 2048 workload in the launch shapes the benchmark
     # times; every 8th grid point per axis against the oracle's values
     H, rows, norms = _golden()
-    prob = c2_problem()
+    prob = free_2d_256_problem()
     prob.nsteps, prob.T = steps, prob.dt * steps
-    print(f"case C2 steps={steps} H={H}", flush=True)
+    print(f"case free space 256^2 steps={steps} H={H}", flush=True)
     plan = gpu_plan(prob, H=H)
     u = plan.run(prob.u0).cpu().numpy()
     plan.close()

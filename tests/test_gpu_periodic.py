@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle.periodic import PeriodicOracle
-from workloads import Problem, c0_problem, periodic_grid, periodic_problem_from_seed
+from workloads import Problem, periodic_1d_256_problem, periodic_grid, periodic_problem_from_seed
 
 pytestmark = pytest.mark.gpu
 
@@ -53,8 +53,8 @@ def check(prob, tol=TOL):
     return r
 
 
-def test_c0_1d_full():
-    check(c0_problem())
+def test_periodic_1d_256_full():
+    check(periodic_1d_256_problem())
 
 
 @pytest.mark.parametrize("M", [(64, 96), (96, 8), (48, 384), (1024, 16), (16, 2048), (24, 24)])
@@ -107,12 +107,12 @@ def test_step_in_pieces_is_bitwise_run():
     assert plan.query(1) == 30.0
 
 
-def test_c1_size_200_steps():
+def test_periodic_2d_512_200_steps():
     # the 512 x 512 kernels and launch shapes timed by the benchmark, 200 steps at dt = 1e-3
     check(periodic_problem_from_seed(1, 2, (512, 512), 0.2, 200))
 
 
-def test_trapezoid_invariant_full_c1():
+def test_trapezoid_invariant_periodic_2d_512():
     # order 2: ||(1 + i dt/2 V(t_N)) u_N|| = ||(1 + i dt/2 V(0)) u_0|| exactly, at full size and length
     from paper_2001_06113_amd.tdse import Plan
 

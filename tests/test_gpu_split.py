@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle.periodic import PeriodicOracle
-from workloads import c3_problem, periodic_problem_from_seed
+from workloads import periodic_2d_1024_problem, periodic_problem_from_seed
 
 pytestmark = pytest.mark.gpu
 BAR = 1e-6
@@ -50,20 +50,20 @@ def test_split_vs_oracle(M, N):
     assert 1e-12 < r <= BAR
 
 
-def test_split_c3_size_vs_oracle_short():
-    prob = c3_problem(nsteps=20, T=0.02)
+def test_split_1024_vs_oracle_short():
+    prob = periodic_2d_1024_problem(nsteps=20, T=0.02)
     u = run(prob)
     ref, _ = PeriodicOracle(prob).run()
     r = rel(u, ref)
-    print(f"C3 1024^2, 20 steps: rel-L2 vs oracle = {r:.3e}", flush=True)
+    print(f"1024^2 split, 20 steps: rel-L2 vs oracle = {r:.3e}", flush=True)
     assert r <= BAR
 
 
-def test_split_c3_full_vs_fp64_gpu():
-    # full C3: 1024 x 1024, T = 2, 2000 steps; reference = the FP64 GPU path
-    split = run(c3_problem())
-    fp64 = run(c3_problem(precision="fp64"))
+def test_split_1024_full_vs_fp64_gpu():
+    # the full 1024 x 1024 split run:, T = 2, 2000 steps; reference = the FP64 GPU path
+    split = run(periodic_2d_1024_problem())
+    fp64 = run(periodic_2d_1024_problem(precision="fp64"))
     r = rel(split, fp64)
-    print(f"C3 full: rel-L2 split vs FP64 = {r:.3e}", flush=True)
+    print(f"1024^2 split, full run: rel-L2 split vs FP64 = {r:.3e}", flush=True)
     assert np.all(np.isfinite(split))
     assert r <= BAR

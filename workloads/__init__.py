@@ -8,11 +8,11 @@ from .synth import (  # noqa: F401
     Problem,
     periodic_grid,
     free_grid,
-    c0_problem,
-    c1_problem,
-    c2_problem,
-    c3_problem,
-    c4_problems,
+    periodic_1d_256_problem,
+    periodic_2d_512_problem,
+    free_2d_256_problem,
+    periodic_2d_1024_problem,
+    batch_64_problems,
     periodic_problem_from_seed,
     free_problem_from_seed,
 )

@@ -122,7 +122,7 @@ def _normalize(u: np.ndarray, cell: float) -> np.ndarray:
     return u / np.sqrt(np.sum(np.abs(u) ** 2) * cell)
 
 
-def c0_problem(seed: int = 0, M: int = 256, T: float = 1.0, nsteps: int = 100, order: int = 8) -> Problem:
+def periodic_1d_256_problem(seed: int = 0, M: int = 256, T: float = 1.0, nsteps: int = 100, order: int = 8) -> Problem:
     """1D periodic well V = -a cos x, A = 0, Gaussian u0 (seed 0)."""
     rng = np.random.default_rng(seed)
     a = rng.uniform(1.0, 5.0)
@@ -132,7 +132,7 @@ def c0_problem(seed: int = 0, M: int = 256, T: float = 1.0, nsteps: int = 100, o
     V0 = -a * np.cos(x)
     u0 = _periodized_gauss([x], [x0], sig, images=2).astype(np.complex128)
     u0 = _normalize(u0, TWO_PI / M)
-    return Problem(name="C0", dim=1, domain="periodic", M=(M,), T=T, nsteps=nsteps, order=order,
+    return Problem(name="periodic-1d-256", dim=1, domain="periodic", M=(M,), T=T, nsteps=nsteps, order=order,
                    u0=u0, V_fields=[V0], f_kind=["const"], f_params=[(0.0, 0.0)],
                    meta=dict(a=a, x0=x0, sigma=sig))
 
@@ -185,18 +185,18 @@ def periodic_problem_from_seed(seed: int, dim: int, M: Sequence[int], T: float, 
     return prob
 
 
-def c1_problem(seed: int = 1, M: int = 512, T: float = 2.0, nsteps: int = 2000, order: int = 8) -> Problem:
+def periodic_2d_512_problem(seed: int = 1, M: int = 512, T: float = 2.0, nsteps: int = 2000, order: int = 8) -> Problem:
     """2D periodic, 512 x 512, T = 2, 2000 steps, FP64 (seed 1)."""
-    return periodic_problem_from_seed(seed, 2, (M, M), T, nsteps, order, name="C1")
+    return periodic_problem_from_seed(seed, 2, (M, M), T, nsteps, order, name="periodic-2d-512")
 
 
-def c3_problem(seed: int = 3, M: int = 1024, T: float = 2.0, nsteps: int = 2000, order: int = 8,
+def periodic_2d_1024_problem(seed: int = 3, M: int = 1024, T: float = 2.0, nsteps: int = 2000, order: int = 8,
                precision: str = "fp32split") -> Problem:
     """The 2D periodic recipe at 1024 x 1024 (seed 3), FP32-split by default."""
-    return periodic_problem_from_seed(seed, 2, (M, M), T, nsteps, order, precision=precision, name="C3")
+    return periodic_problem_from_seed(seed, 2, (M, M), T, nsteps, order, precision=precision, name="periodic-2d-1024")
 
 
-def c4_problems(T: float = 2.0, nsteps: int = 500, order: int = 8, precision: str = "fp32split",
+def batch_64_problems(T: float = 2.0, nsteps: int = 500, order: int = 8, precision: str = "fp32split",
                 count: int = 64, scale: int = 1) -> List[Problem]:
     """64 periodic instances of uneven sizes: i < 32 are 1D with M in
     {256, 512, 1024, 2048}; i >= 32 are 2D with M in {128, 256, 384, 512}^2.
@@ -207,11 +207,11 @@ def c4_problems(T: float = 2.0, nsteps: int = 500, order: int = 8, precision: st
         if i < count // 2:
             m = [256, 512, 1024, 2048][i % 4] // scale
             prob = periodic_problem_from_seed(4000 + i, 1, (m,), T, nsteps, order, precision,
-                                              name=f"C4[{i}]", A_kind="stepwise")
+                                              name=f"batch-64[{i}]", A_kind="stepwise")
         else:
             m = [128, 256, 384, 512][i % 4] // scale
             prob = periodic_problem_from_seed(4000 + i, 2, (m, m), T, nsteps, order, precision,
-                                              name=f"C4[{i}]", A_kind="stepwise")
+                                              name=f"batch-64[{i}]", A_kind="stepwise")
         out.append(prob)
     return out
 
@@ -272,8 +272,8 @@ def free_problem_from_seed(seed: int, dim: int, M: Sequence[int], T: float, nste
     return prob
 
 
-def c2_problem(seed: int = 2, M: int = 256, T: float = 1.0, nsteps: int = 1000, order: int = 8,
+def free_2d_256_problem(seed: int = 2, M: int = 256, T: float = 1.0, nsteps: int = 1000, order: int = 8,
                nu: int = 2048) -> Problem:
     """2D free space, 256 x 256 physical points, eps = 1e-10, p = 8, q = 10,
     one Gauss panel per side, FFT size nu = 2048 per axis (seed 2)."""
-    return free_problem_from_seed(seed, 2, (M, M), T, nsteps, order, nu=(nu, nu), name="C2")
+    return free_problem_from_seed(seed, 2, (M, M), T, nsteps, order, nu=(nu, nu), name="free-2d-256")
