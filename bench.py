@@ -60,6 +60,38 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_read": a.numel() * 16, "copy_bytes_written": b.numel() * 16, "copies": 5}))
 
 
+def device_copy_gbps(dev, mib: int = 512, reps: int = 10) -> float:
+    """Bandwidth of a plain device-to-device copy (bytes read + written per
+    second), timed with events on the current stream: the practical HBM ceiling
+    the roofline fraction is also quoted against."""
+    import torch
+
+    n = mib * (1 << 20) // 16
+    a = torch.ones(n, dtype=torch.complex128, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n * 16 / (ms * 1e-3) / 1e9
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(prob, nsteps: int) -> dict:
     """Time the FP64 oracle (as written) on the first `nsteps` steps."""
     from threadpoolctl import threadpool_limits
@@ -77,6 +109,8 @@ def cpu_baseline(prob, nsteps: int) -> dict:
         "unit": "mode-updates/s",
         "cores": 1,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
+        "host_cores_available": len(os.sched_getaffinity(0)),
         "sample": f"{prob.name} at full size ({'x'.join(map(str, prob.M))}), first {nsteps} of {prob.nsteps} "
                   f"steps (6 Richardson start-up steps + {nsteps - prob.start_steps} Adams steps), "
                   f"numpy/pocketfft single thread, {dt:.1f} s",
@@ -306,6 +340,7 @@ def main():
 
     ms_per_run = wall * 1e3 / args.steps
     value = modes * prob.nsteps * args.steps / wall
+    copy_gbps = device_copy_gbps(dev)
     row_us, col_us = row_ms * 1e3 / max(n_row, 1), col_ms * 1e3 / max(n_col, 1)
     row_b, col_b = plan.query(Q_BYTES_ROW), plan.query(Q_BYTES_COL)
     dom_b, dom_us, dom = (row_b, row_us, "row") if row_us * 1 >= col_us else (col_b, col_us, "col")
@@ -338,6 +373,8 @@ def main():
             "mean_launch_us": dom_us,
             "row_pass_us": row_us,
             "col_pass_us": col_us,
+            "device_copy_GBps": copy_gbps,
+            "frac_of_device_copy": achieved / copy_gbps if achieved else None,
         },
         "adams_step_us_eager": row_us + col_us,
         "graph_us_per_time_step": wall * 1e6 / (args.steps * prob.nsteps),
