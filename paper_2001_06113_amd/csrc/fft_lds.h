@@ -196,6 +196,75 @@ __device__ __forceinline__ void fft_regs_rec(C* v, int t, C* line, const TW& tw)
   }
 }
 
+// Two independent lines transformed together, each in its own direction
+// (INVA, INVB) and LDS scratch: every exchange round writes both lines, waits
+// at one barrier and reads both back, so two lines cost the barriers of one.
+template <int N, int TL, int Ns, bool INVA, bool INVB, typename C, typename TW>
+__device__ __forceinline__ void fft_regs_dual_rec(C* va, C* vb, int t, C* la, C* lb, const TW& tw) {
+  constexpr int EPT = N / TL;
+  constexpr int R = pick_radix(N / Ns, EPT);
+  constexpr int B = EPT / R;
+  constexpr int TWS = N / (Ns * R);
+  constexpr bool LAST = (Ns * R == N);
+  C xa[B][R], xb[B][R];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = t + b * TL;
+    const int k = (Ns == 1) ? 0 : (j % Ns);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      xa[b][r] = va[b + r * B];
+      xb[b][r] = vb[b + r * B];
+    }
+    if constexpr (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const C w = twiddle<false>(tw, r * k * TWS);
+        const C wa = INVA ? C{w.x, -w.y} : w, wb = INVB ? C{w.x, -w.y} : w;
+        xa[b][r] = cmul(xa[b][r], wa);
+        xb[b][r] = cmul(xb[b][r], wb);
+      }
+    }
+    dft_small<R, INVA>(xa[b]);
+    dft_small<R, INVB>(xb[b]);
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        va[b + r * B] = xa[b][r];
+        vb[b + r * B] = xb[b][r];
+      }
+  } else {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + b * TL;
+      const int k = (Ns == 1) ? 0 : (j % Ns);
+      const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        la[lds_slot(base + r * Ns)] = xa[b][r];
+        lb[lds_slot(base + r * Ns)] = xb[b][r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      va[m] = la[lds_slot(t + TL * m)];
+      vb[m] = lb[lds_slot(t + TL * m)];
+    }
+    __syncthreads();
+    fft_regs_dual_rec<N, TL, Ns * R, INVA, INVB>(va, vb, t, la, lb, tw);
+  }
+}
+
+template <int N, int TL, bool INVA, bool INVB, typename C, typename TW>
+__device__ __forceinline__ void fft_regs_dual(C* va, C* vb, int t, C* la, C* lb, const TW& tw) {
+  static_assert(plan_ok(N, N / TL), "line length must factor into radices dividing N/TL");
+  if constexpr (N > 1) fft_regs_dual_rec<N, TL, 1, INVA, INVB>(va, vb, t, la, lb, tw);
+}
+
 // FFT of one line held as v[m] = x[t + TL*m]; `line` is lds_line_len(N)
 // elements of LDS scratch for this line.  Every thread of the block must call it (barriers).
 template <int N, int TL, bool INV, typename C, typename TW>

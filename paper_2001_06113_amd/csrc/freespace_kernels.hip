@@ -64,9 +64,11 @@ __device__ __forceinline__ void build_phase_table_fs(const FSArgs& a, int nthrea
 // them in.  N_E = nu/2 - 13 < nu/2 = 4 TL, so only m < RAY = 4 can hold a
 // ray mode: the rays are carried as four values per thread, and the other
 // four FFT slots are compile-time zeros going into the inverse FFTs.  The
-// N_D dense modes N_E + q live in LDS (dm).  The dense block's forward sums
-// are split over (mode, chunk) pairs and reduced through LDS (part,
-// N_D * max(1, TL / N_D) entries).
+// two rays' nu-point FFTs run together (fft_regs_dual), each line with its
+// own LDS exchange buffer, so they share every exchange barrier.  The N_D
+// dense modes N_E + q live in LDS (dm).  The dense block's forward sums are
+// split over (mode, chunk) pairs and reduced through LDS (part, N_D *
+// max(1, TL / N_D) entries, in the second exchange line once its FFT is done).
 constexpr int RAY = 4;
 
 // nu-point twiddles from two small tables in LDS (TwPair): 2^LF fine and
@@ -87,39 +89,29 @@ __device__ __forceinline__ typename fs_tw<NU>::type stage_twiddles(const CFAxis&
 // forward transform of f[0..M) (LDS); ends with dm complete (a barrier)
 template <int NU>
 __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY], double2 (&v1)[RAY], double2* dm,
-                                           double2* part, double2* fline, const CFAxis& ax,
+                                           double2* part, double2* fline, double2* fline2, const CFAxis& ax,
                                            const typename fs_tw<NU>::type& tw, int t) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
   const int M = ax.M, NE = ax.NE, ND = ax.ND;
   // Table reads use an in-range twin index (min(e, n - 1)) and the result is
   // selected afterwards, so they carry no branch and issue together.
-  double2 w[EPT];
+  double2 w[EPT], w1[EPT];
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     const int e = t + TL * m, ec = min(e, M - 1);
-    const double2 x = cmul(ax.pre3[ec], f[ec]);
+    const double2 x = cmul(ax.pre3[ec], f[ec]), y = cmul(ax.pre1[ec], f[ec]);
     w[m] = e < M ? x : double2{0.0, 0.0};
+    w1[m] = e < M ? y : double2{0.0, 0.0};
   }
-  fft_regs<NU, TL, false>(w, t, fline, tw);
+  fft_regs_dual<NU, TL, false, true>(w, w1, t, fline, fline2, tw);
 #pragma unroll
   for (int m = 0; m < RAY; ++m) {
     const int e = t + TL * m;
     const double2 x = cmul(ax.post3[min(e, NE - 1)], w[m]);
     v3[m] = e < NE ? x : double2{0.0, 0.0};
-  }
-#pragma unroll
-  for (int m = 0; m < EPT; ++m) {
-    const int e = t + TL * m, ec = min(e, M - 1);
-    const double2 x = cmul(ax.pre1[ec], f[ec]);
-    w[m] = e < M ? x : double2{0.0, 0.0};
-  }
-  fft_regs<NU, TL, true>(w, t, fline, tw);
-#pragma unroll
-  for (int m = 0; m < RAY; ++m) {
-    const int e = t + TL * m;
-    const double2 x = cmul(ax.post1[min(e, NE - 1)], w[m]);
-    v1[m] = e < NE ? x : double2{0.0, 0.0};
+    const double2 y = cmul(ax.post1[min(e, NE - 1)], w1[m]);
+    v1[m] = e < NE ? y : double2{0.0, 0.0};
   }
   // dense modes: thread (q, c) sums the contiguous chunk j0 <= j < j0 + L of
   // the row q of Dfwd.  Entries along a row form a geometric sequence
@@ -153,46 +145,38 @@ __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY],
 // without a barrier
 template <int NU>
 __device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const double2 (&v1)[RAY], const double2* dm,
-                                           double2* fline, const CFAxis& ax, const typename fs_tw<NU>::type& tw,
-                                           int t, double2* u) {
+                                           double2* fline, double2* fline2, const CFAxis& ax,
+                                           const typename fs_tw<NU>::type& tw, int t, double2* u) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
   const int M = ax.M, NE = ax.NE, ND = ax.ND;
-  double2 w[EPT];
+  double2 w[EPT], w1[EPT];
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     const int e = t + TL * m;
     if (m < RAY) {
       const double2 x = cmul(ax.ipre3[min(e, NE - 1)], v3[m < RAY ? m : 0]);
       w[m] = e < NE ? x : double2{0.0, 0.0};
+      const double2 y = cmul(ax.ipre1[min(e, NE - 1)], v1[m < RAY ? m : 0]);
+      w1[m] = e < NE ? y : double2{0.0, 0.0};
     } else {
       w[m] = double2{0.0, 0.0};
+      w1[m] = double2{0.0, 0.0};
     }
   }
-  fft_regs<NU, TL, true>(w, t, fline, tw);
+  fft_regs_dual<NU, TL, true, false>(w, w1, t, fline, fline2, tw);
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     const int e = t + TL * m;
     if (e < M) u[e] = cmul(ax.ipost3[e], w[m]);
   }
-#pragma unroll
-  for (int m = 0; m < EPT; ++m) {
-    const int e = t + TL * m;
-    if (m < RAY) {
-      const double2 x = cmul(ax.ipre1[min(e, NE - 1)], v1[m < RAY ? m : 0]);
-      w[m] = e < NE ? x : double2{0.0, 0.0};
-    } else {
-      w[m] = double2{0.0, 0.0};
-    }
-  }
-  fft_regs<NU, TL, false>(w, t, fline, tw);
   // E1 part, then the dense modes in batches of DB matrix entries
   constexpr int DB = 18;
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     const int e = t + TL * m;
     if (e < M) {
-      double2 s = cadd(u[e], cmul(ax.ipost1[e], w[m]));
+      double2 s = cadd(u[e], cmul(ax.ipost1[e], w1[m]));
       for (int q0 = 0; q0 < ND; q0 += DB) {
         double2 d[DB];
 #pragma unroll
@@ -207,12 +191,13 @@ __device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const doubl
   }
 }
 
-// dynamic LDS of a line kernel: f[M] | FFT exchange line | dm[ND] | part[ND * C] | twiddles
-__host__ __device__ constexpr int fs_part_len(int TL, int ND) { return ND * (TL / ND > 1 ? TL / ND : 1); }
+// LDS of a line kernel: dynamic f[M] | first FFT exchange line | dm[ND] |
+// twiddles, and a static second exchange line that also holds the dense
+// partials.  At nu = 2048 with M = 256 that is 79.9 KB, two workgroups per CU.
 template <int NU>
 size_t fs_lds_bytes(int M, int ND) {
   return sizeof(double2) *
-         (size_t)(M + lds_line_len(NU) + ND + fs_part_len(NU / 8, ND) + fs_tw<NU>::NC + fs_tw<NU>::NF);
+         (size_t)(M + lds_line_len(NU) + ND + fs_tw<NU>::NC + fs_tw<NU>::NF);
 }
 
 // The per-mode step of the row pass for mode g = row_m + k; W is the mode of
@@ -270,13 +255,14 @@ template <int NU>
 __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fs_row(FSArgs a) {
   constexpr int TL = NU / 8;
   HIP_DYNAMIC_SHARED(double2, fs_lds)
+  __shared__ double2 fline2[lds_line_len(NU)];
+  double2* part = fline2;
   const CFAxis& ax = a.ax2;
   const int M2 = ax.M, N2 = ax.N, NE = ax.NE, ND = ax.ND;
   double2* fin = fs_lds;
   double2* fline = fin + M2;
   double2* dm = fline + lds_line_len(NU);
-  double2* part = dm + ND;
-  double2* tws = part + fs_part_len(TL, ND);
+  double2* tws = dm + ND;
   const int t = threadIdx.x;
   const int k1 = blockIdx.x;
   const auto tw = stage_twiddles<NU>(ax, tws, t);   // read after the first barrier below
@@ -290,7 +276,7 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   if (need_fwd) {
     for (int j = t; j < M2; j += TL) fin[j] = a.src[row_p + j];
     __syncthreads();
-    cf_forward<NU>(fin, v3, v1, dm, part, fline, ax, tw, t);
+    cf_forward<NU>(fin, v3, v1, dm, part, fline, fline2, ax, tw, t);
   } else {
 #pragma unroll
     for (int m = 0; m < RAY; ++m) v3[m] = v1[m] = double2{0.0, 0.0};
@@ -433,7 +419,7 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   }
   if (mode == R_UHACC) return;
   __syncthreads();
-  cf_inverse<NU>(v3, v1, dm, fline, ax, tw, t, fin);   // the forward input is no longer needed
+  cf_inverse<NU>(v3, v1, dm, fline, fline2, ax, tw, t, fin);   // the forward input is no longer needed
   for (int e = t; e < M2; e += TL) a.dst[row_p + e] = fin[e];
 }
 
@@ -452,14 +438,15 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
   HIP_DYNAMIC_SHARED(double2, fs_lds)
+  __shared__ double2 fline2[lds_line_len(NU)];
+  double2* part = fline2;
   const CFAxis& ax = a.ax1;
   const int M1 = ax.M, N1 = ax.N, NE = ax.NE, ND = ax.ND;
   const int M2 = a.ax2.M;
   double2* fin = fs_lds;
   double2* fline = fin + M1;
   double2* dm = fline + lds_line_len(NU);
-  double2* part = dm + ND;
-  double2* tws = part + fs_part_len(TL, ND);
+  double2* tws = dm + ND;
   const int t = threadIdx.x;
   const int y = fs_col_of(blockIdx.x, gridDim.x);   // physical column (axis 1)
   const auto tw = stage_twiddles<NU>(ax, tws, t);   // read after the first barrier below
@@ -476,7 +463,7 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
     }
     for (int q = t; q < ND; q += TL) dm[q] = a.src[(int64_t)(NE + q) * M2 + y];
     __syncthreads();
-    cf_inverse<NU>(v3, v1, dm, fline, ax, tw, t, fin);   // w = F^-1 B on the column, in place of the forward input
+    cf_inverse<NU>(v3, v1, dm, fline, fline2, ax, tw, t, fin);   // w = F^-1 B on the column, in place of the forward input
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
       const int e = t + TL * m;
@@ -509,7 +496,7 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
     }
   }
   __syncthreads();
-  cf_forward<NU>(fin, v3, v1, dm, part, fline, ax, tw, t);
+  cf_forward<NU>(fin, v3, v1, dm, part, fline, fline2, ax, tw, t);
 #pragma unroll
   for (int m = 0; m < RAY; ++m) {
     const int e = t + TL * m;
