@@ -359,9 +359,19 @@ struct tdse_plan_s {
     gexec = nullptr;
     graph = nullptr;
   }
+  // batch: the schedule families of one pass run concurrently, families 1
+  // and 2 on side streams forked from and joined back to the bound stream
+  hipStream_t fam_st[2] = {nullptr, nullptr};
+  hipEvent_t fam_fork = nullptr, fam_join[2] = {nullptr, nullptr};
+
   ~tdse_plan_s() {
     drop_graph();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (int i = 0; i < 2; ++i) {
+      if (fam_join[i]) (void)hipEventDestroy(fam_join[i]);
+      if (fam_st[i]) (void)hipStreamDestroy(fam_st[i]);
+    }
+    if (fam_fork) (void)hipEventDestroy(fam_fork);
     for (tdse_plan_s* q : sub) delete q;
   }
 
@@ -1350,19 +1360,37 @@ int batch_exec(tdse_plan_s* p, const std::vector<tdse_plan_s::GLaunch>& L, const
     const int prec = p->sub[0]->st[gl.g].prec;
     const LineArgs* args = (const LineArgs*)args_dev + gl.arg0;
     const BatchTile* tiles = (const BatchTile*)(p->ws + p->o_tiles) + ts.off;
+    const bool timed = p->prof && gl.timed;
+    // the families touch disjoint instances: with more than one, the later
+    // ones go to side streams (not when each launch is being timed)
+    const int nfam = (ts.cnt[0] > 0) + (ts.cnt[1] > 0) + (ts.cnt[2] > 0);
+    const bool fork = nfam > 1 && !timed && p->fam_fork;
+    if (fork) HIP_TRY(hipEventRecord(p->fam_fork, p->stream));
+    int side = 0;
+    bool on_main = false;
     for (int f = 0; f < 3; ++f) {
       if (!ts.cnt[f]) continue;
+      hipStream_t s = p->stream;
+      if (fork && on_main) {
+        s = p->fam_st[side++];
+        HIP_TRY(hipStreamWaitEvent(s, p->fam_fork, 0));
+      }
+      on_main = true;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       const size_t first = p->ev_used;
-      if (p->prof && gl.timed) {
+      if (timed) {
         e0 = next_event(p);
         e1 = next_event(p);
         if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
       }
       const hipError_t e = launch_batch_pass(prec, gl.kind == 0, f, args, tiles + ts.first[f], ts.cnt[f], ts.lds[f],
-                                             p->stream, e0, e1);
+                                             s, e0, e1);
       if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
       if (e0) p->prof_marks.push_back({first, gl.kind});
+    }
+    for (int i = 0; i < side; ++i) {
+      HIP_TRY(hipEventRecord(p->fam_join[i], p->fam_st[i]));
+      HIP_TRY(hipStreamWaitEvent(p->stream, p->fam_join[i], 0));
     }
   }
   return TDSE_OK;
@@ -1480,6 +1508,13 @@ int plan_batch(const tdse_problem_t* probs, int count, tdse_plan_s** out) {
 int bind_batch(tdse_plan_s* p) {
   int dev = 0, v = 0;
   HIP_TRY(hipGetDevice(&dev));
+  if (!p->fam_fork) {   // default priority, non-blocking
+    HIP_TRY(hipEventCreateWithFlags(&p->fam_fork, hipEventDisableTiming));
+    for (int i = 0; i < 2; ++i) {
+      HIP_TRY(hipStreamCreateWithFlags(&p->fam_st[i], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&p->fam_join[i], hipEventDisableTiming));
+    }
+  }
   HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   p->lds_max = (size_t)v;
   for (size_t i = 0; i < p->sub.size(); ++i) {
