@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--split-steps", type=int, default=3)
     ap.add_argument("--no-free", action="store_true", help="skip the free-space 256x256 leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched leg")
+    ap.add_argument("--no-well", action="store_true", help="skip the moving-well (potential on the fly) leg")
     ap.add_argument("--batch-runs", type=int, default=3)
     ap.add_argument("--free-runs", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -175,6 +176,43 @@ def split_leg(steps: int) -> dict:
     return {"workload": "2D periodic TDSE 1024x1024, T=2, 2000 steps AM8, FP32-split",
             "value": res["fp32split"], "unit": "mode-updates/s", "fp64_value": res["fp64"],
             "speedup_vs_fp64": res["fp32split"] / res["fp64"], "rel_l2_vs_fp64": err, "bar": 1e-6}
+
+
+def moving_well_leg(runs: int = 5) -> dict:
+    """Potential evaluated on the fly: Example 1 of Section 6 at its own size
+    (1D, M = 256, moving Gaussian well V0 = 300, beta = 0.2, c = 30, T = 2 pi/15,
+    400 steps), and the same well moving at (30, 15) on the 512 x 512 grid
+    with 2000 steps, where the column pass computes V instead of reading it."""
+    import torch
+
+    from paper_2001_06113_amd.tdse import Q_PROF_MS_COL, Q_PROF_N_COL, Plan
+    from workloads import moving_well_problem
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for key, prob in (("example1_1d", moving_well_problem(c=(30.0,), M=(256,), nsteps=400)),
+                      ("grid_512x512", moving_well_problem(c=(30.0, 15.0), M=(512, 512), nsteps=2000))):
+        plan = Plan.from_problem(prob, device=dev)
+        u0 = torch.as_tensor(prob.u0).to(dev)
+        res = torch.empty_like(u0)
+        plan.use_graph(True)
+        plan.run(u0, res)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(runs):
+            plan.run(u0, res)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / runs
+        plan.use_graph(False)
+        plan.profile(True)
+        plan.run(u0, res)
+        col_us = plan.query(Q_PROF_MS_COL) * 1e3 / max(plan.query(Q_PROF_N_COL), 1)
+        plan.profile(False)
+        plan.close()
+        out[key] = {"ms_per_run": wall * 1e3, "value": u0.numel() * prob.nsteps / wall, "unit": "mode-updates/s",
+                    "col_pass_us": col_us, "finite": bool(torch.isfinite(torch.view_as_real(res)).all().item())}
+    return {"workload": "moving periodic Gaussian well (V0=300, beta=0.2), potential on the fly: "
+                        "1D M=256 c=30 400 steps; 2D 512x512 c=(30,15) 2000 steps, FP64", **out}
 
 
 def free_space_leg(runs: int) -> dict:
@@ -384,6 +422,8 @@ def main():
         res["split"] = split_leg(args.split_steps)
     if not args.no_free:
         res["free_space"] = free_space_leg(args.free_runs)
+    if not args.no_well:
+        res["moving_well"] = moving_well_leg()
     if not args.no_batch:
         res["batch"] = batch_leg(args.batch_runs)
     if not args.no_cpu:

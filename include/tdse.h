@@ -64,6 +64,14 @@ extern "C" {
 #define TDSE_F_SIN       1     /* f_r(t) = 1 + f_params[2r] sin(f_params[2r+1] t) */
 #define TDSE_F_CALLBACK  2     /* f_r(t) = f_fn(r, t, f_ctx)                   */
 
+/* potential kinds (V_kind) */
+#define TDSE_V_FIELDS    0     /* V = sum_r f_r(t) V_r(x) from nV stored fields */
+#define TDSE_V_MOVING_WELL 1   /* Example 1 of Section 6: periodic Gaussian well moving at constant velocity,
+                                  V = -V0 sum_k exp(-|x - 2 pi k - c t|^2 / (2 beta^2)), evaluated on the fly;
+                                  V_params = {V0, beta, c[0], c[1]} (c[a] along axis a; 0 < beta <= 1, so at most
+                                  three images per axis lie within 9.2 beta of a point);
+                                  periodic plans; no fields (nV = 0, V_fields NULL) */
+
 #define TDSE_A_NONE      0     /* A = 0                                        */
 #define TDSE_A_PULSE_SIN2 1    /* A = E0 sin^2(pi t/Tp) sin(w t) dir; A_params = {E0, w, Tp, dir[0..d-1]} */
 #define TDSE_A_CALLBACK  2     /* A(t) from A_fn; phi = int A by Gauss-Legendre per step */
@@ -83,7 +91,7 @@ typedef struct {
   int32_t order;           /* implicit Adams order n in {2,4,6,8}            */
   int32_t n_start;         /* Richardson start-up steps; < 0 means n - 2     */
   int32_t precision;       /* TDSE_FP64 | TDSE_FP32_SPLIT                    */
-  int32_t nV;              /* number of spatial fields, 1..8                 */
+  int32_t nV;              /* number of spatial fields, 1..8 (0: V_kind well) */
   const double* V_fields;  /* host [nV][prod M] real, last axis fastest      */
   int32_t f_kind;          /* TDSE_F_*                                       */
   const double* f_params;  /* TDSE_F_SIN: [nV][2] = (amp, omega)             */
@@ -101,6 +109,9 @@ typedef struct {
   int32_t p, q, panels;
   int32_t nu[2];
   double  H;
+  /* potential kind (TDSE_V_*; 0 = stored fields) and its parameters */
+  int32_t V_kind;
+  double  V_params[4];
 } tdse_problem_t;
 
 typedef struct tdse_plan_s* tdse_plan_t;   /* opaque, owned by the library  */

@@ -113,10 +113,39 @@ class PeriodicOracle:
     # --- problem data ---------------------------------------------------------
     def V(self, t: float) -> np.ndarray:
         p = self.prob
+        if getattr(p, "V_kind", "fields") == "moving_well":
+            return self.moving_well(t)
         out = np.zeros(self.shape)
         for r, Vr in enumerate(p.V_fields):
             out = out + p.f(r, t) * Vr
         return out
+
+    def moving_well(self, t: float) -> np.ndarray:
+        """Example 1 of Section 6: the periodic extension of a Gaussian well
+        of depth V0 and width beta whose centre moves as c t,
+            V(x, t) = sum over k in Z^d of -V0 exp(-|x - 2 pi k - c t|^2 / (2 beta^2)),
+        summed over every image within 3 periods of the centre (for beta <= 1
+        the rest are below exp(-(5 pi)^2 / 2)).  Cached per time."""
+        key = float(t)
+        cache = self.__dict__.setdefault("_well_cache", {})
+        if key in cache:
+            return cache[key].copy()
+        p = self.prob
+        V0, beta = p.V_well[0], p.V_well[1]
+        c = np.asarray(p.V_well[2:2 + p.dim], dtype=np.float64)
+        axes = [-np.pi + 2.0 * np.pi * np.arange(m) / m for m in p.M]
+        X = np.meshgrid(*axes, indexing="ij")
+        out = np.zeros(self.shape)
+        # the images that matter have x - 2 pi k - c t in [-pi, pi): k near -c t / (2 pi)
+        k0 = [int(np.round(-c[a] * t / (2.0 * np.pi))) for a in range(p.dim)]
+        ranges = [range(k0[a] - 3, k0[a] + 4) for a in range(p.dim)]
+        for ks in np.array(np.meshgrid(*ranges, indexing="ij")).reshape(p.dim, -1).T:
+            r2 = np.zeros(self.shape)
+            for a in range(p.dim):
+                r2 = r2 + (X[a] - 2.0 * np.pi * ks[a] - c[a] * t) ** 2
+            out = out - V0 * np.exp(-r2 / (2.0 * beta * beta))
+        cache[key] = out
+        return out.copy()
 
     def phi_at(self, t: float) -> np.ndarray:
         key = float(t)

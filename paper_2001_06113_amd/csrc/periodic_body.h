@@ -96,6 +96,22 @@ __device__ __forceinline__ void build_phase_table(const LineArgs& a, int nthread
   }
 }
 
+// Moving periodic Gaussian well (Example 1 of Section 6), one axis:
+// sum_{|k| <= K} exp(-(d + 2 pi k)^2 s) for the offset d = x - centre
+// wrapped into [-pi, pi), s = 1/(2 beta^2).  The host picks K so that every
+// image within 9.2 beta of x is kept; the ones left out are below
+// exp(-42) ~ 4e-19 of the well depth.
+__device__ __forceinline__ double well_images(double d, double s, int K) {
+  constexpr double TWO_PI = 6.28318530717958647692528676655900577;
+  d -= TWO_PI * floor((d + 0.5 * TWO_PI) / TWO_PI);
+  double acc = exp(-(d * d) * s);
+  for (int k = 1; k <= K; ++k) {
+    const double y1 = d + TWO_PI * k, y2 = d - TWO_PI * k;
+    acc += exp(-(y1 * y1) * s) + exp(-(y2 * y2) * s);
+  }
+  return acc;
+}
+
 // Workgroups are dealt to the eight XCDs round-robin.  Neighbouring column
 // tiles share 128-byte lines (of the tile data and of the potential), so the
 // G tiles Gq..Gq+G-1 go to workgroups b, b+8, ..., b+8(G-1), which sit on the
@@ -187,6 +203,18 @@ __device__ __forceinline__ void col_body(const LineArgs& a, int line0, int blk, 
 #pragma unroll
     for (int m = 0; m < EPT; ++m) v0[m] = V[g0 + m * gs];
   }
+  // moving well: V = -V0 prod_axes well_images(x_a - centre_a); the last
+  // axis' factor is fixed along a column (x of the column index, or of the
+  // point itself for a 1D problem)
+  constexpr double PI = 3.14159265358979323846264338327950288;
+  const bool well = a.vkind == 1;
+  const int wK = well ? (int)a.fV[4] : 0;
+  const double wline = well ? a.fV[0] * well_images(-PI + 2.0 * PI * line / a.M2 - a.fV[3], a.fV[1], wK) : 0.0;
+  auto V_at = [&](int m) -> double {
+    if (!well) return vv[m] + f0 * v0[m];
+    if (a.M1 == 1) return wline;
+    return wline * well_images(-PI + 2.0 * PI * (t + TL * m) / a.M1 - a.fV[2], a.fV[1], wK);
+  };
   auto more_fields = [&]() {
     if (!active) return;
     for (int r = 1; r < a.nV; ++r) {
@@ -205,7 +233,7 @@ __device__ __forceinline__ void col_body(const LineArgs& a, int line0, int blk, 
     more_fields();
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
-      const double Vs = vv[m] + f0 * v0[m];
+      const double Vs = V_at(m);
       const double cr = a.alpha_re + a.beta_re * Vs, ci = a.alpha_im + a.beta_im * Vs;
       const double2 u = F64 ? to_d(v[m]) : u0[m];
       v[m] = from_d<C>(double2{(cr * u.x - ci * u.y) * a.scale, (cr * u.y + ci * u.x) * a.scale});
@@ -216,7 +244,7 @@ __device__ __forceinline__ void col_body(const LineArgs& a, int line0, int blk, 
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
       const C w = v[m];
-      const double Vs = vv[m] + f0 * v0[m];
+      const double Vs = V_at(m);
       const R q = (R)(a.csolve * Vs);
       const R inv = R(1) / (R(1) + q * q);
       // u = w (1 - i q) / (1 + q^2)

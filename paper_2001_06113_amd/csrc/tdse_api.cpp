@@ -389,8 +389,21 @@ struct tdse_plan_s {
   bool split() const { return precision == TDSE_FP32_SPLIT && !force_fp64; }
 
   double t_at(int m) const { return m * dt; }
+  // moving well (TDSE_V_MOVING_WELL): V0, 1/(2 beta^2), velocity per axis
+  int vkind = TDSE_V_FIELDS;
+  double well[4] = {0.0, 0.0, 0.0, 0.0};
+  double well_k = 0.0;
   void fV_at(double t, double* f) const {
     for (int r = 0; r < MAXV; ++r) f[r] = r < nV ? tf.f(r, t) : 0.0;
+    if (vkind == TDSE_V_MOVING_WELL) {
+      // the centre c t, wrapped into [-pi, pi) (V is 2 pi periodic in it)
+      auto wrap = [](double x) { return x - 2.0 * M_PI * std::floor((x + M_PI) / (2.0 * M_PI)); };
+      f[0] = -well[0];
+      f[1] = well[1];
+      f[2] = dim == 2 ? wrap(well[2] * t) : 0.0;
+      f[3] = wrap((dim == 2 ? well[3] : well[2]) * t);
+      f[4] = well_k;   // periodic images per side that can lie within 9.2 beta of a point
+    }
   }
 };
 
@@ -416,6 +429,7 @@ LineArgs base_args(const tdse_plan_s* p, int g) {
   a.M2 = p->M2;
   a.V = p->V(g);
   a.nV = p->nV;
+  a.vkind = p->vkind;
   a.vstride = p->P;
   a.scale = 1.0 / (double)p->P;
   a.ring = p->ring(g);
@@ -1794,6 +1808,7 @@ int adj_workers(const tdse_plan_s* p) { return std::max(1, std::min(p->adj_strea
 int adjoint_single(tdse_plan_s* p, char* w, size_t wbytes, int K, const void* u0, const void* lam, int on_device,
                    double* dF_dA, void* dF_du0) {
   if (p->free_space) return fail(TDSE_EUNSUPPORTED, "the adjoint covers the periodic scheme");
+  if (p->vkind != TDSE_V_FIELDS) return fail(TDSE_EUNSUPPORTED, "the adjoint takes potentials from stored fields");
   if (p->tf.A_kind != TDSE_A_STEPWISE) return fail(TDSE_EUNSUPPORTED, "the adjoint differentiates stepwise field samples");
   AdjRun R;
   R.p = p;
@@ -2110,7 +2125,17 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
     if (!good_len(prob->M[a])) return fail(TDSE_EINVAL, "grid size must be 2^a or 3*2^a, 8..3072");
   if (!(prob->T > 0.0) || prob->nsteps < 1) return fail(TDSE_EINVAL, "need T > 0 and nsteps >= 1");
   if (prob->order < 2 || prob->order > 8 || prob->order % 2) return fail(TDSE_EINVAL, "order must be 2, 4, 6 or 8");
-  if (prob->nV < 1 || prob->nV > MAXV || !prob->V_fields) return fail(TDSE_EINVAL, "need 1..8 potential fields");
+  const bool well = prob->V_kind == TDSE_V_MOVING_WELL;
+  if (prob->V_kind != TDSE_V_FIELDS && !well) return fail(TDSE_EINVAL, "bad V_kind");
+  if (well) {
+    if (prob->domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "the moving well is a periodic potential");
+    if (!(prob->V_params[1] > 0.0 && prob->V_params[1] <= 1.0))
+      return fail(TDSE_EINVAL, "moving well: need 0 < beta <= 1 (at most three periodic images per axis)");
+    for (int k = 0; k < 4; ++k)
+      if (!std::isfinite(prob->V_params[k])) return fail(TDSE_EINVAL, "moving well: non-finite parameter");
+  } else if (prob->nV < 1 || prob->nV > MAXV || !prob->V_fields) {
+    return fail(TDSE_EINVAL, "need 1..8 potential fields");
+  }
   if (prob->f_kind == TDSE_F_SIN && !prob->f_params) return fail(TDSE_EINVAL, "f_params missing");
   if (prob->f_kind == TDSE_F_CALLBACK && !prob->f_fn) return fail(TDSE_EINVAL, "f_fn missing");
   if (prob->f_kind < 0 || prob->f_kind > 2) return fail(TDSE_EINVAL, "bad f_kind");
@@ -2135,7 +2160,16 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   p->nsteps = prob->nsteps;
   p->T = prob->T;
   p->dt = prob->T / prob->nsteps;
-  p->nV = prob->nV;
+  p->nV = well ? 0 : prob->nV;
+  if (well) {
+    p->vkind = TDSE_V_MOVING_WELL;
+    p->well[0] = prob->V_params[0];
+    p->well[1] = 1.0 / (2.0 * prob->V_params[1] * prob->V_params[1]);
+    // |x - centre + 2 pi k| <= 9.2 beta with |x - centre| <= pi
+    p->well_k = std::floor((9.2 * prob->V_params[1] + M_PI) / (2.0 * M_PI));
+    p->well[2] = prob->V_params[2];
+    p->well[3] = prob->V_params[3];
+  }
   p->precision = prob->precision;
   p->mu = adams_weights(p->order);
   p->rich = richardson_weights(p->L);
@@ -2148,7 +2182,8 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
     // the potential stays FP64 in both forms: rounded to FP32 it would be a
     // fixed perturbation of the Hamiltonian whose error grows linearly in time
     S.real = 8;
-    if (g == 0) S.Vhost.assign((const char*)prob->V_fields, (const char*)(prob->V_fields + (size_t)p->nV * p->P));
+    if (g == 0 && p->nV > 0)
+      S.Vhost.assign((const char*)prob->V_fields, (const char*)(prob->V_fields + (size_t)p->nV * p->P));
   }
 
   TimeFns& tf = p->tf;

@@ -47,11 +47,15 @@ struct LineArgs {
   int M1, M2;          // grid (M1 = 1 for a 1D problem)
   const void* tw;      // twiddles of this line length (transform precision)
   int mode;
-  // potential V = sum_r fV[r] V_r
+  // potential V = sum_r fV[r] V_r (vkind 0), or for vkind 1 the moving
+  // periodic Gaussian well evaluated on the fly, with fV = {-V0, 1/(2 beta^2),
+  // centre along axis 0 (2D), centre along the last axis, images per side}
+  // at the pass's time
   const void* V;
   int nV;
   int64_t vstride;
   double fV[MAXV];
+  int vkind;
   // column pass
   double csolve;       // u = w / (1 + i csolve V)
   double scale;        // 1/(M1 M2) folded into the forward transform input

@@ -42,10 +42,14 @@ def problem_struct(*, dim: int, M: Sequence[int], T: float, nsteps: int, V_field
                    n_start: int = -1, precision: str = "fp64", f_kind: str = "const", f_params=None,
                    A_kind: str = "none", A_params=None, A_steps=None, domain: str = "periodic",
                    eps: float = 1e-10, p: int = 8, q: int = 10, panels: int = 1, nu: Sequence[int] = (),
-                   H: float = 0.0):
-    """Fill a tdse_problem_t; returns it with the arrays it points into (keep them alive)."""
+                   H: float = 0.0, V_kind: str = "fields", V_params: Sequence[float] = ()):
+    """Fill a tdse_problem_t; returns it with the arrays it points into (keep them alive).
+    V_kind "moving_well" takes V_params = (V0, beta, c_0[, c_1]) and no fields."""
     M = tuple(int(m) for m in M)
-    V = np.ascontiguousarray(np.asarray(V_fields, dtype=np.float64).reshape(-1, *M))
+    well = V_kind == "moving_well"
+    if V_kind not in ("fields", "moving_well"):
+        raise ValueError(f"unknown V_kind {V_kind!r}")
+    V = None if well else np.ascontiguousarray(np.asarray(V_fields, dtype=np.float64).reshape(-1, *M))
     prob = _lib.Problem()
     prob.dim = dim
     prob.domain = PERIODIC if domain == "periodic" else FREE
@@ -56,9 +60,16 @@ def problem_struct(*, dim: int, M: Sequence[int], T: float, nsteps: int, V_field
     prob.order = int(order)
     prob.n_start = int(n_start)
     prob.precision = FP64 if precision == "fp64" else FP32_SPLIT
-    prob.nV = V.shape[0]
-    keep = [V]
-    prob.V_fields = _dptr(V)
+    keep = []
+    if well:
+        prob.nV = 0
+        prob.V_kind = 1
+        for k, v in enumerate(tuple(V_params) + (0.0,) * (4 - len(V_params))):
+            prob.V_params[k] = float(v)
+    else:
+        prob.nV = V.shape[0]
+        keep.append(V)
+        prob.V_fields = _dptr(V)
     prob.f_kind = F_KINDS[f_kind]
     if f_params is not None:
         fp = np.ascontiguousarray(np.asarray(f_params, dtype=np.float64).ravel())
@@ -92,7 +103,10 @@ def problem_kwargs(prob) -> dict:
     f_params = None
     if sin:
         f_params = [tuple(fp) if k == "sin" else (0.0, 0.0) for fp, k in zip(prob.f_params, prob.f_kind)]
-    return dict(dim=prob.dim, M=prob.M, T=prob.T, nsteps=prob.nsteps, V_fields=np.stack(prob.V_fields),
+    well = getattr(prob, "V_kind", "fields") == "moving_well"
+    return dict(dim=prob.dim, M=prob.M, T=prob.T, nsteps=prob.nsteps,
+                V_fields=None if well else np.stack(prob.V_fields),
+                V_kind="moving_well" if well else "fields", V_params=tuple(prob.V_well) if well else (),
                 order=prob.order, n_start=-1 if prob.n_start is None else prob.n_start,
                 precision=prob.precision, f_kind="sin" if sin else "const", f_params=f_params,
                 A_kind=prob.A_kind, A_params=prob.A_params if prob.A_kind == "pulse_sin2" else None,

@@ -40,10 +40,17 @@ class EmuPlan:
         p.order = prob.order
         p.n_start = -1 if prob.n_start is None else prob.n_start
         p.precision = 0 if prob.precision == "fp64" else 1
-        V = np.ascontiguousarray(np.stack(prob.V_fields).astype(np.float64))
-        self._keep = [V]
-        p.nV = V.shape[0]
-        p.V_fields = V.ctypes.data_as(C.POINTER(C.c_double))
+        self._keep = []
+        if getattr(prob, "V_kind", "fields") == "moving_well":
+            p.nV = 0
+            p.V_kind = 1
+            for k, v in enumerate(tuple(prob.V_well) + (0.0,) * (4 - len(prob.V_well))):
+                p.V_params[k] = v
+        else:
+            V = np.ascontiguousarray(np.stack(prob.V_fields).astype(np.float64))
+            self._keep.append(V)
+            p.nV = V.shape[0]
+            p.V_fields = V.ctypes.data_as(C.POINTER(C.c_double))
         if any(k == "sin" for k in prob.f_kind):
             fp = np.array([tuple(f) if k == "sin" else (0.0, 0.0) for f, k in zip(prob.f_params, prob.f_kind)],
                           dtype=np.float64).ravel()

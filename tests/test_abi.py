@@ -105,6 +105,26 @@ def test_plan_rejects(lib, kw, status):
     assert lib.tdse_last_error().decode()
 
 
+@pytest.mark.parametrize("V_kind,params,domain,status", [
+    (2, (300.0, 0.2, 15.0, 0.0), 0, -1),        # unknown potential kind
+    (1, (300.0, 0.2, 15.0, 0.0), 1, -2),        # the moving well is periodic only
+    (1, (300.0, 1.5, 15.0, 0.0), 0, -1),        # beta > 1
+    (1, (300.0, 0.0, 15.0, 0.0), 0, -1),
+    (1, (300.0, 0.2, float("nan"), 0.0), 0, -1),
+    (1, (300.0, 0.2, 15.0, 0.0), 0, 0),         # valid, with no fields
+])
+def test_moving_well_planning(lib, V_kind, params, domain, status):
+    p = _problem(dim=1, M=(64,), domain=domain, nV=0)
+    p.V_kind = V_kind
+    for k, v in enumerate(params):
+        p.V_params[k] = v
+    p.V_fields = C.POINTER(C.c_double)()
+    st, h = _plan(lib, p)
+    assert st == status, lib.tdse_last_error()
+    if st == 0:
+        lib.tdse_destroy(h)
+
+
 def test_calls_out_of_order(lib):
     st, h = _plan(lib, _problem())
     assert st == 0

@@ -81,3 +81,13 @@ def test_emulated_batch_adjoint_on_several_streams(emu):
         assert np.linalg.norm(res[4][1][i] - g0) <= 1e-12 * np.linalg.norm(g0)
     assert emu.tdse_adjoint_streams(b.h, 0) != 0
     assert emu.tdse_adjoint_streams(b.h, 17) != 0
+
+
+def test_adjoint_rejects_the_moving_well(emu):
+    # the adjoint's point kernels take the potential from stored fields
+    from emu.emu_plan import EmuPlan, emu_adjoint
+    from workloads import moving_well_problem
+
+    prob = moving_well_problem(c=(15.0,), M=(64,), T=0.05, nsteps=8)
+    with pytest.raises(RuntimeError, match="stored fields"):
+        emu_adjoint(EmuPlan(emu, prob), prob.u0, prob.u0)

@@ -68,3 +68,25 @@ def test_emulated_split_long_run_high_potential(emu):
     u = EmuPlan(emu, prob).run(prob.u0)
     ref, _ = PeriodicOracle(prob).run()
     assert _rel(u, ref) < 1e-6
+
+
+WELL_CASES = [
+    dict(M=(64,), c=(15.0,), N=30, precision="fp64", tol=1e-12),
+    dict(M=(16, 24), c=(15.0, -7.5), N=20, precision="fp64", tol=1e-12),
+    dict(M=(64,), c=(45.0,), N=30, precision="fp32split", tol=1e-6),
+    dict(M=(16, 24), c=(15.0, -7.5), N=20, precision="fp64", tol=1e-12, beta=0.8),   # one image per side
+]
+
+
+@pytest.mark.parametrize("case", WELL_CASES, ids=[f"well-{c['M']}-{c['precision']}-b{c.get('beta', 0.2)}" for c in WELL_CASES])
+def test_emulated_moving_well_matches_oracle(emu, case):
+    # the moving periodic Gaussian well (Example 1), evaluated on the fly in
+    # the column pass, against the oracle's image sum
+    from emu.emu_plan import EmuPlan
+    from workloads import moving_well_problem
+
+    prob = moving_well_problem(c=case["c"], M=case["M"], T=0.05, nsteps=case["N"], precision=case["precision"],
+                               beta=case.get("beta", 0.2))
+    u = EmuPlan(emu, prob).run(prob.u0)
+    ref, _ = PeriodicOracle(prob).run()
+    assert _rel(u, ref) < case["tol"]

@@ -15,4 +15,5 @@ from .synth import (  # noqa: F401
     batch_64_problems,
     periodic_problem_from_seed,
     free_problem_from_seed,
+    moving_well_problem,
 )

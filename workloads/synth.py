@@ -57,6 +57,10 @@ class Problem:
     q: int = 10
     panels: int = 1
     nu: Tuple[int, ...] = ()
+    # potential kind: "fields" (V_fields with time factors) or "moving_well"
+    # with V_well = (V0, beta, c_0[, c_1]) (Example 1 of Section 6)
+    V_kind: str = "fields"
+    V_well: Tuple[float, ...] = ()
     meta: dict = field(default_factory=dict)
 
     @property
@@ -226,6 +230,28 @@ def _bump(s: np.ndarray) -> np.ndarray:
     inside = np.abs(s) < 1.0
     out[inside] = np.exp(1.0 - 1.0 / (1.0 - s[inside] ** 2))
     return out
+
+
+def moving_well_problem(c: Sequence[float] = (15.0,), M: Sequence[int] = (256,), T: float = 2.0 * np.pi / 15.0,
+                        nsteps: int = 400, V0: float = 300.0, beta: float = 0.2, order: int = 8,
+                        precision: str = "fp64", name: str = "moving-well") -> Problem:
+    """Example 1 of Section 6 (a periodic Gaussian well of depth V0 and width
+    beta moving with constant velocity c, A = 0), in 1D or 2D (len(M)).  The
+    paper starts from the well's ground state computed with Chebfun, which is
+    not available here; u0 is a periodized Gaussian of the width of the
+    harmonic approximation to that ground state, exp(-|x|^2 / (2 s^2)) with
+    s = (2 V0 / beta^2)^(-1/4), centred on the well, normalized."""
+    dim = len(M)
+    X = [periodic_grid(m) for m in M]
+    X = list(np.meshgrid(*X, indexing="ij")) if dim == 2 else X
+    s_w = (2.0 * V0 / beta ** 2) ** -0.25
+    u0 = _periodized_gauss(X, [0.0] * dim, np.sqrt(2.0) * s_w, images=2).astype(np.complex128)
+    cell = float(np.prod([TWO_PI / m for m in M]))
+    u0 = _normalize(u0, cell)
+    c = tuple(float(x) for x in c)
+    return Problem(name=name, dim=dim, domain="periodic", M=tuple(int(m) for m in M), T=T, nsteps=nsteps,
+                   order=order, u0=u0, V_fields=[], f_kind=[], f_params=[], precision=precision,
+                   V_kind="moving_well", V_well=(V0, beta) + c)
 
 
 def free_problem_from_seed(seed: int, dim: int, M: Sequence[int], T: float, nsteps: int,
