@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFS = 78.6   # 256 CUs x 64 FP64 FMA lanes x 2 flops x 2.4 GHz
 
 
 def parse():
@@ -247,6 +248,7 @@ def free_space_leg(runs: int) -> dict:
     n_modes = plan.query(81) * plan.query(82)
     row_b, col_b = plan.query(Q_BYTES_ROW), plan.query(Q_BYTES_COL)
     ach = row_b / (row_us * 1e-6) / 1e9
+    far = far_field_eval(plan, dev)
     plan.close()
     return {"workload": "2D free-space TDSE 256x256, nu=2048 per axis, eps=1e-10, p=8, q=10, 1 panel, "
                         "T=1, 1000 steps AM8",
@@ -257,7 +259,40 @@ def free_space_leg(runs: int) -> dict:
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                          "traffic": measured_traffic("k_fs_row_2048_traffic.txt", FS_KERNEL_SOURCES),
                          "bytes_per_launch": row_b, "mean_launch_us": row_us, "row_pass_us": row_us,
-                         "col_pass_us": col_us, "col_bytes_per_launch": col_b}}
+                         "col_pass_us": col_us, "col_bytes_per_launch": col_b},
+            "far_field": far}
+
+
+def far_field_eval(plan, dev, n: int = 512, box: float = 2.0, reps: int = 5) -> dict:
+    """u(T) of a free-space plan on an n x n grid of [-box, box]^2 from its
+    complex-frequency representation (tdse_far_eval): wall time per call, and
+    the first product (the contraction over the last axis, 8 N1 N2 n flops)
+    timed by dispatch-recorded HIP events against the FP64 vector peak."""
+    import torch
+
+    from paper_2001_06113_amd.tdse import Q_PROF_MS_FAR, Q_PROF_N_FAR
+
+    pts = torch.linspace(-box, box, n, dtype=torch.float64, device=dev)
+    out = plan.far_eval(pts, pts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = plan.far_eval(pts, pts)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    plan.profile(True)
+    for _ in range(reps):
+        plan.far_eval(pts, pts)
+    g_us = plan.query(Q_PROF_MS_FAR) * 1e3 / max(plan.query(Q_PROF_N_FAR), 1)
+    plan.profile(False)
+    N1, N2 = plan.query(81), plan.query(82)
+    flops = 8.0 * N1 * N2 * n
+    ach = flops / (g_us * 1e-6) / 1e12
+    return {"points": [n, n], "box": [-box, box], "ms_per_eval": wall * 1e3,
+            "finite": bool(torch.isfinite(torch.view_as_real(out)).all().item()),
+            "roofline": {"bound": "alu", "kernel": "far-field product over the last axis (k_far_gemm)",
+                         "achieved": ach, "peak": FP64_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+                         "frac": ach / FP64_VECTOR_PEAK_TFS, "flops_per_launch": flops, "mean_launch_us": g_us}}
 
 
 def batch_leg(runs: int) -> dict:

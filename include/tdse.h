@@ -147,6 +147,32 @@ int tdse_get_state(tdse_plan_t plan, void* u, int32_t on_device);
 /* set_state(u0) + step(all remaining) + get_state(uT). */
 int tdse_run(tdse_plan_t plan, const void* u0, void* uT, int32_t on_device);
 
+/* ---- evaluation of a free-space solution at arbitrary points -----------
+ *
+ * Once uhat(zeta, t) is resolved on Gamma_K, the complex-frequency
+ * representation u(x, t) = (1/2pi) int_{Gamma_K} exp(i zeta . x) uhat d zeta
+ * (Section 3.2) holds at every real x, inside [-1,1]^d or outside it (Remark
+ * on evaluation outside [-1,1]).  tdse_far_eval evaluates its discretization
+ * on the plan's own nodes and weights (eq. (uciftdisc)),
+ *   u(x_i, y_j) = sum_{k1,k2} (w_k1 w_k2 / 4 pi^2) exp(i (zeta_k1 x_i + zeta_k2 y_j)) uhat_k1k2,
+ * on the tensor grid of the axis-0 points xs[0..nx) and the last-axis points
+ * ys[0..ny) (a 1D plan: nx = 1, xs ignored, may be NULL).  The nodes are not
+ * refined, so accuracy falls off with |x| - 1 as exp(H (|x| - 1)) amplifies
+ * rounding and truncation (about 1e-12 at |x| = 2 for the wave packet of
+ * Section 6, Example 2 with eps = 1e-12).
+ *
+ * The mode state exists at t = 0 (uhat = F u0), after each start-up step, and
+ * at t = T (uhat_N = B_N - i mu_0 dt F(V u_N)); at other times ESTATE.
+ * xs, ys, out (complex128, nx x ny row-major: out[i ny + j] = u(xs[i], ys[j]))
+ * and work (caller-owned, 256-byte aligned, size from tdse_far_workspace_size)
+ * are device pointers; the call is asynchronous on the bound stream.  Free-space
+ * plans only (EUNSUPPORTED otherwise); 1 <= nx, ny <= 2^24.  With profiling on
+ * (tdse_profile), the first product (the contraction over the last axis) is
+ * timed into TDSE_Q_PROF_MS_FAR. */
+int tdse_far_workspace_size(tdse_plan_t plan, int32_t nx, int32_t ny, size_t* bytes);
+int tdse_far_eval(tdse_plan_t plan, const double* xs, int32_t nx, const double* ys, int32_t ny, void* out,
+                  void* work, size_t bytes);
+
 /* Scalar queries (keys below). */
 #define TDSE_Q_MODES          0   /* modes per instance (prod M)               */
 #define TDSE_Q_STEPS_DONE     1   /* steps taken since set_state               */
@@ -158,6 +184,8 @@ int tdse_run(tdse_plan_t plan, const void* u0, void* uT, int32_t on_device);
 #define TDSE_Q_PROF_N_ROW    11   /* profiling: number of timed row passes     */
 #define TDSE_Q_BYTES_COL     12   /* algorithmic HBM bytes of one Adams column pass */
 #define TDSE_Q_BYTES_ROW     13   /* algorithmic HBM bytes of one Adams row pass    */
+#define TDSE_Q_PROF_MS_FAR   14   /* profiling: summed ms of tdse_far_eval's first product */
+#define TDSE_Q_PROF_N_FAR    15   /* profiling: number of timed tdse_far_eval calls        */
 #define TDSE_Q_MU             16  /* + j: Adams weight mu_j                    */
 #define TDSE_Q_RICHARDSON     32  /* + l: weight of the 2^l-sub-step result    */
 #define TDSE_Q_PHI            64  /* + axis: phi_axis(T)                       */

@@ -87,6 +87,19 @@ class FreeSpaceOracle:
             out = np.moveaxis(np.tensordot(self.Ginv[a], np.moveaxis(out, a, 0), axes=(1, 0)), 0, a)
         return out
 
+    def evaluate(self, uhat: np.ndarray, points) -> np.ndarray:
+        """u on the tensor grid points[0] x ... x points[d-1] from the modes
+        uhat on Gamma_K: the discrete representation (eq. (uciftdisc)) taken at
+        arbitrary real coordinates, which may lie outside [-1,1] (Remark on
+        evaluation outside [-1,1]); the nodes are not refined."""
+        out = np.asarray(uhat, dtype=np.complex128)
+        for a in range(self.d):
+            zeta, w, _ = self.nodes[a]
+            x = np.asarray(points[a], dtype=np.float64)
+            E = (w[None, :] / (2 * np.pi)) * np.exp(1j * np.outer(x, zeta))
+            out = np.moveaxis(np.tensordot(E, np.moveaxis(out, a, 0), axes=(1, 0)), 0, a)
+        return out
+
     # --- problem data ----------------------------------------------------------
     def V(self, t: float) -> np.ndarray:
         p = self.prob

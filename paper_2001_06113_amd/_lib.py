@@ -32,7 +32,7 @@ EXPORTS = [
     "tdse_get_state", "tdse_run", "tdse_query", "tdse_destroy", "tdse_status_string",
     "tdse_last_error", "tdse_profile", "tdse_graph", "tdse_plan_batch", "tdse_autotune",
     "tdse_set_instance_state", "tdse_get_instance_state", "tdse_set_field", "tdse_adjoint_workspace_size",
-    "tdse_adjoint", "tdse_adjoint_streams",
+    "tdse_adjoint", "tdse_adjoint_streams", "tdse_far_workspace_size", "tdse_far_eval",
 ]
 
 _lib = None
@@ -67,6 +67,8 @@ def load() -> C.CDLL:
     lib.tdse_adjoint_workspace_size.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
     lib.tdse_adjoint.argtypes = [P, P, C.c_size_t, C.c_int32, P, P, C.c_int32, C.POINTER(C.c_double), P]
     lib.tdse_adjoint_streams.argtypes = [P, C.c_int32]
+    lib.tdse_far_workspace_size.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+    lib.tdse_far_eval.argtypes = [P, P, C.c_int32, P, C.c_int32, P, P, C.c_size_t]
     lib.tdse_destroy.argtypes = [P]
     lib.tdse_destroy.restype = None
     lib.tdse_status_string.argtypes = [C.c_int]
@@ -76,7 +78,8 @@ def load() -> C.CDLL:
     for name in ("tdse_plan", "tdse_workspace_size", "tdse_bind", "tdse_set_state", "tdse_step",
                  "tdse_get_state", "tdse_run", "tdse_query", "tdse_plan_batch", "tdse_autotune",
                  "tdse_set_instance_state", "tdse_get_instance_state", "tdse_set_field",
-                 "tdse_adjoint_workspace_size", "tdse_adjoint", "tdse_adjoint_streams"):
+                 "tdse_adjoint_workspace_size", "tdse_adjoint", "tdse_adjoint_streams", "tdse_far_workspace_size",
+                 "tdse_far_eval"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -1,0 +1,115 @@
+// Evaluation of a free-space solution at arbitrary points from its
+// complex-frequency representation on Gamma_K (Section 3.2 and the Remark
+// on evaluation outside [-1,1]), gfx950:
+//   u(x_i, y_j) = sum_{k1,k2} E1[k1][i] E2[k2][j] uhat[k1][k2],
+//   E_a[k][i]   = (w_k / 2 pi) exp(i zeta_k x_i)      (quadrature of axis a),
+// as a table kernel per axis and two complex FP64 products,
+//   S = uhat E2 (N1 x ny), then u = E1^T S (nx x ny).
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include "tdse_internal.h"
+
+namespace tdse {
+
+// E[k * n + i] = (w_k / 2 pi) exp(i zeta_k x_i), k < N, i < n
+__global__ __launch_bounds__(256) void k_far_table(const double2* __restrict__ zeta, const double2* __restrict__ w,
+                                                   int N, const double* __restrict__ x, int n,
+                                                   double2* __restrict__ E) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (int64_t)N * n) return;
+  const int k = (int)(g / n), i = (int)(g % n);
+  constexpr double INV_2PI = 0.159154943091895335768883763372514362;
+  const double2 z = zeta[k], wk = w[k];
+  const double xi = x[i];
+  // exp(i zeta x) = exp(-Im(zeta) x) (cos(Re(zeta) x) + i sin(Re(zeta) x))
+  double s, c;
+  sincos(z.x * xi, &s, &c);
+  const double m = exp(-z.y * xi) * INV_2PI;
+  const double er = m * c, ei = m * s;
+  E[g] = double2{wk.x * er - wk.y * ei, wk.x * ei + wk.y * er};
+}
+
+// C[m][n] = sum_k A[m sam + k sak] B[k sbk + n sbn] (complex128), C row-major
+// with leading dimension ldc.  A workgroup computes a 64 x 64 tile of C: 256
+// threads in a 16 x 16 layout, each owning the 4 x 4 outputs m0 + tm + 16 a,
+// n0 + tn + 16 b; K advances in chunks of 16 staged through LDS, with zeros
+// beyond the operands' edges.  Tiles are numbered along n first.
+constexpr int FAR_T = 64, FAR_K = 16;
+__global__ __launch_bounds__(256) void k_far_gemm(int M, int N, int K, const double2* __restrict__ A, int64_t sam,
+                                                  int64_t sak, const double2* __restrict__ B, int64_t sbk,
+                                                  int64_t sbn, double2* __restrict__ C, int64_t ldc) {
+  __shared__ double2 As[FAR_K][FAR_T + 1];
+  __shared__ double2 Bs[FAR_K][FAR_T + 1];
+  const int tid = threadIdx.x;
+  const int tm = tid / 16, tn = tid % 16;
+  const int ntn = (N + FAR_T - 1) / FAR_T;
+  const int m0 = (blockIdx.x / ntn) * FAR_T, n0 = (blockIdx.x % ntn) * FAR_T;
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = double2{0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += FAR_K) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;   // 0 .. FAR_T * FAR_K - 1
+      // A: consecutive threads along k when A is contiguous in k, else along m
+      const int ka = sak == 1 ? e % FAR_K : e / FAR_T, ma = sak == 1 ? e / FAR_K : e % FAR_T;
+      const int gm = m0 + ma, gka = k0 + ka;
+      As[ka][ma] = (gm < M && gka < K) ? A[(int64_t)gm * sam + (int64_t)gka * sak] : double2{0.0, 0.0};
+      // B: consecutive threads along n
+      const int kb = e / FAR_T, nb = e % FAR_T;
+      const int gn = n0 + nb, gkb = k0 + kb;
+      Bs[kb][nb] = (gn < N && gkb < K) ? B[(int64_t)gkb * sbk + (int64_t)gn * sbn] : double2{0.0, 0.0};
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < FAR_K; ++kk) {
+      double2 av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][tm + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tn + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          acc[a][b].x += av[a].x * bv[b].x - av[a].y * bv[b].y;
+          acc[a][b].y += av[a].x * bv[b].y + av[a].y * bv[b].x;
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int gm = m0 + tm + 16 * a, gn = n0 + tn + 16 * b;
+      if (gm < M && gn < N) C[(int64_t)gm * ldc + gn] = acc[a][b];
+    }
+}
+
+hipError_t launch_far_table(const double2* zeta, const double2* w, int N, const double* x, int n, double2* E,
+                            hipStream_t s) {
+  const int64_t tot = (int64_t)N * n;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_far_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, zeta, w, N, x, n, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_far_gemm(int M, int N, int K, const double2* A, int64_t sam, int64_t sak, const double2* B,
+                           int64_t sbk, int64_t sbn, double2* C, int64_t ldc, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int64_t tiles = (int64_t)((M + FAR_T - 1) / FAR_T) * ((N + FAR_T - 1) / FAR_T);
+  // with events, recorded at the kernel's own start and end
+  if (e0)
+    hipExtLaunchKernelGGL(k_far_gemm, dim3((unsigned)tiles), dim3(256), 0, s, e0, e1, 0, M, N, K, A, sam, sak, B, sbk,
+                          sbn, C, ldc);
+  else
+    hipLaunchKernelGGL(k_far_gemm, dim3((unsigned)tiles), dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace tdse

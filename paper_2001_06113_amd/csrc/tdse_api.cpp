@@ -907,8 +907,9 @@ void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels) 
     const double2 zz = F.zeta[NE + q2];
     rfwd[q2] = cexp_ld((LD)zz.y * 2.0L / (LD)M, -(LD)zz.x * 2.0L / (LD)M);
   }
+  std::vector<double2> wv(F.w);
   std::vector<std::vector<double2>*> parts = {&pre3, &pre1, &ipost3, &ipost1, &post3, &post1, &ipre3,
-                                              &ipre1, &Dfwd, &Dinv, &twt, &z, &rfwd};
+                                              &ipre1, &Dfwd, &Dinv, &twt, &z, &rfwd, &wv};
   size_t bytes = 0;
   for (auto* v : parts) bytes = align256(bytes + v->size() * sizeof(double2));
   F.tables.assign(bytes, 0);
@@ -952,6 +953,7 @@ CFAxis cf_axis(const tdse_plan_s* p, int axis) {
   c.tw = take(F.nu);
   c.zeta = take(F.N);
   c.rfwd = take(F.ND);
+  c.wq = take(F.N);
   return c;
 }
 
@@ -2361,6 +2363,95 @@ int tdse_get_state(tdse_plan_t p, void* u, int32_t on_device) {
   return TDSE_OK;
 }
 
+// ---------------------------------------------- evaluation at arbitrary points
+
+namespace {
+struct FarLayout {
+  size_t uh = 0, e1 = 0, e2 = 0, S = 0, total = 0;
+};
+FarLayout far_layout(const tdse_plan_s* p, int nx, int ny) {
+  FarLayout L;
+  const size_t N1 = (size_t)p->fx[0].N, N2 = (size_t)p->fx[1].N, z = sizeof(double2);
+  size_t off = 0;
+  L.uh = off; off = align256(off + (size_t)p->NM * z);
+  L.e2 = off; off = align256(off + N2 * ny * z);
+  if (p->dim == 2) {
+    L.e1 = off; off = align256(off + N1 * nx * z);
+    L.S = off; off = align256(off + N1 * ny * z);
+  }
+  L.total = off;
+  return L;
+}
+int far_check(const tdse_plan_s* p, int nx, int ny) {
+  if (p->is_batch() || !p->free_space) return fail(TDSE_EUNSUPPORTED, "evaluation at arbitrary points is for free-space plans");
+  if (ny < 1 || nx < 1 || ny > (1 << 24) || nx > (1 << 24)) return fail(TDSE_EINVAL, "need 1 <= nx, ny <= 2^24");
+  if (p->dim == 1 && nx != 1) return fail(TDSE_EINVAL, "a 1D plan takes nx = 1");
+  return TDSE_OK;
+}
+}  // namespace
+
+int tdse_far_workspace_size(tdse_plan_t p, int32_t nx, int32_t ny, size_t* bytes) {
+  if (!p || !bytes) return fail(TDSE_EINVAL, "NULL argument");
+  const int s = far_check(p, nx, ny);
+  if (s) return s;
+  *bytes = far_layout(p, nx, ny).total;
+  return TDSE_OK;
+}
+
+int tdse_far_eval(tdse_plan_t p, const double* xs, int32_t nx, const double* ys, int32_t ny, void* out, void* work,
+                  size_t bytes) {
+  if (!p || !ys || !out || !work || (p->dim == 2 && !xs)) return fail(TDSE_EINVAL, "NULL argument");
+  int s = far_check(p, nx, ny);
+  if (s) return s;
+  if (!p->bound || p->cur < 0) return fail(TDSE_ESTATE, "no state");
+  const FarLayout L = far_layout(p, nx, ny);
+  if (bytes < L.total) return fail(TDSE_ENOMEM, "far-evaluation workspace too small");
+  if (((uintptr_t)work) % 256) return fail(TDSE_EINVAL, "far-evaluation workspace must be 256-byte aligned");
+  char* w = (char*)work;
+  double2* uh = (double2*)(w + L.uh);
+  // uhat at the current time
+  if (p->cur == 0) {
+    s = fs_forward(p, 0.0, 1.0, 0.0, 0.0, 0.0, uh);   // F u0 (Section 3.3)
+  } else if (p->cur <= p->ns) {
+    HIP_TRY(hipMemcpyAsync(uh, p->UH(p->uh_cur), (size_t)p->NM * sizeof(double2), hipMemcpyDeviceToDevice, p->stream));
+  } else if (p->cur == p->nsteps) {
+    // uhat_N = B_N - i mu_0 dt F(V(t_N) u_N) (the implicit Adams step's mode update)
+    s = fs_forward(p, p->t_at(p->nsteps), 0.0, 0.0, 0.0, -p->mu[0] * p->dt, uh);
+    if (!s) {
+      const hipError_t e = launch_adj_axpy(p->NM, p->B(), uh, 1.0, 0.0, uh, p->stream);
+      if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("axpy: ") + hipGetErrorString(e));
+    }
+  } else {
+    return fail(TDSE_ESTATE, "the mode state is kept at t = 0, the start-up steps and t = T only");
+  }
+  if (s) return s;
+  const CFAxis a1 = cf_axis(p, 0), a2 = cf_axis(p, 1);
+  const int N1 = a1.N, N2 = a2.N;
+  double2* E2 = (double2*)(w + L.e2);
+  hipError_t e = launch_far_table(a2.zeta, a2.wq, N2, ys, ny, E2, p->stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const size_t first = p->ev_used;
+  if (p->prof) {
+    e0 = next_event(p);
+    e1 = next_event(p);
+    if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
+  }
+  if (p->dim == 1) {
+    // u(y_j) = sum_k uhat[k] E2[k][j]
+    if (e == hipSuccess) e = launch_far_gemm(1, ny, N2, uh, N2, 1, E2, ny, 1, (double2*)out, ny, p->stream, e0, e1);
+  } else {
+    double2* E1 = (double2*)(w + L.e1);
+    double2* S = (double2*)(w + L.S);
+    if (e == hipSuccess) e = launch_far_table(a1.zeta, a1.wq, N1, xs, nx, E1, p->stream);
+    // S[k1][j] = sum_k2 uhat[k1][k2] E2[k2][j]; u[i][j] = sum_k1 E1[k1][i] S[k1][j]
+    if (e == hipSuccess) e = launch_far_gemm(N1, ny, N2, uh, N2, 1, E2, ny, 1, S, ny, p->stream, e0, e1);
+    if (e == hipSuccess) e = launch_far_gemm(nx, ny, N1, E1, 1, nx, S, ny, 1, (double2*)out, ny, p->stream);
+  }
+  if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("far-evaluation kernels: ") + hipGetErrorString(e));
+  if (e0) p->prof_marks.push_back({first, 2});
+  return TDSE_OK;
+}
+
 int tdse_run(tdse_plan_t p, const void* u0, void* uT, int32_t on_device) {
   int s = tdse_set_state(p, u0, on_device);
   if (s) return s;
@@ -2483,9 +2574,12 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     *value = per * (double)p->P;
     return TDSE_OK;
   }
-  if (key >= TDSE_Q_PROF_MS_COL && key <= TDSE_Q_PROF_N_ROW) {
-    const int kind = (key == TDSE_Q_PROF_MS_COL || key == TDSE_Q_PROF_N_COL) ? 0 : 1;
-    const bool count = key >= TDSE_Q_PROF_N_COL;
+  if ((key >= TDSE_Q_PROF_MS_COL && key <= TDSE_Q_PROF_N_ROW) || key == TDSE_Q_PROF_MS_FAR ||
+      key == TDSE_Q_PROF_N_FAR) {
+    const int kind = (key == TDSE_Q_PROF_MS_FAR || key == TDSE_Q_PROF_N_FAR)
+                         ? 2
+                         : ((key == TDSE_Q_PROF_MS_COL || key == TDSE_Q_PROF_N_COL) ? 0 : 1);
+    const bool count = key == TDSE_Q_PROF_N_COL || key == TDSE_Q_PROF_N_ROW || key == TDSE_Q_PROF_N_FAR;
     if (!p->prof_marks.empty()) HIP_TRY(hipStreamSynchronize(p->stream));
     double ms = 0.0, nk = 0.0;
     for (auto& mk : p->prof_marks) {

@@ -94,6 +94,7 @@ struct CFAxis {
   const double2* tw;            // nu-point twiddles
   const double2* zeta;          // [N] nodes (for the phase factors)
   const double2* rfwd;          // [ND] exp(-i zeta_q 2/M): Dfwd[q][j+1] = Dfwd[q][j] rfwd[q]
+  const double2* wq;            // [N] quadrature weights of the nodes zeta
 };
 
 struct FSArgs {
@@ -207,6 +208,15 @@ hipError_t launch_fs_phase(const FSArgs& a, hipStream_t s);
 bool fs_nu_supported(int nu);
 int fs_max_modes(int nu);
 size_t fs_line_lds_bytes(int nu, int M, int ND);   // dynamic LDS of a line workgroup
+
+// Evaluation of a free-space representation at arbitrary points (far_kernels.hip).
+// E[k n + i] = (w_k / 2 pi) exp(i zeta_k x_i), k < N, i < n
+hipError_t launch_far_table(const double2* zeta, const double2* w, int N, const double* x, int n, double2* E,
+                            hipStream_t s);
+// C[m][n] = sum_k A[m sam + k sak] B[k sbk + n sbn], complex128, C row-major (ldc)
+hipError_t launch_far_gemm(int M, int N, int K, const double2* A, int64_t sam, int64_t sak, const double2* B,
+                           int64_t sbk, int64_t sbn, double2* C, int64_t ldc, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 
 // Launchers (periodic_kernels.hip).  Non-null events e0/e1 are recorded at
 // the kernel's own start and end.  Return a hipError_t.

@@ -18,6 +18,7 @@ A_KINDS = {"none": 0, "pulse_sin2": 1, "callback": 2, "stepwise": 3}
 Q_MODES, Q_STEPS_DONE, Q_DT, Q_BYTES_PER_STEP = 0, 1, 2, 3
 Q_PROF_MS_COL, Q_PROF_MS_ROW, Q_PROF_N_COL, Q_PROF_N_ROW = 8, 9, 10, 11
 Q_BYTES_COL, Q_BYTES_ROW = 12, 13
+Q_PROF_MS_FAR, Q_PROF_N_FAR = 14, 15
 Q_MU, Q_RICHARDSON, Q_PHI = 16, 32, 64
 Q_INSTANCES, Q_INST_OFFSET, Q_INST_EPT_COL, Q_INST_EPT_ROW = 4, 4096, 8192, 12288
 
@@ -221,6 +222,26 @@ class Plan:
                                      1, _dptr(gA), C.c_void_p(g0.data_ptr())), "tdse_adjoint")
         self._leave()
         return self._split_field(gA), g0
+
+    def far_eval(self, ys, xs=None) -> torch.Tensor:
+        """u at the tensor grid xs x ys (1D: ys only) from the free-space mode
+        state at the current time (tdse_far_eval); complex128 [nx, ny] (2D) or [ny]."""
+        yd = torch.as_tensor(ys, dtype=torch.float64).to(self.device).contiguous().reshape(-1)
+        xd = None if xs is None else torch.as_tensor(xs, dtype=torch.float64).to(self.device).contiguous().reshape(-1)
+        nx = 1 if xd is None else xd.numel()
+        ny = yd.numel()
+        size = C.c_size_t()
+        _check(self.lib.tdse_far_workspace_size(self.handle, nx, ny, C.byref(size)), "tdse_far_workspace_size")
+        if getattr(self, "_far_ws", None) is None or self._far_ws.numel() < size.value:
+            self._far_ws = torch.empty(max(size.value, 1), dtype=torch.uint8, device=self.device)
+        out = torch.empty((nx, ny), dtype=torch.complex128, device=self.device)
+        self._enter()
+        _check(self.lib.tdse_far_eval(self.handle, None if xd is None else C.c_void_p(xd.data_ptr()), nx,
+                                      C.c_void_p(yd.data_ptr()), ny, C.c_void_p(out.data_ptr()),
+                                      C.c_void_p(self._far_ws.data_ptr()), self._far_ws.numel()), "tdse_far_eval")
+        self._leave()
+        self._far_keep = (xd, yd)   # inputs stay alive until the stream has used them
+        return out if self.dim == 2 else out.reshape(ny)
 
     def adjoint_streams(self, streams: int) -> None:
         """Host threads / streams of a batch adjoint (tdse_adjoint_streams; 1 = one instance at a time)."""

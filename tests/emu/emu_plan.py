@@ -106,6 +106,32 @@ class EmuPlan:
             raise RuntimeError(self.lib.tdse_last_error().decode())
         return out
 
+    def call(self, name, *args):
+        st = getattr(self.lib, name)(self.h, *args)
+        if st:
+            raise RuntimeError(self.lib.tdse_last_error().decode())
+
+    def set_state(self, u0):
+        self._u0 = np.ascontiguousarray(np.asarray(u0, dtype=np.complex128))
+        self.call("tdse_set_state", C.c_void_p(self._u0.ctypes.data), 1)
+
+    def step(self, k):
+        self.call("tdse_step", int(k))
+
+    def far_eval(self, ys, xs=None):
+        """tdse_far_eval on the tensor grid xs x ys (1D: ys only)."""
+        yd = np.ascontiguousarray(ys, dtype=np.float64)
+        xd = None if xs is None else np.ascontiguousarray(xs, dtype=np.float64)
+        nx, ny = (1 if xd is None else xd.size), yd.size
+        sz = C.c_size_t()
+        self.call("tdse_far_workspace_size", nx, ny, C.byref(sz))
+        raw = np.zeros(sz.value + 512, dtype=np.uint8)
+        off = (-raw.ctypes.data) % 256
+        out = np.zeros((nx, ny), dtype=np.complex128)
+        self.call("tdse_far_eval", None if xd is None else C.c_void_p(xd.ctypes.data), nx, C.c_void_p(yd.ctypes.data),
+                  ny, C.c_void_p(out.ctypes.data), C.c_void_p(raw.ctypes.data + off), sz.value)
+        return out if xd is not None else out.reshape(ny)
+
     def __del__(self):
         try:
             self.lib.tdse_destroy(self.h)

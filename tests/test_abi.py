@@ -295,3 +295,37 @@ def test_batch_planner_rejects(lib):
     assert lib.tdse_query(h, 4096 + 1, C.byref(v)) == 0 and v.value == 64 * 128
     assert lib.tdse_autotune(h, 3) == -6                            # not bound
     lib.tdse_destroy(h)
+
+
+def test_far_evaluation_sizing_and_checks(lib):
+    # workspace of tdse_far_eval: uhat (N1 N2 modes), E2 (N2 ny), and in 2D
+    # E1 (N1 nx) and S (N1 ny), each 256-byte aligned; free-space plans only
+    al = lambda b: (b + 255) // 256 * 256
+    st, h = _plan(lib, _problem(domain=1, M=(32, 64), nu=(256, 512), q=10, panels=1))
+    assert st == 0, lib.tdse_last_error()
+    v = C.c_double()
+    N = []
+    for a in range(2):
+        assert lib.tdse_query(h, 81 + a, C.byref(v)) == 0
+        N.append(int(v.value))
+    for nx, ny in ((1, 1), (37, 130), (512, 512)):
+        sz = C.c_size_t()
+        assert lib.tdse_far_workspace_size(h, nx, ny, C.byref(sz)) == 0
+        want = al(16 * N[0] * N[1]) + al(16 * N[1] * ny) + al(16 * N[0] * nx) + al(16 * N[0] * ny)
+        assert sz.value == want, (nx, ny)
+    sz = C.c_size_t()
+    assert lib.tdse_far_workspace_size(h, 0, 5, C.byref(sz)) == -1
+    ys = np.zeros(4)
+    # before bind and set_state: a state error, no device call
+    assert lib.tdse_far_eval(h, ys.ctypes.data_as(C.c_void_p), 1, ys.ctypes.data_as(C.c_void_p), 4,
+                             ys.ctypes.data_as(C.c_void_p), C.c_void_p(256), 1 << 20) == -6
+    lib.tdse_destroy(h)
+    st, h = _plan(lib, _problem(dim=1, M=(64,), domain=1, nu=(512, 0), q=10, panels=1))
+    assert st == 0, lib.tdse_last_error()
+    assert lib.tdse_far_workspace_size(h, 1, 9, C.byref(sz)) == 0
+    assert lib.tdse_far_workspace_size(h, 2, 9, C.byref(sz)) == -1
+    lib.tdse_destroy(h)
+    st, h = _plan(lib, _problem())
+    assert st == 0
+    assert lib.tdse_far_workspace_size(h, 4, 4, C.byref(sz)) == -2
+    lib.tdse_destroy(h)

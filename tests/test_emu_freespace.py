@@ -50,3 +50,55 @@ def test_emulated_free_space_given_H_and_partial_runs(emu):
         assert plan.query(80) == 1.75
         ref, _ = FreeSpaceOracle(pr, H=1.75).run()
         assert _rel(plan.run(pr.u0), ref) < 1e-12
+
+
+FAR_CASES = [
+    dict(seed=5, dim=1, M=(32,), nu=(256,), T=0.05, N=12, q=8, panels=1),
+    dict(seed=6, dim=1, M=(96,), nu=(512,), T=0.03, N=7, q=10, panels=3),     # T reached in the start-up
+    dict(seed=9, dim=2, M=(24, 32), nu=(256, 256), T=0.04, N=9, q=6, panels=2),
+    dict(seed=10, dim=2, M=(40, 16), nu=(512, 256), T=0.04, N=8, q=4, panels=1),
+]
+
+
+@pytest.mark.parametrize("case", FAR_CASES, ids=[f"{c['M']}-{c['nu']}-{c['N']}" for c in FAR_CASES])
+def test_emulated_far_evaluation_matches_oracle(emu, case):
+    # tdse_far_eval at t = 0, after a start-up step and at T, on points inside
+    # and outside [-1,1]^d (Remark on evaluation outside [-1,1]), against the
+    # oracle's discrete representation of its own uhat
+    from emu.emu_plan import EmuPlan
+
+    prob = free_problem_from_seed(case["seed"], case["dim"], case["M"], case["T"], case["N"], nu=case["nu"],
+                                  eps=1e-11, q=case["q"], panels=case["panels"])
+    rng = np.random.default_rng(1)
+    pts = [np.sort(rng.uniform(-2, 2, 37 + 4 * a)) for a in range(prob.dim)]
+    for stop in (0, 2, case["N"]):
+        plan = EmuPlan(emu, prob)
+        plan.set_state(prob.u0)
+        plan.step(stop)
+        got = plan.far_eval(pts[-1], pts[0] if prob.dim == 2 else None)
+        orc = FreeSpaceOracle(prob)
+        _, info = orc.run(stop)
+        ref = orc.evaluate(info["uhat"], pts)
+        assert got.shape == ref.shape
+        assert _rel(got, ref) < 1e-11, stop
+
+
+def test_emulated_far_evaluation_errors(emu):
+    from emu.emu_plan import EmuPlan
+    from workloads import periodic_problem_from_seed
+
+    prob = free_problem_from_seed(5, 1, (32,), 0.05, 12, nu=(256,), eps=1e-11, q=8, panels=1)
+    plan = EmuPlan(emu, prob)
+    ys = np.linspace(-1.5, 1.5, 7)
+    with pytest.raises(RuntimeError, match="no state"):
+        plan.far_eval(ys)
+    plan.set_state(prob.u0)
+    plan.step(prob.nsteps - 2)    # past the start-up, before T: no mode state kept
+    with pytest.raises(RuntimeError, match="mode state"):
+        plan.far_eval(ys)
+    with pytest.raises(RuntimeError, match="nx = 1"):
+        plan.far_eval(ys, xs=np.zeros(3))
+    per = EmuPlan(emu, periodic_problem_from_seed(3, 1, (32,), 0.05, 10))
+    per.set_state(np.ones(32, dtype=complex))
+    with pytest.raises(RuntimeError, match="free-space"):
+        per.far_eval(ys)

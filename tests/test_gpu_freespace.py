@@ -148,3 +148,64 @@ def test_free_space_pieces_and_graph_replay_are_bitwise():
         torch.cuda.synchronize()
         plan.use_graph(True)
     plan.close()
+
+
+# --- evaluation at arbitrary points (Remark on evaluation outside [-1,1]) ---
+
+FAR_CASES = [
+    dict(seed=5, dim=1, M=(32,), nu=(256,), T=0.05, N=12, q=8, panels=1),
+    dict(seed=21, dim=1, M=(256,), nu=(2048,), T=0.05, N=20, q=10, panels=1),
+    dict(seed=9, dim=2, M=(24, 32), nu=(256, 256), T=0.04, N=9, q=6, panels=2),
+    dict(seed=23, dim=2, M=(48, 96), nu=(256, 1024), T=0.03, N=10, q=10, panels=1),
+]
+
+
+@pytest.mark.parametrize("case", FAR_CASES, ids=[f"{c['M']}-{c['nu']}-{c['N']}" for c in FAR_CASES])
+def test_far_evaluation_matches_oracle(case):
+    # tdse_far_eval at t = 0, after a start-up step and at T, on ragged point
+    # sets (not multiples of the 64 x 64 product tiles) inside and outside
+    # [-1,1]^d, against the oracle's representation of its own uhat
+    prob = free_problem_from_seed(case["seed"], case["dim"], case["M"], case["T"], case["N"], nu=case["nu"],
+                                  eps=1e-11, q=case["q"], panels=case["panels"])
+    rng = np.random.default_rng(2)
+    pts = [np.sort(rng.uniform(-2, 2, 67 + 30 * a)) for a in range(prob.dim)]
+    plan = gpu_plan(prob)
+    for stop in (0, 2, prob.nsteps):
+        print(f"case far M={prob.M} nu={prob.nu} stop={stop}", flush=True)
+        plan.set_state(prob.u0)
+        plan.step(stop)
+        got = plan.far_eval(pts[-1], pts[0] if prob.dim == 2 else None).cpu().numpy()
+        orc = FreeSpaceOracle(prob)
+        _, info = orc.run(stop)
+        ref = orc.evaluate(info["uhat"], pts)
+        r = rel(got, ref)
+        print(f"  rel-L2 = {r:.3e}", flush=True)
+        assert got.shape == ref.shape
+        assert r <= TOL, r
+    plan.close()
+
+
+def test_far_evaluation_exact_wavepacket_at_full_size():
+    # V = 0 with a field pulse on 256 x 256 points, nu = 2048, with the
+    # q = 16, two-panel rule of Section 6, Example 2: the representation at T
+    # equals the exact packet outside [-1,1]^2 as well (the packet has spread
+    # past the box by T = 0.2)
+    M, nu, T, N = 256, 2048, 0.2, 200
+    x = free_grid(M)
+    u0 = np.multiply.outer(_wavepacket(x - 0.1, 0, 0.12), _wavepacket(x + 0.05, 0, 0.1))
+    prob = Problem(name="wp", dim=2, domain="free", M=(M, M), T=T, nsteps=N, order=8, u0=u0.astype(complex),
+                   V_fields=[np.zeros((M, M))], f_kind=["const"], f_params=[(0, 0)], A_kind="pulse_sin2",
+                   A_params=(1.5, 10.0, 1.0, 1.0, 0.0), eps=1e-10, q=16, panels=2, nu=(nu, nu))
+    print("case far wavepacket 256^2", flush=True)
+    plan = gpu_plan(prob)
+    plan.run(prob.u0)
+    ph = [plan.query(64), plan.query(65)]
+    px, py = np.linspace(-2.0, 2.0, 97), np.linspace(-1.75, 1.75, 130)
+    got = plan.far_eval(py, px).cpu().numpy()
+    plan.close()
+    ex = np.multiply.outer(_wavepacket(px - 0.1 + ph[0], T, 0.12), _wavepacket(py + 0.05 + ph[1], T, 0.1))
+    outside = (np.abs(px)[:, None] > 1) | (np.abs(py)[None, :] > 1)
+    err = np.max(np.abs(got - ex))
+    print(f"  max error vs exact = {err:.3e}, max |u| outside the box = {np.abs(ex[outside]).max():.3f}", flush=True)
+    assert np.abs(ex[outside]).max() > 0.05
+    assert err <= 1e-10, err

@@ -118,3 +118,64 @@ def test_H_rule():
     # Remark on the choice of H: log(eps / ((1 + ||V||) eps_m)) / (2 d (1 + phimax))
     H = choose_H(1e-10, 3.0, 0.5, 2)
     assert abs(H - np.log(1e-10 / (4.0 * 2.0 ** -52)) / 6.0) < 1e-14
+
+
+# --- evaluation at arbitrary points (Remark on evaluation outside [-1,1]) ---
+
+def _wp_problem(M, nu, T, nsteps, E0):
+    x = free_grid(M)
+    return Problem(name="wp", dim=1, domain="free", M=(M,), T=T, nsteps=nsteps, order=8,
+                   u0=_wavepacket(x, 0, 0.1).astype(complex), V_fields=[np.zeros(M)], f_kind=["const"],
+                   f_params=[(0, 0)], A_kind="pulse_sin2" if E0 else "none",
+                   A_params=(E0, 50.0, T, 1.0) if E0 else (), eps=1e-12, q=16, panels=2, nu=(nu,))
+
+
+@pytest.mark.parametrize("E0", [0.0, 20.0])
+def test_far_evaluation_matches_exact_wavepacket_outside_the_box(E0):
+    # V = 0: uhat(T) on Gamma_K is the exact transform times the exact
+    # propagator, so the representation gives the exact wave packet at any
+    # real x; by T = 0.1 the packet has spread well past [-1,1]
+    prob = _wp_problem(128, 1024, 0.1, 20, E0)
+    orc = FreeSpaceOracle(prob)
+    _, info = orc.run()
+    ph = orc.phi(0.1)[0]
+    xs = np.linspace(-2.0, 2.0, 161)
+    ex = _wavepacket(xs + ph, 0.1, 0.1)
+    assert np.max(np.abs(ex[np.abs(xs) > 1.2])) > 0.3
+    got = orc.evaluate(info["uhat"], [xs])
+    assert np.max(np.abs(got - ex)) < 2e-11
+    # the error grows with |x| - 1 as exp(H (|x| - 1)) amplifies the
+    # truncation and rounding on Gamma_K; at |x| = 3 it is still below 1e-7
+    xs3 = np.array([-3.0, -2.5, 2.5, 3.0])
+    assert np.max(np.abs(orc.evaluate(info["uhat"], [xs3]) - _wavepacket(xs3 + ph, 0.1, 0.1))) < 1e-7
+
+
+def test_far_evaluation_2d_exact_wavepacket():
+    M, nu, T = 64, 512, 0.05
+    x = free_grid(M)
+    u0 = np.multiply.outer(_wavepacket(x - 0.1, 0, 0.12), _wavepacket(x + 0.05, 0, 0.1))
+    prob = Problem(name="wp2", dim=2, domain="free", M=(M, M), T=T, nsteps=10, order=8, u0=u0.astype(complex),
+                   V_fields=[np.zeros((M, M))], f_kind=["const"], f_params=[(0, 0)], A_kind="pulse_sin2",
+                   A_params=(15.0, 40.0, T, 1.0, 0.0), eps=1e-12, q=16, panels=2, nu=(nu, nu))
+    orc = FreeSpaceOracle(prob)
+    _, info = orc.run()
+    ph = orc.phi(T)
+    px, py = np.linspace(-1.6, 1.6, 23), np.linspace(-1.8, 1.4, 19)
+    ex = np.multiply.outer(_wavepacket(px - 0.1 + ph[0], T, 0.12), _wavepacket(py + 0.05 + ph[1], T, 0.1))
+    assert np.max(np.abs(orc.evaluate(info["uhat"], [px, py]) - ex)) < 1e-11
+
+
+def test_far_evaluation_at_grid_points_reproduces_the_marched_solution():
+    # with V != 0 the mode state at T is B_N - i mu_0 dt F(V u_N) while the
+    # marched grid values are F^-1(B_N) / (1 + i mu_0 dt V): the two agree on
+    # the grid to the accuracy of F applied to V u (1.5e-9 here), and flipping
+    # the sign of the V term breaks the agreement by O(mu_0 dt |V u|) (5e-2)
+    prob = free_problem_from_seed(5, 1, (64,), 0.1, 10, nu=(512,), eps=1e-12, q=16, panels=2)
+    orc = FreeSpaceOracle(prob)
+    u, info = orc.run()
+    x = free_grid(64)
+    got = orc.evaluate(info["uhat"], [x])
+    assert np.max(np.abs(got - u)) < 1e-8      # 1.5e-9 measured
+    W = orc.F(orc.V(prob.T) * u)
+    wrong = orc.evaluate(info["uhat"] + 2j * orc.mu[0] * prob.dt * W, [x])
+    assert np.max(np.abs(wrong - u)) > 1e-4
