@@ -3,7 +3,7 @@
 // on evaluation outside [-1,1]), gfx950:
 //   u(x_i, y_j) = sum_{k1,k2} E1[k1][i] E2[k2][j] uhat[k1][k2],
 //   E_a[k][i]   = (w_k / 2 pi) exp(i zeta_k x_i)      (quadrature of axis a),
-// as a table kernel per axis and two complex FP64 products,
+// as a table kernel per axis and two complex FP64 matrix-core products,
 //   S = uhat E2 (N1 x ny), then u = E1^T S (nx x ny).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -31,10 +31,15 @@ __global__ __launch_bounds__(256) void k_far_table(const double2* __restrict__ z
 }
 
 // C[m][n] = sum_k A[m sam + k sak] B[k sbk + n sbn] (complex128), C row-major
-// with leading dimension ldc.  A workgroup computes a 64 x 64 tile of C: 256
-// threads in a 16 x 16 layout, each owning the 4 x 4 outputs m0 + tm + 16 a,
-// n0 + tn + 16 b; K advances in chunks of 16 staged through LDS, with zeros
-// beyond the operands' edges.  Tiles are numbered along n first.
+// with leading dimension ldc, on the FP64 matrix cores.  A workgroup of four
+// waves computes a 64 x 64 tile of C, each wave a 32 x 32 quarter as 2 x 2
+// blocks of the 16 x 16 x 4 FP64 MFMA.  K advances in chunks of 16 staged
+// through LDS (zeros beyond the operands' edges), four MFMA k-steps a chunk.
+// Operand lanes: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; the
+// result D[q + 4 r][j] sits in lane j + 16 q, element r.  A complex product
+// takes four real ones: Re C += Re A Re B - Im A Im B, Im C += Re A Im B +
+// Im A Re B.  Tiles are numbered along n first.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int FAR_T = 64, FAR_K = 16;
 __global__ __launch_bounds__(256) void k_far_gemm(int M, int N, int K, const double2* __restrict__ A, int64_t sam,
                                                   int64_t sak, const double2* __restrict__ B, int64_t sbk,
@@ -42,52 +47,77 @@ __global__ __launch_bounds__(256) void k_far_gemm(int M, int N, int K, const dou
   __shared__ double2 As[FAR_K][FAR_T + 1];
   __shared__ double2 Bs[FAR_K][FAR_T + 1];
   const int tid = threadIdx.x;
-  const int tm = tid / 16, tn = tid % 16;
+  const int lane = tid % 64, wave = tid / 64;
+  const int wm = 32 * (wave / 2), wn = 32 * (wave % 2);
+  const int li = lane % 16, lk = lane / 16;
   const int ntn = (N + FAR_T - 1) / FAR_T;
   const int m0 = (blockIdx.x / ntn) * FAR_T, n0 = (blockIdx.x % ntn) * FAR_T;
-  double2 acc[4][4];
+  f64x4 cr[2][2], ci[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = double2{0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += FAR_K) {
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cr[a][b][r] = 0.0;
+        ci[a][b][r] = 0.0;
+      }
+  // the next chunk's operands are loaded into registers while the MFMAs
+  // work on the current chunk in LDS
+  double2 ra[4], rb[4];
+  auto load_chunk = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int e = tid + 256 * r;   // 0 .. FAR_T * FAR_K - 1
       // A: consecutive threads along k when A is contiguous in k, else along m
       const int ka = sak == 1 ? e % FAR_K : e / FAR_T, ma = sak == 1 ? e / FAR_K : e % FAR_T;
       const int gm = m0 + ma, gka = k0 + ka;
-      As[ka][ma] = (gm < M && gka < K) ? A[(int64_t)gm * sam + (int64_t)gka * sak] : double2{0.0, 0.0};
+      ra[r] = (gm < M && gka < K) ? A[(int64_t)gm * sam + (int64_t)gka * sak] : double2{0.0, 0.0};
       // B: consecutive threads along n
       const int kb = e / FAR_T, nb = e % FAR_T;
       const int gn = n0 + nb, gkb = k0 + kb;
-      Bs[kb][nb] = (gn < N && gkb < K) ? B[(int64_t)gkb * sbk + (int64_t)gn * sbn] : double2{0.0, 0.0};
+      rb[r] = (gn < N && gkb < K) ? B[(int64_t)gkb * sbk + (int64_t)gn * sbn] : double2{0.0, 0.0};
+    }
+  };
+  if (K > 0) load_chunk(0);
+  for (int k0 = 0; k0 < K; k0 += FAR_K) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      const int ka = sak == 1 ? e % FAR_K : e / FAR_T, ma = sak == 1 ? e / FAR_K : e % FAR_T;
+      As[ka][ma] = ra[r];
+      Bs[e / FAR_T][e % FAR_T] = rb[r];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < FAR_K; ++kk) {
-      double2 av[4], bv[4];
+    if (k0 + FAR_K < K) load_chunk(k0 + FAR_K);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[kk][tm + 16 * a];
+    for (int ks = 0; ks < FAR_K; ks += 4) {
+      double2 av[2], bv[2];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tn + 16 * b];
+      for (int a = 0; a < 2; ++a) av[a] = As[ks + lk][wm + 16 * a + li];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[ks + lk][wn + 16 * b + li];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          acc[a][b].x += av[a].x * bv[b].x - av[a].y * bv[b].y;
-          acc[a][b].y += av[a].x * bv[b].y + av[a].y * bv[b].x;
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[b].y, cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
         }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int gm = m0 + tm + 16 * a, gn = n0 + tn + 16 * b;
-      if (gm < M && gn < N) C[(int64_t)gm * ldc + gn] = acc[a][b];
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + 16 * a + lk + 4 * r, gn = n0 + wn + 16 * b + li;
+        if (gm < M && gn < N) C[(int64_t)gm * ldc + gn] = double2{cr[a][b][r], ci[a][b][r]};
+      }
 }
 
 hipError_t launch_far_table(const double2* zeta, const double2* w, int N, const double* x, int n, double2* E,

@@ -41,6 +41,9 @@ extern dim3 blockDim, gridDim;
 // scheduling hints of the GPU compiler have no meaning on the CPU
 inline void __builtin_amdgcn_sched_barrier(int) {}
 #define __shared__ static
+// clang's vector extension, as GCC's (element count -> bytes, for double)
+#define ext_vector_type(n) vector_size(8 * (n))
+typedef double emu_f64x4 __attribute__((vector_size(32)));
 #define __restrict__
 
 typedef int hipError_t;
@@ -127,6 +130,27 @@ inline void barrier_wait() {
 }  // namespace emu
 
 inline void __syncthreads() { emu::barrier_wait(); }
+// FP64 16x16x4 matrix product of one wave (gfx950 lane layout: A[i][k] in
+// lane i + 16k, B[k][j] in lane j + 16k, D[q + 4r][j] in lane j + 16q,
+// element r).
+// Emulated with a block-wide rendezvous, so every thread of the block must
+// reach each call in the same order (as the kernels that use it do).
+inline emu_f64x4 __builtin_amdgcn_mfma_f64_16x16x4f64(double a, double b, emu_f64x4 c, int, int, int) {
+  static double sa[1024], sb[1024];
+  const unsigned t = threadIdx.x;
+  sa[t] = a;
+  sb[t] = b;
+  __syncthreads();
+  const unsigned w0 = t & ~63u, l = t & 63u, j = l % 16, q = l / 16;
+  emu_f64x4 d = c;
+  for (unsigned r = 0; r < 4; ++r) {
+    double s = 0.0;
+    for (unsigned k = 0; k < 4; ++k) s += sa[w0 + q + 4 * r + 16 * k] * sb[w0 + j + 16 * k];
+    d[r] += s;
+  }
+  __syncthreads();
+  return d;
+}
 inline void sincos(double x, double* s, double* c) { *s = std::sin(x); *c = std::cos(x); }
 inline void sincosf(float x, float* s, float* c) { *s = std::sin(x); *c = std::cos(x); }
 using std::min;
