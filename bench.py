@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-free", action="store_true", help="skip the free-space 256x256 leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched leg")
     ap.add_argument("--no-well", action="store_true", help="skip the moving-well (potential on the fly) leg")
+    ap.add_argument("--no-ionization", action="store_true", help="skip the 1D ionization (Example 3) leg")
     ap.add_argument("--batch-runs", type=int, default=3)
     ap.add_argument("--free-runs", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -295,6 +296,40 @@ def far_field_eval(plan, dev, n: int = 512, box: float = 2.0, reps: int = 5) -> 
                          "frac": ach / FP64_MFMA_PEAK_TFS, "flops_per_launch": flops, "mean_launch_us": g_us}}
 
 
+def ionization_leg(runs: int = 3, nsteps: int = 4000) -> dict:
+    """Section 6, Example 3: 1D ionization from the ground state of a Gaussian
+    well (V0 = 1400, beta = 0.1) by the cosine pulse A0 = 100, omega = 50, 100,
+    200, free space, M = 100, nu = 1024 (h = 0.31), eps = 1e-10, q = 10,
+    T = 0.5: graph-replayed whole runs, time steps per second, and the
+    ionization fractions 1 - int_{-1}^{1} |u(T)|^2."""
+    import torch
+
+    from paper_2001_06113_amd.tdse import Plan
+    from workloads import ionization_1d_problem
+
+    dev = torch.device("cuda:0")
+    out = {"workload": f"Example 3 ionization, 1D free space M=100, nu=1024, eps=1e-10, q=10, T=0.5, {nsteps} steps AM8",
+           "cases": []}
+    for om in (50.0, 100.0, 200.0):
+        prob = ionization_1d_problem(om, nsteps=nsteps)
+        plan = Plan.from_problem(prob, device=dev)
+        u0 = torch.as_tensor(prob.u0).to(dev)
+        u = torch.empty_like(u0)
+        plan.use_graph(True)
+        plan.run(u0, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(runs):
+            plan.run(u0, u)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / runs
+        ion = 100.0 * (1.0 - float(torch.sum(torch.abs(u) ** 2)) * 2.0 / prob.M[0])
+        plan.close()
+        out["cases"].append({"omega": om, "ionization_percent": ion, "ms_per_run": wall * 1e3,
+                             "time_steps_per_s": nsteps / wall})
+    return out
+
+
 def batch_leg(runs: int) -> dict:
     """Batched form on the 64-instance workload (seed 4000 + i; 32 1D with
     M in {256..2048}, 32 2D with M in {128..512}^2; 500 steps, FP32-split,
@@ -459,6 +494,8 @@ def main():
         res["free_space"] = free_space_leg(args.free_runs)
     if not args.no_well:
         res["moving_well"] = moving_well_leg()
+    if not args.no_ionization:
+        res["ionization"] = ionization_leg()
     if not args.no_batch:
         res["batch"] = batch_leg(args.batch_runs)
     if not args.no_cpu:

@@ -76,6 +76,7 @@ extern "C" {
 #define TDSE_A_PULSE_SIN2 1    /* A = E0 sin^2(pi t/Tp) sin(w t) dir; A_params = {E0, w, Tp, dir[0..d-1]} */
 #define TDSE_A_CALLBACK  2     /* A(t) from A_fn; phi = int A by Gauss-Legendre per step */
 #define TDSE_A_STEPWISE  3     /* A constant on each step: A_steps[nsteps][d]  */
+#define TDSE_A_PULSE_COS2 4    /* eq. (apulse): A = E0 sin^2(pi t/Tp) cos(w t) dir; A_params as for PULSE_SIN2 */
 
 typedef double (*tdse_scalar_fn)(int32_t r, double t, void* ctx);
 typedef void (*tdse_vector_fn)(double t, double* A_out, void* ctx);
@@ -97,7 +98,7 @@ typedef struct {
   const double* f_params;  /* TDSE_F_SIN: [nV][2] = (amp, omega)             */
   tdse_scalar_fn f_fn; void* f_ctx;
   int32_t A_kind;          /* TDSE_A_*                                       */
-  const double* A_params;  /* TDSE_A_PULSE_SIN2: {E0, omega, Tp, dir[d]}     */
+  const double* A_params;  /* TDSE_A_PULSE_SIN2/COS2: {E0, omega, Tp, dir[d]} */
   const double* A_steps;   /* TDSE_A_STEPWISE: host [nsteps][d]              */
   tdse_vector_fn A_fn; void* A_ctx;
   /* free space (Sections 3.4 and 4): tolerance eps for the choice of H

@@ -183,6 +183,14 @@ struct TimeFns {
     return 0.5 * E0 * (g(w) - 0.5 * (g(w + Om) + g(w - Om)));
   }
 
+  // int_0^t E0 sin^2(pi s/Tp) cos(w s) ds (the pulse of eq. (apulse)) by the
+  // same identities, with int_0^t cos(c s) ds = sin(c t)/c (t at c = 0).
+  static double pulse_cos_integral(double t, double E0, double w, double Tp) {
+    const double Om = 2.0 * M_PI / Tp;
+    auto g = [t](double c) { return c == 0.0 ? t : std::sin(c * t) / c; };
+    return 0.5 * E0 * (g(w) - 0.5 * (g(w + Om) + g(w - Om)));
+  }
+
   void A_at(double t, double* out) const {
     if (A_kind == TDSE_A_CALLBACK) {
       A_fn(t, out, A_ctx);
@@ -220,8 +228,10 @@ struct TimeFns {
   void phi(double t, double* out) const {
     for (int a = 0; a < 2; ++a) out[a] = 0.0;
     switch (A_kind) {
-      case TDSE_A_PULSE_SIN2: {
-        const double s = pulse_integral(t, A_params[0], A_params[1], A_params[2]);
+      case TDSE_A_PULSE_SIN2:
+      case TDSE_A_PULSE_COS2: {
+        const double s = A_kind == TDSE_A_PULSE_SIN2 ? pulse_integral(t, A_params[0], A_params[1], A_params[2])
+                                                     : pulse_cos_integral(t, A_params[0], A_params[1], A_params[2]);
         for (int a = 0; a < dim; ++a) out[a] = s * A_params[3 + a];
         return;
       }
@@ -2141,10 +2151,11 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   if (prob->f_kind == TDSE_F_SIN && !prob->f_params) return fail(TDSE_EINVAL, "f_params missing");
   if (prob->f_kind == TDSE_F_CALLBACK && !prob->f_fn) return fail(TDSE_EINVAL, "f_fn missing");
   if (prob->f_kind < 0 || prob->f_kind > 2) return fail(TDSE_EINVAL, "bad f_kind");
-  if (prob->A_kind == TDSE_A_PULSE_SIN2 && !prob->A_params) return fail(TDSE_EINVAL, "A_params missing");
+  if ((prob->A_kind == TDSE_A_PULSE_SIN2 || prob->A_kind == TDSE_A_PULSE_COS2) && !prob->A_params)
+    return fail(TDSE_EINVAL, "A_params missing");
   if (prob->A_kind == TDSE_A_STEPWISE && !prob->A_steps) return fail(TDSE_EINVAL, "A_steps missing");
   if (prob->A_kind == TDSE_A_CALLBACK && !prob->A_fn) return fail(TDSE_EINVAL, "A_fn missing");
-  if (prob->A_kind < 0 || prob->A_kind > 3) return fail(TDSE_EINVAL, "bad A_kind");
+  if (prob->A_kind < 0 || prob->A_kind > 4) return fail(TDSE_EINVAL, "bad A_kind");
 
   tdse_plan_s* p = new (std::nothrow) tdse_plan_s();
   if (!p) return fail(TDSE_ENOMEM, "host allocation failed");
@@ -2198,7 +2209,8 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   tf.f_fn = prob->f_fn;
   tf.f_ctx = prob->f_ctx;
   tf.A_kind = prob->A_kind;
-  if (prob->A_kind == TDSE_A_PULSE_SIN2) tf.A_params.assign(prob->A_params, prob->A_params + 3 + p->dim);
+  if (prob->A_kind == TDSE_A_PULSE_SIN2 || prob->A_kind == TDSE_A_PULSE_COS2)
+    tf.A_params.assign(prob->A_params, prob->A_params + 3 + p->dim);
   if (prob->A_kind == TDSE_A_STEPWISE) tf.A_steps.assign(prob->A_steps, prob->A_steps + (size_t)p->nsteps * p->dim);
   tf.A_fn = prob->A_fn;
   tf.A_ctx = prob->A_ctx;

@@ -14,7 +14,7 @@ from . import _lib
 PERIODIC, FREE = 0, 1
 FP64, FP32_SPLIT = 0, 1
 F_KINDS = {"const": 0, "sin": 1, "callback": 2}
-A_KINDS = {"none": 0, "pulse_sin2": 1, "callback": 2, "stepwise": 3}
+A_KINDS = {"none": 0, "pulse_sin2": 1, "callback": 2, "stepwise": 3, "pulse_cos2": 4}
 Q_MODES, Q_STEPS_DONE, Q_DT, Q_BYTES_PER_STEP = 0, 1, 2, 3
 Q_PROF_MS_COL, Q_PROF_MS_ROW, Q_PROF_N_COL, Q_PROF_N_ROW = 8, 9, 10, 11
 Q_BYTES_COL, Q_BYTES_ROW = 12, 13
@@ -110,7 +110,7 @@ def problem_kwargs(prob) -> dict:
                 V_kind="moving_well" if well else "fields", V_params=tuple(prob.V_well) if well else (),
                 order=prob.order, n_start=-1 if prob.n_start is None else prob.n_start,
                 precision=prob.precision, f_kind="sin" if sin else "const", f_params=f_params,
-                A_kind=prob.A_kind, A_params=prob.A_params if prob.A_kind == "pulse_sin2" else None,
+                A_kind=prob.A_kind, A_params=prob.A_params if prob.A_kind in ("pulse_sin2", "pulse_cos2") else None,
                 A_steps=prob.A_steps if prob.A_kind == "stepwise" else None,
                 domain=prob.domain, eps=prob.eps, p=prob.p, q=prob.q, panels=prob.panels, nu=prob.nu)
 

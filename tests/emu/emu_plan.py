@@ -57,9 +57,9 @@ class EmuPlan:
             self._keep.append(fp)
             p.f_kind = 1
             p.f_params = fp.ctypes.data_as(C.POINTER(C.c_double))
-        kinds = {"none": 0, "pulse_sin2": 1, "stepwise": 3}
+        kinds = {"none": 0, "pulse_sin2": 1, "stepwise": 3, "pulse_cos2": 4}
         p.A_kind = kinds[prob.A_kind]
-        if prob.A_kind == "pulse_sin2":
+        if prob.A_kind in ("pulse_sin2", "pulse_cos2"):
             ap = np.asarray(prob.A_params, dtype=np.float64)
             self._keep.append(ap)
             p.A_params = ap.ctypes.data_as(C.POINTER(C.c_double))

@@ -181,6 +181,32 @@ def test_planner_phi_closed_form(lib):
     lib.tdse_destroy(h)
 
 
+@pytest.mark.parametrize("om", [9.7, np.pi])   # the second has omega - 2 pi/Tp = 0
+def test_planner_phi_closed_form_cosine_pulse(lib, om):
+    # eq. (apulse), A = E0 sin^2(pi t/Tp) cos(w t): phi at T = 0.7 Tp vs the
+    # same independent Gauss-Legendre sum
+    E0, Tp = 1.3, 2.0
+    T = 0.7 * Tp
+    p = _problem(A=[E0, om, Tp, 0.0, 1.0], T=T)
+    p.A_kind = 4
+    st, h = _plan(lib, p)
+    assert st == 0, lib.tdse_last_error()
+    v = C.c_double()
+    gx, gw = np.polynomial.legendre.leggauss(20)
+    edges = np.linspace(0, T, 2001)
+    tot = 0.0
+    for a, b in zip(edges[:-1], edges[1:]):
+        s = 0.5 * (a + b) + 0.5 * (b - a) * gx
+        tot += 0.5 * (b - a) * np.sum(gw * E0 * np.sin(np.pi * s / Tp) ** 2 * np.cos(om * s))
+    assert lib.tdse_query(h, 65, C.byref(v)) == 0
+    assert abs(v.value - tot) < 1e-13
+    assert lib.tdse_query(h, 64, C.byref(v)) == 0 and v.value == 0.0
+    lib.tdse_destroy(h)
+    p.A_kind = 5
+    st, h = _plan(lib, p)
+    assert st == -1
+
+
 def test_free_space_planner_alpert_rule_matches_oracle(lib):
     # the planner's long-double modified-Chebyshev/Golub-Welsch construction
     # against the oracle's exact Hankel solve and mpmath roots

@@ -102,3 +102,15 @@ def test_emulated_far_evaluation_errors(emu):
     per.set_state(np.ones(32, dtype=complex))
     with pytest.raises(RuntimeError, match="free-space"):
         per.far_eval(ys)
+
+
+def test_emulated_cosine_pulse_ionization_setup(emu):
+    # the Example 3 set-up (ground state of the Gaussian well, cosine pulse of
+    # eq. (apulse)) on a short interval, against the oracle
+    from emu.emu_plan import EmuPlan
+    from workloads import ionization_1d_problem
+
+    prob = ionization_1d_problem(100.0, nu=256, T=0.01, nsteps=12)
+    u = EmuPlan(emu, prob).run(prob.u0)
+    ref, _ = FreeSpaceOracle(prob).run()
+    assert _rel(u, ref) < 1e-12

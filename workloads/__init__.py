@@ -16,4 +16,6 @@ from .synth import (  # noqa: F401
     periodic_problem_from_seed,
     free_problem_from_seed,
     moving_well_problem,
+    gaussian_well_ground_state,
+    ionization_1d_problem,
 )

@@ -46,7 +46,7 @@ class Problem:
     V_fields: List[np.ndarray]       # real float64 arrays, shape M
     f_kind: List[str]                # per field: "const" | "sin"
     f_params: List[Tuple[float, float]]  # per field: (amp, omega) for 1 + amp sin(omega t)
-    A_kind: str = "none"             # "none" | "pulse_sin2" | "stepwise"
+    A_kind: str = "none"             # "none" | "pulse_sin2" | "pulse_cos2" | "stepwise"
     A_params: Tuple[float, ...] = ()  # pulse: (E0, omega, Tp, dir_0, dir_1)
     A_steps: Optional[np.ndarray] = None  # stepwise: [nsteps, dim] values on each step
     precision: str = "fp64"          # "fp64" | "fp32split"
@@ -83,10 +83,11 @@ class Problem:
         out = np.zeros(self.dim)
         if self.A_kind == "none":
             return out
-        if self.A_kind == "pulse_sin2":
+        if self.A_kind in ("pulse_sin2", "pulse_cos2"):
             E0, om, Tp = self.A_params[:3]
             d = np.asarray(self.A_params[3:3 + self.dim], dtype=np.float64)
-            return E0 * np.sin(np.pi * t / Tp) ** 2 * np.sin(om * t) * d
+            carrier = np.sin(om * t) if self.A_kind == "pulse_sin2" else np.cos(om * t)
+            return E0 * np.sin(np.pi * t / Tp) ** 2 * carrier * d
         if self.A_kind == "stepwise":
             dt = self.dt
             m = int(np.floor(t / dt + 1e-12))
@@ -303,3 +304,48 @@ def free_2d_256_problem(seed: int = 2, M: int = 256, T: float = 1.0, nsteps: int
     """2D free space, 256 x 256 physical points, eps = 1e-10, p = 8, q = 10,
     one Gauss panel per side, FFT size nu = 2048 per axis (seed 2)."""
     return free_problem_from_seed(seed, 2, (M, M), T, nsteps, order, nu=(nu, nu), name="free-2d-256")
+
+
+def gaussian_well_ground_state(V0: float, beta: float, L: float = 2.0, n: int = 512):
+    """Ground state of -u'' + V u = E u for the well V(x) = -V0 exp(-x^2/(2 beta^2))
+    of Section 6, Examples 3 and 4 (1D), which the paper computes with
+    Chebfun.  Fourier pseudo-spectral discretization on the periodic box
+    [-L, L) with n points (the state is below 1e-15 at |x| = L for the wells
+    used here), dense symmetric eigensolve.  Returns (E, evaluate) where
+    evaluate(x) is the L^2(R)-normalized, real, positive state at points x
+    in [-L, L) by trigonometric interpolation."""
+    x = -L + 2.0 * L * np.arange(n) / n
+    k = np.fft.fftfreq(n, d=2.0 * L / n) * 2.0 * np.pi
+    F = np.fft.fft(np.eye(n), axis=0)
+    D2 = np.real(np.fft.ifft(-(k ** 2)[:, None] * F, axis=0))
+    Hm = -D2 + np.diag(-V0 * np.exp(-x ** 2 / (2.0 * beta ** 2)))
+    Hm = 0.5 * (Hm + Hm.T)
+    E, vecs = np.linalg.eigh(Hm)
+    g = vecs[:, 0]
+    g = g / np.sqrt(np.sum(g ** 2) * (2.0 * L / n))
+    if g[n // 2] < 0:
+        g = -g
+    c = np.fft.fft(g) / n
+
+    def evaluate(pts):
+        pts = np.asarray(pts, dtype=np.float64)
+        return np.real(np.exp(1j * np.outer(pts + L, k)) @ c)
+
+    return float(E[0]), evaluate
+
+
+def ionization_1d_problem(omega: float, A0: float = 100.0, V0: float = 1400.0, beta: float = 0.1, M: int = 100,
+                          nu: int = 1024, T: float = 0.5, nsteps: int = 4000, eps: float = 1e-10, q: int = 10,
+                          panels: int = 1, order: int = 8) -> Problem:
+    """Section 6, Example 3: ionization from the ground state of the Gaussian
+    well V = -V0 exp(-x^2/(2 beta^2)) (V0 = 1400, beta = 0.1) by the pulse
+    A = A0 sin^2(pi t/T) cos(omega t) of eq. (apulse), in free space on
+    M = 100 points, eps = 1e-10, q = 10, T = 0.5."""
+    x = free_grid(M)
+    E, gs = gaussian_well_ground_state(V0, beta)
+    V = -V0 * np.exp(-x ** 2 / (2.0 * beta ** 2))
+    prob = Problem(name=f"ionization-1d-omega{omega:g}", dim=1, domain="free", M=(M,), T=T, nsteps=nsteps,
+                   order=order, u0=gs(x).astype(np.complex128), V_fields=[V], f_kind=["const"], f_params=[(0.0, 0.0)],
+                   A_kind="pulse_cos2", A_params=(A0, omega, T, 1.0), eps=eps, q=q, panels=panels, nu=(nu,))
+    prob.ground_energy = E
+    return prob
