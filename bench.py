@@ -327,6 +327,30 @@ def ionization_leg(runs: int = 3, nsteps: int = 4000) -> dict:
         plan.close()
         out["cases"].append({"omega": om, "ionization_percent": ion, "ms_per_run": wall * 1e3,
                              "time_steps_per_s": nsteps / wall})
+    # Example 4 (2D, field along x), omega = 100, the paper's two accuracy settings
+    from workloads import ionization_2d_problem
+
+    out["cases_2d"] = []
+    for label, nu, eps, n2 in (("eps=1e-10, h=0.31 both axes", (1024, 1024), 1e-10, 8000),
+                               ("eps=1e-5, h=1.23 both axes", (256, 256), 1e-5, 4000)):
+        prob = ionization_2d_problem(100.0, nu=nu, eps=eps, nsteps=n2)
+        plan = Plan.from_problem(prob, device=dev)
+        u0 = torch.as_tensor(prob.u0).to(dev)
+        u = torch.empty_like(u0)
+        plan.use_graph(True)
+        plan.run(u0, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(runs):
+            plan.run(u0, u)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / runs
+        ion = 100.0 * (1.0 - float(torch.sum(torch.abs(u) ** 2)) * (2.0 / prob.M[0]) ** 2)
+        modes = plan.query(81) * plan.query(82)
+        plan.close()
+        out["cases_2d"].append({"setting": label, "omega": 100.0, "nu": list(nu), "time_steps": n2,
+                                "modes": int(modes), "ionization_percent": ion, "ms_per_run": wall * 1e3,
+                                "time_steps_per_s": n2 / wall})
     return out
 
 

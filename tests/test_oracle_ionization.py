@@ -67,3 +67,24 @@ def test_oracle_ionization_matches_the_printed_fractions(omega):
     prob = ionization_1d_problem(omega, nsteps=4000)
     u, _ = FreeSpaceOracle(prob).run()
     assert abs(ionization_percent(u, prob.M[0]) - ion_paper) < 0.005
+
+
+def test_2d_ground_state_matches_the_printed_eigenvalue():
+    # Section 6, Example 4: eigenvalue about -922, state below 1e-11 outside [-1,1]^2
+    from workloads import gaussian_well_ground_state_2d
+
+    E, gs = gaussian_well_ground_state_2d(1400.0, 0.1)
+    assert abs(E - (-922.0)) < 0.5                    # -922.068
+    E2, gs2 = gaussian_well_ground_state_2d(1400.0, 0.1, n=160)
+    assert abs(E - E2) < 1e-7
+    x = np.linspace(-1.9, 1.9, 39)
+    assert np.max(np.abs(gs(x, x) - gs2(x, x))) < 1e-8
+    edge = np.linspace(-2, 2, 81)
+    g = np.abs(gs(edge, edge))
+    out = (np.abs(edge)[:, None] > 1) | (np.abs(edge)[None, :] > 1)
+    assert g[out].max() < 1e-11
+    xf = np.linspace(-2, 2, 401)[:-1]
+    assert abs(np.sum(gs(xf, xf) ** 2) * 0.01 ** 2 - 1.0) < 1e-10
+    # radially symmetric, as the well is
+    r = np.linspace(0.0, 0.5, 11)
+    assert np.max(np.abs(gs(r, [0.0])[:, 0] - np.diag(gs(r / np.sqrt(2), r / np.sqrt(2))))) < 1e-9

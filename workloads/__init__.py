@@ -18,4 +18,6 @@ from .synth import (  # noqa: F401
     moving_well_problem,
     gaussian_well_ground_state,
     ionization_1d_problem,
+    gaussian_well_ground_state_2d,
+    ionization_2d_problem,
 )
