@@ -159,6 +159,32 @@ def test_moving_well_example_1d(c):
     check(moving_well_problem(c=(c,), M=(256,), nsteps=400, name=f"moving-well-c{c:g}"))
 
 
+def test_moving_well_exact_boosted_ground_state():
+    # the well's ground state (eigenvalue about -243, as Example 1 prints)
+    # boosted by e^{i c x/2} rides the well moving at c = 30 exactly:
+    # u = e^{i(c x/2 - c^2 t/4)} e^{-i E t} psi_0(x - c t); 1600 steps
+    from paper_2001_06113_amd.tdse import Plan
+    from workloads import moving_well_problem, periodic_well_ground_state
+
+    M, c, T = 256, 30.0, 2 * np.pi / 15
+    E, g = periodic_well_ground_state(300.0, 0.2, M)
+    x = periodic_grid(M)
+    prob = moving_well_problem(c=(c,), M=(M,), nsteps=1600)
+    prob.u0 = (np.exp(1j * c * x / 2) * g).astype(np.complex128)
+    k = np.fft.fftfreq(M, d=2 * np.pi / M) * 2 * np.pi
+    shifted = np.real(np.fft.ifft(np.fft.fft(g) * np.exp(-1j * k * c * T)))
+    ex = np.exp(1j * (c * x / 2 - c * c * T / 4)) * np.exp(-1j * E * T) * shifted
+    print(f"case moving well exact boosted ground state c={c} steps=1600 (E = {E:.4f})", flush=True)
+    plan = Plan.from_problem(prob, device="cuda:0")
+    u = plan.run(prob.u0).cpu().numpy()
+    plan.close()
+    ref, _ = PeriodicOracle(prob).run()
+    r_ex, r_or = rel(u, ex), rel(u, ref)
+    print(f"  rel-L2 vs exact {r_ex:.3e}, vs oracle {r_or:.3e}", flush=True)
+    assert r_or <= 1e-11, r_or
+    assert r_ex <= 1e-8, r_ex
+
+
 @pytest.mark.parametrize("M,c,beta", [((128, 256), (0.0, 30.0), 0.2), ((96, 64), (15.0, -45.0), 0.2),
                                       ((64, 128), (30.0, 15.0), 0.9)])
 def test_moving_well_2d(M, c, beta):

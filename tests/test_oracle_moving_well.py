@@ -8,7 +8,12 @@
   2 pi periodic, and with c T a multiple of 2 pi the shift vanishes on the
   grid at t = T, so the two discrete runs must agree to the scheme's
   accuracy (their time-discretization errors differ at O(dt^8)).
+* The ground state of the well at rest (the paper's u0) has the eigenvalue
+  the example prints (about -243); boosted by e^{i c x/2}, it rides the
+  moving well as an exact solution, which the oracle reaches at eighth order.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -64,3 +69,53 @@ def test_covariance_fails_for_the_wrong_velocity():
     w, _ = PeriodicOracle(_static_twin(p, np.exp(15j * x) * p.u0)).run()
     pred = np.exp(-15j * x) * np.exp(-225j * T) * w
     assert _rel(u, pred) > 1e-2
+
+
+# --- Example 1 with the well's ground state ---------------------------------
+
+def _golden_example1():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "example1_moving_well.txt")
+    vals = {}
+    for line in open(path):
+        if not line.startswith("#") and line.strip():
+            k, v = line.split()
+            vals[k] = float(v)
+    return vals
+
+
+def test_periodic_well_ground_state_matches_the_printed_eigenvalue():
+    from workloads import periodic_well_ground_state
+
+    g = _golden_example1()
+    E, u = periodic_well_ground_state(g["V0"], g["beta"], 256)
+    assert abs(E - g["ground_eigenvalue"]) < 0.5              # -243.48
+    E2, _ = periodic_well_ground_state(g["V0"], g["beta"], 512)
+    assert abs(E - E2) < 1e-9
+    assert abs(np.sum(np.abs(u) ** 2) * 2 * np.pi / 256 - 1.0) < 1e-12
+
+
+def _shifted(g, s):
+    # g(x - s) on the periodic grid by trigonometric interpolation
+    k = np.fft.fftfreq(g.size, d=2 * np.pi / g.size) * 2 * np.pi
+    return np.real(np.fft.ifft(np.fft.fft(g) * np.exp(-1j * k * s)))
+
+
+@pytest.mark.parametrize("c", [0.0, 30.0])
+def test_boosted_ground_state_rides_the_moving_well_exactly(c):
+    # u0 = e^{i c x/2} psi_0 makes u = e^{i(c x/2 - c^2 t/4)} e^{-i E t} psi_0(x - c t)
+    # an exact solution with the well moving at c (c/2 integral keeps the
+    # boost periodic); the oracle converges to it at eighth order in dt
+    from workloads import periodic_well_ground_state
+
+    M, T = 256, 2 * np.pi / 15
+    E, g = periodic_well_ground_state(300.0, 0.2, M)
+    x = periodic_grid(M)
+    ex = np.exp(1j * (c * x / 2 - c * c * T / 4)) * np.exp(-1j * E * T) * _shifted(g, c * T)
+    errs = []
+    for N in (800, 1600):
+        prob = moving_well_problem(c=(c,), M=(M,), nsteps=N)
+        prob.u0 = (np.exp(1j * c * x / 2) * g).astype(np.complex128)
+        u, _ = PeriodicOracle(prob).run()
+        errs.append(np.linalg.norm(u - ex) / np.linalg.norm(ex))
+    assert errs[1] < 1e-8, errs                    # 5.1e-9 measured
+    assert errs[0] / errs[1] > 150, errs           # 2^8 = 256 asymptotically

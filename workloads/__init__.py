@@ -19,5 +19,6 @@ from .synth import (  # noqa: F401
     gaussian_well_ground_state,
     ionization_1d_problem,
     gaussian_well_ground_state_2d,
+    periodic_well_ground_state,
     ionization_2d_problem,
 )

@@ -237,18 +237,20 @@ def moving_well_problem(c: Sequence[float] = (15.0,), M: Sequence[int] = (256,),
                         nsteps: int = 400, V0: float = 300.0, beta: float = 0.2, order: int = 8,
                         precision: str = "fp64", name: str = "moving-well") -> Problem:
     """Example 1 of Section 6 (a periodic Gaussian well of depth V0 and width
-    beta moving with constant velocity c, A = 0), in 1D or 2D (len(M)).  The
-    paper starts from the well's ground state computed with Chebfun, which is
-    not available here; u0 is a periodized Gaussian of the width of the
-    harmonic approximation to that ground state, exp(-|x|^2 / (2 s^2)) with
-    s = (2 V0 / beta^2)^(-1/4), centred on the well, normalized."""
+    beta moving with constant velocity c, A = 0), in 1D or 2D (len(M)).  In
+    1D, u0 is the well's normalized ground state (periodic_well_ground_state),
+    as in the paper.  The 2D variant is not in the paper; there u0 is a
+    periodized Gaussian of the width of the harmonic approximation to the
+    ground state, exp(-|x|^2 / (2 s^2)) with s = (2 V0 / beta^2)^(-1/4),
+    centred on the well, normalized."""
     dim = len(M)
-    X = [periodic_grid(m) for m in M]
-    X = list(np.meshgrid(*X, indexing="ij")) if dim == 2 else X
-    s_w = (2.0 * V0 / beta ** 2) ** -0.25
-    u0 = _periodized_gauss(X, [0.0] * dim, np.sqrt(2.0) * s_w, images=2).astype(np.complex128)
-    cell = float(np.prod([TWO_PI / m for m in M]))
-    u0 = _normalize(u0, cell)
+    if dim == 1:
+        u0 = periodic_well_ground_state(V0, beta, int(M[0]))[1].astype(np.complex128)
+    else:
+        X = list(np.meshgrid(*[periodic_grid(m) for m in M], indexing="ij"))
+        s_w = (2.0 * V0 / beta ** 2) ** -0.25
+        u0 = _periodized_gauss(X, [0.0] * dim, np.sqrt(2.0) * s_w, images=2).astype(np.complex128)
+        u0 = _normalize(u0, float(np.prod([TWO_PI / m for m in M])))
     c = tuple(float(x) for x in c)
     return Problem(name=name, dim=dim, domain="periodic", M=tuple(int(m) for m in M), T=T, nsteps=nsteps,
                    order=order, u0=u0, V_fields=[], f_kind=[], f_params=[], precision=precision,
@@ -407,3 +409,25 @@ def ionization_2d_problem(omega: float, A0: float = 100.0, V0: float = 1400.0, b
                    panels=panels, nu=tuple(nu))
     prob.ground_energy = E
     return prob
+
+
+def periodic_well_ground_state(V0: float, beta: float, M: int, images: int = 2):
+    """Ground state of -u'' + V u = E u on the periodic interval [-pi, pi) for
+    the periodic Gaussian well V(x) = -V0 sum_k exp(-(x - 2 pi k)^2/(2 beta^2))
+    of Section 6, Example 1 (the well at rest), which the paper computes with
+    Chebfun: Fourier pseudo-spectral discretization on the M-point periodic
+    grid, dense symmetric eigensolve.  Returns (E, u) with u on the grid,
+    real, positive at the well's centre and normalized in L^2([-pi, pi))."""
+    x = periodic_grid(M)
+    k = np.fft.fftfreq(M, d=TWO_PI / M) * TWO_PI
+    F = np.fft.fft(np.eye(M), axis=0)
+    D2 = np.real(np.fft.ifft(-(k ** 2)[:, None] * F, axis=0))
+    V = -V0 * sum(np.exp(-(x - TWO_PI * j) ** 2 / (2.0 * beta ** 2)) for j in range(-images, images + 1))
+    Hm = -D2 + np.diag(V)
+    Hm = 0.5 * (Hm + Hm.T)
+    E, vecs = np.linalg.eigh(Hm)
+    g = vecs[:, 0]
+    g = g / np.sqrt(np.sum(g ** 2) * TWO_PI / M)
+    if g[np.argmin(np.abs(x))] < 0:
+        g = -g
+    return float(E[0]), g
