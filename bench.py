@@ -331,7 +331,7 @@ def ionization_leg(runs: int = 3, nsteps: int = 4000) -> dict:
     from workloads import ionization_2d_problem
 
     out["cases_2d"] = []
-    for label, nu, eps, n2 in (("eps=1e-10, h=0.31 both axes", (1024, 1024), 1e-10, 8000),
+    for label, nu, eps, n2 in (("eps=1e-10, h1=0.31, h2=0.61", (1024, 512), 1e-10, 8000),
                                ("eps=1e-5, h=1.23 both axes", (256, 256), 1e-5, 4000)):
         prob = ionization_2d_problem(100.0, nu=nu, eps=eps, nsteps=n2)
         plan = Plan.from_problem(prob, device=dev)

@@ -102,7 +102,8 @@ typedef struct {
   const double* A_steps;   /* TDSE_A_STEPWISE: host [nsteps][d]              */
   tdse_vector_fn A_fn; void* A_ctx;
   /* free space (Sections 3.4 and 4): tolerance eps for the choice of H
-   * (Remark on H), Alpert order p (8: 16th order, kappa = 7 omitted nodes),
+   * (Remark on H, applied per axis with that axis' quiver radius),
+   * Alpert order p (8: 16th order, kappa = 7 omitted nodes),
    * q Gauss nodes per panel and `panels` dyadic panels per side of Gamma_2,
    * FFT size nu per axis (N_E = nu/2 - 2 kappa + 1 equispaced nodes per ray,
    * h = pi M / nu); H > 0 overrides the rule for H. */
@@ -190,9 +191,10 @@ int tdse_far_eval(tdse_plan_t plan, const double* xs, int32_t nx, const double* 
 #define TDSE_Q_MU             16  /* + j: Adams weight mu_j                    */
 #define TDSE_Q_RICHARDSON     32  /* + l: weight of the 2^l-sub-step result    */
 #define TDSE_Q_PHI            64  /* + axis: phi_axis(T)                       */
-#define TDSE_Q_FS_H           80  /* free space: contour parameter H          */
+#define TDSE_Q_FS_H           80  /* free space: contour parameter H of axis 0 */
 #define TDSE_Q_FS_MODES       81  /* + axis: complex-frequency modes N_axis     */
 #define TDSE_Q_FS_NE          83  /* + axis: equispaced nodes per ray N_E      */
+#define TDSE_Q_FS_H_AXIS      86  /* + axis: contour parameter H of that axis   */
 #define TDSE_Q_ALPERT_X       96  /* + k: Alpert node x_k (units of h), k < p   */
 #define TDSE_Q_ALPERT_W      112  /* + k: Alpert weight w_k, k < p              */
 #define TDSE_Q_INSTANCES       4  /* batch: number of instances                 */

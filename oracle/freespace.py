@@ -47,13 +47,15 @@ class FreeSpaceOracle:
         self.phi = make_phi(p)
         self.mu = [float(m) for m in adams_coefficients(p.order)]
         self.xs = [free_grid(m) for m in self.shape]
-        if self.H is None:
-            self.H = self.default_H()
+        # one contour parameter per axis (self.Hs); an H given by the caller
+        # applies to every axis; self.H is that of axis 0
+        self.Hs = self.default_H() if self.H is None else [float(self.H)] * self.d
+        self.H = self.Hs[0]
         kappa = KAPPA[p.p]
         self.nodes = []
         self.G, self.Ginv = [], []
         for a in range(self.d):
-            zeta, w, info = gamma_rule(self.shape[a], self.H, p.nu[a], p.p, kappa, p.q, p.panels)
+            zeta, w, info = gamma_rule(self.shape[a], self.Hs[a], p.nu[a], p.p, kappa, p.q, p.panels)
             x = self.xs[a]
             self.nodes.append((zeta, w, info))
             self.G.append((2.0 / self.shape[a]) * np.exp(-1j * np.outer(zeta, x)))
@@ -63,16 +65,18 @@ class FreeSpaceOracle:
         self.Z2 = sum(z * z for z in Z)
 
     # --- parameter choice (Remark on H, Section 3.2) -------------------------
-    def default_H(self) -> float:
+    def default_H(self):
+        """The Remark's rule in each dimension, with that axis' quiver radius
+        max_t |phi_a(t)| (the analysis bounds the growth per dimension)."""
         p = self.prob
         dt = p.dt
         cell = np.prod([2.0 / m for m in self.shape])
-        normV, phimax = 0.0, 0.0
+        normV, phimax = 0.0, np.zeros(self.d)
         for n in range(p.nsteps + 1):
             t = n * dt
             normV = max(normV, float(np.sqrt(np.sum(self.V(t) ** 2) * cell)))
-            phimax = max(phimax, float(np.linalg.norm(self.phi(t))))
-        return choose_H(p.eps, normV, phimax, self.d)
+            phimax = np.maximum(phimax, np.abs(np.asarray(self.phi(t), dtype=np.float64)))
+        return [choose_H(p.eps, normV, float(phimax[a]), self.d) for a in range(self.d)]
 
     # --- transforms ----------------------------------------------------------
     def F(self, f: np.ndarray) -> np.ndarray:

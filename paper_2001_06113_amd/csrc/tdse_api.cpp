@@ -294,7 +294,8 @@ struct tdse_plan_s {
 
   // ---- free space (Sections 3.4 and 4)
   bool free_space = false;
-  double H = 0.0;
+  double H = 0.0;              // contour parameter of physical axis 0
+  double Hfx[2] = {0.0, 0.0};  // per transform axis fx[a] (1D: fx[1])
   std::vector<double> alp_x, alp_w;   // Alpert end correction, units of h
   struct FAxis {
     int M = 1, N = 1, NE = 0, ND = 0, nu = 0;
@@ -821,7 +822,7 @@ void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels) 
   typedef long double LD;
   tdse_plan_s::FAxis& F = p->fx[axis];
   const int kappa = 7, pp = (int)p->alp_x.size();
-  const LD H = p->H;
+  const LD H = p->Hfx[axis];
   const LD PI = 3.14159265358979323846264338327950288L;
   F.M = M;
   F.nu = nu;
@@ -1158,13 +1159,15 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
   if (!(prob->eps > 0.0 && prob->eps < 1.0) && !(prob->H > 0.0)) return fail(TDSE_EINVAL, "need 0 < eps < 1 or H > 0");
   p->free_space = true;
   alpert_rule(8, 7, p->alp_x, p->alp_w);
-  // H from the Remark on its choice: log(eps / ((1 + ||V||_{2,inf}) eps_m)) / (2 d (1 + phi_max)),
+  // H from the Remark on its choice, log(eps / ((1 + ||V||_{2,inf}) eps_m)) / (2 d (1 + phi_max)),
+  // taken in each dimension, as the analysis of the complex-frequency
+  // representation bounds it, with that axis' quiver radius max_t |phi_a(t)|;
   // maxima over the step times
   if (prob->H > 0.0) {
-    p->H = prob->H;
+    p->Hfx[0] = p->Hfx[1] = prob->H;
   } else {
     const double cell = (p->dim == 2 ? 4.0 / ((double)p->M1 * p->M2) : 2.0 / p->M2);
-    double normV = 0.0, phimax = 0.0;
+    double normV = 0.0, phimax[2] = {0.0, 0.0};
     std::vector<double> f(MAXV);
     for (int n = 0; n <= p->nsteps; ++n) {
       const double t = p->t_at(n);
@@ -1178,11 +1181,15 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
       normV = std::max(normV, std::sqrt(s2 * cell));
       double ph[2];
       p->tf.phi(t, ph);
-      phimax = std::max(phimax, std::sqrt(ph[0] * ph[0] + (p->dim == 2 ? ph[1] * ph[1] : 0.0)));
+      for (int a = 0; a < p->dim; ++a) phimax[a] = std::max(phimax[a], std::fabs(ph[a]));
     }
-    p->H = std::log(prob->eps / ((1.0 + normV) * std::ldexp(1.0, -52))) / (2.0 * p->dim * (1.0 + phimax));
+    const double num = std::log(prob->eps / ((1.0 + normV) * std::ldexp(1.0, -52)));
+    // physical axis a is transform axis fx[a] in 2D and fx[1] in 1D
+    for (int a = 0; a < p->dim; ++a) p->Hfx[p->dim == 2 ? a : 1] = num / (2.0 * p->dim * (1.0 + phimax[a]));
   }
-  if (!(p->H > 0.0)) return fail(TDSE_EINVAL, "the rule for H gives H <= 0 (eps too small)");
+  p->H = p->Hfx[p->dim == 2 ? 0 : 1];
+  for (int a = 0; a < p->dim; ++a)
+    if (!(p->Hfx[p->dim == 2 ? a : 1] > 0.0)) return fail(TDSE_EINVAL, "the rule for H gives H <= 0 (eps too small)");
   const int axes[2] = {p->dim == 2 ? prob->M[0] : 1, p->dim == 2 ? prob->M[1] : prob->M[0]};
   const int nus[2] = {p->dim == 2 ? prob->nu[0] : 0, p->dim == 2 ? prob->nu[1] : prob->nu[0]};
   for (int a = 0; a < 2; ++a) {
@@ -2559,6 +2566,13 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
   if (key == TDSE_Q_FS_H) {
     if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");
     *value = p->H;
+    return TDSE_OK;
+  }
+  if (key >= TDSE_Q_FS_H_AXIS && key < TDSE_Q_FS_H_AXIS + 2) {
+    if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");
+    const int axis = key - TDSE_Q_FS_H_AXIS;
+    if (axis >= p->dim) return fail(TDSE_EINVAL, "axis out of range");
+    *value = p->Hfx[p->dim == 2 ? axis : 1];
     return TDSE_OK;
   }
   if ((key >= TDSE_Q_FS_MODES && key < TDSE_Q_FS_MODES + 2) || (key >= TDSE_Q_FS_NE && key < TDSE_Q_FS_NE + 2)) {

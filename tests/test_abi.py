@@ -254,6 +254,14 @@ def test_free_space_planner_contour_matches_oracle(lib, dim, M, nu):
     assert lib.tdse_query(h, 80, C.byref(v)) == 0
     assert abs(v.value - orc.H) < 1e-12 * orc.H
     for a in range(dim):
+        # per-axis H: the field lies along axis 0, so a field-free axis 1 gets
+        # the rule's value at phi_max = 0, larger than axis 0's
+        assert lib.tdse_query(h, 86 + a, C.byref(v)) == 0
+        assert abs(v.value - orc.Hs[a]) < 1e-12 * orc.Hs[a]
+    if dim == 2:
+        assert orc.Hs[1] > orc.Hs[0]
+    assert lib.tdse_query(h, 86 + dim, C.byref(v)) == -1
+    for a in range(dim):
         assert lib.tdse_query(h, 81 + a, C.byref(v)) == 0
         assert v.value == orc.nodes[a][2]["N"]
         assert lib.tdse_query(h, 83 + a, C.byref(v)) == 0

@@ -66,9 +66,12 @@ def test_ionization_2d_matches_oracle():
 
 def test_ionization_2d_accuracy_settings():
     # omega = 100 against a reference with eps = 1e-10, h = 0.31 on both axes
-    # and 16000 steps: the paper's lower-accuracy setting (eps = 1e-5,
-    # h ~ 1.2-1.6, 4000 steps) keeps about five digits, and 8000 steps at the
-    # reference's contour are within 2e-7 (eighth order in dt)
+    # and 16000 steps: the paper's higher-accuracy setting (eps = 1e-10,
+    # h1 ~ 0.3, h2 ~ 0.5; here 0.31 and 0.61, the field-free axis with its own
+    # larger H) is accurate to about ten digits once the time step is small
+    # enough, and to 2e-7 at 8000 steps (eighth order in dt); the
+    # lower-accuracy setting (eps = 1e-5, h ~ 1.2-1.6, 4000 steps) keeps about
+    # five digits
     from paper_2001_06113_amd.tdse import Plan
     from workloads import ionization_2d_problem
 
@@ -82,8 +85,11 @@ def test_ionization_2d_accuracy_settings():
 
     ref = run((1024, 1024), 1e-10, 16000)
     rel = lambda a: np.linalg.norm(a - ref) / np.linalg.norm(ref)
+    hi16 = rel(run((1024, 512), 1e-10, 16000))
+    hi8 = rel(run((1024, 512), 1e-10, 8000))
     lo = rel(run((256, 256), 1e-5, 4000))
-    hi = rel(run((1024, 1024), 1e-10, 8000))
-    print(f"  rel-L2: lower-accuracy setting {lo:.2e}, 8000 steps {hi:.2e}", flush=True)
+    print(f"  rel-L2: higher-accuracy setting {hi16:.2e} (16000 steps), {hi8:.2e} (8000 steps); "
+          f"lower-accuracy setting {lo:.2e}", flush=True)
+    assert hi16 < 2e-9, hi16
+    assert hi8 < 2e-7, hi8
     assert lo < 1e-4, lo
-    assert hi < 2e-7, hi
