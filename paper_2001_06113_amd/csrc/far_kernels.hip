@@ -32,49 +32,56 @@ __global__ __launch_bounds__(256) void k_far_table(const double2* __restrict__ z
 
 // C[m][n] = sum_k A[m sam + k sak] B[k sbk + n sbn] (complex128), C row-major
 // with leading dimension ldc, on the FP64 matrix cores.  A workgroup of four
-// waves computes a 64 x 64 tile of C, each wave a 32 x 32 quarter as 2 x 2
-// blocks of the 16 x 16 x 4 FP64 MFMA.  K advances in chunks of 16 staged
-// through LDS (zeros beyond the operands' edges), four MFMA k-steps a chunk.
-// Operand lanes: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; the
-// result D[q + 4 r][j] sits in lane j + 16 q, element r.  A complex product
-// takes four real ones: Re C += Re A Re B - Im A Im B, Im C += Re A Im B +
-// Im A Re B.  Tiles are numbered along n first.
+// waves computes a T x T tile of C (T = 32 WB), each wave a quarter of it as
+// WB x WB blocks of the 16 x 16 x 4 FP64 MFMA.  K advances in chunks of 16
+// staged through LDS (zeros beyond the operands' edges), four MFMA k-steps a
+// chunk, and the next chunk's operands are loaded into registers while the
+// MFMAs work on the current one.  Operand lanes: A[i][k] in lane i + 16 k,
+// B[k][j] in lane j + 16 k; the result D[q + 4 r][j] sits in lane j + 16 q,
+// element r.  A complex product takes four real ones: Re C += Re A Re B -
+// Im A Im B, Im C += Re A Im B + Im A Re B.  Tiles are numbered along n first.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int FAR_T = 64, FAR_K = 16;
+constexpr int FAR_K = 16;
+template <int WB>
 __global__ __launch_bounds__(256) void k_far_gemm(int M, int N, int K, const double2* __restrict__ A, int64_t sam,
                                                   int64_t sak, const double2* __restrict__ B, int64_t sbk,
                                                   int64_t sbn, double2* __restrict__ C, int64_t ldc) {
-  __shared__ double2 As[FAR_K][FAR_T + 1];
-  __shared__ double2 Bs[FAR_K][FAR_T + 1];
+  constexpr int T = 32 * WB;           // output tile edge
+  constexpr int LD = T * FAR_K / 256;  // operand elements per thread and chunk
+  __shared__ double2 As[FAR_K][T + 1];
+  __shared__ double2 Bs[FAR_K][T + 1];
   const int tid = threadIdx.x;
   const int lane = tid % 64, wave = tid / 64;
-  const int wm = 32 * (wave / 2), wn = 32 * (wave % 2);
+  const int wm = 16 * WB * (wave / 2), wn = 16 * WB * (wave % 2);
   const int li = lane % 16, lk = lane / 16;
-  const int ntn = (N + FAR_T - 1) / FAR_T;
-  const int m0 = (blockIdx.x / ntn) * FAR_T, n0 = (blockIdx.x % ntn) * FAR_T;
-  f64x4 cr[2][2], ci[2][2];
+  const int ntn = (N + T - 1) / T;
+  const int m0 = (blockIdx.x / ntn) * T, n0 = (blockIdx.x % ntn) * T;
+  f64x4 cr[WB][WB], ci[WB][WB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < WB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < WB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         cr[a][b][r] = 0.0;
         ci[a][b][r] = 0.0;
       }
-  // the next chunk's operands are loaded into registers while the MFMAs
-  // work on the current chunk in LDS
-  double2 ra[4], rb[4];
+  double2 ra[LD], rb[LD];
+  // element e of a chunk: A along k when A is contiguous in k, else along m;
+  // B along n
+  auto a_at = [&](int e, int& ka, int& ma) {
+    ka = sak == 1 ? e % FAR_K : e / T;
+    ma = sak == 1 ? e / FAR_K : e % T;
+  };
   auto load_chunk = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = tid + 256 * r;   // 0 .. FAR_T * FAR_K - 1
-      // A: consecutive threads along k when A is contiguous in k, else along m
-      const int ka = sak == 1 ? e % FAR_K : e / FAR_T, ma = sak == 1 ? e / FAR_K : e % FAR_T;
+    for (int r = 0; r < LD; ++r) {
+      const int e = tid + 256 * r;   // 0 .. T * FAR_K - 1
+      int ka, ma;
+      a_at(e, ka, ma);
       const int gm = m0 + ma, gka = k0 + ka;
       ra[r] = (gm < M && gka < K) ? A[(int64_t)gm * sam + (int64_t)gka * sak] : double2{0.0, 0.0};
-      // B: consecutive threads along n
-      const int kb = e / FAR_T, nb = e % FAR_T;
+      const int kb = e / T, nb = e % T;
       const int gn = n0 + nb, gkb = k0 + kb;
       rb[r] = (gn < N && gkb < K) ? B[(int64_t)gkb * sbk + (int64_t)gn * sbn] : double2{0.0, 0.0};
     }
@@ -82,25 +89,26 @@ __global__ __launch_bounds__(256) void k_far_gemm(int M, int N, int K, const dou
   if (K > 0) load_chunk(0);
   for (int k0 = 0; k0 < K; k0 += FAR_K) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < LD; ++r) {
       const int e = tid + 256 * r;
-      const int ka = sak == 1 ? e % FAR_K : e / FAR_T, ma = sak == 1 ? e / FAR_K : e % FAR_T;
+      int ka, ma;
+      a_at(e, ka, ma);
       As[ka][ma] = ra[r];
-      Bs[e / FAR_T][e % FAR_T] = rb[r];
+      Bs[e / T][e % T] = rb[r];
     }
     __syncthreads();
     if (k0 + FAR_K < K) load_chunk(k0 + FAR_K);
 #pragma unroll
     for (int ks = 0; ks < FAR_K; ks += 4) {
-      double2 av[2], bv[2];
+      double2 av[WB], bv[WB];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[ks + lk][wm + 16 * a + li];
+      for (int a = 0; a < WB; ++a) av[a] = As[ks + lk][wm + 16 * a + li];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[ks + lk][wn + 16 * b + li];
+      for (int b = 0; b < WB; ++b) bv[b] = Bs[ks + lk][wn + 16 * b + li];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < WB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < WB; ++b) {
           cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
           cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[b].y, cr[a][b], 0, 0, 0);
           ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
@@ -110,9 +118,9 @@ __global__ __launch_bounds__(256) void k_far_gemm(int M, int N, int K, const dou
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < WB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < WB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm + 16 * a + lk + 4 * r, gn = n0 + wn + 16 * b + li;
@@ -132,13 +140,25 @@ hipError_t launch_far_gemm(int M, int N, int K, const double2* A, int64_t sam, i
                            int64_t sbk, int64_t sbn, double2* C, int64_t ldc, hipStream_t s, hipEvent_t e0,
                            hipEvent_t e1) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  const int64_t tiles = (int64_t)((M + FAR_T - 1) / FAR_T) * ((N + FAR_T - 1) / FAR_T);
+  // 64 x 64 tiles when they give every compute unit two or more, else
+  // 32 x 32 tiles (four times as many workgroups for small outputs)
+  const int64_t tiles64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+  const bool big = tiles64 >= 512;
+  const int64_t tiles = big ? tiles64 : (int64_t)((M + 31) / 32) * ((N + 31) / 32);
   // with events, recorded at the kernel's own start and end
-  if (e0)
-    hipExtLaunchKernelGGL(k_far_gemm, dim3((unsigned)tiles), dim3(256), 0, s, e0, e1, 0, M, N, K, A, sam, sak, B, sbk,
-                          sbn, C, ldc);
+#define FAR_LAUNCH(KER)                                                                                             \
+  do {                                                                                                              \
+    if (e0)                                                                                                         \
+      hipExtLaunchKernelGGL(KER, dim3((unsigned)tiles), dim3(256), 0, s, e0, e1, 0, M, N, K, A, sam, sak, B, sbk,    \
+                            sbn, C, ldc);                                                                           \
+    else                                                                                                            \
+      hipLaunchKernelGGL(KER, dim3((unsigned)tiles), dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc);   \
+  } while (0)
+  if (big)
+    FAR_LAUNCH(k_far_gemm<2>);
   else
-    hipLaunchKernelGGL(k_far_gemm, dim3((unsigned)tiles), dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc);
+    FAR_LAUNCH(k_far_gemm<1>);
+#undef FAR_LAUNCH
   return hipGetLastError();
 }
 

@@ -200,7 +200,9 @@ def test_far_evaluation_exact_wavepacket_at_full_size():
     plan = gpu_plan(prob)
     plan.run(prob.u0)
     ph = [plan.query(64), plan.query(65)]
-    px, py = np.linspace(-2.0, 2.0, 97), np.linspace(-1.75, 1.75, 130)
+    # 1024 last-axis points: the first product (2102 x 2102 x 1024) takes the
+    # 64 x 64 tiles, the second (97 x 2102 x 1024) the 32 x 32 ones
+    px, py = np.linspace(-2.0, 2.0, 97), np.linspace(-1.75, 1.75, 1024)
     got = plan.far_eval(py, px).cpu().numpy()
     plan.close()
     ex = np.multiply.outer(_wavepacket(px - 0.1 + ph[0], T, 0.12), _wavepacket(py + 0.05 + ph[1], T, 0.1))
