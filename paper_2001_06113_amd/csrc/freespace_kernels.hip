@@ -596,8 +596,10 @@ hipError_t launch_fs_row(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0, 
 }
 
 hipError_t launch_fs_col(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (nu == 0) {   // 1D: pointwise
-    TDSE_FS_LAUNCH(k_fs_point, dim3((a.ax2.M + 255) / 256), dim3(256), s, e0, e1, a);
+  if (nu == 0) {   // 1D: pointwise, with enough workgroups for one phase entry per thread
+    const int64_t entries = (int64_t)a.req.nj * (a.N1 + a.N2);
+    const int64_t blocks = std::max<int64_t>((a.ax2.M + 255) / 256, std::min<int64_t>((entries + 255) / 256, 1024));
+    TDSE_FS_LAUNCH(k_fs_point, dim3((unsigned)blocks), dim3(256), s, e0, e1, a);
     return hipGetLastError();
   }
   switch (nu) {
@@ -614,7 +616,9 @@ hipError_t launch_fs_col(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0, 
 }
 
 hipError_t launch_fs_phase(const FSArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_fs_phase, dim3(8), dim3(256), 0, s, a);
+  const int64_t entries = (int64_t)a.req.nj * (a.N1 + a.N2);
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((entries + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_fs_phase, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
