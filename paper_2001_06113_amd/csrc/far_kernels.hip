@@ -132,6 +132,7 @@ hipError_t launch_far_table(const double2* zeta, const double2* w, int N, const 
                             hipStream_t s) {
   const int64_t tot = (int64_t)N * n;
   if (tot <= 0) return hipSuccess;
+  if ((tot + 255) / 256 > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_far_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, zeta, w, N, x, n, E);
   return hipGetLastError();
 }
@@ -145,6 +146,7 @@ hipError_t launch_far_gemm(int M, int N, int K, const double2* A, int64_t sam, i
   const int64_t tiles64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
   const bool big = tiles64 >= 512;
   const int64_t tiles = big ? tiles64 : (int64_t)((M + 31) / 32) * ((N + 31) / 32);
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   // with events, recorded at the kernel's own start and end
 #define FAR_LAUNCH(KER)                                                                                             \
   do {                                                                                                              \

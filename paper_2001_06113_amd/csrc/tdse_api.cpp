@@ -2405,6 +2405,11 @@ int far_check(const tdse_plan_s* p, int nx, int ny) {
   if (p->is_batch() || !p->free_space) return fail(TDSE_EUNSUPPORTED, "evaluation at arbitrary points is for free-space plans");
   if (ny < 1 || nx < 1 || ny > (1 << 24) || nx > (1 << 24)) return fail(TDSE_EINVAL, "need 1 <= nx, ny <= 2^24");
   if (p->dim == 1 && nx != 1) return fail(TDSE_EINVAL, "a 1D plan takes nx = 1");
+  // every table and product launch must fit a one-dimensional grid
+  const int64_t N1 = p->fx[0].N, N2 = p->fx[1].N, lim = (int64_t)1 << 30;
+  if (N2 * ny > lim || N1 * nx > lim || ((N1 + 31) / 32) * ((ny + 31) / 32) > lim ||
+      ((nx + 31) / 32) * ((ny + 31) / 32) > lim)
+    return fail(TDSE_EINVAL, "too many evaluation points");
   return TDSE_OK;
 }
 }  // namespace

@@ -349,6 +349,8 @@ def test_far_evaluation_sizing_and_checks(lib):
         assert sz.value == want, (nx, ny)
     sz = C.c_size_t()
     assert lib.tdse_far_workspace_size(h, 0, 5, C.byref(sz)) == -1
+    # launches that would not fit a one-dimensional grid are refused up front
+    assert lib.tdse_far_workspace_size(h, 1 << 24, 1 << 24, C.byref(sz)) == -1
     ys = np.zeros(4)
     # before bind and set_state: a state error, no device call
     assert lib.tdse_far_eval(h, ys.ctypes.data_as(C.c_void_p), 1, ys.ctypes.data_as(C.c_void_p), 4,
