@@ -65,13 +65,25 @@ bool line_length_supported(int N) {
     else hipLaunchKernelGGL(K, G, B, 0, S, A);                    \
   } while (0)
 
+// The pointwise pass of a 1D problem (length 1) fills one workgroup with its
+// M2 points; it gets extra, inactive workgroups so that the next row pass's
+// phase table has one entry per thread.
+inline int64_t col_blocks(int N, const LineArgs& a, int L, int T) {
+  int64_t nb = (a.nlines + L - 1) / L;
+  if (N == 1) {
+    const int64_t entries = (int64_t)a.req.nj * (a.M1 + a.M2);
+    nb = std::max<int64_t>(nb, std::min<int64_t>((entries + L * T - 1) / (L * T), 1024));
+  }
+  return nb;
+}
+
 template <typename C>
 hipError_t col_pass(int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (N) {
 #define X(n)                                                                                      \
   case n: {                                                                                       \
     constexpr int L = col_lpw(n), T = col_tl(n);                                                  \
-    TDSE_LAUNCH((k_col<C, n, L, T>), dim3((a.nlines + L - 1) / L), dim3(L * T), s, e0, e1, a);   \
+    TDSE_LAUNCH((k_col<C, n, L, T>), dim3((unsigned)col_blocks(n, a, L, T)), dim3(L * T), s, e0, e1, a); \
     break;                                                                                        \
   }
     X(1)
