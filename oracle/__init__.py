@@ -14,8 +14,13 @@ Modules
   adams      implicit Adams coefficients (Section 2.2, Table 1) and the
              iterated Richardson weights (Section 2.2)
   periodic   the periodic scheme (Sections 2.1-2.2): trapezoid sub-step,
-             Richardson start-up, implicit Adams marching
+             Richardson start-up, implicit Adams marching; the moving
+             periodic Gaussian well of Section 6, Example 1
   quadrature Gauss-Legendre and Alpert end-corrected trapezoid rules on the
              contour Gamma (Section 3.4)
-  freespace  the complex-frequency scheme by dense transforms (Sections 3.3-3.4)
+  freespace  the complex-frequency scheme by dense transforms (Sections 3.3-3.4),
+             and its representation evaluated at arbitrary points (Remark on
+             evaluation outside [-1,1])
+  adjoint    the discrete reverse sweep of the periodic scheme (gradients with
+             respect to stepwise field samples and u0)
 """
