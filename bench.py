@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=60, help="time steps in the oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=100, help="Adams steps in the oracle sample (after the start-up)")
     ap.add_argument("--workload", default="periodic-2d-512", choices=["periodic-2d-512", "periodic-2d-1024-fp64"])
     ap.add_argument("--prof-runs", type=int, default=3, help="eager runs timed per kernel with HIP events")
     ap.add_argument("--no-split", action="store_true", help="skip the FP32-split 1024x1024 leg")
@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched leg")
     ap.add_argument("--no-well", action="store_true", help="skip the moving-well (potential on the fly) leg")
     ap.add_argument("--no-ionization", action="store_true", help="skip the 1D ionization (Example 3) leg")
+    ap.add_argument("--no-1d", action="store_true", help="skip the 1D periodic M = 256 leg")
     ap.add_argument("--batch-runs", type=int, default=3)
     ap.add_argument("--free-runs", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -65,8 +66,11 @@ def calibrate_copy():
 
 def device_copy_gbps(dev, mib: int = 512, reps: int = 10) -> float:
     """Bandwidth of a plain device-to-device copy (bytes read + written per
-    second), timed with events on the current stream: the practical HBM ceiling
-    the roofline fraction is also quoted against."""
+    second), timed with events on the current stream.  At 512 MiB the copy
+    streams from HBM: the practical HBM ceiling.  At 32 MiB source and
+    destination together (64 MiB) stay in the 256 MB last-level cache (MALL)
+    between repetitions: the ceiling of a working set that fits there, as the
+    512 x 512 and 1024 x 1024 periodic runs do."""
     import torch
 
     n = mib * (1 << 20) // 16
@@ -95,29 +99,79 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(prob, nsteps: int) -> dict:
-    """Time the FP64 oracle (as written) on the first `nsteps` steps."""
+def cpu_baseline(prob, adams_steps: int) -> dict:
+    """Time the FP64 oracle (as written) on the host: the Richardson start-up
+    alone, then start-up plus `adams_steps` implicit Adams steps, one thread
+    (numpy's FFT is single-threaded).  End to end = modes x steps / time of
+    the second run; steady state = modes x adams_steps / (difference of the
+    two).  Beside it, for context only, the same oracle with its transforms
+    taken by scipy.fft on all available cores."""
     from threadpoolctl import threadpool_limits
 
     from oracle.periodic import PeriodicOracle
 
-    with threadpool_limits(limits=1):
-        orc = PeriodicOracle(prob)
-        t0 = time.perf_counter()
-        orc.run(nsteps=nsteps)
-        dt = time.perf_counter() - t0
+    ns = prob.start_steps
     modes = float(prob.u0.size)
-    return {
-        "value": modes * nsteps / dt,
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        PeriodicOracle(prob).run(nsteps=ns)
+        t_start = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        PeriodicOracle(prob).run(nsteps=ns + adams_steps)
+        t_full = time.perf_counter() - t0
+    out = {
+        "value": modes * (ns + adams_steps) / t_full,
         "unit": "mode-updates/s",
         "cores": 1,
         "kind": "oracle",
+        "steady_state_value": modes * adams_steps / max(t_full - t_start, 1e-9),
         "cpu_model": cpu_model(),
         "host_cores_available": len(os.sched_getaffinity(0)),
-        "sample": f"{prob.name} at full size ({'x'.join(map(str, prob.M))}), first {nsteps} of {prob.nsteps} "
-                  f"steps (6 Richardson start-up steps + {nsteps - prob.start_steps} Adams steps), "
-                  f"numpy/pocketfft single thread, {dt:.1f} s",
+        "sample": f"{prob.name} at full size ({'x'.join(map(str, prob.M))}): the {ns} Richardson start-up steps "
+                  f"({t_start:.1f} s), then start-up + {adams_steps} Adams steps ({t_full:.1f} s) of {prob.nsteps}, "
+                  f"numpy/pocketfft single thread",
     }
+    try:
+        import scipy.fft as sfft
+
+        cores = len(os.sched_getaffinity(0))
+
+        class AllCores(PeriodicOracle):
+            def F(self, f):
+                return sfft.fftn(f, workers=cores) / f.size
+
+            def Finv(self, g):
+                return sfft.ifftn(g, workers=cores) * g.size
+
+        t0 = time.perf_counter()
+        AllCores(prob).run(nsteps=ns + adams_steps)
+        t_all = time.perf_counter() - t0
+        out["all_cores_scipy_fft"] = {"value": modes * (ns + adams_steps) / t_all, "cores": cores,
+                                      "note": "the oracle with scipy.fft transforms on all cores (context)"}
+    except ImportError:
+        pass
+    return out
+
+
+def oracle_error(case: str, u, inst: int = 0, bar: float = 1e-11) -> dict:
+    """Error of a computed u(T) against the stored oracle samples of the same
+    workload (tests/golden/<case>_oracle_sample.txt): Section 6's err(T) on
+    the stored sub-grid."""
+    from workloads.golden import load_samples, sampled_error
+
+    e = sampled_error(u.detach().cpu().numpy() if hasattr(u, "detach") else u, load_samples(case)[inst])
+    return {"rel_l2_vs_oracle": e["rel_l2"], "max_abs_rel_vs_oracle": e["max_abs_rel"],
+            "sampled_points": e["points"], "bar": bar, "pass": e["rel_l2"] <= bar}
+
+
+def end_to_end(bytes_per_step: float, nsteps: int, seconds: float, copies: dict) -> dict:
+    """Algorithmic bytes of every nominal time step over the whole-run wall
+    time, against the datasheet HBM peak and the measured copy ceilings."""
+    gbps = bytes_per_step * nsteps / seconds / 1e9
+    out = {"algorithmic_bytes_per_step": bytes_per_step, "GBps": gbps, "frac_of_peak": gbps / HBM_PEAK_GBS}
+    for k, v in copies.items():
+        out[f"frac_of_copy_{k}"] = gbps / v
+    return out
 
 
 KERNEL_SOURCES = ("paper_2001_06113_amd/csrc/periodic_kernels.hip", "paper_2001_06113_amd/csrc/periodic_body.h",
@@ -146,17 +200,17 @@ def measured_traffic(name: str, sources=KERNEL_SOURCES):
     return float(kv["traffic_bytes"])
 
 
-def split_leg(steps: int) -> dict:
+def split_leg(steps: int, copies: dict) -> dict:
     """FP32-split form on the 1024 x 1024 workload (seed 3): throughput of
-    graph-replayed runs, and rel-L2 of u(T) against the FP64 GPU path."""
+    graph-replayed runs, rel-L2 of u(T) against the FP64 GPU path, and both
+    runs against the stored oracle samples."""
     import torch
 
-    from paper_2001_06113_amd.tdse import Plan
+    from paper_2001_06113_amd.tdse import Q_BYTES_PER_STEP, Plan
     from workloads import periodic_2d_1024_problem
 
     dev = torch.device("cuda:0")
-    res = {}
-    outs = {}
+    res, outs, walls, e2e, err = {}, {}, {}, {}, {}
     for prec in ("fp32split", "fp64"):
         prob = periodic_2d_1024_problem(precision=prec)
         plan = Plan.from_problem(prob, device=dev)
@@ -165,19 +219,25 @@ def split_leg(steps: int) -> dict:
         out = torch.empty_like(u0)
         plan.run(u0, out)
         torch.cuda.synchronize()
-        n = steps if prec == "fp32split" else 1
+        n = steps
         t0 = time.perf_counter()
         for _ in range(n):
             plan.run(u0, out)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        wall = (time.perf_counter() - t0) / n
         outs[prec] = out.clone()
-        res[prec] = u0.numel() * prob.nsteps * n / wall
+        walls[prec] = wall
+        res[prec] = u0.numel() * prob.nsteps / wall
+        e2e[prec] = end_to_end(plan.query(Q_BYTES_PER_STEP), prob.nsteps, wall, copies)
+        err[prec] = oracle_error("periodic_2d_1024", out, bar=1e-6 if prec == "fp32split" else 1e-11)
         plan.close()
-    err = (torch.linalg.vector_norm(outs["fp32split"] - outs["fp64"]) / torch.linalg.vector_norm(outs["fp64"])).item()
+    rel = (torch.linalg.vector_norm(outs["fp32split"] - outs["fp64"]) / torch.linalg.vector_norm(outs["fp64"])).item()
     return {"workload": "2D periodic TDSE 1024x1024, T=2, 2000 steps AM8, FP32-split",
-            "value": res["fp32split"], "unit": "mode-updates/s", "fp64_value": res["fp64"],
-            "speedup_vs_fp64": res["fp32split"] / res["fp64"], "rel_l2_vs_fp64": err, "bar": 1e-6}
+            "value": res["fp32split"], "unit": "mode-updates/s", "ms_per_run": walls["fp32split"] * 1e3,
+            "end_to_end": e2e["fp32split"], "error": err["fp32split"],
+            "fp64_value": res["fp64"], "fp64_ms_per_run": walls["fp64"] * 1e3, "fp64_end_to_end": e2e["fp64"],
+            "fp64_error": err["fp64"],
+            "speedup_vs_fp64": res["fp32split"] / res["fp64"], "rel_l2_vs_fp64": rel, "bar": 1e-6}
 
 
 def moving_well_leg(runs: int = 5) -> dict:
@@ -213,11 +273,13 @@ def moving_well_leg(runs: int = 5) -> dict:
         plan.close()
         out[key] = {"ms_per_run": wall * 1e3, "value": u0.numel() * prob.nsteps / wall, "unit": "mode-updates/s",
                     "col_pass_us": col_us, "finite": bool(torch.isfinite(torch.view_as_real(res)).all().item())}
+        if key == "grid_512x512":
+            out[key]["error"] = oracle_error("moving_well_2d_512", res)
     return {"workload": "moving periodic Gaussian well (V0=300, beta=0.2), potential on the fly: "
                         "1D M=256 c=30 400 steps; 2D 512x512 c=(30,15) 2000 steps, FP64", **out}
 
 
-def free_space_leg(runs: int) -> dict:
+def free_space_leg(runs: int, copies: dict) -> dict:
     """Free-space FP64 form on the 256 x 256 workload (seed 2, nu = 2048 per
     axis, eps = 1e-10, 1000 steps): graph-replayed whole runs, and the
     per-pass durations of one eager run from dispatch-recorded HIP events."""
@@ -240,6 +302,7 @@ def free_space_leg(runs: int) -> dict:
         plan.run(u0, out)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / runs
+    err = oracle_error("free_2d_256_default_h", out)
     plan.use_graph(False)
     plan.profile(True)
     plan.run(u0, out)
@@ -248,6 +311,7 @@ def free_space_leg(runs: int) -> dict:
     plan.profile(False)
     n_modes = plan.query(81) * plan.query(82)
     row_b, col_b = plan.query(Q_BYTES_ROW), plan.query(Q_BYTES_COL)
+    plan_H = [plan.query(86), plan.query(87)]
     ach = row_b / (row_us * 1e-6) / 1e9
     far = far_field_eval(plan, dev)
     plan.close()
@@ -256,6 +320,8 @@ def free_space_leg(runs: int) -> dict:
             "value": n_modes * prob.nsteps / wall, "unit": "mode-updates/s",
             "modes": int(n_modes), "grid_points": int(u0.numel()),
             "grid_point_updates_per_s": u0.numel() * prob.nsteps / wall, "ms_per_run": wall * 1e3,
+            "contour_H": [plan_H[0], plan_H[1]], "error": err,
+            "end_to_end": end_to_end(row_b + col_b, prob.nsteps, wall, copies),
             "roofline": {"bound": "hbm", "kernel": "free-space Adams row pass (k_fs_row)", "achieved": ach,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                          "traffic": measured_traffic("k_fs_row_2048_traffic.txt", FS_KERNEL_SOURCES),
@@ -354,7 +420,35 @@ def ionization_leg(runs: int = 3, nsteps: int = 4000) -> dict:
     return out
 
 
-def batch_leg(runs: int) -> dict:
+def periodic_1d_leg(runs: int = 20) -> dict:
+    """The 1D periodic workload (M = 256, seed 0, T = 1, 100 steps, FP64):
+    graph-replayed whole runs and the error against the stored oracle values
+    (every grid point)."""
+    import torch
+
+    from paper_2001_06113_amd.tdse import Plan
+    from workloads import periodic_1d_256_problem
+
+    dev = torch.device("cuda:0")
+    prob = periodic_1d_256_problem()
+    plan = Plan.from_problem(prob, device=dev)
+    u0 = torch.as_tensor(prob.u0).to(dev)
+    out = torch.empty_like(u0)
+    plan.use_graph(True)
+    plan.run(u0, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        plan.run(u0, out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / runs
+    plan.close()
+    return {"workload": "1D periodic TDSE M=256, V=-a cos x, T=1, 100 steps AM8 (6 Richardson start-up steps), FP64",
+            "value": u0.numel() * prob.nsteps / wall, "unit": "mode-updates/s", "ms_per_run": wall * 1e3,
+            "us_per_time_step": wall * 1e6 / prob.nsteps, "error": oracle_error("periodic_1d_256", out)}
+
+
+def batch_leg(runs: int, copies: dict) -> dict:
     """Batched form on the 64-instance workload (seed 4000 + i; 32 1D with
     M in {256..2048}, 32 2D with M in {128..512}^2; 500 steps, FP32-split,
     stepwise field): autotuned schedules, graph-replayed whole runs, against
@@ -384,6 +478,8 @@ def batch_leg(runs: int) -> dict:
     nsteps = probs[0].nsteps
     value = b.total * nsteps / wall
     bytes_step = b.query(Q_BYTES_PER_STEP)
+    errs = [oracle_error("batch_64", u, inst=i, bar=1e-6) for i, u in enumerate(b.unpack(out))]
+    worst = max(errs, key=lambda e: e["rel_l2_vs_oracle"])
     # the same work one plan after another (each replayed from its own graph)
     seq = 0.0
     for p in probs:
@@ -411,7 +507,9 @@ def batch_leg(runs: int) -> dict:
     return {"workload": "64 periodic instances (32 1D M=256..2048, 32 2D M=128^2..512^2), T=2, 500 steps AM8, "
                         "FP32-split, stepwise A",
             "value": value, "unit": "mode-updates/s", "ms_per_run": wall * 1e3, "modes": int(b.total),
-            "algorithmic_GBps": bytes_step * nsteps / wall / 1e9,
+            "end_to_end": end_to_end(bytes_step, nsteps, wall, copies),
+            "error": {"worst_instance": errs.index(worst), **worst,
+                      "all_pass": all(e["pass"] for e in errs)},
             "one_plan_at_a_time_value": b.total * nsteps / seq, "speedup_vs_one_plan_at_a_time": seq / wall,
             "autotune_s": tune_s, "schedules_col_row": sorted(set(chosen)),
             "adjoint_s_all_instances": adj_s, "adjoint_samples": int(sum(g.size for g in gAs))}
@@ -428,8 +526,8 @@ def main():
     import torch
 
     from paper_2001_06113_amd import _lib
-    from paper_2001_06113_amd.tdse import (Q_BYTES_COL, Q_BYTES_ROW, Q_PROF_MS_COL, Q_PROF_MS_ROW,
-                                           Q_PROF_N_COL, Q_PROF_N_ROW, Plan)
+    from paper_2001_06113_amd.tdse import (Q_BYTES_COL, Q_BYTES_PER_STEP, Q_BYTES_ROW, Q_PROF_MS_COL,
+                                           Q_PROF_MS_ROW, Q_PROF_N_COL, Q_PROF_N_ROW, Plan)
     from workloads import periodic_2d_512_problem, periodic_problem_from_seed
 
     if not os.path.exists(_lib.LIB_PATH):
@@ -472,7 +570,10 @@ def main():
 
     ms_per_run = wall * 1e3 / args.steps
     value = modes * prob.nsteps * args.steps / wall
+    err = oracle_error("periodic_2d_512" if args.workload == "periodic-2d-512" else "periodic_2d_1024", out)
     copy_gbps = device_copy_gbps(dev)
+    copy_mall_gbps = device_copy_gbps(dev, mib=32, reps=200)
+    copies = {"512MiB": copy_gbps, "32MiB_in_MALL": copy_mall_gbps}
     row_us, col_us = row_ms * 1e3 / max(n_row, 1), col_ms * 1e3 / max(n_col, 1)
     row_b, col_b = plan.query(Q_BYTES_ROW), plan.query(Q_BYTES_COL)
     dom_b, dom_us, dom = (row_b, row_us, "row") if row_us * 1 >= col_us else (col_b, col_us, "col")
@@ -507,21 +608,27 @@ def main():
             "col_pass_us": col_us,
             "device_copy_GBps": copy_gbps,
             "frac_of_device_copy": achieved / copy_gbps if achieved else None,
+            "device_copy_32MiB_in_MALL_GBps": copy_mall_gbps,
+            "frac_of_device_copy_in_MALL": achieved / copy_mall_gbps if achieved else None,
         },
+        "error": err,
+        "end_to_end": end_to_end(plan.query(Q_BYTES_PER_STEP), prob.nsteps, wall / args.steps, copies),
         "adams_step_us_eager": row_us + col_us,
         "graph_us_per_time_step": wall * 1e6 / (args.steps * prob.nsteps),
         "steady_mode_updates_per_s_eager": modes / ((row_us + col_us) * 1e-6) if row_us > 0 else None,
     }
+    if not args.no_1d:
+        res["periodic_1d"] = periodic_1d_leg()
     if not args.no_split:
-        res["split"] = split_leg(args.split_steps)
+        res["split"] = split_leg(args.split_steps, copies)
     if not args.no_free:
-        res["free_space"] = free_space_leg(args.free_runs)
+        res["free_space"] = free_space_leg(args.free_runs, copies)
     if not args.no_well:
         res["moving_well"] = moving_well_leg()
     if not args.no_ionization:
         res["ionization"] = ionization_leg()
     if not args.no_batch:
-        res["batch"] = batch_leg(args.batch_runs)
+        res["batch"] = batch_leg(args.batch_runs, copies)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     print(json.dumps(res), flush=True)

@@ -365,16 +365,20 @@ class TDSEFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, A_steps, plan, u0, checkpoint_every=0):
-        plan.set_field(A_steps.detach().cpu().numpy())
+        # the field this output was computed with: backward restores it, since
+        # the plan may have been given another field (or run again) meanwhile
+        A_host = np.array(A_steps.detach().cpu().numpy(), dtype=np.float64, copy=True)
+        plan.set_field(A_host)
         u0d = plan._as_device(u0.detach() if isinstance(u0, torch.Tensor) else u0).clone()
         out = plan.run(u0d)
-        ctx.plan, ctx.u0, ctx.k = plan, u0d, int(checkpoint_every)
+        ctx.plan, ctx.u0, ctx.k, ctx.A_host = plan, u0d, int(checkpoint_every), A_host
         ctx.A_meta = (A_steps.dtype, A_steps.device)
         ctx.u0_is_tensor = isinstance(u0, torch.Tensor)
         return out
 
     @staticmethod
     def backward(ctx, grad_uT):
+        ctx.plan.set_field(ctx.A_host)
         gA, g0 = ctx.plan.adjoint(ctx.u0, grad_uT.detach().contiguous(), ctx.k)
         dtype, device = ctx.A_meta
         gA_t = torch.as_tensor(np.asarray(gA), dtype=dtype, device=device)

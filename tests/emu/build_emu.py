@@ -15,6 +15,10 @@ SOURCES = [os.path.join(CSRC, "periodic_kernels.hip"), os.path.join(CSRC, "frees
            os.path.join(HERE, "emu_globals.cpp")]
 
 
+TSAN_DRIVER = os.path.join(HERE, "tsan_batch_adjoint.cpp")
+TSAN_OUT = os.path.join(HERE, "tsan_batch_adjoint")
+
+
 def build(sanitize: bool = False) -> str:
     flags = ["-O1", "-g", "-std=c++17", "-fPIC", "-shared", "-pthread", "-include", os.path.join(HERE, "hip_emu.h"),
              f"-I{os.path.join(HERE, 'stub')}", f"-I{CSRC}", f"-I{os.path.join(ROOT, 'include')}", "-x", "c++"]
@@ -25,6 +29,19 @@ def build(sanitize: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(" ".join(cmd) + "\n" + r.stderr[-4000:])
     return OUT
+
+
+def build_tsan_driver() -> str:
+    """The library's host code and kernels with the batch-adjoint driver in one
+    ThreadSanitizer executable (host CPU build; no GPU code is involved)."""
+    flags = ["-O1", "-g", "-std=c++17", "-pthread", "-fsanitize=thread", "-fno-omit-frame-pointer",
+             "-include", os.path.join(HERE, "hip_emu.h"), f"-I{os.path.join(HERE, 'stub')}", f"-I{CSRC}",
+             f"-I{os.path.join(ROOT, 'include')}", "-x", "c++"]
+    cmd = ["g++", *flags, *SOURCES, TSAN_DRIVER, "-o", TSAN_OUT]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(" ".join(cmd) + "\n" + r.stderr[-4000:])
+    return TSAN_OUT
 
 
 if __name__ == "__main__":

@@ -2,5 +2,5 @@
 #include "hip_emu.h"
 thread_local uint3_ threadIdx;
 thread_local uint3_ blockIdx;
-dim3 blockDim, gridDim;
-emu::Block* emu::g_block = nullptr;
+thread_local dim3 blockDim, gridDim;
+thread_local emu::Block* emu::g_block = nullptr;

@@ -3,10 +3,17 @@
 // The kernel sources are compiled with g++ after this header (which
 // pre-empts <hip/hip_runtime.h>).  A launch runs the blocks one after
 // another; the blockDim.x threads of a block are cooperative fibers on one OS
-// thread that switch at __syncthreads().  __shared__ arrays become function statics,
-// shared by the threads of the (single) running block.  "Device" memory is
-// host memory.  This exercises indexing, barriers and arithmetic of the
-// kernels on the CPU; it says nothing about timing.
+// thread that switch at __syncthreads().  __shared__ arrays become
+// thread-local function statics, shared by the threads of the (single)
+// running block.  "Device" memory is host memory.  This exercises indexing,
+// barriers and arithmetic of the kernels on the CPU; it says nothing about
+// timing.
+//
+// All emulated grid state (grid and block sizes, the running block, fiber
+// stacks, __shared__ arrays) belongs to the launching host thread, so host
+// threads launch concurrently with no lock between them: a ThreadSanitizer
+// build (fibers announced to it below) sees the library's host code exactly
+// as concurrent as the library makes it.
 #pragma once
 #define HIP_INCLUDE_HIP_HIP_RUNTIME_H 1
 
@@ -18,8 +25,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
-#include <mutex>
 #include <vector>
+#if defined(__SANITIZE_THREAD__)
+#include <sanitizer/tsan_interface.h>
+#endif
 
 struct double2 { double x, y; };
 struct float2 { float x, y; };
@@ -31,7 +40,7 @@ struct uint3_ { unsigned x = 0, y = 0, z = 0; };
 
 extern thread_local uint3_ threadIdx;
 extern thread_local uint3_ blockIdx;
-extern dim3 blockDim, gridDim;
+extern thread_local dim3 blockDim, gridDim;
 
 #define __global__
 #define __device__
@@ -40,7 +49,7 @@ extern dim3 blockDim, gridDim;
 #define __launch_bounds__(...)
 // scheduling hints of the GPU compiler have no meaning on the CPU
 inline void __builtin_amdgcn_sched_barrier(int) {}
-#define __shared__ static
+#define __shared__ static thread_local
 // clang's vector extension, as GCC's (element count -> bytes, for double)
 #define ext_vector_type(n) vector_size(8 * (n))
 typedef double emu_f64x4 __attribute__((vector_size(32)));
@@ -59,37 +68,48 @@ struct Fiber {
   ucontext_t ctx;
   bool done = false;
   unsigned tid = 0;
+  void* tsan = nullptr;   // ThreadSanitizer's fiber handle (sanitizer builds)
 };
 constexpr size_t kStack = 1 << 17;
-inline char* stack_for(unsigned t) {  // one uninitialised stack per fiber slot, reused
-  static std::vector<char*> pool;
-  while (pool.size() <= t) pool.push_back(new char[kStack]);
-  return pool[t];
+inline char* stack_for(unsigned t) {  // one uninitialised stack per fiber slot and host thread, reused
+  struct Pool {
+    std::vector<char*> s;
+    ~Pool() {
+      for (char* p : s) delete[] p;
+    }
+  };
+  static thread_local Pool pool;
+  while (pool.s.size() <= t) pool.s.push_back(new char[kStack]);
+  return pool.s[t];
 }
 struct Block {
   ucontext_t sched;
+  void* tsan_sched = nullptr;
   std::vector<Fiber> fibers;
   std::function<void()> body;
   int current = -1;
 };
-extern Block* g_block;
+extern thread_local Block* g_block;
+// announce a context switch to ThreadSanitizer (it then keeps one shadow
+// stack per fiber and orders the switch like a synchronization)
+inline void tsan_switch(void* to) {
+#if defined(__SANITIZE_THREAD__)
+  __tsan_switch_to_fiber(to, 0);
+#else
+  (void)to;
+#endif
+}
 inline void fiber_entry() {
   Block* b = g_block;
   Fiber& f = b->fibers[b->current];
   threadIdx.x = f.tid;
   b->body();
   f.done = true;
+  tsan_switch(b->tsan_sched);
   swapcontext(&f.ctx, &b->sched);
-}
-// kernels run one at a time, whichever host thread launches them (the
-// emulated grid state, fiber stacks and __shared__ arrays are process-wide)
-inline std::mutex& launch_mutex() {
-  static std::mutex m;
-  return m;
 }
 template <typename K, typename... Args>
 void launch(K kernel, dim3 grid, dim3 block, Args... args) {
-  std::lock_guard<std::mutex> hold(launch_mutex());
   gridDim = grid;
   blockDim = block;
   for (unsigned bi = 0; bi < grid.x; ++bi) {
@@ -98,6 +118,9 @@ void launch(K kernel, dim3 grid, dim3 block, Args... args) {
     blockIdx.x = bi;
     b.body = [&]() { kernel(args...); };
     b.fibers.resize(block.x);
+#if defined(__SANITIZE_THREAD__)
+    b.tsan_sched = __tsan_get_current_fiber();
+#endif
     for (unsigned t = 0; t < block.x; ++t) {
       Fiber& f = b.fibers[t];
       f.tid = t;
@@ -106,6 +129,9 @@ void launch(K kernel, dim3 grid, dim3 block, Args... args) {
       f.ctx.uc_stack.ss_size = kStack;
       f.ctx.uc_link = nullptr;
       makecontext(&f.ctx, (void (*)())fiber_entry, 0);
+#if defined(__SANITIZE_THREAD__)
+      f.tsan = __tsan_create_fiber(0);
+#endif
     }
     bool any = true;
     while (any) {
@@ -114,16 +140,21 @@ void launch(K kernel, dim3 grid, dim3 block, Args... args) {
         if (b.fibers[t].done) continue;
         b.current = (int)t;
         threadIdx.x = t;
+        tsan_switch(b.fibers[t].tsan);
         swapcontext(&b.sched, &b.fibers[t].ctx);
         if (!b.fibers[t].done) any = true;
       }
     }
+#if defined(__SANITIZE_THREAD__)
+    for (Fiber& f : b.fibers) __tsan_destroy_fiber(f.tsan);
+#endif
     g_block = nullptr;
   }
 }
 inline void barrier_wait() {
   Block* b = g_block;
   Fiber& f = b->fibers[b->current];
+  tsan_switch(b->tsan_sched);
   swapcontext(&f.ctx, &b->sched);
   threadIdx.x = f.tid;
 }
@@ -136,7 +167,7 @@ inline void __syncthreads() { emu::barrier_wait(); }
 // Emulated with a block-wide rendezvous, so every thread of the block must
 // reach each call in the same order (as the kernels that use it do).
 inline emu_f64x4 __builtin_amdgcn_mfma_f64_16x16x4f64(double a, double b, emu_f64x4 c, int, int, int) {
-  static double sa[1024], sb[1024];
+  static thread_local double sa[1024], sb[1024];
   const unsigned t = threadIdx.x;
   sa[t] = a;
   sb[t] = b;
@@ -199,4 +230,4 @@ inline hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = (hipEv
 inline hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
 inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 160 * 1024; return hipSuccess; }
 // dynamic LDS: one static buffer per kernel and element type, as large as a CU's LDS
-#define HIP_DYNAMIC_SHARED(type, var) static type var[160 * 1024 / sizeof(type)];
+#define HIP_DYNAMIC_SHARED(type, var) static thread_local type var[160 * 1024 / sizeof(type)];

@@ -75,6 +75,41 @@ def test_autograd_function_dipole_gradient():
     plan.close()
 
 
+def test_autograd_function_keeps_its_own_field():
+    # two applications on one plan with different fields: backpropagating the
+    # first output must use the first field, not the one the plan holds last
+    import copy
+
+    import torch
+
+    from paper_2001_06113_amd.tdse import TDSEFunction
+
+    prob = periodic_problem_from_seed(82, 1, (128,), 0.2, 30, A_kind="stepwise")
+    other = copy.deepcopy(prob)
+    other.A_steps = np.asarray(prob.A_steps)[::-1].copy() * -1.5
+    plan = _plan(prob)
+    u0 = torch.as_tensor(prob.u0).to("cuda:0")
+    A1 = torch.tensor(np.asarray(prob.A_steps), dtype=torch.float64, requires_grad=True)
+    A2 = torch.tensor(np.asarray(other.A_steps), dtype=torch.float64, requires_grad=True)
+    x = torch.as_tensor(-np.pi + 2 * np.pi * np.arange(128) / 128, device="cuda:0")
+    w = 2 * np.pi / 128
+    u1 = TDSEFunction.apply(A1, plan, u0)
+    u2 = TDSEFunction.apply(A2, plan, u0)
+    J1 = w * torch.sum(x * torch.abs(u1) ** 2)
+    J1.backward()
+    gA, _ = adjoint(prob, dipole_seed(prob, PeriodicOracle(prob).run()[0]))
+    r = np.max(np.abs(A1.grad.numpy() - gA)) / np.max(np.abs(gA))
+    print(f"case autograd twice on one plan: first field's gradient rel {r:.2e}", flush=True)
+    assert r <= 1e-10
+    J2 = w * torch.sum(x * torch.abs(u2) ** 2)
+    J2.backward()
+    gB, _ = adjoint(other, dipole_seed(other, PeriodicOracle(other).run()[0]))
+    r2 = np.max(np.abs(A2.grad.numpy() - gB)) / np.max(np.abs(gB))
+    print(f"  second field's gradient rel {r2:.2e}", flush=True)
+    assert r2 <= 1e-10
+    plan.close()
+
+
 def test_batch_adjoint_streams_agree():
     # a batch's adjoints from 8 host threads on 8 streams (more instances than
     # workers) equal the one-stream run bit for bit: each instance's arithmetic
