@@ -175,6 +175,19 @@ int tdse_far_workspace_size(tdse_plan_t plan, int32_t nx, int32_t ny, size_t* by
 int tdse_far_eval(tdse_plan_t plan, const double* xs, int32_t nx, const double* ys, int32_t ny, void* out,
                   void* work, size_t bytes);
 
+/* Allocation-free evaluation, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same results as tdse_far_eval, with the workspace taken
+ * from a library-owned device array of TDSE_FAR_SCRATCH_BYTES per GPU
+ * (part of the library's code object, held until the process ends) instead
+ * of a caller buffer.  Calls no allocation routine.  TDSE_ENOMEM when
+ * tdse_far_workspace_size for (nx, ny) exceeds TDSE_FAR_SCRATCH_BYTES.
+ * Every call on one GPU shares that array: calls ordered on one stream are
+ * safe, calls that overlap on one GPU (several streams or host threads) race.
+ * Arguments and errors otherwise as for tdse_far_eval (no profiling). */
+#define TDSE_FAR_SCRATCH_BYTES ((size_t)64 << 20)
+int tdse_far_eval_noalloc(tdse_plan_t plan, const double* xs, int32_t nx, const double* ys, int32_t ny, void* out);
+
 /* Scalar queries (keys below). */
 #define TDSE_Q_MODES          0   /* modes per instance (prod M)               */
 #define TDSE_Q_STEPS_DONE     1   /* steps taken since set_state               */

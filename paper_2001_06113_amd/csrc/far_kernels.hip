@@ -8,9 +8,38 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "tdse_internal.h"
 
 namespace tdse {
+
+// Device memory of the allocation-free evaluation (tdse_far_eval_noalloc):
+// one array per GPU, part of the code object, so it needs no allocation call
+// and lives until the process ends.  In host code its name is only a
+// stand-in: its device address on the current GPU comes from
+// hipGetSymbolAddress, looked up once per device and kept.
+static __device__ __align__(256) unsigned char scratch[FAR_SCRATCH_BYTES];
+
+hipError_t far_scratch(void** ptr) {
+  constexpr int MAXDEV = 64;
+  static std::mutex lock;
+  static void* addr[MAXDEV] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> hold(lock);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
 
 // E[k * n + i] = (w_k / 2 pi) exp(i zeta_k x_i), k < N, i < n
 __global__ __launch_bounds__(256) void k_far_table(const double2* __restrict__ zeta, const double2* __restrict__ w,

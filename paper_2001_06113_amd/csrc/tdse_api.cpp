@@ -2422,16 +2422,13 @@ int tdse_far_workspace_size(tdse_plan_t p, int32_t nx, int32_t ny, size_t* bytes
   return TDSE_OK;
 }
 
-int tdse_far_eval(tdse_plan_t p, const double* xs, int32_t nx, const double* ys, int32_t ny, void* out, void* work,
-                  size_t bytes) {
-  if (!p || !ys || !out || !work || (p->dim == 2 && !xs)) return fail(TDSE_EINVAL, "NULL argument");
-  int s = far_check(p, nx, ny);
-  if (s) return s;
-  if (!p->bound || p->cur < 0) return fail(TDSE_ESTATE, "no state");
-  const FarLayout L = far_layout(p, nx, ny);
-  if (bytes < L.total) return fail(TDSE_ENOMEM, "far-evaluation workspace too small");
-  if (((uintptr_t)work) % 256) return fail(TDSE_EINVAL, "far-evaluation workspace must be 256-byte aligned");
-  char* w = (char*)work;
+namespace {
+// u at the tensor grid xs x ys from the mode state, with `work` (L.total
+// bytes) holding uhat, the two tables and the first product; `timed`: the
+// first product may be bracketed by profiling events
+int far_eval(tdse_plan_s* p, const double* xs, int32_t nx, const double* ys, int32_t ny, void* out, char* w,
+             const FarLayout& L, bool timed) {
+  int s = TDSE_OK;
   double2* uh = (double2*)(w + L.uh);
   // uhat at the current time
   if (p->cur == 0) {
@@ -2455,7 +2452,7 @@ int tdse_far_eval(tdse_plan_t p, const double* xs, int32_t nx, const double* ys,
   hipError_t e = launch_far_table(a2.zeta, a2.wq, N2, ys, ny, E2, p->stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const size_t first = p->ev_used;
-  if (p->prof) {
+  if (p->prof && timed) {
     e0 = next_event(p);
     e1 = next_event(p);
     if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
@@ -2474,6 +2471,34 @@ int tdse_far_eval(tdse_plan_t p, const double* xs, int32_t nx, const double* ys,
   if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("far-evaluation kernels: ") + hipGetErrorString(e));
   if (e0) p->prof_marks.push_back({first, 2});
   return TDSE_OK;
+}
+}  // namespace
+
+int tdse_far_eval(tdse_plan_t p, const double* xs, int32_t nx, const double* ys, int32_t ny, void* out, void* work,
+                  size_t bytes) {
+  if (!p || !ys || !out || !work || (p->dim == 2 && !xs)) return fail(TDSE_EINVAL, "NULL argument");
+  int s = far_check(p, nx, ny);
+  if (s) return s;
+  if (!p->bound || p->cur < 0) return fail(TDSE_ESTATE, "no state");
+  const FarLayout L = far_layout(p, nx, ny);
+  if (bytes < L.total) return fail(TDSE_ENOMEM, "far-evaluation workspace too small");
+  if (((uintptr_t)work) % 256) return fail(TDSE_EINVAL, "far-evaluation workspace must be 256-byte aligned");
+  return far_eval(p, xs, nx, ys, ny, out, (char*)work, L, true);
+}
+
+int tdse_far_eval_noalloc(tdse_plan_t p, const double* xs, int32_t nx, const double* ys, int32_t ny, void* out) {
+  if (!p || !ys || !out || (p->dim == 2 && !xs)) return fail(TDSE_EINVAL, "NULL argument");
+  int s = far_check(p, nx, ny);
+  if (s) return s;
+  if (!p->bound || p->cur < 0) return fail(TDSE_ESTATE, "no state");
+  const FarLayout L = far_layout(p, nx, ny);
+  if (L.total > FAR_SCRATCH_BYTES)
+    return fail(TDSE_ENOMEM, "tdse_far_eval_noalloc: needs " + std::to_string(L.total) + " bytes of workspace, above its " +
+                                 std::to_string(FAR_SCRATCH_BYTES) + "-byte library array; use tdse_far_eval");
+  void* scr = nullptr;
+  const hipError_t e = far_scratch(&scr);
+  if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("library scratch array: ") + hipGetErrorString(e));
+  return far_eval(p, xs, nx, ys, ny, out, (char*)scr, L, false);
 }
 
 int tdse_run(tdse_plan_t p, const void* u0, void* uT, int32_t on_device) {

@@ -210,6 +210,10 @@ int fs_max_modes(int nu);
 size_t fs_line_lds_bytes(int nu, int M, int ND);   // dynamic LDS of a line workgroup
 
 // Evaluation of a free-space representation at arbitrary points (far_kernels.hip).
+// far_scratch: device address, on the current GPU, of the library-owned array
+// of FAR_SCRATCH_BYTES that the allocation-free evaluation uses as workspace.
+constexpr size_t FAR_SCRATCH_BYTES = (size_t)64 << 20;
+hipError_t far_scratch(void** ptr);
 // E[k n + i] = (w_k / 2 pi) exp(i zeta_k x_i), k < N, i < n
 hipError_t launch_far_table(const double2* zeta, const double2* w, int N, const double* x, int n, double2* E,
                             hipStream_t s);

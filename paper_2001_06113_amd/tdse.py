@@ -243,6 +243,23 @@ class Plan:
         self._far_keep = (xd, yd)   # inputs stay alive until the stream has used them
         return out if self.dim == 2 else out.reshape(ny)
 
+    def far_eval_noalloc(self, ys, xs=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """far_eval through the allocation-free entry point (tdse_far_eval_noalloc):
+        the library's own device array is the workspace; `out` may be given."""
+        yd = torch.as_tensor(ys, dtype=torch.float64).to(self.device).contiguous().reshape(-1)
+        xd = None if xs is None else torch.as_tensor(xs, dtype=torch.float64).to(self.device).contiguous().reshape(-1)
+        nx = 1 if xd is None else xd.numel()
+        ny = yd.numel()
+        if out is None:
+            out = torch.empty((nx, ny), dtype=torch.complex128, device=self.device)
+        self._enter()
+        _check(self.lib.tdse_far_eval_noalloc(self.handle, None if xd is None else C.c_void_p(xd.data_ptr()), nx,
+                                              C.c_void_p(yd.data_ptr()), ny, C.c_void_p(out.data_ptr())),
+               "tdse_far_eval_noalloc")
+        self._leave()
+        self._far_keep = (xd, yd)
+        return out if self.dim == 2 else out.reshape(ny)
+
     def adjoint_streams(self, streams: int) -> None:
         """Host threads / streams of a batch adjoint (tdse_adjoint_streams; 1 = one instance at a time)."""
         _check(self.lib.tdse_adjoint_streams(self.handle, int(streams)), "tdse_adjoint_streams")

@@ -83,6 +83,31 @@ def test_emulated_far_evaluation_matches_oracle(emu, case):
         assert _rel(got, ref) < 1e-11, stop
 
 
+def test_emulated_far_evaluation_without_allocation(emu):
+    # tdse_far_eval_noalloc (workspace in the library's own array) equals
+    # tdse_far_eval, twice in a row with a smaller second call
+    import ctypes as C
+
+    from emu.emu_plan import EmuPlan
+
+    prob = free_problem_from_seed(9, 2, (24, 32), 0.04, 9, nu=(256, 256), eps=1e-11, q=6, panels=2)
+    plan = EmuPlan(emu, prob)
+    plan.set_state(prob.u0)
+    plan.step(prob.nsteps)
+    rng = np.random.default_rng(3)
+    for nx, ny in ((21, 33), (5, 7)):
+        px, py = np.sort(rng.uniform(-2, 2, nx)), np.sort(rng.uniform(-2, 2, ny))
+        ref = plan.far_eval(py, px)
+        out = np.zeros((nx, ny), dtype=np.complex128)
+        plan.call("tdse_far_eval_noalloc", C.c_void_p(px.ctypes.data), nx, C.c_void_p(py.ctypes.data), ny,
+                  C.c_void_p(out.ctypes.data))
+        assert np.array_equal(out, ref)
+    big = np.zeros(1 << 20)
+    with pytest.raises(RuntimeError, match="library array"):
+        plan.call("tdse_far_eval_noalloc", C.c_void_p(big.ctypes.data), 64, C.c_void_p(big.ctypes.data), 1 << 20,
+                  C.c_void_p(big.ctypes.data))
+
+
 def test_emulated_far_evaluation_errors(emu):
     from emu.emu_plan import EmuPlan
     from workloads import periodic_problem_from_seed
