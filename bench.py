@@ -269,10 +269,16 @@ def moving_well_leg(runs: int = 5) -> dict:
         plan.profile(True)
         plan.run(u0, res)
         col_us = plan.query(Q_PROF_MS_COL) * 1e3 / max(plan.query(Q_PROF_N_COL), 1)
+        run1d_us = plan.query(24) * 1e3 / max(plan.query(25), 1)
         plan.profile(False)
         plan.close()
         out[key] = {"ms_per_run": wall * 1e3, "value": u0.numel() * prob.nsteps / wall, "unit": "mode-updates/s",
-                    "col_pass_us": col_us, "finite": bool(torch.isfinite(torch.view_as_real(res)).all().item())}
+                    "us_per_time_step": wall * 1e6 / prob.nsteps,
+                    "finite": bool(torch.isfinite(torch.view_as_real(res)).all().item())}
+        if prob.dim == 1:
+            out[key]["one_workgroup_run_kernel_us"] = run1d_us
+        else:
+            out[key]["col_pass_us"] = col_us
         if key == "grid_512x512":
             out[key]["error"] = oracle_error("moving_well_2d_512", res)
     return {"workload": "moving periodic Gaussian well (V0=300, beta=0.2), potential on the fly: "
@@ -442,10 +448,16 @@ def periodic_1d_leg(runs: int = 20) -> dict:
         plan.run(u0, out)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / runs
+    err = oracle_error("periodic_1d_256", out)
+    plan.use_graph(False)
+    plan.profile(True)
+    plan.run(u0, out)
+    k_us = plan.query(24) * 1e3 / max(plan.query(25), 1)
+    plan.profile(False)
     plan.close()
     return {"workload": "1D periodic TDSE M=256, V=-a cos x, T=1, 100 steps AM8 (6 Richardson start-up steps), FP64",
             "value": u0.numel() * prob.nsteps / wall, "unit": "mode-updates/s", "ms_per_run": wall * 1e3,
-            "us_per_time_step": wall * 1e6 / prob.nsteps, "error": oracle_error("periodic_1d_256", out)}
+            "us_per_time_step": wall * 1e6 / prob.nsteps, "one_workgroup_run_kernel_us": k_us, "error": err}
 
 
 def batch_leg(runs: int, copies: dict) -> dict:

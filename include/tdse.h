@@ -202,6 +202,8 @@ int tdse_far_eval_noalloc(tdse_plan_t plan, const double* xs, int32_t nx, const 
 #define TDSE_Q_PROF_MS_FAR   14   /* profiling: summed ms of tdse_far_eval's first product */
 #define TDSE_Q_PROF_N_FAR    15   /* profiling: number of timed tdse_far_eval calls        */
 #define TDSE_Q_MU             16  /* + j: Adams weight mu_j                    */
+#define TDSE_Q_PROF_MS_RUN1D  24  /* profiling: summed ms of one-workgroup 1D runs (1D periodic FP64 plans, M <= 512) */
+#define TDSE_Q_PROF_N_RUN1D   25  /* profiling: number of timed one-workgroup 1D runs */
 #define TDSE_Q_RICHARDSON     32  /* + l: weight of the 2^l-sub-step result    */
 #define TDSE_Q_PHI            64  /* + axis: phi_axis(T)                       */
 #define TDSE_Q_FS_H           80  /* free space: contour parameter H of axis 0 */

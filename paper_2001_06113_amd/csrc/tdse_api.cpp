@@ -358,6 +358,15 @@ struct tdse_plan_s {
   size_t lds_max = 65536;                       // device limit of LDS per workgroup
   bool is_batch() const { return !sub.empty(); }
 
+  // one-workgroup run of a 1D periodic FP64 plan (run1d_kernels.hip): the
+  // per-step scalar table and the static phase factors, at the end of the
+  // workspace (total_core: the workspace without them)
+  bool run1d = false;
+  std::vector<double> r1tab;
+  std::vector<double2> r1stab;
+  size_t o_r1tab = 0, o_r1stab = 0, total_core = 0;
+  int64_t r1_oH = 0, r1_oR = 0, r1_oA = 0, r1_oD = 0;
+
   // whole-run graph (tdse_graph): captured on the first tdse_run, replayed after
   bool use_graph = false;
   hipGraph_t graph = nullptr;
@@ -1231,6 +1240,121 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
 }
 
 
+// ============================================================ 1D, one workgroup
+//
+// Tables of the one-workgroup 1D run (layout in tdse_internal.h): the time
+// factors and phase increments of every step and start-up sub-step, in the
+// order the kernel consumes them, and the static phase factors
+// exp(-i k^2 tau) of the Adams intervals tau = j dt and of the sub-steps
+// tau = dt / 2^l, from extended precision.
+void build_run1d(tdse_plan_s* p) {
+  const int N = p->nsteps, ns = p->ns, L = p->L, M = p->M2, nh = p->order - 1;
+  std::vector<double>& T = p->r1tab;
+  T.clear();
+  double f[MAXV];
+  p->r1_oH = 0;
+  for (int m = 0; m <= ns; ++m) {
+    p->fV_at(p->t_at(m), f);
+    T.insert(T.end(), f, f + MAXV);
+  }
+  p->r1_oR = (int64_t)T.size();
+  double pb[2], pa[2];
+  for (int m = 1; m <= ns; ++m) {
+    const double t = p->t_at(m - 1);
+    for (int l = 0; l < L; ++l) {
+      const int nsub = 1 << l;
+      const double delta = p->dt / nsub;
+      for (int k = 0; k < nsub; ++k) {
+        const double ts1 = (t + k * delta) + delta;   // end of sub-step k
+        p->fV_at(ts1, f);
+        T.insert(T.end(), f, f + MAXV);
+        p->tf.phi(ts1, pb);
+        p->tf.phi(ts1 - delta, pa);
+        T.push_back(pb[0] - pa[0]);
+      }
+    }
+  }
+  p->r1_oA = (int64_t)T.size();
+  for (int m = ns + 1; m <= N; ++m) {
+    p->fV_at(p->t_at(m), f);
+    T.insert(T.end(), f, f + MAXV);
+  }
+  p->r1_oD = (int64_t)T.size();
+  for (int i = 1; i <= N; ++i) {
+    p->tf.phi(p->t_at(i), pb);
+    p->tf.phi(p->t_at(i - 1), pa);
+    T.push_back(pb[0] - pa[0]);
+  }
+  p->r1stab.assign((size_t)(nh + L) * M, double2{0.0, 0.0});
+  for (int r = 0; r < nh + L; ++r) {
+    const long double tau = r < nh ? (long double)(r + 1) * (long double)p->dt
+                                   : (long double)p->dt / (long double)(1 << (r - nh));
+    for (int idx = 0; idx < M; ++idx) {
+      const long double k = (long double)(idx < M / 2 ? idx : idx - M);
+      const long double th = -k * k * tau;
+      p->r1stab[(size_t)r * M + idx] = double2{(double)cosl(th), (double)sinl(th)};
+    }
+  }
+}
+
+int upload_run1d(tdse_plan_s* p) {
+  HIP_TRY(hipMemcpyAsync(p->ws + p->o_r1tab, p->r1tab.data(), p->r1tab.size() * sizeof(double), hipMemcpyHostToDevice,
+                         p->stream));
+  HIP_TRY(hipMemcpyAsync(p->ws + p->o_r1stab, p->r1stab.data(), p->r1stab.size() * sizeof(double2),
+                         hipMemcpyHostToDevice, p->stream));
+  return TDSE_OK;
+}
+
+// Steps cur+1 .. end of a 1D plan in one launch; u(t_end) is left where the
+// multi-launch path leaves it (the physical buffer flips once per start-up step).
+int run1d_step(tdse_plan_s* p, int end) {
+  Run1DArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.M = p->M2;
+  a.order = p->order;
+  a.ns = p->ns;
+  a.nsteps = p->nsteps;
+  a.L = p->L;
+  a.m0 = p->cur;
+  a.m1 = end;
+  a.nV = p->nV;
+  a.vkind = p->vkind;
+  a.write_u = 1;
+  a.has_phase = p->tf.A_kind != TDSE_A_NONE;
+  a.stab_rows = p->order - 1 + p->L;
+  a.dt = p->dt;
+  a.c0 = p->mu[0] * p->dt;
+  for (int j = 1; j < p->order; ++j) a.ch[j] = p->dt * p->mu[j];
+  for (int l = 0; l < p->L; ++l) a.rich[l] = p->rich[l];
+  a.V = (const double*)p->V(0);
+  a.vstride = p->P;
+  a.tab = (const double*)(p->ws + p->o_r1tab);
+  a.oH = p->r1_oH;
+  a.oR = p->r1_oR;
+  a.oA = p->r1_oA;
+  a.oD = p->r1_oD;
+  const int uo = std::min(end, p->ns) % 2;
+  a.u_in = p->u(p->ucur);
+  a.u_out = p->u(uo);
+  a.B = p->B();
+  a.ring = (double2*)p->ring(0);
+  a.stab = (const double2*)(p->ws + p->o_r1stab);
+  a.tw = (const double2*)p->tw(0, 1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const size_t first = p->ev_used;
+  if (p->prof) {
+    e0 = next_event(p);
+    e1 = next_event(p);
+    if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
+  }
+  const hipError_t e = launch_run1d(a, p->stream, e0, e1);
+  if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("1D run kernel: ") + hipGetErrorString(e));
+  if (e0) p->prof_marks.push_back({first, 3});
+  p->cur = end;
+  p->ucur = uo;
+  return TDSE_OK;
+}
+
 // Step m of one instance (write_u: leave u(t_m) in the physical buffer).
 int do_step(tdse_plan_s* p, int m, bool write_u) {
   if (p->free_space) return fs_step(p, m, write_u);
@@ -1475,6 +1599,10 @@ int plan_batch(const tdse_problem_t* probs, int count, tdse_plan_s** out) {
     tdse_plan_s* q = nullptr;
     const int s = tdse_plan(&probs[i], &q);
     if (s) return s;
+    if (q->run1d) {   // batches march every instance with the batched passes
+      q->run1d = false;
+      q->total = q->total_core;
+    }
     p->sub.push_back(q);
     const tdse_plan_s* q0 = p->sub[0];
     if (q->order != q0->order || q->nsteps != q0->nsteps || q->ns != q0->ns || q->precision != q0->precision)
@@ -2271,6 +2399,13 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
     p->o_ph32 = off;
     off = align256(off + (size_t)(p->order - 1) * (p->M1 + p->M2) * sizeof(float2));
   }
+  p->total_core = off;
+  if (p->dim == 1 && !split && run1d_supported(p->M2)) {
+    p->run1d = true;
+    build_run1d(p);
+    p->o_r1tab = off; off = align256(off + p->r1tab.size() * sizeof(double));
+    p->o_r1stab = off; off = align256(off + p->r1stab.size() * sizeof(double2));
+  }
   p->total = off;
   *out = p;
   return TDSE_OK;
@@ -2306,6 +2441,10 @@ int tdse_bind(tdse_plan_t p, void* ws, size_t bytes, void* stream) {
       HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw1, S.tw1.data(), S.tw1.size(), hipMemcpyHostToDevice, p->stream));
     if (!S.tw2.empty())
       HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw2, S.tw2.data(), S.tw2.size(), hipMemcpyHostToDevice, p->stream));
+  }
+  if (p->run1d) {
+    const int s = upload_run1d(p);
+    if (s) return s;
   }
   if (p->free_space) {
     HIP_TRY(hipMemcpyAsync(p->ws + p->o_Vf, p->Vsrc.data(), p->Vsrc.size() * sizeof(double), hipMemcpyHostToDevice,
@@ -2351,6 +2490,7 @@ int tdse_step(tdse_plan_t p, int32_t k) {
   if (p->cur + k > p->nsteps) return fail(TDSE_ESTATE, "stepping past T");
   if (p->is_batch()) return batch_step(p, k);
   const int end = p->cur + k;
+  if (p->run1d) return k > 0 ? run1d_step(p, end) : TDSE_OK;
   for (int m = p->cur + 1; m <= end; ++m) {
     const int s = do_step(p, m, m == end);
     if (s) return s;
@@ -2631,11 +2771,12 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     return TDSE_OK;
   }
   if ((key >= TDSE_Q_PROF_MS_COL && key <= TDSE_Q_PROF_N_ROW) || key == TDSE_Q_PROF_MS_FAR ||
-      key == TDSE_Q_PROF_N_FAR) {
-    const int kind = (key == TDSE_Q_PROF_MS_FAR || key == TDSE_Q_PROF_N_FAR)
-                         ? 2
-                         : ((key == TDSE_Q_PROF_MS_COL || key == TDSE_Q_PROF_N_COL) ? 0 : 1);
-    const bool count = key == TDSE_Q_PROF_N_COL || key == TDSE_Q_PROF_N_ROW || key == TDSE_Q_PROF_N_FAR;
+      key == TDSE_Q_PROF_N_FAR || key == TDSE_Q_PROF_MS_RUN1D || key == TDSE_Q_PROF_N_RUN1D) {
+    const int kind = (key == TDSE_Q_PROF_MS_FAR || key == TDSE_Q_PROF_N_FAR)        ? 2
+                     : (key == TDSE_Q_PROF_MS_RUN1D || key == TDSE_Q_PROF_N_RUN1D) ? 3
+                     : ((key == TDSE_Q_PROF_MS_COL || key == TDSE_Q_PROF_N_COL) ? 0 : 1);
+    const bool count = key == TDSE_Q_PROF_N_COL || key == TDSE_Q_PROF_N_ROW || key == TDSE_Q_PROF_N_FAR ||
+                       key == TDSE_Q_PROF_N_RUN1D;
     if (!p->prof_marks.empty()) HIP_TRY(hipStreamSynchronize(p->stream));
     double ms = 0.0, nk = 0.0;
     for (auto& mk : p->prof_marks) {
@@ -2735,6 +2876,13 @@ int tdse_set_field(tdse_plan_t p, const double* A_steps) {
   p->tf.A_steps.assign(A_steps, A_steps + (size_t)p->nsteps * p->dim);
   p->tf.prepare();
   p->drop_graph();
+  if (p->run1d) {
+    build_run1d(p);
+    if (p->bound) {
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      HIP_TRY(hipMemcpy(p->ws + p->o_r1tab, p->r1tab.data(), p->r1tab.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+  }
   return TDSE_OK;
 }
 

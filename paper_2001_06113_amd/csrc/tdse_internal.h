@@ -222,6 +222,39 @@ hipError_t launch_far_gemm(int M, int N, int K, const double2* A, int64_t sam, i
                            int64_t sbk, int64_t sbn, double2* C, int64_t ldc, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
 
+// One-workgroup run of a 1D periodic FP64 problem (run1d_kernels.hip): steps
+// m0+1 .. m1 of the scheme in one launch.  Per-step scalars come from `tab`:
+//   oH + 8 m                      f_r(t_m), m = 0..ns (history at the start-up times)
+//   oR + 9 ((m-1)(2^L-1) + 2^l - 1 + k)
+//                                 start-up step m, level l, sub-step k: f_r at its end
+//                                 time [8], then the phase increment phi(end) - phi(start)
+//   oA + 8 (m - ns - 1)           f_r(t_m), Adams step m
+//   oD + i - 1                    phi(t_i) - phi(t_{i-1}), i = 1..nsteps
+// (f_r: the eight potential time factors, or the moving well's parameters).
+// stab holds exp(-i k^2 j dt), j = 1..n-1, then exp(-i k^2 dt / 2^l), l < L.
+struct Run1DArgs {
+  int M, order, ns, nsteps, L;
+  int m0, m1;
+  int nV, vkind;
+  int write_u, has_phase, stab_rows;
+  double dt, c0;
+  double ch[MAXH + 1];
+  double rich[4];
+  const double* V;
+  int64_t vstride;
+  const double* tab;
+  int64_t oH, oR, oA, oD;
+  const double2* u_in;
+  double2* u_out;
+  double2* B;
+  double2* ring;
+  const double2* stab;
+  const double2* tw;
+};
+bool run1d_supported(int N);
+size_t run1d_lds_bytes(int N, int stab_rows, int nV);
+hipError_t launch_run1d(const Run1DArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+
 // Launchers (periodic_kernels.hip).  Non-null events e0/e1 are recorded at
 // the kernel's own start and end.  Return a hipError_t.
 hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
