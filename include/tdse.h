@@ -204,6 +204,10 @@ int tdse_far_eval_noalloc(tdse_plan_t plan, const double* xs, int32_t nx, const 
 #define TDSE_Q_MU             16  /* + j: Adams weight mu_j                    */
 #define TDSE_Q_PROF_MS_RUN1D  24  /* profiling: summed ms of one-workgroup 1D runs (1D periodic FP64 plans, M <= 512) */
 #define TDSE_Q_PROF_N_RUN1D   25  /* profiling: number of timed one-workgroup 1D runs */
+#define TDSE_Q_PROF_MS_PERSIST 26 /* profiling: summed ms of persistent 2D launches */
+#define TDSE_Q_PROF_N_PERSIST 27  /* profiling: number of timed persistent 2D launches */
+#define TDSE_Q_PATH           28  /* how tdse_step marches: 0 kernel passes per step, 1 one-workgroup 1D run,
+                                     2 persistent 2D launch for the Adams steps (eligible and enabled) */
 #define TDSE_Q_RICHARDSON     32  /* + l: weight of the 2^l-sub-step result    */
 #define TDSE_Q_PHI            64  /* + axis: phi_axis(T)                       */
 #define TDSE_Q_FS_H           80  /* free space: contour parameter H of axis 0 */
@@ -217,6 +221,18 @@ int tdse_far_eval_noalloc(tdse_plan_t plan, const double* xs, int32_t nx, const 
 #define TDSE_Q_INST_EPT_COL 8192  /* batch, + i: elements per thread of i's Adams column pass */
 #define TDSE_Q_INST_EPT_ROW 12288 /* batch, + i: elements per thread of i's Adams row pass    */
 int tdse_query(tdse_plan_t plan, int32_t key, double* value);
+
+/* Plan options.  TDSE_CFG_PERSISTENT (default 1): a square 2D periodic FP64
+ * plan (M = 32..512, a power of two, stored potential fields) marches its
+ * implicit Adams steps in one launch of a co-resident grid (one workgroup per
+ * two lines; the multistep state stays in registers and LDS, the grid
+ * synchronizes between the two transform directions of each step), falling
+ * back to two kernel passes per step when the device cannot hold the grid;
+ * 0 always takes the passes.  Not while a run is under way (ESTATE).  The
+ * persistent launch synchronizes the stream once, to check that no grid
+ * barrier timed out (TDSE_EDEVICE if one did). */
+#define TDSE_CFG_PERSISTENT 0
+int tdse_configure(tdse_plan_t plan, int32_t key, int32_t value);
 
 /* Per-kernel timing: with enable != 0 every implicit Adams column and row
  * pass is bracketed by HIP events on the bound stream; the TDSE_Q_PROF_*

@@ -33,6 +33,7 @@ EXPORTS = [
     "tdse_last_error", "tdse_profile", "tdse_graph", "tdse_plan_batch", "tdse_autotune",
     "tdse_set_instance_state", "tdse_get_instance_state", "tdse_set_field", "tdse_adjoint_workspace_size",
     "tdse_adjoint", "tdse_adjoint_streams", "tdse_far_workspace_size", "tdse_far_eval", "tdse_far_eval_noalloc",
+    "tdse_configure",
 ]
 
 _lib = None
@@ -70,6 +71,7 @@ def load() -> C.CDLL:
     lib.tdse_far_workspace_size.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
     lib.tdse_far_eval.argtypes = [P, P, C.c_int32, P, C.c_int32, P, P, C.c_size_t]
     lib.tdse_far_eval_noalloc.argtypes = [P, P, C.c_int32, P, C.c_int32, P]
+    lib.tdse_configure.argtypes = [P, C.c_int32, C.c_int32]
     lib.tdse_destroy.argtypes = [P]
     lib.tdse_destroy.restype = None
     lib.tdse_status_string.argtypes = [C.c_int]
@@ -80,7 +82,7 @@ def load() -> C.CDLL:
                  "tdse_get_state", "tdse_run", "tdse_query", "tdse_plan_batch", "tdse_autotune",
                  "tdse_set_instance_state", "tdse_get_instance_state", "tdse_set_field",
                  "tdse_adjoint_workspace_size", "tdse_adjoint", "tdse_adjoint_streams", "tdse_far_workspace_size",
-                 "tdse_far_eval", "tdse_far_eval_noalloc"):
+                 "tdse_far_eval", "tdse_far_eval_noalloc", "tdse_configure"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

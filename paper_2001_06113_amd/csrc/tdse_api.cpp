@@ -367,6 +367,19 @@ struct tdse_plan_s {
   size_t o_r1tab = 0, o_r1stab = 0, total_core = 0;
   int64_t r1_oH = 0, r1_oR = 0, r1_oA = 0, r1_oD = 0;
 
+  // persistent Adams steps of a square 2D periodic FP64 plan
+  // (persist2d_kernels.hip): per-step scalars, static column factors and the
+  // barrier words, at the end of the workspace
+  bool persist = false;       // the plan qualifies
+  bool persist_on = true;     // tdse_configure(TDSE_CFG_PERSISTENT)
+  int persist_cap = -1;       // co-resident workgroups of the device (-1: not asked yet)
+  std::vector<double> p2tab;
+  std::vector<double2> p2S2;
+  size_t o_p2tab = 0, o_p2S2 = 0, o_p2bar = 0;
+  int64_t p2_oD2 = 0;
+  bool p2_ph2 = false;
+  static constexpr int P2_OSTEP = 16;
+
   // whole-run graph (tdse_graph): captured on the first tdse_run, replayed after
   bool use_graph = false;
   hipGraph_t graph = nullptr;
@@ -1355,6 +1368,125 @@ int run1d_step(tdse_plan_s* p, int end) {
   return TDSE_OK;
 }
 
+// ============================================================ 2D, persistent
+//
+// Tables of the persistent 2D Adams steps (layout in tdse_internal.h): per
+// Adams step m = ns+1..N the potential time factors at t_m and the axis-0
+// phase differences of the n-1 intervals ending at t_{m+1}; the axis-1 phase
+// increments of every step; the static axis-1 factors exp(-i k2^2 j dt) from
+// extended precision.
+void build_persist2d(tdse_plan_s* p) {
+  const int N = p->nsteps, ns = p->ns, M = p->M2, nh = p->order - 1;
+  std::vector<double>& T = p->p2tab;
+  T.clear();
+  double f[MAXV], pb[2], pa[2];
+  for (int m = ns + 1; m <= N; ++m) {
+    p->fV_at(p->t_at(m), f);
+    T.insert(T.end(), f, f + MAXV);
+    p->tf.phi(p->t_at(m + 1), pb);
+    for (int j = 1; j <= MAXH - 1; ++j) {
+      if (j <= nh) {
+        p->tf.phi(p->t_at(m + 1 - j), pa);
+        T.push_back(pb[0] - pa[0]);
+      } else {
+        T.push_back(0.0);
+      }
+    }
+    T.push_back(0.0);
+  }
+  p->p2_oD2 = (int64_t)T.size();
+  p->p2_ph2 = false;
+  for (int i = 1; i <= N; ++i) {
+    p->tf.phi(p->t_at(i), pb);
+    p->tf.phi(p->t_at(i - 1), pa);
+    T.push_back(pb[1] - pa[1]);
+    if (pb[1] - pa[1] != 0.0) p->p2_ph2 = true;
+  }
+  p->p2S2.assign((size_t)nh * M, double2{0.0, 0.0});
+  for (int j = 1; j <= nh; ++j)
+    for (int idx = 0; idx < M; ++idx) {
+      const long double k = (long double)(idx < M / 2 ? idx : idx - M);
+      const long double th = -k * k * (long double)j * (long double)p->dt;
+      p->p2S2[(size_t)(j - 1) * M + idx] = double2{(double)cosl(th), (double)sinl(th)};
+    }
+}
+
+int upload_persist2d(tdse_plan_s* p) {
+  HIP_TRY(hipMemcpyAsync(p->ws + p->o_p2tab, p->p2tab.data(), p->p2tab.size() * sizeof(double), hipMemcpyHostToDevice,
+                         p->stream));
+  HIP_TRY(hipMemcpyAsync(p->ws + p->o_p2S2, p->p2S2.data(), p->p2S2.size() * sizeof(double2), hipMemcpyHostToDevice,
+                         p->stream));
+  return TDSE_OK;
+}
+
+// Adams steps cur+1 .. end (cur > ns, after the Adams start) in one persistent
+// launch.  Returns 1 (and clears p->persist) when the device cannot hold the
+// co-resident grid, so the caller takes the two-pass path.
+int persist2d_step(tdse_plan_s* p, int end, bool write_u) {
+  const int grid = p->M2 / 2;
+  if (p->persist_cap < 0) p->persist_cap = persist2d_capacity(p->M2, p->order, p->p2_ph2);
+  if (p->persist_cap < grid) {
+    p->persist = false;
+    return 1;
+  }
+  Persist2DArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.N = p->M2;
+  a.order = p->order;
+  a.nsteps = p->nsteps;
+  a.m0 = p->cur;
+  a.m1 = end;
+  a.mbase = p->ns + 1;
+  a.ostep = tdse_plan_s::P2_OSTEP;
+  a.nV = p->nV;
+  a.write_u = write_u ? 1 : 0;
+  a.ph2 = p->p2_ph2 ? 1 : 0;
+  a.spin_limit = 1000000;
+  a.dt = p->dt;
+  a.c0 = p->mu[0] * p->dt;
+  a.scale = 1.0 / (double)p->P;
+  for (int j = 1; j < p->order; ++j) a.ch[j] = p->dt * p->mu[j];
+  a.V = (const double*)p->V(0);
+  a.vstride = p->P;
+  a.tab = (const double*)(p->ws + p->o_p2tab);
+  a.oD2 = p->p2_oD2;
+  a.tile = (double2*)p->tmp(0);
+  a.xbuf = p->u(1 - p->ucur);   // the start-up's second physical buffer, free in the Adams phase
+  a.B = p->B();
+  a.ring = (double2*)p->ring(0);
+  a.S2 = (const double2*)(p->ws + p->o_p2S2);
+  a.tw = (const double2*)p->tw(0, 1);
+  a.uout = p->u(p->ucur);
+  a.bar = (unsigned*)(p->ws + p->o_p2bar);
+  a.flag = a.bar + 32 * 9;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const size_t first = p->ev_used;
+  if (p->prof) {
+    e0 = next_event(p);
+    e1 = next_event(p);
+    if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
+    HIP_TRY(hipEventRecord(e0, p->stream));
+  }
+  const hipError_t e = launch_persist2d(a, p->stream);
+  if (e == hipErrorCooperativeLaunchTooLarge) {
+    (void)hipGetLastError();
+    p->persist = false;
+    return 1;
+  }
+  if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("persistent 2D kernel: ") + hipGetErrorString(e));
+  if (e1) {
+    HIP_TRY(hipEventRecord(e1, p->stream));
+    p->prof_marks.push_back({first, 4});
+  }
+  // a grid barrier that timed out leaves the run unusable: report it now
+  unsigned flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, a.flag, sizeof(flag), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (flag) return fail(TDSE_EDEVICE, "persistent 2D kernel: a grid barrier timed out (co-resident grid not scheduled)");
+  p->cur = end;
+  return TDSE_OK;
+}
+
 // Step m of one instance (write_u: leave u(t_m) in the physical buffer).
 int do_step(tdse_plan_s* p, int m, bool write_u) {
   if (p->free_space) return fs_step(p, m, write_u);
@@ -1599,8 +1731,9 @@ int plan_batch(const tdse_problem_t* probs, int count, tdse_plan_s** out) {
     tdse_plan_s* q = nullptr;
     const int s = tdse_plan(&probs[i], &q);
     if (s) return s;
-    if (q->run1d) {   // batches march every instance with the batched passes
+    if (q->run1d || q->persist) {   // batches march every instance with the batched passes
       q->run1d = false;
+      q->persist = false;
       q->total = q->total_core;
     }
     p->sub.push_back(q);
@@ -2400,6 +2533,14 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
     off = align256(off + (size_t)(p->order - 1) * (p->M1 + p->M2) * sizeof(float2));
   }
   p->total_core = off;
+  if (p->dim == 2 && !split && p->M1 == p->M2 && persist2d_supported(p->M2) && p->vkind == TDSE_V_FIELDS &&
+      p->nsteps > p->ns + 1) {
+    p->persist = true;
+    build_persist2d(p);
+    p->o_p2tab = off; off = align256(off + p->p2tab.size() * sizeof(double));
+    p->o_p2S2 = off; off = align256(off + p->p2S2.size() * sizeof(double2));
+    p->o_p2bar = off; off = align256(off + P2_BAR_WORDS * sizeof(unsigned));
+  }
   if (p->dim == 1 && !split && run1d_supported(p->M2)) {
     p->run1d = true;
     build_run1d(p);
@@ -2444,6 +2585,10 @@ int tdse_bind(tdse_plan_t p, void* ws, size_t bytes, void* stream) {
   }
   if (p->run1d) {
     const int s = upload_run1d(p);
+    if (s) return s;
+  }
+  if (p->persist) {
+    const int s = upload_persist2d(p);
     if (s) return s;
   }
   if (p->free_space) {
@@ -2491,6 +2636,16 @@ int tdse_step(tdse_plan_t p, int32_t k) {
   if (p->is_batch()) return batch_step(p, k);
   const int end = p->cur + k;
   if (p->run1d) return k > 0 ? run1d_step(p, end) : TDSE_OK;
+  if (p->persist && p->persist_on && end > p->ns + 1) {
+    // start-up and the Adams start by the passes, the rest in one persistent launch
+    for (int m = p->cur + 1; m <= p->ns + 1; ++m) {
+      const int s = do_step(p, m, m == end);
+      if (s) return s;
+      p->cur = m;
+    }
+    const int s = persist2d_step(p, end, true);
+    if (s <= 0) return s;
+  }
   for (int m = p->cur + 1; m <= end; ++m) {
     const int s = do_step(p, m, m == end);
     if (s) return s;
@@ -2649,11 +2804,14 @@ int tdse_run(tdse_plan_t p, const void* u0, void* uT, int32_t on_device) {
     if (s) return s;
     return tdse_get_state(p, uT, on_device);
   }
+  // with persistent Adams steps the graph holds the start-up and the Adams
+  // start; the persistent launch (one per run) follows it outside the graph
+  const int pre = (p->persist && p->persist_on) ? p->ns + 1 : p->nsteps;
   if (!p->gexec) {
     // capture the whole step sequence once; kernel arguments depend only on
     // the plan and the bound workspace
     HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-    s = tdse_step(p, p->nsteps);
+    s = tdse_step(p, pre);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(p->stream, &g);
     if (s) {
@@ -2671,11 +2829,15 @@ int tdse_run(tdse_plan_t p, const void* u0, void* uT, int32_t on_device) {
     p->graph_ucur = p->ucur;
   }
   HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
-  p->cur = p->nsteps;
+  p->cur = pre;
   p->ucur = p->graph_ucur;
   for (tdse_plan_s* q : p->sub) {
     q->ucur = p->ucur_after[p->nsteps];
     q->cur = p->nsteps;
+  }
+  if (pre < p->nsteps) {
+    s = tdse_step(p, p->nsteps - pre);
+    if (s) return s;
   }
   return tdse_get_state(p, uT, on_device);
 }
@@ -2723,6 +2885,10 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
   if (key == TDSE_Q_MODES) { *value = (double)p->P; return TDSE_OK; }
   if (key == TDSE_Q_STEPS_DONE) { *value = (double)p->cur; return TDSE_OK; }
   if (key == TDSE_Q_DT) { *value = p->dt; return TDSE_OK; }
+  if (key == TDSE_Q_PATH) {
+    *value = p->run1d ? 1.0 : (p->persist && p->persist_on) ? 2.0 : 0.0;
+    return TDSE_OK;
+  }
   if (p->free_space && (key == TDSE_Q_BYTES_PER_STEP || key == TDSE_Q_BYTES_COL || key == TDSE_Q_BYTES_ROW)) {
     // column pass: tile (N1 x M2) in and out (32 per element) and the
     // potential fields (8 nV per grid point); row pass: tile in and out,
@@ -2771,12 +2937,14 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     return TDSE_OK;
   }
   if ((key >= TDSE_Q_PROF_MS_COL && key <= TDSE_Q_PROF_N_ROW) || key == TDSE_Q_PROF_MS_FAR ||
-      key == TDSE_Q_PROF_N_FAR || key == TDSE_Q_PROF_MS_RUN1D || key == TDSE_Q_PROF_N_RUN1D) {
+      key == TDSE_Q_PROF_N_FAR || key == TDSE_Q_PROF_MS_RUN1D || key == TDSE_Q_PROF_N_RUN1D ||
+      key == TDSE_Q_PROF_MS_PERSIST || key == TDSE_Q_PROF_N_PERSIST) {
     const int kind = (key == TDSE_Q_PROF_MS_FAR || key == TDSE_Q_PROF_N_FAR)        ? 2
                      : (key == TDSE_Q_PROF_MS_RUN1D || key == TDSE_Q_PROF_N_RUN1D) ? 3
+                     : (key == TDSE_Q_PROF_MS_PERSIST || key == TDSE_Q_PROF_N_PERSIST) ? 4
                      : ((key == TDSE_Q_PROF_MS_COL || key == TDSE_Q_PROF_N_COL) ? 0 : 1);
     const bool count = key == TDSE_Q_PROF_N_COL || key == TDSE_Q_PROF_N_ROW || key == TDSE_Q_PROF_N_FAR ||
-                       key == TDSE_Q_PROF_N_RUN1D;
+                       key == TDSE_Q_PROF_N_RUN1D || key == TDSE_Q_PROF_N_PERSIST;
     if (!p->prof_marks.empty()) HIP_TRY(hipStreamSynchronize(p->stream));
     double ms = 0.0, nk = 0.0;
     for (auto& mk : p->prof_marks) {
@@ -2807,6 +2975,18 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     return TDSE_OK;
   }
   return fail(TDSE_EINVAL, "unknown query key");
+}
+
+int tdse_configure(tdse_plan_t p, int32_t key, int32_t value) {
+  if (!p) return fail(TDSE_EINVAL, "NULL plan");
+  if (key == TDSE_CFG_PERSISTENT) {
+    if (value != 0 && value != 1) return fail(TDSE_EINVAL, "TDSE_CFG_PERSISTENT takes 0 or 1");
+    if (p->cur > 0 && p->cur < p->nsteps) return fail(TDSE_ESTATE, "change the step path before or after a run");
+    p->persist_on = value != 0;
+    p->drop_graph();
+    return TDSE_OK;
+  }
+  return fail(TDSE_EINVAL, "unknown configuration key");
 }
 
 int tdse_profile(tdse_plan_t p, int32_t enable) {
@@ -2881,6 +3061,13 @@ int tdse_set_field(tdse_plan_t p, const double* A_steps) {
     if (p->bound) {
       HIP_TRY(hipStreamSynchronize(p->stream));
       HIP_TRY(hipMemcpy(p->ws + p->o_r1tab, p->r1tab.data(), p->r1tab.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+  }
+  if (p->persist) {
+    build_persist2d(p);
+    if (p->bound) {
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      HIP_TRY(hipMemcpy(p->ws + p->o_p2tab, p->p2tab.data(), p->p2tab.size() * sizeof(double), hipMemcpyHostToDevice));
     }
   }
   return TDSE_OK;

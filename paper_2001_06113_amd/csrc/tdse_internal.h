@@ -255,6 +255,40 @@ bool run1d_supported(int N);
 size_t run1d_lds_bytes(int N, int stab_rows, int nV);
 hipError_t launch_run1d(const Run1DArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
+// Persistent implicit Adams steps of a square 2D periodic FP64 problem
+// (persist2d_kernels.hip): steps m0+1 .. m1 (all past the Adams start) by one
+// co-resident grid of N/2 workgroups.  Per step m, tab + ostep (m - mbase)
+// holds the eight potential time factors at t_m and phi_1(t_{m+1}) -
+// phi_1(t_{m+1-j}), j = 1..7; tab[oD2 + i - 1] = phi_2(t_i) - phi_2(t_{i-1}).
+// S2 holds exp(-i k2^2 j dt), j = 1..n-1.  tile: the row-major tile of the
+// two-pass path (read by the first step, written by a launch that ends
+// before T); xbuf: an N x N complex128 exchange buffer (blocked layout).
+// bar: P2_BAR_WORDS words of barrier counters, flag: the timeout flag (both
+// reset by the launch).
+struct Persist2DArgs {
+  int N, order, nsteps, m0, m1, mbase, ostep, nV, write_u, ph2, spin_limit;
+  double dt, c0, scale;
+  double ch[MAXH + 1];
+  const double* V;
+  int64_t vstride;
+  const double* tab;
+  int64_t oD2;
+  double2* tile;
+  double2* xbuf;
+  double2* B;
+  double2* ring;
+  const double2* S2;
+  const double2* tw;
+  double2* uout;
+  unsigned* bar;
+  unsigned* flag;
+};
+constexpr int P2_BAR_WORDS = 32 * 9 + 32;   // grid counter, eight XCD counters (128 bytes apart), flag
+bool persist2d_supported(int N);
+size_t persist2d_lds_bytes(int N, int order);
+int persist2d_capacity(int N, int order, bool ph2);   // co-resident workgroups the device holds
+hipError_t launch_persist2d(const Persist2DArgs& a, hipStream_t s);
+
 // Launchers (periodic_kernels.hip).  Non-null events e0/e1 are recorded at
 // the kernel's own start and end.  Return a hipError_t.
 hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,

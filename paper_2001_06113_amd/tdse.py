@@ -21,6 +21,8 @@ Q_BYTES_COL, Q_BYTES_ROW = 12, 13
 Q_PROF_MS_FAR, Q_PROF_N_FAR = 14, 15
 Q_MU, Q_RICHARDSON, Q_PHI = 16, 32, 64
 Q_INSTANCES, Q_INST_OFFSET, Q_INST_EPT_COL, Q_INST_EPT_ROW = 4, 4096, 8192, 12288
+Q_PROF_MS_RUN1D, Q_PROF_N_RUN1D, Q_PROF_MS_PERSIST, Q_PROF_N_PERSIST, Q_PATH = 24, 25, 26, 27, 28
+CFG_PERSISTENT = 0
 
 
 class TDSEError(RuntimeError):
@@ -269,6 +271,10 @@ class Plan:
 
     def _split_field(self, flat):
         return flat.reshape(self.nsteps, self.dim)
+
+    def configure(self, key: int, value: int) -> None:
+        """Plan option (tdse_configure), e.g. CFG_PERSISTENT."""
+        _check(self.lib.tdse_configure(self.handle, int(key), int(value)), "tdse_configure")
 
     def profile(self, enable: bool) -> None:
         _check(self.lib.tdse_profile(self.handle, 1 if enable else 0), "tdse_profile")

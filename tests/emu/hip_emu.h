@@ -57,7 +57,13 @@ typedef double emu_f64x4 __attribute__((vector_size(32)));
 
 typedef int hipError_t;
 typedef void* hipStream_t;
-enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorInvalidDevice = 101, hipErrorInvalidSymbol = 701 };
+enum {
+  hipSuccess = 0,
+  hipErrorInvalidValue = 1,
+  hipErrorInvalidDevice = 101,
+  hipErrorInvalidSymbol = 701,
+  hipErrorCooperativeLaunchTooLarge = 720
+};
 #define __align__(n) __attribute__((aligned(n)))
 // a __device__ variable is a host variable here: its address is the symbol's
 #define HIP_SYMBOL(x) (&(x))
@@ -165,9 +171,157 @@ inline void barrier_wait() {
   swapcontext(&f.ctx, &b->sched);
   threadIdx.x = f.tid;
 }
+
+// Cooperative (co-resident) launches: every thread of every block is a fiber
+// of one scheduler, each block has its own dynamic LDS and its own barrier
+// (a generation count), and a fiber that spins (s_sleep) or waits at a
+// barrier yields to the others, so grid-wide waits make progress.
+struct CoopFiber {
+  ucontext_t ctx;
+  bool done = false;
+  unsigned tid = 0, bid = 0;
+  void* tsan = nullptr;
+};
+struct CoopBlock {
+  unsigned arrived = 0, gen = 0;
+  std::vector<double> lds;
+};
+struct CoopRun {
+  ucontext_t sched;
+  void* tsan_sched = nullptr;
+  std::vector<CoopFiber> fibers;
+  std::vector<CoopBlock> blocks;
+  std::function<void()> body;
+  int current = -1;
+};
+extern thread_local CoopRun* g_coop;
+inline void coop_yield() {
+  CoopRun* r = g_coop;
+  CoopFiber& f = r->fibers[r->current];
+  tsan_switch(r->tsan_sched);
+  swapcontext(&f.ctx, &r->sched);
+  threadIdx.x = f.tid;
+  blockIdx.x = f.bid;
+}
+inline void coop_barrier() {
+  CoopRun* r = g_coop;
+  CoopBlock& b = r->blocks[r->fibers[r->current].bid];
+  const unsigned my = b.gen;
+  if (++b.arrived == blockDim.x) {
+    b.arrived = 0;
+    ++b.gen;
+  } else {
+    while (b.gen == my) coop_yield();
+  }
+}
+inline void coop_entry() {
+  CoopRun* r = g_coop;
+  CoopFiber& f = r->fibers[r->current];
+  threadIdx.x = f.tid;
+  blockIdx.x = f.bid;
+  r->body();
+  f.done = true;
+  tsan_switch(r->tsan_sched);
+  swapcontext(&f.ctx, &r->sched);
+}
+template <typename F>
+void launch_coop(F body, dim3 grid, dim3 block, size_t lds_bytes) {
+  gridDim = grid;
+  blockDim = block;
+  CoopRun r;
+  g_coop = &r;
+  r.body = body;
+  r.blocks.resize(grid.x);
+  for (CoopBlock& b : r.blocks) b.lds.assign((std::max<size_t>(lds_bytes, 16) + 7) / 8, 0.0);
+  const unsigned n = grid.x * block.x;
+  r.fibers.resize(n);
+#if defined(__SANITIZE_THREAD__)
+  r.tsan_sched = __tsan_get_current_fiber();
+#endif
+  for (unsigned i = 0; i < n; ++i) {
+    CoopFiber& f = r.fibers[i];
+    f.bid = i / block.x;
+    f.tid = i % block.x;
+    getcontext(&f.ctx);
+    f.ctx.uc_stack.ss_sp = stack_for(i);
+    f.ctx.uc_stack.ss_size = kStack;
+    f.ctx.uc_link = nullptr;
+    makecontext(&f.ctx, (void (*)())coop_entry, 0);
+#if defined(__SANITIZE_THREAD__)
+    f.tsan = __tsan_create_fiber(0);
+#endif
+  }
+  bool any = true;
+  while (any) {
+    any = false;
+    for (unsigned i = 0; i < n; ++i) {
+      if (r.fibers[i].done) continue;
+      r.current = (int)i;
+      threadIdx.x = r.fibers[i].tid;
+      blockIdx.x = r.fibers[i].bid;
+      tsan_switch(r.fibers[i].tsan);
+      swapcontext(&r.sched, &r.fibers[i].ctx);
+      if (!r.fibers[i].done) any = true;
+    }
+  }
+#if defined(__SANITIZE_THREAD__)
+  for (CoopFiber& f : r.fibers) __tsan_destroy_fiber(f.tsan);
+#endif
+  g_coop = nullptr;
+}
+// dynamic LDS: the running block's own buffer in a cooperative launch, else
+// one buffer per host thread (blocks of ordinary launches run one at a time)
+inline void* dyn_lds() {
+  if (g_coop) return g_coop->blocks[g_coop->fibers[g_coop->current].bid].lds.data();
+  static thread_local std::vector<double> buf(160 * 1024 / sizeof(double));
+  return buf.data();
+}
 }  // namespace emu
 
-inline void __syncthreads() { emu::barrier_wait(); }
+inline void __syncthreads() {
+  if (emu::g_coop) emu::coop_barrier();
+  else emu::barrier_wait();
+}
+// scheduling and memory-model builtins of the device code
+inline void __builtin_amdgcn_s_sleep(int) {
+  if (emu::g_coop) emu::coop_yield();
+}
+inline void __builtin_amdgcn_s_waitcnt(int) {}
+inline void __builtin_amdgcn_fence(int, const char*) {}
+// buffer resources: the base pointer and the byte size; 16-byte loads and
+// stores (cache policy bits have no meaning here)
+struct __amdgpu_buffer_rsrc_t {
+  char* base;
+  int bytes;
+};
+struct emu_u32x4 {
+  unsigned v[4];
+};
+inline __amdgpu_buffer_rsrc_t __builtin_amdgcn_make_buffer_rsrc(void* p, short, int bytes, int) {
+  return __amdgpu_buffer_rsrc_t{(char*)p, bytes};
+}
+inline emu_u32x4 __builtin_amdgcn_raw_buffer_load_b128(__amdgpu_buffer_rsrc_t r, int off, int soff, int) {
+  emu_u32x4 x{};
+  if (off + soff >= 0 && off + soff + 16 <= r.bytes) std::memcpy(&x, r.base + off + soff, 16);
+  else std::abort();   // an access outside the buffer is a bug in the kernel
+  return x;
+}
+inline void __builtin_amdgcn_raw_buffer_store_b128(emu_u32x4 x, __amdgpu_buffer_rsrc_t r, int off, int soff, int) {
+  if (off + soff >= 0 && off + soff + 16 <= r.bytes) std::memcpy(r.base + off + soff, &x, 16);
+  else std::abort();
+}
+#define __HIP_MEMORY_SCOPE_WORKGROUP 2
+#define __HIP_MEMORY_SCOPE_AGENT 3
+template <typename T>
+inline T __hip_atomic_load(const T* p, int, int) { return *p; }
+template <typename T>
+inline void __hip_atomic_store(T* p, T v, int, int) { *p = v; }
+template <typename T>
+inline T __hip_atomic_fetch_add(T* p, T v, int, int) {
+  const T old = *p;
+  *p = old + v;
+  return old;
+}
 // FP64 16x16x4 matrix product of one wave (gfx950 lane layout: A[i][k] in
 // lane i + 16k, B[k][j] in lane j + 16k, D[q + 4r][j] in lane j + 16q,
 // element r).
@@ -227,14 +381,27 @@ inline hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) {
   std::memcpy(d, s, n);
   return hipSuccess;
 }
-enum hipDeviceAttribute_t { hipDeviceAttributeMaxSharedMemoryPerBlock };
+enum hipDeviceAttribute_t { hipDeviceAttributeMaxSharedMemoryPerBlock, hipDeviceAttributeMultiprocessorCount };
 inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+template <typename K>
+inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, K, int, size_t) {
+  *n = 1;
+  return hipSuccess;
+}
+template <typename A>
+inline hipError_t hipLaunchCooperativeKernel(void (*k)(A), dim3 grid, dim3 block, void** args, unsigned lds, hipStream_t) {
+  const A arg = *(const A*)args[0];
+  emu::launch_coop([&]() { k(arg); }, grid, block, lds);
+  return hipSuccess;
+}
 inline hipError_t hipSetDevice(int) { return hipSuccess; }
 constexpr unsigned hipStreamNonBlocking = 1, hipEventDisableTiming = 2;
 inline hipError_t hipStreamCreateWithFlags(hipStream_t* st, unsigned) { *st = (hipStream_t)new char[1]; return hipSuccess; }
 inline hipError_t hipStreamDestroy(hipStream_t st) { delete[] (char*)st; return hipSuccess; }
 inline hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = (hipEvent_t)new char[1]; return hipSuccess; }
 inline hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
-inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 160 * 1024; return hipSuccess; }
-// dynamic LDS: one static buffer per kernel and element type, as large as a CU's LDS
-#define HIP_DYNAMIC_SHARED(type, var) static thread_local type var[160 * 1024 / sizeof(type)];
+inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int) {
+  *v = a == hipDeviceAttributeMultiprocessorCount ? 256 : 160 * 1024;
+  return hipSuccess;
+}
+#define HIP_DYNAMIC_SHARED(type, var) type* var = (type*)emu::dyn_lds();
