@@ -4,15 +4,19 @@ Workload: 2D periodic TDSE, 512 x 512 grid, T = 2, 2000 steps of the 8th-order
 implicit Adams scheme (6 Richardson start-up steps), four-well potential with
 sinusoidal modulation and a sin^2 pulse, seed 1, complex128 (synthetic inputs).
 One benchmark "step" is one whole run [0, T] on inputs already resident in
-device memory: start-up plus 1994 Adams steps.
+device memory: start-up plus 1994 Adams steps (the library's default path:
+the start-up replayed from a captured graph, the Adams steps in one
+persistent launch; the two-pass path is timed beside it).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--workload periodic-2d-512|periodic-2d-1024-fp64]
 
 Prints one JSON line.  value = modes x time steps / wall time of the K timed
 runs (whole job).  roofline: algorithmic bytes of the dominant kernel (the
-Adams row pass) per launch / its mean duration measured with HIP events on the
-library's stream during the timed runs.  cpu_baseline: the FP64 oracle on the
-host on a bounded sample of the same workload.
+persistent Adams launch: 216 B per mode and step times the steps it takes)
+per launch / its mean duration measured with HIP events on the library's
+stream in eager runs of the same workload.  Every leg reports its error
+against the stored oracle samples.  cpu_baseline: the FP64 oracle on the host
+on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -175,11 +179,13 @@ def end_to_end(bytes_per_step: float, nsteps: int, seconds: float, copies: dict)
 
 
 KERNEL_SOURCES = ("paper_2001_06113_amd/csrc/periodic_kernels.hip", "paper_2001_06113_amd/csrc/periodic_body.h",
-                  "paper_2001_06113_amd/csrc/fft_lds.h", "paper_2001_06113_amd/csrc/tdse_internal.h")
+                  "paper_2001_06113_amd/csrc/fft_lds.h")
 
 
-FS_KERNEL_SOURCES = ("paper_2001_06113_amd/csrc/freespace_kernels.hip", "paper_2001_06113_amd/csrc/fft_lds.h",
-                     "paper_2001_06113_amd/csrc/tdse_internal.h")
+P2_KERNEL_SOURCES = ("paper_2001_06113_amd/csrc/persist2d_kernels.hip", "paper_2001_06113_amd/csrc/fft_lds.h")
+
+
+FS_KERNEL_SOURCES = ("paper_2001_06113_amd/csrc/freespace_kernels.hip", "paper_2001_06113_amd/csrc/fft_lds.h")
 
 
 def measured_traffic(name: str, sources=KERNEL_SOURCES):
@@ -206,7 +212,7 @@ def split_leg(steps: int, copies: dict) -> dict:
     runs against the stored oracle samples."""
     import torch
 
-    from paper_2001_06113_amd.tdse import Q_BYTES_PER_STEP, Plan
+    from paper_2001_06113_amd.tdse import Q_BYTES_PER_STEP, Q_RESIDUAL, Plan
     from workloads import periodic_2d_1024_problem
 
     dev = torch.device("cuda:0")
@@ -230,6 +236,11 @@ def split_leg(steps: int, copies: dict) -> dict:
         res[prec] = u0.numel() * prob.nsteps / wall
         e2e[prec] = end_to_end(plan.query(Q_BYTES_PER_STEP), prob.nsteps, wall, copies)
         err[prec] = oracle_error("periodic_2d_1024", out, bar=1e-6 if prec == "fp32split" else 1e-11)
+        # the history residual of the last Adams step before T (FP64 recomputation)
+        plan.use_graph(False)
+        plan.set_state(u0)
+        plan.step(prob.nsteps - 1)
+        err[prec]["history_residual_step_N-1"] = plan.query(Q_RESIDUAL)
         plan.close()
     rel = (torch.linalg.vector_norm(outs["fp32split"] - outs["fp64"]) / torch.linalg.vector_norm(outs["fp64"])).item()
     return {"workload": "2D periodic TDSE 1024x1024, T=2, 2000 steps AM8, FP32-split",
@@ -538,8 +549,9 @@ def main():
     import torch
 
     from paper_2001_06113_amd import _lib
-    from paper_2001_06113_amd.tdse import (Q_BYTES_COL, Q_BYTES_PER_STEP, Q_BYTES_ROW, Q_PROF_MS_COL,
-                                           Q_PROF_MS_ROW, Q_PROF_N_COL, Q_PROF_N_ROW, Plan)
+    from paper_2001_06113_amd.tdse import (CFG_PERSISTENT, Q_BYTES_COL, Q_BYTES_PER_STEP, Q_BYTES_ROW, Q_PATH,
+                                           Q_PROF_MS_COL, Q_PROF_MS_PERSIST, Q_PROF_MS_ROW, Q_PROF_N_COL,
+                                           Q_PROF_N_PERSIST, Q_PROF_N_ROW, Plan)
     from workloads import periodic_2d_512_problem, periodic_problem_from_seed
 
     if not os.path.exists(_lib.LIB_PATH):
@@ -572,23 +584,51 @@ def main():
     ok = bool(torch.isfinite(torch.view_as_real(out)).all().item())
 
     # per-kernel durations: the same runs launched eagerly, every Adams
-    # column and row pass bracketed by HIP events on the library's stream
+    # launch bracketed by HIP events on the library's stream
+    path = plan.query(Q_PATH)
+    plan.profile(True)
+    for _ in range(args.prof_runs):
+        plan.run(u0, out)
+    p_ms, p_n = plan.query(Q_PROF_MS_PERSIST), plan.query(Q_PROF_N_PERSIST)
+    plan.profile(False)
+    ms_per_run = wall * 1e3 / args.steps
+    value = modes * prob.nsteps * args.steps / wall
+    err = oracle_error("periodic_2d_512" if args.workload == "periodic-2d-512" else "periodic_2d_1024", out)
+    bytes_step = plan.query(Q_BYTES_PER_STEP)
+    adams_steps = prob.nsteps - prob.start_steps - 1   # the Adams steps after the first (inside the persistent launch)
+
+    # the same workload on the two-pass path (one column and one row launch per step)
+    plan.configure(CFG_PERSISTENT, 0)
+    plan.run(u0, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run(u0, out)
+    torch.cuda.synchronize()
+    wall2 = (time.perf_counter() - t0) / args.steps
+    err2 = oracle_error("periodic_2d_512" if args.workload == "periodic-2d-512" else "periodic_2d_1024", out)
     plan.profile(True)
     for _ in range(args.prof_runs):
         plan.run(u0, out)
     row_ms, col_ms = plan.query(Q_PROF_MS_ROW), plan.query(Q_PROF_MS_COL)
     n_row, n_col = plan.query(Q_PROF_N_ROW), plan.query(Q_PROF_N_COL)
     plan.profile(False)
+    plan.configure(CFG_PERSISTENT, 1)
 
-    ms_per_run = wall * 1e3 / args.steps
-    value = modes * prob.nsteps * args.steps / wall
-    err = oracle_error("periodic_2d_512" if args.workload == "periodic-2d-512" else "periodic_2d_1024", out)
     copy_gbps = device_copy_gbps(dev)
     copy_mall_gbps = device_copy_gbps(dev, mib=32, reps=200)
     copies = {"512MiB": copy_gbps, "32MiB_in_MALL": copy_mall_gbps}
     row_us, col_us = row_ms * 1e3 / max(n_row, 1), col_ms * 1e3 / max(n_col, 1)
     row_b, col_b = plan.query(Q_BYTES_ROW), plan.query(Q_BYTES_COL)
-    dom_b, dom_us, dom = (row_b, row_us, "row") if row_us * 1 >= col_us else (col_b, col_us, "col")
+    row_ach = row_b / (row_us * 1e-6) / 1e9 if row_us > 0 else None
+    if path == 2.0 and p_n > 0:
+        dom_us = p_ms * 1e3 / p_n
+        dom_b = bytes_step * adams_steps
+        kernel = f"persistent Adams launch (k_persist2d, {adams_steps} steps per launch)"
+        traffic = measured_traffic("k_persist2d_512_traffic.txt", P2_KERNEL_SOURCES)
+    else:
+        dom_us, dom_b, kernel = row_us, row_b, "Adams row pass (k_row)"
+        traffic = measured_traffic("k_row_512_fp64_traffic.txt")
     achieved = dom_b / (dom_us * 1e-6) / 1e9 if dom_us > 0 else None
     res = {
         "metric": "mode-updates/s",
@@ -605,29 +645,35 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "grid": list(prob.M), "time_steps": prob.nsteps,
                    "order": prob.order, "modes": int(modes), "seed": 1 if args.workload == "periodic-2d-512" else 3,
-                   "finite": ok},
+                   "finite": ok, "path": {0.0: "two passes per step", 2.0: "persistent Adams launch"}.get(path)},
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": measured_traffic("k_row_512_fp64_traffic.txt") if dom == "row" else None,
-            "kernel": f"Adams {dom} pass (k_{dom})",
+            "traffic": traffic,
+            "kernel": kernel,
             "bytes_per_launch": dom_b,
             "mean_launch_us": dom_us,
-            "row_pass_us": row_us,
-            "col_pass_us": col_us,
             "device_copy_GBps": copy_gbps,
             "frac_of_device_copy": achieved / copy_gbps if achieved else None,
             "device_copy_32MiB_in_MALL_GBps": copy_mall_gbps,
             "frac_of_device_copy_in_MALL": achieved / copy_mall_gbps if achieved else None,
         },
         "error": err,
-        "end_to_end": end_to_end(plan.query(Q_BYTES_PER_STEP), prob.nsteps, wall / args.steps, copies),
-        "adams_step_us_eager": row_us + col_us,
+        "end_to_end": end_to_end(bytes_step, prob.nsteps, wall / args.steps, copies),
         "graph_us_per_time_step": wall * 1e6 / (args.steps * prob.nsteps),
-        "steady_mode_updates_per_s_eager": modes / ((row_us + col_us) * 1e-6) if row_us > 0 else None,
+        "two_pass": {
+            "value": modes * prob.nsteps / wall2, "ms_per_run": wall2 * 1e3,
+            "us_per_time_step": wall2 * 1e6 / prob.nsteps, "error": err2,
+            "end_to_end": end_to_end(bytes_step, prob.nsteps, wall2, copies),
+            "row_pass_us": row_us, "col_pass_us": col_us, "row_bytes_per_launch": row_b,
+            "col_bytes_per_launch": col_b,
+            "row_pass_roofline": {"achieved": row_ach, "frac": row_ach / HBM_PEAK_GBS if row_ach else None,
+                                  "traffic": measured_traffic("k_row_512_fp64_traffic.txt")},
+            "adams_step_us_eager": row_us + col_us,
+        },
     }
     if not args.no_1d:
         res["periodic_1d"] = periodic_1d_leg()

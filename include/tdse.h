@@ -208,12 +208,22 @@ int tdse_far_eval_noalloc(tdse_plan_t plan, const double* xs, int32_t nx, const 
 #define TDSE_Q_PROF_N_PERSIST 27  /* profiling: number of timed persistent 2D launches */
 #define TDSE_Q_PATH           28  /* how tdse_step marches: 0 kernel passes per step, 1 one-workgroup 1D run,
                                      2 persistent 2D launch for the Adams steps (eligible and enabled) */
+#define TDSE_Q_RESIDUAL       29  /* single periodic plans, at an Adams step before T: relative L2 difference of the
+                                     history entry What_n = F(V(t_n) u_n) as the plan stores it (complex64 in the
+                                     split form) from its FP64 recomputation out of u_n; measures the transform
+                                     precision's error injected per step (about 1e-7 split, 1e-16 FP64; the implicit
+                                     solve itself is a diagonal division, Section 2.1).  Synchronizes the stream;
+                                     ESTATE before the Adams start or at T, EUNSUPPORTED for batches and free space */
+#define TDSE_Q_STATE_NORM     30  /* 2-norm of the state at the last guard check (TDSE_CFG_GUARD); ESTATE if none ran */
 #define TDSE_Q_RICHARDSON     32  /* + l: weight of the 2^l-sub-step result    */
 #define TDSE_Q_PHI            64  /* + axis: phi_axis(T)                       */
 #define TDSE_Q_FS_H           80  /* free space: contour parameter H of axis 0 */
 #define TDSE_Q_FS_MODES       81  /* + axis: complex-frequency modes N_axis     */
 #define TDSE_Q_FS_NE          83  /* + axis: equispaced nodes per ray N_E      */
 #define TDSE_Q_FS_H_AXIS      86  /* + axis: contour parameter H of that axis   */
+#define TDSE_Q_FS_HSTEP       88  /* + axis: node spacing h = pi M / nu           */
+#define TDSE_Q_FS_NU          90  /* + axis: FFT size nu                          */
+#define TDSE_Q_FS_K           92  /* + axis: truncation K of Gamma_K (the last equispaced node is K - kappa h) */
 #define TDSE_Q_ALPERT_X       96  /* + k: Alpert node x_k (units of h), k < p   */
 #define TDSE_Q_ALPERT_W      112  /* + k: Alpert weight w_k, k < p              */
 #define TDSE_Q_INSTANCES       4  /* batch: number of instances                 */
@@ -232,6 +242,13 @@ int tdse_query(tdse_plan_t plan, int32_t key, double* value);
  * persistent launch synchronizes the stream once, to check that no grid
  * barrier timed out (TDSE_EDEVICE if one did). */
 #define TDSE_CFG_PERSISTENT 0
+/* TDSE_CFG_GUARD (default 0, off): with value K >= 1, tdse_step marches in
+ * pieces of at most K steps and after each piece, and tdse_run after the
+ * run, scans the physical solution u(t) (every instance of a batch) on the
+ * device for entries that are not finite and sums its squared norm
+ * (TDSE_Q_STATE_NORM); a non-finite state stops the call with
+ * TDSE_ENONFINITE.  Each check synchronizes the stream. */
+#define TDSE_CFG_GUARD 1
 int tdse_configure(tdse_plan_t plan, int32_t key, int32_t value);
 
 /* Per-kernel timing: with enable != 0 every implicit Adams column and row

@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtdse.so")
 
 HIP_SOURCES = ["periodic_kernels.hip", "freespace_kernels.hip", "batch_fp64.hip", "batch_split.hip",
-               "adjoint_kernels.hip", "far_kernels.hip", "run1d_kernels.hip", "persist2d_kernels.hip"]
+               "adjoint_kernels.hip", "far_kernels.hip", "run1d_kernels.hip", "persist2d_kernels.hip",
+               "diag_kernels.hip"]
 HOST_SOURCES = ["tdse_api.cpp"]
 ARCH = os.environ.get("TDSE_OFFLOAD_ARCH", "gfx950")
 

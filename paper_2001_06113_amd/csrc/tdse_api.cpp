@@ -380,6 +380,13 @@ struct tdse_plan_s {
   bool p2_ph2 = false;
   static constexpr int P2_OSTEP = 16;
 
+  // failure guard (tdse_configure TDSE_CFG_GUARD): check every guard_every
+  // steps; diagnostics words at o_diag (two doubles and a flag); o_dbuf: an
+  // FP64 mode array for the residual of periodic FP64 plans
+  int guard_every = 0;
+  size_t o_diag = 0, o_dbuf = 0;
+  double state_norm = -1.0;
+
   // whole-run graph (tdse_graph): captured on the first tdse_run, replayed after
   bool use_graph = false;
   hipGraph_t graph = nullptr;
@@ -1487,6 +1494,74 @@ int persist2d_step(tdse_plan_s* p, int end, bool write_u) {
   return TDSE_OK;
 }
 
+// ============================================================ diagnostics
+//
+// The failure guard: the physical solution u(t_cur) (of every instance of a
+// batch) is scanned on the device for entries that are not finite, and its
+// squared norm summed; the stream is then synchronized to read the flag.
+int guard_check(tdse_plan_s* p) {
+  double* acc = (double*)(p->ws + p->o_diag);
+  unsigned* flag = (unsigned*)(acc + 2);
+  std::vector<tdse_plan_s*> inst;
+  if (p->is_batch()) inst = p->sub;
+  else inst.push_back(p);
+  for (size_t i = 0; i < inst.size(); ++i) {
+    const tdse_plan_s* q = inst[i];
+    const hipError_t e = launch_guard((const double*)q->u(q->ucur), 2 * q->P, acc, flag, i == 0, p->stream);
+    if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("guard kernel: ") + hipGetErrorString(e));
+  }
+  double h[3] = {0.0, 0.0, 0.0};
+  HIP_TRY(hipMemcpyAsync(h, acc, 3 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  unsigned bad = 0;
+  std::memcpy(&bad, &h[2], sizeof(bad));
+  p->state_norm = std::sqrt(h[0]);
+  if (bad) {
+    p->state_norm = NAN;
+    return fail(TDSE_ENONFINITE, "the state is not finite after step " + std::to_string(p->cur));
+  }
+  return TDSE_OK;
+}
+
+// Drift of the history entry of the current Adams step: What_n as stored in
+// the ring (in the transform precision of the plan) against F(V(t_n) u_n)
+// recomputed in FP64 from the physical solution, relative L2.
+int history_residual(tdse_plan_s* p, double* value) {
+  if (p->is_batch() || p->free_space) return fail(TDSE_EUNSUPPORTED, "the residual is kept for single periodic plans");
+  if (!p->bound || !(p->cur > p->ns && p->cur < p->nsteps))
+    return fail(TDSE_ESTATE, "the residual needs a state past the Adams start and before T");
+  const int n = p->cur, nh = p->order - 1;
+  const bool split = p->precision == TDSE_FP32_SPLIT;
+  double2* X = p->u(1 - p->ucur);                                  // free in the Adams phase
+  double2* Y = split ? (double2*)p->ring_slot(0, 0) : (double2*)(p->ws + p->o_dbuf);
+  LineArgs a = base_args(p, 0);
+  col_geom(p, 0, a);
+  a.mode = C_FWD;
+  a.src = p->u(p->ucur);
+  a.dst = X;
+  p->fV_at(p->t_at(n), a.fV);
+  a.alpha_re = 0.0; a.alpha_im = 0.0; a.beta_re = 1.0; a.beta_im = 0.0;
+  int s = launch(p, 0, true, a);
+  if (s) return s;
+  LineArgs r = base_args(p, 0);
+  row_geom(p, 0, r);
+  r.mode = R_FWD;
+  r.src = X;
+  r.fdst = Y;
+  s = launch(p, 0, false, r);
+  if (s) return s;
+  double* acc = (double*)(p->ws + p->o_diag);
+  const void* W = p->ring_slot(1, n % nh);
+  const hipError_t e = launch_diffnorm(split ? (const float2*)W : nullptr, split ? nullptr : (const double2*)W, Y, p->P,
+                                       acc, (unsigned*)(acc + 2), p->stream);
+  if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("residual kernel: ") + hipGetErrorString(e));
+  double h[2] = {0.0, 0.0};
+  HIP_TRY(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  *value = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : 0.0;
+  return TDSE_OK;
+}
+
 // Step m of one instance (write_u: leave u(t_m) in the physical buffer).
 int do_step(tdse_plan_s* p, int m, bool write_u) {
   if (p->free_space) return fs_step(p, m, write_u);
@@ -1794,6 +1869,8 @@ int plan_batch(const tdse_problem_t* probs, int count, tdse_plan_s** out) {
   off = align256(off + std::max<size_t>(p->cap_targs, 1) * sizeof(LineArgs));
   p->o_tiles = off;
   off = align256(off + (size_t)(2 * p->cap_tiles[0] + 2 * p->cap_tiles[1]) * sizeof(BatchTile));
+  p->o_diag = off;
+  off = align256(off + 64);
   p->total = off;
   *out = p.release();
   return TDSE_OK;
@@ -2493,6 +2570,8 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
       delete p;
       return s;
     }
+    p->o_diag = p->total;
+    p->total = align256(p->total + 64);
     *out = p;
     return TDSE_OK;
   }
@@ -2531,6 +2610,11 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   if (split) {   // the same table rounded to complex64, read by the split row pass
     p->o_ph32 = off;
     off = align256(off + (size_t)(p->order - 1) * (p->M1 + p->M2) * sizeof(float2));
+  }
+  p->o_diag = off; off = align256(off + 64);
+  if (!split) {
+    p->o_dbuf = off;
+    off = align256(off + cbytes);
   }
   p->total_core = off;
   if (p->dim == 2 && !split && p->M1 == p->M2 && persist2d_supported(p->M2) && p->vkind == TDSE_V_FIELDS &&
@@ -2628,11 +2712,29 @@ int tdse_set_state(tdse_plan_t p, const void* u0, int32_t on_device) {
   return TDSE_OK;
 }
 
+namespace {
+int step_range(tdse_plan_s* p, int k);
+}
+
 int tdse_step(tdse_plan_t p, int32_t k) {
   if (!p) return fail(TDSE_EINVAL, "NULL plan");
   if (!p->bound || p->cur < 0) return fail(TDSE_ESTATE, "tdse_set_state must come first");
   if (k < 0) return fail(TDSE_EINVAL, "negative step count");
   if (p->cur + k > p->nsteps) return fail(TDSE_ESTATE, "stepping past T");
+  if (p->guard_every <= 0) return step_range(p, k);
+  // guarded: pieces of at most guard_every steps, each followed by the check
+  while (k > 0) {
+    const int c = std::min(k, p->guard_every);
+    int s = step_range(p, c);
+    if (!s) s = guard_check(p);
+    if (s) return s;
+    k -= c;
+  }
+  return TDSE_OK;
+}
+
+namespace {
+int step_range(tdse_plan_s* p, int k) {
   if (p->is_batch()) return batch_step(p, k);
   const int end = p->cur + k;
   if (p->run1d) return k > 0 ? run1d_step(p, end) : TDSE_OK;
@@ -2653,6 +2755,7 @@ int tdse_step(tdse_plan_t p, int32_t k) {
   }
   return TDSE_OK;
 }
+}  // namespace
 
 int tdse_get_state(tdse_plan_t p, void* u, int32_t on_device) {
   if (!p || !u) return fail(TDSE_EINVAL, "NULL argument");
@@ -2811,7 +2914,10 @@ int tdse_run(tdse_plan_t p, const void* u0, void* uT, int32_t on_device) {
     // capture the whole step sequence once; kernel arguments depend only on
     // the plan and the bound workspace
     HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    const int guard = p->guard_every;
+    p->guard_every = 0;   // the check synchronizes: it runs after the replay
     s = tdse_step(p, pre);
+    p->guard_every = guard;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(p->stream, &g);
     if (s) {
@@ -2830,6 +2936,10 @@ int tdse_run(tdse_plan_t p, const void* u0, void* uT, int32_t on_device) {
   }
   HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
   p->cur = pre;
+  if (p->guard_every > 0) {
+    s = guard_check(p);
+    if (s) return s;
+  }
   p->ucur = p->graph_ucur;
   for (tdse_plan_s* q : p->sub) {
     q->ucur = p->ucur_after[p->nsteps];
@@ -2840,6 +2950,7 @@ int tdse_run(tdse_plan_t p, const void* u0, void* uT, int32_t on_device) {
     if (s) return s;
   }
   return tdse_get_state(p, uT, on_device);
+  // (a guarded run checks the state after the graph and after every guarded piece)
 }
 
 int tdse_graph(tdse_plan_t p, int32_t enable) {
@@ -2855,6 +2966,12 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
   if (p->is_batch()) {
     const int n = (int)p->sub.size();
     if (key == TDSE_Q_INSTANCES) { *value = n; return TDSE_OK; }
+    if (key == TDSE_Q_RESIDUAL) return history_residual(p, value);
+    if (key == TDSE_Q_STATE_NORM) {
+      if (p->state_norm < 0.0) return fail(TDSE_ESTATE, "no guard check has run");
+      *value = p->state_norm;
+      return TDSE_OK;
+    }
     if (key == TDSE_Q_MODES) { *value = (double)p->P; return TDSE_OK; }
     if (key == TDSE_Q_STEPS_DONE) { *value = (double)p->cur; return TDSE_OK; }
     if (key >= TDSE_Q_INST_OFFSET && key < TDSE_Q_INST_OFFSET + n) {
@@ -2885,6 +3002,12 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
   if (key == TDSE_Q_MODES) { *value = (double)p->P; return TDSE_OK; }
   if (key == TDSE_Q_STEPS_DONE) { *value = (double)p->cur; return TDSE_OK; }
   if (key == TDSE_Q_DT) { *value = p->dt; return TDSE_OK; }
+  if (key == TDSE_Q_RESIDUAL) return history_residual(p, value);
+  if (key == TDSE_Q_STATE_NORM) {
+    if (p->state_norm < 0.0) return fail(TDSE_ESTATE, "no guard check has run");
+    *value = p->state_norm;
+    return TDSE_OK;
+  }
   if (key == TDSE_Q_PATH) {
     *value = p->run1d ? 1.0 : (p->persist && p->persist_on) ? 2.0 : 0.0;
     return TDSE_OK;
@@ -2909,6 +3032,19 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     const int axis = key - TDSE_Q_FS_H_AXIS;
     if (axis >= p->dim) return fail(TDSE_EINVAL, "axis out of range");
     *value = p->Hfx[p->dim == 2 ? axis : 1];
+    return TDSE_OK;
+  }
+  if ((key >= TDSE_Q_FS_HSTEP && key < TDSE_Q_FS_HSTEP + 2) || (key >= TDSE_Q_FS_NU && key < TDSE_Q_FS_NU + 2) ||
+      (key >= TDSE_Q_FS_K && key < TDSE_Q_FS_K + 2)) {
+    if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");
+    const int base = key < TDSE_Q_FS_NU ? TDSE_Q_FS_HSTEP : key < TDSE_Q_FS_K ? TDSE_Q_FS_NU : TDSE_Q_FS_K;
+    const int axis = key - base;
+    if (axis >= p->dim) return fail(TDSE_EINVAL, "axis out of range");
+    const int fa = p->dim == 2 ? axis : 1;
+    const tdse_plan_s::FAxis& F = p->fx[fa];
+    if (base == TDSE_Q_FS_HSTEP) *value = F.h;
+    else if (base == TDSE_Q_FS_NU) *value = F.nu;
+    else *value = p->Hfx[fa] + (2.0 * 7 + F.NE - 1) * F.h;   // the last equispaced node is K - kappa h (kappa = 7)
     return TDSE_OK;
   }
   if ((key >= TDSE_Q_FS_MODES && key < TDSE_Q_FS_MODES + 2) || (key >= TDSE_Q_FS_NE && key < TDSE_Q_FS_NE + 2)) {
@@ -2983,6 +3119,12 @@ int tdse_configure(tdse_plan_t p, int32_t key, int32_t value) {
     if (value != 0 && value != 1) return fail(TDSE_EINVAL, "TDSE_CFG_PERSISTENT takes 0 or 1");
     if (p->cur > 0 && p->cur < p->nsteps) return fail(TDSE_ESTATE, "change the step path before or after a run");
     p->persist_on = value != 0;
+    p->drop_graph();
+    return TDSE_OK;
+  }
+  if (key == TDSE_CFG_GUARD) {
+    if (value < 0) return fail(TDSE_EINVAL, "TDSE_CFG_GUARD takes a step count >= 0");
+    p->guard_every = value;
     p->drop_graph();
     return TDSE_OK;
   }

@@ -289,6 +289,15 @@ size_t persist2d_lds_bytes(int N, int order);
 int persist2d_capacity(int N, int order, bool ph2);   // co-resident workgroups the device holds
 hipError_t launch_persist2d(const Persist2DArgs& a, hipStream_t s);
 
+// Diagnostics (diag_kernels.hip).  acc: two doubles, flag: one word, both
+// cleared by the launch (the guard: unless clear is false, to accumulate
+// several arrays).  Guard: acc[0] += sum x_i^2 over n doubles, flag set if one
+// is not finite.  Difference: acc[0] += sum |a - b|^2, acc[1] += sum |b|^2
+// over n complex entries, a complex64 (a32) or complex128 (a64).
+hipError_t launch_guard(const double* x, int64_t n, double* acc, unsigned* flag, bool clear, hipStream_t s);
+hipError_t launch_diffnorm(const float2* a32, const double2* a64, const double2* b, int64_t n, double* acc,
+                           unsigned* flag, hipStream_t s);
+
 // Launchers (periodic_kernels.hip).  Non-null events e0/e1 are recorded at
 // the kernel's own start and end.  Return a hipError_t.
 hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,

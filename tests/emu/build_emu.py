@@ -12,6 +12,7 @@ SOURCES = [os.path.join(CSRC, "periodic_kernels.hip"), os.path.join(CSRC, "frees
            os.path.join(CSRC, "batch_fp64.hip"), os.path.join(CSRC, "batch_split.hip"),
            os.path.join(CSRC, "adjoint_kernels.hip"), os.path.join(CSRC, "far_kernels.hip"),
            os.path.join(CSRC, "run1d_kernels.hip"), os.path.join(CSRC, "persist2d_kernels.hip"),
+           os.path.join(CSRC, "diag_kernels.hip"),
            os.path.join(CSRC, "tdse_api.cpp"),
            os.path.join(HERE, "emu_globals.cpp")]
 

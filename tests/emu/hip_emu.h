@@ -310,6 +310,17 @@ inline void __builtin_amdgcn_raw_buffer_store_b128(emu_u32x4 x, __amdgpu_buffer_
   if (off + soff >= 0 && off + soff + 16 <= r.bytes) std::memcpy(r.base + off + soff, &x, 16);
   else std::abort();
 }
+inline double atomicAdd(double* p, double v) {
+  const double old = *p;
+  *p = old + v;
+  return old;
+}
+inline unsigned atomicOr(unsigned* p, unsigned v) {
+  const unsigned old = *p;
+  *p = old | v;
+  return old;
+}
+using std::isfinite;
 #define __HIP_MEMORY_SCOPE_WORKGROUP 2
 #define __HIP_MEMORY_SCOPE_AGENT 3
 template <typename T>
