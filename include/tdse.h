@@ -221,9 +221,9 @@ int tdse_far_eval_noalloc(tdse_plan_t plan, const double* xs, int32_t nx, const 
 #define TDSE_Q_FS_MODES       81  /* + axis: complex-frequency modes N_axis     */
 #define TDSE_Q_FS_NE          83  /* + axis: equispaced nodes per ray N_E      */
 #define TDSE_Q_FS_H_AXIS      86  /* + axis: contour parameter H of that axis   */
-#define TDSE_Q_FS_HSTEP       88  /* + axis: node spacing h = pi M / nu           */
-#define TDSE_Q_FS_NU          90  /* + axis: FFT size nu                          */
-#define TDSE_Q_FS_K           92  /* + axis: truncation K of Gamma_K (the last equispaced node is K - kappa h) */
+#define TDSE_Q_FS_HSTEP      128  /* + axis: node spacing h = pi M / nu           */
+#define TDSE_Q_FS_NU         130  /* + axis: FFT size nu                          */
+#define TDSE_Q_FS_K          132  /* + axis: truncation K of Gamma_K (the last equispaced node is K - kappa h) */
 #define TDSE_Q_ALPERT_X       96  /* + k: Alpert node x_k (units of h), k < p   */
 #define TDSE_Q_ALPERT_W      112  /* + k: Alpert weight w_k, k < p              */
 #define TDSE_Q_INSTANCES       4  /* batch: number of instances                 */

@@ -69,9 +69,9 @@ def test_free_space_parameter_queries(emu):
     prob = free_problem_from_seed(5, 2, (24, 32), 0.04, 9, nu=(256, 512), eps=1e-11, q=6, panels=2)
     plan = EmuPlan(emu, prob)
     for a, (M, nu) in enumerate(zip(prob.M, prob.nu)):
-        h = plan.query(88 + a)
+        h = plan.query(128 + a)
         assert h == pytest.approx(np.pi * M / nu, rel=1e-15)
-        assert plan.query(90 + a) == nu
+        assert plan.query(130 + a) == nu
         NE, H = plan.query(83 + a), plan.query(86 + a)
         assert NE == nu // 2 - 13
-        assert plan.query(92 + a) == pytest.approx(H + (14 + NE - 1) * h, rel=1e-15)
+        assert plan.query(132 + a) == pytest.approx(H + (14 + NE - 1) * h, rel=1e-15)
