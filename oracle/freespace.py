@@ -6,6 +6,10 @@ Transforms are dense (no FFT), axis by axis:
   forward  (eq. (fzdft)):     fhat(zeta_k) = (2/M) sum_j exp(-i zeta_k x_j) f(x_j)
   inverse  (eq. (uciftdisc)): u(x_j) = (1/2pi) sum_k w_k exp(i zeta_k x_j) uhat(zeta_k)
 on the grid x_j = -1 + 2 j / M and the Gamma nodes of ``quadrature.gamma_rule``.
+The C-type block (nodes on Gamma_2) goes through the Chebyshev interpolant of
+``chebyshev`` (Section 4.1) when the problem asks for it or when it has fewer
+terms than Gamma_2 has nodes; in 2D the two axes' transforms compose, which
+is the (C,E) and (C,C) forms of Section 4.2 with the sums in tensor order.
 Propagator over [t_a, t_b] (Lemma 3.1, eq. (uhatzinteq)):
   P = exp(-i (zeta . zeta)(t_b - t_a) + i zeta . (phi(t_b) - phi(t_a))).
 Order-2 sub-step (eqs. (uhatzfd), (utrapzfd)) carries (u, uhat):
@@ -24,6 +28,7 @@ from typing import Optional
 import numpy as np
 
 from .adams import adams_coefficients, richardson_extrapolate
+from .chebyshev import c_forward, c_inverse, choose_NT
 from .periodic import make_phi
 from .quadrature import choose_H, gamma_rule
 
@@ -60,6 +65,10 @@ class FreeSpaceOracle:
             self.nodes.append((zeta, w, info))
             self.G.append((2.0 / self.shape[a]) * np.exp(-1j * np.outer(zeta, x)))
             self.Ginv.append((w[None, :] / (2 * np.pi)) * np.exp(1j * np.outer(x, zeta)))
+        # C-type transforms (Section 4.1): direct sums, or through the
+        # Chebyshev interpolant of eqs. (expintrpm)/(expintrpp) with NT terms
+        # per axis (prob.cheb: 0 automatic, NT < N_C; -1 direct; n > 0 forced)
+        self.NT = [self._cheb_terms(a) for a in range(self.d)]
         Z = np.meshgrid(*[n[0] for n in self.nodes], indexing="ij")
         self.Z = Z
         self.Z2 = sum(z * z for z in Z)
@@ -78,17 +87,52 @@ class FreeSpaceOracle:
             phimax = np.maximum(phimax, np.abs(np.asarray(self.phi(t), dtype=np.float64)))
         return [choose_H(p.eps, normV, float(phimax[a]), self.d) for a in range(self.d)]
 
+    def _cheb_terms(self, a: int) -> int:
+        mode = int(getattr(self.prob, "cheb", 0))
+        NC = self.nodes[a][2]["NC"]
+        if mode < 0:
+            return 0
+        if mode > 0:
+            return mode
+        NT = choose_NT(self.Hs[a])
+        return NT if NT < NC else 0
+
+    def _c_block(self, a: int) -> slice:
+        info = self.nodes[a][2]
+        return slice(info["NE"] + info["p"], info["NE"] + info["p"] + info["NC"])
+
     # --- transforms ----------------------------------------------------------
+    def _fwd_axis(self, a: int, f: np.ndarray) -> np.ndarray:
+        """Transform along axis 0 of f (grid of axis a) to the nodes of axis a;
+        the C-type rows by the interpolant when it is on (Section 4.1)."""
+        out = np.tensordot(self.G[a], f, axes=(1, 0))
+        if self.NT[a]:
+            c = self._c_block(a)
+            tau_c = self.nodes[a][0][c].real
+            out[c] = (2.0 / self.shape[a]) * c_forward(f, self.xs[a], tau_c, self.Hs[a], self.NT[a])
+        return out
+
+    def _inv_axis(self, a: int, g: np.ndarray) -> np.ndarray:
+        if not self.NT[a]:
+            return np.tensordot(self.Ginv[a], g, axes=(1, 0))
+        c = self._c_block(a)
+        keep = np.ones(g.shape[0], dtype=bool)
+        keep[c] = False
+        out = np.tensordot(self.Ginv[a][:, keep], g[keep], axes=(1, 0))
+        zeta, w, _ = self.nodes[a]
+        wc = (w[c] / (2 * np.pi)).reshape((-1,) + (1,) * (g.ndim - 1))
+        return out + c_inverse(wc * g[c], self.xs[a], zeta[c].real, self.Hs[a], self.NT[a])
+
     def F(self, f: np.ndarray) -> np.ndarray:
         out = f
         for a in range(self.d):
-            out = np.moveaxis(np.tensordot(self.G[a], np.moveaxis(out, a, 0), axes=(1, 0)), 0, a)
+            out = np.moveaxis(self._fwd_axis(a, np.moveaxis(out, a, 0)), 0, a)
         return out
 
     def Finv(self, g: np.ndarray) -> np.ndarray:
         out = g
         for a in range(self.d):
-            out = np.moveaxis(np.tensordot(self.Ginv[a], np.moveaxis(out, a, 0), axes=(1, 0)), 0, a)
+            out = np.moveaxis(self._inv_axis(a, np.moveaxis(out, a, 0)), 0, a)
         return out
 
     def evaluate(self, uhat: np.ndarray, points) -> np.ndarray:

@@ -57,6 +57,7 @@ class Problem:
     q: int = 10
     panels: int = 1
     nu: Tuple[int, ...] = ()
+    cheb: int = 0                    # C-type transforms: 0 automatic, -1 direct sums, n > 0 interpolant of n terms
     # potential kind: "fields" (V_fields with time factors) or "moving_well"
     # with V_well = (V0, beta, c_0[, c_1]) (Example 1 of Section 6)
     V_kind: str = "fields"
