@@ -114,6 +114,18 @@ typedef struct {
   /* potential kind (TDSE_V_*; 0 = stored fields) and its parameters */
   int32_t V_kind;
   double  V_params[4];
+  /* free space: the C-type transforms on Gamma_2 (Section 4.1).  Either
+   * direct sums over the N_C = 2 q panels Gauss nodes, or the Chebyshev
+   * interpolant of eqs. (expintrpm)/(expintrpp) on [-H, H] with NT terms,
+   * which costs O(M NT + NT N_C) per line instead of O(M N_C).  The library
+   * evaluates the interpolant through its values at the NT Chebyshev points of
+   * the first kind (the same polynomial as the paper's coefficient form).
+   * 0: automatic: the interpolant when its NT < N_C, NT the smallest count
+   *    with 4 sum_{l >= NT} I_l(sqrt(2) H) <= 2^-52 (exact to rounding);
+   * -1: direct sums; 2..64: the interpolant with that many terms.
+   * In 2D the axes' transforms compose, which gives the (C,E) and (C,C)
+   * subsets of Section 4.2 with the sums in tensor order. */
+  int32_t cheb;
 } tdse_problem_t;
 
 typedef struct tdse_plan_s* tdse_plan_t;   /* opaque, owned by the library  */
@@ -224,6 +236,7 @@ int tdse_far_eval_noalloc(tdse_plan_t plan, const double* xs, int32_t nx, const 
 #define TDSE_Q_FS_HSTEP      128  /* + axis: node spacing h = pi M / nu           */
 #define TDSE_Q_FS_NU         130  /* + axis: FFT size nu                          */
 #define TDSE_Q_FS_K          132  /* + axis: truncation K of Gamma_K (the last equispaced node is K - kappa h) */
+#define TDSE_Q_FS_CHEB       134  /* + axis: terms NT of the C-type Chebyshev interpolant (0: direct sums) */
 #define TDSE_Q_ALPERT_X       96  /* + k: Alpert node x_k (units of h), k < p   */
 #define TDSE_Q_ALPERT_W      112  /* + k: Alpert weight w_k, k < p              */
 #define TDSE_Q_INSTANCES       4  /* batch: number of instances                 */

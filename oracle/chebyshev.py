@@ -47,13 +47,14 @@ def cheb_T(NT: int, s: np.ndarray) -> np.ndarray:
 
 
 def choose_NT(H: float) -> int:
-    """Smallest NT with 4 sum_{l >= NT} I_l(sqrt(2) H) <= 2^-52 (see the reading above)."""
+    """Smallest NT with 4 sum_{l >= NT} I_l(sqrt(2) H) <= 2^-52 (see the reading
+    above); 0 if that takes more than NT_MAX terms (direct sums then)."""
     r = np.sqrt(2.0) * H
     for n in range(2, NT_MAX + 1):
         tail = 4.0 * sum(iv(l, r) for l in range(n, n + 60))
         if tail <= TOL:
             return n
-    raise ValueError(f"H = {H}: the Chebyshev interpolant needs more than {NT_MAX} terms")
+    return 0
 
 
 def interp_coeffs(values: np.ndarray) -> np.ndarray:

@@ -95,7 +95,7 @@ class FreeSpaceOracle:
         if mode > 0:
             return mode
         NT = choose_NT(self.Hs[a])
-        return NT if NT < NC else 0
+        return NT if 0 < NT < NC else 0
 
     def _c_block(self, a: int) -> slice:
         info = self.nodes[a][2]

@@ -86,8 +86,9 @@ __device__ __forceinline__ typename fs_tw<NU>::type stage_twiddles(const CFAxis&
   return typename fs_tw<NU>::type{tws, tws + NC};
 }
 
-// forward transform of f[0..M) (LDS); ends with dm complete (a barrier)
-template <int NU>
+// forward transform of f[0..M) (LDS); ends with dm complete (a barrier).
+// CH: the C-type block through the interpolant (ax.NT > 0).
+template <int NU, bool CH>
 __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY], double2 (&v1)[RAY], double2* dm,
                                            double2* part, double2* fline, double2* fline2, const CFAxis& ax,
                                            const typename fs_tw<NU>::type& tw, int t) {
@@ -113,13 +114,15 @@ __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY],
     const double2 y = cmul(ax.post1[min(e, NE - 1)], w1[m]);
     v1[m] = e < NE ? y : double2{0.0, 0.0};
   }
-  // dense modes: thread (q, c) sums the contiguous chunk j0 <= j < j0 + L of
+  // dense rows: thread (q, c) sums the contiguous chunk j0 <= j < j0 + L of
   // the row q of Dfwd.  Entries along a row form a geometric sequence
   // (equispaced x_j), so the chunk is Dfwd[q][j0] times a Horner sum in the
   // ratio rfwd[q]: two table reads per chunk, L LDS reads.
-  const int C = TL / ND > 1 ? TL / ND : 1;
+  const int NR = CH ? ax.NR : ND;
+  double2* dr = CH ? dm + ND : dm;   // the rows' sums (the modes themselves without the interpolant)
+  const int C = TL / NR > 1 ? TL / NR : 1;
   const int L = (M + C - 1) / C;
-  for (int i = t; i < ND * C; i += TL) {   // more dense modes than threads: several pairs per thread
+  for (int i = t; i < NR * C; i += TL) {   // more dense rows than threads: several pairs per thread
     const int q = i / C, c = i - q * C;
     const int j0 = c * L, j1 = min(j0 + L, M);
     double2 acc = {0.0, 0.0};
@@ -132,24 +135,79 @@ __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY],
     part[i] = acc;
   }
   __syncthreads();
-  for (int q = t; q < ND; q += TL) {
+  for (int q = t; q < NR; q += TL) {
     double2 acc = {0.0, 0.0};
     for (int c = 0; c < C; ++c) acc = cadd(acc, part[q * C + c]);
-    dm[q] = acc;
+    dr[q] = acc;
   }
   __syncthreads();
+  if (CH) {
+    // C-modes from the transform's values at the interpolation nodes
+    // (Section 4.1, eq. (expintrpm) in the form of its values): the Alpert
+    // rows are modes already
+    const int P = ax.NP, NT = ax.NT, NC = ND - 2 * P;
+    for (int q = t; q < ND; q += TL) {
+      double2 v;
+      if (q < P) {
+        v = dr[q];
+      } else if (q >= P + NC) {
+        v = dr[q - NC + NT];
+      } else {
+        const double* __restrict__ pr = ax.Pf + (int64_t)(q - P) * NT;
+        v = double2{0.0, 0.0};
+        for (int m = 0; m < NT; ++m) {
+          const double w = pr[m];
+          const double2 x = dr[P + m];
+          v.x += w * x.x;
+          v.y += w * x.y;
+        }
+      }
+      dm[q] = v;
+    }
+    __syncthreads();
+  }
 }
 
 // inverse transform of the modes (v3, v1 registers, dm LDS) into u[0..M)
 // (LDS); thread t writes u[t + TL m] only, so it may read those entries back
 // without a barrier
-template <int NU>
-__device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const double2 (&v1)[RAY], const double2* dm,
+template <int NU, bool CH>
+__device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const double2 (&v1)[RAY], double2* dm,
                                            double2* fline, double2* fline2, const CFAxis& ax,
                                            const typename fs_tw<NU>::type& tw, int t, double2* u) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
-  const int M = ax.M, NE = ax.NE, ND = ax.ND;
+  const int M = ax.M, NE = ax.NE, ND = ax.ND, NR = CH ? ax.NR : ND;
+  const double2* drow = dm;   // the dense rows' coefficients
+  if (CH) {
+    // contract the C-modes onto the interpolation nodes (eq. (expintrpp) in
+    // the form of its values), split over (node, chunk) pairs and reduced
+    // through the second exchange line before the FFTs take it
+    const int P = ax.NP, NT = ax.NT, NC = ND - 2 * P;
+    double2* dv = dm + ND;
+    const int C = TL / NR > 1 ? TL / NR : 1;
+    const int L = (NC + C - 1) / C;
+    for (int i = t; i < NR * C; i += TL) {
+      const int r = i / C, c = i - r * C;
+      double2 acc = {0.0, 0.0};
+      if (r < P || r >= P + NT) {
+        if (c == 0) acc = dm[r < P ? r : r - NT + NC];
+      } else {
+        const double2* __restrict__ pr = ax.Pi + (int64_t)(r - P) * NC;
+        const int k1 = min(c * L + L, NC);
+        for (int k = c * L; k < k1; ++k) acc = cadd(acc, cmul(pr[k], dm[P + k]));
+      }
+      fline2[i] = acc;
+    }
+    __syncthreads();
+    for (int r = t; r < NR; r += TL) {
+      double2 acc = {0.0, 0.0};
+      for (int c = 0; c < C; ++c) acc = cadd(acc, fline2[r * C + c]);
+      dv[r] = acc;
+    }
+    __syncthreads();
+    drow = dv;
+  }
   double2 w[EPT], w1[EPT];
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
@@ -170,20 +228,20 @@ __device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const doubl
     const int e = t + TL * m;
     if (e < M) u[e] = cmul(ax.ipost3[e], w[m]);
   }
-  // E1 part, then the dense modes in batches of DB matrix entries
+  // E1 part, then the dense rows in batches of DB matrix entries
   constexpr int DB = 18;
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     const int e = t + TL * m;
     if (e < M) {
       double2 s = cadd(u[e], cmul(ax.ipost1[e], w1[m]));
-      for (int q0 = 0; q0 < ND; q0 += DB) {
+      for (int q0 = 0; q0 < NR; q0 += DB) {
         double2 d[DB];
 #pragma unroll
-        for (int u8 = 0; u8 < DB; ++u8) d[u8] = ax.Dinv[(int64_t)min(q0 + u8, ND - 1) * M + e];
+        for (int u8 = 0; u8 < DB; ++u8) d[u8] = ax.Dinv[(int64_t)min(q0 + u8, NR - 1) * M + e];
 #pragma unroll
         for (int u8 = 0; u8 < DB; ++u8) {
-          if (q0 + u8 < ND) s = cadd(s, cmul(d[u8], dm[q0 + u8]));
+          if (q0 + u8 < NR) s = cadd(s, cmul(d[u8], drow[q0 + u8]));
         }
       }
       u[e] = s;
@@ -191,13 +249,15 @@ __device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const doubl
   }
 }
 
-// LDS of a line kernel: dynamic f[M] | first FFT exchange line | dm[ND] |
+// LDS of a line kernel: dynamic f[M] | first FFT exchange line | dense
+// block (dm[ND], then the node values dr[NR] with the interpolant) |
 // twiddles, and a static second exchange line that also holds the dense
-// partials.  At nu = 2048 with M = 256 that is 79.9 KB, two workgroups per CU.
+// partials.  At nu = 2048 with M = 256 and direct sums that is 79.9 KB, two
+// workgroups per CU.
 template <int NU>
-size_t fs_lds_bytes(int M, int ND) {
+size_t fs_lds_bytes(int M, int ndense) {
   return sizeof(double2) *
-         (size_t)(M + lds_line_len(NU) + ND + fs_tw<NU>::NC + fs_tw<NU>::NF);
+         (size_t)(M + lds_line_len(NU) + ndense + fs_tw<NU>::NC + fs_tw<NU>::NF);
 }
 
 // The per-mode step of the row pass for mode g = row_m + k; W is the mode of
@@ -251,7 +311,7 @@ __device__ __forceinline__ double2 fs_mode_update(const FSArgs& a, const double2
 // Two workgroups per CU with the full register budget: with the history
 // loads batched, spill traffic at a budget of 168 (three per CU) costs more
 // than the latency a third wave per SIMD hides.
-template <int NU>
+template <int NU, bool CH>
 __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fs_row(FSArgs a) {
   constexpr int TL = NU / 8;
   HIP_DYNAMIC_SHARED(double2, fs_lds)
@@ -262,7 +322,7 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   double2* fin = fs_lds;
   double2* fline = fin + M2;
   double2* dm = fline + lds_line_len(NU);
-  double2* tws = dm + ND;
+  double2* tws = dm + cf_dense_lds(ax);
   const int t = threadIdx.x;
   const int k1 = blockIdx.x;
   const auto tw = stage_twiddles<NU>(ax, tws, t);   // read after the first barrier below
@@ -276,7 +336,7 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   if (need_fwd) {
     for (int j = t; j < M2; j += TL) fin[j] = a.src[row_p + j];
     __syncthreads();
-    cf_forward<NU>(fin, v3, v1, dm, part, fline, fline2, ax, tw, t);
+    cf_forward<NU, CH>(fin, v3, v1, dm, part, fline, fline2, ax, tw, t);
   } else {
 #pragma unroll
     for (int m = 0; m < RAY; ++m) v3[m] = v1[m] = double2{0.0, 0.0};
@@ -419,7 +479,7 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   }
   if (mode == R_UHACC) return;
   __syncthreads();
-  cf_inverse<NU>(v3, v1, dm, fline, fline2, ax, tw, t, fin);   // the forward input is no longer needed
+  cf_inverse<NU, CH>(v3, v1, dm, fline, fline2, ax, tw, t, fin);   // the forward input is no longer needed
   for (int e = t; e < M2; e += TL) a.dst[row_p + e] = fin[e];
 }
 
@@ -433,7 +493,7 @@ __device__ __forceinline__ int fs_col_of(int b, int nb) {
   return 8 * ((s / 8) * 8 + x) + (s % 8);
 }
 
-template <int NU>
+template <int NU, bool CH>
 __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
@@ -446,7 +506,7 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
   double2* fin = fs_lds;
   double2* fline = fin + M1;
   double2* dm = fline + lds_line_len(NU);
-  double2* tws = dm + ND;
+  double2* tws = dm + cf_dense_lds(ax);
   const int t = threadIdx.x;
   const int y = fs_col_of(blockIdx.x, gridDim.x);   // physical column (axis 1)
   const auto tw = stage_twiddles<NU>(ax, tws, t);   // read after the first barrier below
@@ -463,7 +523,7 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
     }
     for (int q = t; q < ND; q += TL) dm[q] = a.src[(int64_t)(NE + q) * M2 + y];
     __syncthreads();
-    cf_inverse<NU>(v3, v1, dm, fline, fline2, ax, tw, t, fin);   // w = F^-1 B on the column, in place of the forward input
+    cf_inverse<NU, CH>(v3, v1, dm, fline, fline2, ax, tw, t, fin);   // w = F^-1 B on the column, in place of the forward input
 #pragma unroll
     for (int m = 0; m < EPT; ++m) {
       const int e = t + TL * m;
@@ -496,7 +556,7 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
     }
   }
   __syncthreads();
-  cf_forward<NU>(fin, v3, v1, dm, part, fline, fline2, ax, tw, t);
+  cf_forward<NU, CH>(fin, v3, v1, dm, part, fline, fline2, ax, tw, t);
 #pragma unroll
   for (int m = 0; m < RAY; ++m) {
     const int e = t + TL * m;
@@ -569,11 +629,9 @@ bool fs_nu_supported(int nu) {
   }
 }
 
-int fs_max_modes(int nu) { return nu + 64; }
-
-size_t fs_line_lds_bytes(int nu, int M, int ND) {
+size_t fs_line_lds_bytes(int nu, int M, int ndense) {
   switch (nu) {
-#define X(n) case n: return fs_lds_bytes<n>(M, ND);
+#define X(n) case n: return fs_lds_bytes<n>(M, ndense);
     TDSE_FS_NU(X)
 #undef X
     default:
@@ -585,7 +643,10 @@ hipError_t launch_fs_row(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0, 
   switch (nu) {
 #define X(n)                                                                              \
   case n:                                                                                 \
-    TDSE_FS_LAUNCH_SH((k_fs_row<n>), dim3(a.N1), dim3(n / 8), fs_lds_bytes<n>(a.ax2.M, a.ax2.ND), s, e0, e1, a); \
+    if (a.ax2.NT)                                                                         \
+      TDSE_FS_LAUNCH_SH((k_fs_row<n, true>), dim3(a.N1), dim3(n / 8), fs_lds_bytes<n>(a.ax2.M, cf_dense_lds(a.ax2)), s, e0, e1, a); \
+    else                                                                                  \
+      TDSE_FS_LAUNCH_SH((k_fs_row<n, false>), dim3(a.N1), dim3(n / 8), fs_lds_bytes<n>(a.ax2.M, cf_dense_lds(a.ax2)), s, e0, e1, a); \
     break;
     TDSE_FS_NU(X)
 #undef X
@@ -605,7 +666,10 @@ hipError_t launch_fs_col(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0, 
   switch (nu) {
 #define X(n)                                                                              \
   case n:                                                                                 \
-    TDSE_FS_LAUNCH_SH((k_fs_col<n>), dim3(a.ax2.M), dim3(n / 8), fs_lds_bytes<n>(a.ax1.M, a.ax1.ND), s, e0, e1, a); \
+    if (a.ax1.NT)                                                                         \
+      TDSE_FS_LAUNCH_SH((k_fs_col<n, true>), dim3(a.ax2.M), dim3(n / 8), fs_lds_bytes<n>(a.ax1.M, cf_dense_lds(a.ax1)), s, e0, e1, a); \
+    else                                                                                  \
+      TDSE_FS_LAUNCH_SH((k_fs_col<n, false>), dim3(a.ax2.M), dim3(n / 8), fs_lds_bytes<n>(a.ax1.M, cf_dense_lds(a.ax1)), s, e0, e1, a); \
     break;
     TDSE_FS_NU(X)
 #undef X

@@ -299,10 +299,12 @@ struct tdse_plan_s {
   std::vector<double> alp_x, alp_w;   // Alpert end correction, units of h
   struct FAxis {
     int M = 1, N = 1, NE = 0, ND = 0, nu = 0;
+    int NT = 0, NR = 0, NP = 0;        // interpolation nodes (0: direct C sums), dense rows, Alpert nodes per side
     double h = 0.0;
     std::vector<double2> zeta, w;      // nodes and weights, order E1 A1 C A3 E3
     std::vector<char> tables;          // pre3 pre1 ipost3 ipost1 [M], post3 post1 ipre3 ipre1 [NE],
-                                       // Dfwd [ND][M], Dinv [ND][M], tw [nu], zeta [N]
+                                       // Dfwd [NR][M], Dinv [NR][M], tw [nu], zeta [N], rfwd [NR],
+                                       // w [N], Pf [N_C][NT], Pi [NT][N_C]
     size_t o_tab = 0;                  // workspace offset of the tables
   } fx[2];
   int64_t NM = 1;                      // modes N1 N2
@@ -846,8 +848,37 @@ inline double2 cexp_ld(long double re, long double im) {
   return double2{(double)(m * std::cos(im)), (double)(m * std::sin(im))};
 }
 
+// Terms of the Chebyshev interpolant of tau -> exp(-/+ (1 + i) tau x) on
+// [-H, H], |x| <= 1 (Section 4.1, eqs. (expintrpm), (expintrpp)).  Its
+// Chebyshev coefficients are 2 I_l(z) with |z| <= sqrt(2) H and
+// |I_l(z)| <= I_l(|z|); interpolation at most doubles the tail, so NT is the
+// smallest count with 4 sum_{l >= NT} I_l(sqrt(2) H) <= 2^-52: the
+// interpolant is exact to rounding.  I_l by its power series in long double.
+int cheb_terms(double H) {
+  typedef long double LD;
+  const LD r = std::sqrt(2.0L) * (LD)H, h2 = r * r / 4.0L;
+  auto bessel_i = [&](int l) {
+    LD lead = 1.0L;   // (r/2)^l / l!
+    for (int k = 1; k <= l; ++k) lead *= (r / 2.0L) / (LD)k;
+    LD term = lead, sum = lead;
+    for (int m = 1; m < 400 && term > 1e-40L * sum; ++m) {
+      term *= h2 / ((LD)m * (LD)(l + m));
+      sum += term;
+    }
+    return sum;
+  };
+  for (int n = 2; n <= FS_CHEB_MAX; ++n) {
+    LD tail = 0.0L;
+    for (int l = n; l < n + 60; ++l) tail += bessel_i(l);
+    if (4.0L * tail <= std::ldexp(1.0L, -52)) return n;
+  }
+  return 0;   // more than FS_CHEB_MAX terms
+}
+
 // Nodes, weights and transform tables of one axis (Sections 3.4 and 4.1).
-void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels) {
+// cheb: 0 automatic (the interpolant when it has fewer terms than Gamma_2 has
+// nodes), -1 direct C sums, n > 0 the interpolant with n terms.
+void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels, int cheb) {
   typedef long double LD;
   tdse_plan_s::FAxis& F = p->fx[axis];
   const int kappa = 7, pp = (int)p->alp_x.size();
@@ -901,8 +932,57 @@ void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels) 
     F.zeta[im] = double2{(double)-tc[k], (double)tc[k]};
     F.w[im] = double2{(double)wc[k], (double)-wc[k]};
   }
+  // C-type block: direct sums, or the interpolant through NT nodes
+  const int NC = 2 * half;
+  F.NP = pp;
+  F.NT = 0;
+  if (cheb > 0) {
+    F.NT = cheb;
+  } else if (cheb == 0) {
+    const int nt = cheb_terms((double)H);
+    F.NT = (nt > 0 && nt < NC) ? nt : 0;
+  }
+  F.NR = F.NT ? 2 * pp + F.NT : F.ND;
+  // dense rows r: A1 nodes, interpolation nodes (1 - i) H s_m (s_m the
+  // Chebyshev points of the first kind), A3 nodes; without the interpolant
+  // every dense mode is a row
+  std::vector<double2> rz(F.NR), rw(F.NR);
+  std::vector<LD> sm(F.NT);
+  for (int r = 0; r < F.NR; ++r) {
+    if (!F.NT || r < pp) {
+      rz[r] = F.zeta[F.NE + r];
+      rw[r] = F.w[F.NE + r];
+    } else if (r >= pp + F.NT) {
+      rz[r] = F.zeta[F.NE + r - F.NT + NC];
+      rw[r] = F.w[F.NE + r - F.NT + NC];
+    } else {
+      const int m = r - pp;
+      sm[m] = std::cos(PI * ((LD)m + 0.5L) / (LD)F.NT);
+      rz[r] = double2{(double)(H * sm[m]), (double)(-H * sm[m])};
+      rw[r] = double2{2.0 * PI, 0.0};   // no weight: 2 pi cancels the inverse's 1/(2 pi)
+    }
+  }
+  // P[k][m] = (1/NT) sum_l c_l T_l(tau_k / H) T_l(s_m), c_0 = 1, c_l = 2: the
+  // interpolant's value at the C-node tau_k from its values at the nodes
+  std::vector<double2> Pf((size_t)(NC * F.NT + 1) / 2), Pi((size_t)F.NT * NC);
+  for (int k = 0; k < NC && F.NT; ++k) {
+    const LD sk = (LD)F.zeta[F.NE + pp + k].x / H;
+    for (int m = 0; m < F.NT; ++m) {
+      LD t0a = 1.0L, t1a = sk, t0b = 1.0L, t1b = sm[m];
+      LD acc = 1.0L;
+      for (int l = 1; l < F.NT; ++l) {
+        acc += 2.0L * t1a * t1b;
+        const LD t2a = 2.0L * sk * t1a - t0a, t2b = 2.0L * sm[m] * t1b - t0b;
+        t0a = t1a; t1a = t2a; t0b = t1b; t1b = t2b;
+      }
+      const LD P = acc / (LD)F.NT;
+      ((double*)Pf.data())[(size_t)k * F.NT + m] = (double)P;
+      const double2 wk = F.w[F.NE + pp + k];
+      Pi[(size_t)m * NC + k] = double2{(double)(P * (LD)wk.x / (2.0L * PI)), (double)(P * (LD)wk.y / (2.0L * PI))};
+    }
+  }
   // transform tables
-  const int NE = F.NE, ND = F.ND;
+  const int NE = F.NE, ND = F.NR;
   const LD alpha = H + kappa * h;
   const LD s2M = 2.0L / (LD)M;
   std::vector<double2> pre3(M), pre1(M), ipost3(M), ipost1(M), post3(NE), post1(NE), ipre3(NE), ipre1(NE);
@@ -926,7 +1006,7 @@ void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels) 
     ipre1[e] = double2{(double)(wf * b1.x), (double)(wf * b1.y)};
   }
   for (int q2 = 0; q2 < ND; ++q2) {
-    const double2 zz = F.zeta[NE + q2], ww = F.w[NE + q2];
+    const double2 zz = rz[q2], ww = rw[q2];
     for (int j = 0; j < M; ++j) {
       const LD x = -1.0L + 2.0L * j / (LD)M;
       // exp(-i zeta x) = exp(Im(zeta) x) exp(-i Re(zeta) x)
@@ -944,18 +1024,18 @@ void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels) 
   // ratio of consecutive forward dense entries: Dfwd[q][j+1] = Dfwd[q][j] exp(-i zeta_q 2/M)
   std::vector<double2> rfwd(ND);
   for (int q2 = 0; q2 < ND; ++q2) {
-    const double2 zz = F.zeta[NE + q2];
+    const double2 zz = rz[q2];
     rfwd[q2] = cexp_ld((LD)zz.y * 2.0L / (LD)M, -(LD)zz.x * 2.0L / (LD)M);
   }
   std::vector<double2> wv(F.w);
-  std::vector<std::vector<double2>*> parts = {&pre3, &pre1, &ipost3, &ipost1, &post3, &post1, &ipre3,
-                                              &ipre1, &Dfwd, &Dinv, &twt, &z, &rfwd, &wv};
+  std::vector<std::vector<double2>*> parts = {&pre3, &pre1, &ipost3, &ipost1, &post3, &post1, &ipre3, &ipre1,
+                                              &Dfwd, &Dinv, &twt, &z, &rfwd, &wv, &Pf, &Pi};
   size_t bytes = 0;
   for (auto* v : parts) bytes = align256(bytes + v->size() * sizeof(double2));
   F.tables.assign(bytes, 0);
   size_t off = 0;
   for (auto* v : parts) {
-    std::memcpy(F.tables.data() + off, v->data(), v->size() * sizeof(double2));
+    if (!v->empty()) std::memcpy(F.tables.data() + off, v->data(), v->size() * sizeof(double2));
     off = align256(off + v->size() * sizeof(double2));
   }
 }
@@ -969,6 +1049,9 @@ CFAxis cf_axis(const tdse_plan_s* p, int axis) {
   c.N = F.N;
   c.NE = F.NE;
   c.ND = F.ND;
+  c.NR = F.NR;
+  c.NT = F.NT;
+  c.NP = F.NP;
   if (F.nu == 0) {   // axis without transform (1D problem): one mode at zeta = 0
     c.zeta = (const double2*)(p->ws + F.o_tab);
     return c;
@@ -988,12 +1071,15 @@ CFAxis cf_axis(const tdse_plan_s* p, int axis) {
   c.post1 = take(F.NE);
   c.ipre3 = take(F.NE);
   c.ipre1 = take(F.NE);
-  c.Dfwd = take((size_t)F.ND * F.M);
-  c.Dinv = take((size_t)F.M * F.ND);
+  c.Dfwd = take((size_t)F.NR * F.M);
+  c.Dinv = take((size_t)F.M * F.NR);
   c.tw = take(F.nu);
   c.zeta = take(F.N);
-  c.rfwd = take(F.ND);
+  c.rfwd = take(F.NR);
   c.wq = take(F.N);
+  const int NC = F.ND - 2 * F.NP;
+  c.Pf = (const double*)take(((size_t)NC * F.NT + 1) / 2);
+  c.Pi = take((size_t)F.NT * NC);
   return c;
 }
 
@@ -1185,6 +1271,8 @@ int fs_step(tdse_plan_s* p, int m, bool write_u) {
 int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
   if (prob->p != 8) return fail(TDSE_EUNSUPPORTED, "free space supports the order-16 Alpert rule only (p = 8)");
   if (prob->q < 2 || prob->q > 32 || prob->panels < 1 || prob->panels > 8) return fail(TDSE_EINVAL, "need 2 <= q <= 32, 1 <= panels <= 8");
+  if (prob->cheb < -1 || prob->cheb == 1 || prob->cheb > FS_CHEB_MAX)
+    return fail(TDSE_EINVAL, "cheb must be -1 (direct), 0 (automatic) or 2..64 interpolation terms");
   if (!(prob->eps > 0.0 && prob->eps < 1.0) && !(prob->H > 0.0)) return fail(TDSE_EINVAL, "need 0 < eps < 1 or H > 0");
   p->free_space = true;
   alpert_rule(8, 7, p->alp_x, p->alp_w);
@@ -1232,11 +1320,17 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
     if (!fs_nu_supported(nu)) return fail(TDSE_EINVAL, "nu must be 256, 512, 1024 or 2048");
     const int NE = nu / 2 - 13;
     if (M < 8 || M % 2 || M > nu || NE <= M / 2) return fail(TDSE_EINVAL, "free space needs even M, M <= nu and N_E > M/2");
-    plan_free_axis(p, a, M, nu, prob->q, prob->panels);
+    plan_free_axis(p, a, M, nu, prob->q, prob->panels, prob->cheb);
     // the line kernels carry each ray in the first half of the nu-point FFT
     if (p->fx[a].NE >= nu / 2) return fail(TDSE_EINVAL, "ray modes must number fewer than nu/2");
-    if (p->fx[a].N > fs_max_modes(nu)) return fail(TDSE_EINVAL, "too many Gauss nodes for this nu (2p + 2 q panels > 90)");
-    if (fs_line_lds_bytes(nu, M, p->fx[a].ND) > 65536)
+    // the dense rows' partial sums share the second FFT exchange line
+    if (p->fx[a].NR > nu / 2)
+      return fail(TDSE_EINVAL, "more than nu/2 dense rows (2p + 2 q panels direct sums, or 2p + NT); use the interpolant or a larger nu");
+    tdse::CFAxis probe{};
+    probe.ND = p->fx[a].ND;
+    probe.NR = p->fx[a].NR;
+    probe.NT = p->fx[a].NT;
+    if (fs_line_lds_bytes(nu, M, tdse::cf_dense_lds(probe)) > 65536)
       return fail(TDSE_EINVAL, "free-space line needs more than 64 KiB of LDS (M too large for this nu)");
   }
   p->NM = (int64_t)p->fx[0].N * p->fx[1].N;
@@ -3035,15 +3129,19 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     return TDSE_OK;
   }
   if ((key >= TDSE_Q_FS_HSTEP && key < TDSE_Q_FS_HSTEP + 2) || (key >= TDSE_Q_FS_NU && key < TDSE_Q_FS_NU + 2) ||
-      (key >= TDSE_Q_FS_K && key < TDSE_Q_FS_K + 2)) {
+      (key >= TDSE_Q_FS_K && key < TDSE_Q_FS_K + 2) || (key >= TDSE_Q_FS_CHEB && key < TDSE_Q_FS_CHEB + 2)) {
     if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");
-    const int base = key < TDSE_Q_FS_NU ? TDSE_Q_FS_HSTEP : key < TDSE_Q_FS_K ? TDSE_Q_FS_NU : TDSE_Q_FS_K;
+    const int base = key < TDSE_Q_FS_NU ? TDSE_Q_FS_HSTEP
+                     : key < TDSE_Q_FS_K ? TDSE_Q_FS_NU
+                     : key < TDSE_Q_FS_CHEB ? TDSE_Q_FS_K
+                                            : TDSE_Q_FS_CHEB;
     const int axis = key - base;
     if (axis >= p->dim) return fail(TDSE_EINVAL, "axis out of range");
     const int fa = p->dim == 2 ? axis : 1;
     const tdse_plan_s::FAxis& F = p->fx[fa];
     if (base == TDSE_Q_FS_HSTEP) *value = F.h;
     else if (base == TDSE_Q_FS_NU) *value = F.nu;
+    else if (base == TDSE_Q_FS_CHEB) *value = F.NT;
     else *value = p->Hfx[fa] + (2.0 * 7 + F.NE - 1) * F.h;   // the last equispaced node is K - kappa h (kappa = 7)
     return TDSE_OK;
   }

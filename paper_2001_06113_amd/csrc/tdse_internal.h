@@ -7,6 +7,7 @@ namespace tdse {
 
 constexpr int MAXV = 8;   // spatial potential fields V_r
 constexpr int MAXH = 8;   // history terms of the implicit Adams rule (n - 1 <= 7)
+constexpr int FS_CHEB_MAX = 64;   // terms of the C-type Chebyshev interpolant
 
 // Pass kinds.  A "column" pass transforms along axis 0 (stride M2 in memory),
 // a "row" pass along the last axis (contiguous).
@@ -83,19 +84,31 @@ struct LineArgs {
 // One axis of the free-space complex-frequency transform (freespace_kernels.hip):
 // modes ordered E1 | A1 C A3 | E3 with N = 2 NE + ND.  All tables complex128,
 // device pointers into the plan's workspace.
+// With the C-type block through the Chebyshev interpolant (NT > 0), the
+// dense sums run over NR = 2p + NT rows: the A1 nodes, the NT interpolation
+// nodes (1 - i) H s_m on Gamma_2 and the A3 nodes; the N_C C-modes are the
+// interpolant's values, Pf (forward, [N_C][NT] real) expands the node values
+// into them and Pi (inverse, [NT][N_C], weights w/2pi folded in) contracts
+// them back onto the nodes.  NT = 0: NR = ND, every dense row is a mode.
 struct CFAxis {
   int M, N, NE, ND;             // grid points, modes, E-nodes per side, dense modes
+  int NR, NT, NP;               // dense rows, interpolation nodes (0: direct sums), Alpert nodes per side
   const double2 *pre3, *pre1;   // [M] forward pre-multipliers (E3, E1)
   const double2 *post3, *post1; // [NE] forward post-multipliers incl. 2/M
   const double2 *ipre3, *ipre1; // [NE] inverse pre-multipliers incl. w/(2 pi)
   const double2 *ipost3, *ipost1; // [M] inverse post-multipliers
-  const double2* Dfwd;          // [ND][M] (2/M) exp(-i zeta_q x_j)
-  const double2* Dinv;          // [ND][M] (w_q/2pi) exp(i zeta_q x_j)
+  const double2* Dfwd;          // [NR][M] (2/M) exp(-i zeta_r x_j)
+  const double2* Dinv;          // [NR][M] (w_r/2pi) exp(i zeta_r x_j) (interpolation rows: no weight)
   const double2* tw;            // nu-point twiddles
   const double2* zeta;          // [N] nodes (for the phase factors)
-  const double2* rfwd;          // [ND] exp(-i zeta_q 2/M): Dfwd[q][j+1] = Dfwd[q][j] rfwd[q]
+  const double2* rfwd;          // [NR] exp(-i zeta_r 2/M): Dfwd[r][j+1] = Dfwd[r][j] rfwd[r]
   const double2* wq;            // [N] quadrature weights of the nodes zeta
+  const double* Pf;             // [N_C][NT] interpolation from the nodes to the C-modes
+  const double2* Pi;            // [NT][N_C] its transpose times w_k / 2pi
 };
+// LDS entries of a line's dense block: the modes, and the node values when
+// the interpolant is on
+__host__ __device__ inline int cf_dense_lds(const CFAxis& ax) { return ax.ND + (ax.NT ? ax.NR : 0); }
 
 struct FSArgs {
   int mode;
@@ -206,8 +219,7 @@ hipError_t launch_fs_row(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0 =
 hipError_t launch_fs_col(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_fs_phase(const FSArgs& a, hipStream_t s);
 bool fs_nu_supported(int nu);
-int fs_max_modes(int nu);
-size_t fs_line_lds_bytes(int nu, int M, int ND);   // dynamic LDS of a line workgroup
+size_t fs_line_lds_bytes(int nu, int M, int ndense);   // dynamic LDS of a line workgroup (ndense: cf_dense_lds)
 
 // Evaluation of a free-space representation at arbitrary points (far_kernels.hip).
 // far_scratch: device address, on the current GPU, of the library-owned array

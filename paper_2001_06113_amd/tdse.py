@@ -23,7 +23,7 @@ Q_MU, Q_RICHARDSON, Q_PHI = 16, 32, 64
 Q_INSTANCES, Q_INST_OFFSET, Q_INST_EPT_COL, Q_INST_EPT_ROW = 4, 4096, 8192, 12288
 Q_PROF_MS_RUN1D, Q_PROF_N_RUN1D, Q_PROF_MS_PERSIST, Q_PROF_N_PERSIST, Q_PATH = 24, 25, 26, 27, 28
 Q_RESIDUAL, Q_STATE_NORM = 29, 30
-Q_FS_H_AXIS, Q_FS_HSTEP, Q_FS_NU, Q_FS_K = 86, 128, 130, 132
+Q_FS_H_AXIS, Q_FS_HSTEP, Q_FS_NU, Q_FS_K, Q_FS_CHEB = 86, 128, 130, 132, 134
 CFG_PERSISTENT, CFG_GUARD = 0, 1
 
 
@@ -47,7 +47,7 @@ def problem_struct(*, dim: int, M: Sequence[int], T: float, nsteps: int, V_field
                    n_start: int = -1, precision: str = "fp64", f_kind: str = "const", f_params=None,
                    A_kind: str = "none", A_params=None, A_steps=None, domain: str = "periodic",
                    eps: float = 1e-10, p: int = 8, q: int = 10, panels: int = 1, nu: Sequence[int] = (),
-                   H: float = 0.0, V_kind: str = "fields", V_params: Sequence[float] = ()):
+                   H: float = 0.0, V_kind: str = "fields", V_params: Sequence[float] = (), cheb: int = 0):
     """Fill a tdse_problem_t; returns it with the arrays it points into (keep them alive).
     V_kind "moving_well" takes V_params = (V0, beta, c_0[, c_1]) and no fields."""
     M = tuple(int(m) for m in M)
@@ -97,6 +97,7 @@ def problem_struct(*, dim: int, M: Sequence[int], T: float, nsteps: int, V_field
     for a, n in enumerate(nu):
         prob.nu[a] = int(n)
     prob.H = float(H)
+    prob.cheb = int(cheb)
     return prob, keep
 
 
@@ -116,7 +117,8 @@ def problem_kwargs(prob) -> dict:
                 precision=prob.precision, f_kind="sin" if sin else "const", f_params=f_params,
                 A_kind=prob.A_kind, A_params=prob.A_params if prob.A_kind in ("pulse_sin2", "pulse_cos2") else None,
                 A_steps=prob.A_steps if prob.A_kind == "stepwise" else None,
-                domain=prob.domain, eps=prob.eps, p=prob.p, q=prob.q, panels=prob.panels, nu=prob.nu)
+                domain=prob.domain, eps=prob.eps, p=prob.p, q=prob.q, panels=prob.panels, nu=prob.nu,
+                cheb=getattr(prob, "cheb", 0))
 
 
 class Plan:

@@ -74,6 +74,7 @@ class EmuPlan:
         for a, n in enumerate(prob.nu):
             p.nu[a] = n
         p.H = H
+        p.cheb = int(getattr(prob, "cheb", 0))
         self.prob = p
         h = C.c_void_p()
         st = lib.tdse_plan(C.byref(p), C.byref(h))

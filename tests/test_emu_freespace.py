@@ -139,3 +139,67 @@ def test_emulated_cosine_pulse_ionization_setup(emu):
     u = EmuPlan(emu, prob).run(prob.u0)
     ref, _ = FreeSpaceOracle(prob).run()
     assert _rel(u, ref) < 1e-12
+
+
+# C-type transforms through the Chebyshev interpolant (Section 4.1): the
+# automatic choice, forced term counts, Gamma_2 blocks larger than the direct
+# path's dense limit, and both axes of a 2D plan
+CHEB_CASES = [
+    dict(seed=30, dim=1, M=(64,), nu=(512,), T=0.04, N=10, q=16, panels=5, cheb=0),     # N_C = 160
+    dict(seed=31, dim=1, M=(48,), nu=(256,), T=0.05, N=9, q=12, panels=2, cheb=-1),     # direct, same nodes
+    dict(seed=31, dim=1, M=(48,), nu=(256,), T=0.05, N=9, q=12, panels=2, cheb=30),     # forced NT
+    dict(seed=32, dim=2, M=(32, 24), nu=(256, 256), T=0.04, N=9, q=16, panels=3, cheb=0),
+    dict(seed=33, dim=2, M=(16, 40), nu=(256, 512), T=0.03, N=8, q=8, panels=4, cheb=0, order=6),
+]
+
+
+@pytest.mark.parametrize("case", CHEB_CASES, ids=[f"{c['M']}-q{c['q']}x{c['panels']}-cheb{c['cheb']}" for c in CHEB_CASES])
+def test_emulated_chebyshev_c_type_matches_oracle(emu, case):
+    from emu.emu_plan import EmuPlan
+
+    prob = free_problem_from_seed(case["seed"], case["dim"], case["M"], case["T"], case["N"], nu=case["nu"],
+                                  order=case.get("order", 8), eps=1e-11, q=case["q"], panels=case["panels"])
+    prob.cheb = case["cheb"]
+    plan = EmuPlan(emu, prob)
+    orc = FreeSpaceOracle(prob)
+    for a in range(case["dim"]):
+        assert plan.query(134 + a) == orc.NT[a], (a, plan.query(134 + a), orc.NT)
+    if case["cheb"] != -1:
+        assert all(orc.NT)
+    u = plan.run(prob.u0)
+    ref, _ = orc.run()
+    assert _rel(u, ref) < 1e-12
+
+
+def test_emulated_example2_long_time(emu):
+    # Section 6, Example 2's long-time run (T = 1000, q = 16, n_r = 5) through
+    # the interpolant: the oracle's u(T) and the exact wave packet
+    from emu.emu_plan import EmuPlan
+    from test_oracle_chebyshev import _wavepacket, example2_long_time_problem
+
+    prob = example2_long_time_problem(5, cheb=0, nsteps=40)
+    orc = FreeSpaceOracle(prob)
+    plan = EmuPlan(emu, prob)
+    assert plan.query(134) == orc.NT[0] > 0
+    u = plan.run(prob.u0)
+    ref, _ = orc.run()
+    assert _rel(u, ref) < 1e-12
+    ex = _wavepacket(orc.xs[0] + orc.phi(prob.T)[0], prob.T, 0.1)
+    assert _rel(u, ex) < 1e-13
+
+
+def test_plan_rejects_bad_chebyshev_settings(emu):
+    from emu.emu_plan import EmuPlan
+
+    prob = free_problem_from_seed(34, 1, (32,), 0.05, 4, nu=(256,), eps=1e-11, q=8, panels=1)
+    for bad in (-2, 1, 65):
+        prob.cheb = bad
+        with pytest.raises(Exception):
+            EmuPlan(emu, prob)
+    # more direct-sum rows than half the FFT line: refused, accepted through the interpolant
+    prob = free_problem_from_seed(34, 1, (32,), 0.05, 4, nu=(256,), eps=1e-11, q=32, panels=4)
+    prob.cheb = -1
+    with pytest.raises(Exception):
+        EmuPlan(emu, prob)
+    prob.cheb = 0
+    EmuPlan(emu, prob)
