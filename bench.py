@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-well", action="store_true", help="skip the moving-well (potential on the fly) leg")
     ap.add_argument("--no-ionization", action="store_true", help="skip the 1D ionization (Example 3) leg")
     ap.add_argument("--no-1d", action="store_true", help="skip the 1D periodic M = 256 leg")
+    ap.add_argument("--no-long-time", action="store_true",
+                    help="skip the long-time free-space leg (Chebyshev-interpolated C-type block)")
     ap.add_argument("--batch-runs", type=int, default=3)
     ap.add_argument("--free-runs", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -471,6 +473,68 @@ def periodic_1d_leg(runs: int = 20) -> dict:
             "us_per_time_step": wall * 1e6 / prob.nsteps, "one_workgroup_run_kernel_us": k_us, "error": err}
 
 
+def long_time_leg(runs: int = 5) -> dict:
+    """The C-type block on Gamma_2 through the Chebyshev interpolant against
+    direct sums (Section 4.1): Section 6, Example 2's long-time wave packet
+    (1D, M = 128, nu = 1024, q = 16, n_r = 5, 1000 steps to T = 1000; error
+    against the stored oracle values and the exact packet), and the 256^2,
+    nu = 2048 free-space grid with q = 16, n_r = 5 (N_C = 160 per axis, 200
+    steps of dt = 1e-3): time per step and per row and column pass."""
+    import numpy as np
+    import torch
+
+    from paper_2001_06113_amd.tdse import (Q_FS_CHEB, Q_PHI, Q_PROF_MS_COL, Q_PROF_MS_ROW, Q_PROF_N_COL,
+                                           Q_PROF_N_ROW, Plan)
+    from workloads import example2_long_time_problem, free_grid, free_problem_from_seed, wavepacket
+
+    dev = torch.device("cuda:0")
+
+    def timed(prob, reps):
+        plan = Plan.from_problem(prob, device=dev)
+        u0 = torch.as_tensor(prob.u0).to(dev)
+        out = torch.empty_like(u0)
+        plan.use_graph(True)
+        plan.run(u0, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.run(u0, out)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        plan.use_graph(False)
+        plan.profile(True)
+        plan.run(u0, out)
+        row = plan.query(Q_PROF_MS_ROW) * 1e3 / max(plan.query(Q_PROF_N_ROW), 1)
+        col = plan.query(Q_PROF_MS_COL) * 1e3 / max(plan.query(Q_PROF_N_COL), 1)
+        plan.profile(False)
+        nt = [int(plan.query(Q_FS_CHEB + a)) for a in range(prob.dim)]
+        phi = [plan.query(Q_PHI + a) for a in range(prob.dim)]
+        plan.close()
+        return out.cpu().numpy(), wall, row, col, nt, phi
+
+    res = {"workload": "C-type block through the Chebyshev interpolant vs direct sums: Example 2 long-time "
+                       "wave packet (1D M=128, nu=1024, q=16, n_r=5, T=1000, 1000 steps) and 2D 256x256, "
+                       "nu=2048, q=16, n_r=5 (200 steps)"}
+    for cheb, key in ((0, "example2_interpolant"), (-1, "example2_direct")):
+        prob = example2_long_time_problem(5, cheb=cheb)
+        u, wall, row, col, nt, phi = timed(prob, runs)
+        ex = wavepacket(free_grid(prob.M[0]) + phi[0], prob.T, 0.1)
+        res[key] = {"NT": nt[0], "ms_per_run": wall * 1e3, "us_per_time_step": wall * 1e6 / prob.nsteps,
+                    "row_pass_us": row, "error": oracle_error("example2_long_time_nr5", u),
+                    "rel_l2_vs_exact": float(np.linalg.norm(u - ex) / np.linalg.norm(ex))}
+    grid = {}
+    for cheb, key in ((0, "interpolant"), (-1, "direct")):
+        prob = free_problem_from_seed(2, 2, (256, 256), 0.2, 200, nu=(2048, 2048), eps=1e-10, q=16, panels=5)
+        prob.cheb = cheb
+        u, wall, row, col, nt, _ = timed(prob, 2)
+        grid[key] = {"NT": nt, "us_per_time_step": wall * 1e6 / prob.nsteps, "row_pass_us": row, "col_pass_us": col,
+                     "u": u}
+    ud, uc = grid["direct"].pop("u"), grid["interpolant"].pop("u")
+    grid["rel_l2_interpolant_vs_direct"] = float(np.linalg.norm(uc - ud) / np.linalg.norm(ud))
+    res["grid_256_nr5"] = grid
+    return res
+
+
 def batch_leg(runs: int, copies: dict) -> dict:
     """Batched form on the 64-instance workload (seed 4000 + i; 32 1D with
     M in {256..2048}, 32 2D with M in {128..512}^2; 500 steps, FP32-split,
@@ -685,6 +749,8 @@ def main():
         res["moving_well"] = moving_well_leg()
     if not args.no_ionization:
         res["ionization"] = ionization_leg()
+    if not args.no_long_time:
+        res["long_time"] = long_time_leg()
     if not args.no_batch:
         res["batch"] = batch_leg(args.batch_runs, copies)
     if not args.no_cpu:

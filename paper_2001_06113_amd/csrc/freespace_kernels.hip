@@ -87,6 +87,7 @@ __device__ __forceinline__ typename fs_tw<NU>::type stage_twiddles(const CFAxis&
 }
 
 // forward transform of f[0..M) (LDS); ends with dm complete (a barrier).
+// dm may share f's LDS: it is written only after the last read of f.
 // CH: the C-type block through the interpolant (ax.NT > 0).
 template <int NU, bool CH>
 __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY], double2 (&v1)[RAY], double2* dm,
@@ -119,8 +120,10 @@ __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY],
   // (equispaced x_j), so the chunk is Dfwd[q][j0] times a Horner sum in the
   // ratio rfwd[q]: two table reads per chunk, L LDS reads.
   const int NR = CH ? ax.NR : ND;
-  double2* dr = CH ? dm + ND : dm;   // the rows' sums (the modes themselves without the interpolant)
   const int C = TL / NR > 1 ? TL / NR : 1;
+  // the rows' sums: the modes themselves without the interpolant, else the
+  // node values, kept in the second exchange line behind the partials
+  double2* dr = CH ? part + NR * C : dm;
   const int L = (M + C - 1) / C;
   for (int i = t; i < NR * C; i += TL) {   // more dense rows than threads: several pairs per thread
     const int q = i / C, c = i - q * C;
@@ -170,23 +173,64 @@ __device__ __forceinline__ void cf_forward(const double2* f, double2 (&v3)[RAY],
 
 // inverse transform of the modes (v3, v1 registers, dm LDS) into u[0..M)
 // (LDS); thread t writes u[t + TL m] only, so it may read those entries back
-// without a barrier
+// without a barrier.  With the interpolant (CH) dm shares u's LDS: u is
+// written only after every read of dm.
 template <int NU, bool CH>
-__device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const double2 (&v1)[RAY], double2* dm,
+__device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const double2 (&v1)[RAY], const double2* dm,
                                            double2* fline, double2* fline2, const CFAxis& ax,
                                            const typename fs_tw<NU>::type& tw, int t, double2* u) {
   constexpr int TL = NU / 8;
   constexpr int EPT = 8;
   const int M = ax.M, NE = ax.NE, ND = ax.ND, NR = CH ? ax.NR : ND;
-  const double2* drow = dm;   // the dense rows' coefficients
-  if (CH) {
-    // contract the C-modes onto the interpolation nodes (eq. (expintrpp) in
-    // the form of its values), split over (node, chunk) pairs and reduced
-    // through the second exchange line before the FFTs take it
+  double2 w[EPT], w1[EPT];
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) {
+    const int e = t + TL * m;
+    if (m < RAY) {
+      const double2 x = cmul(ax.ipre3[min(e, NE - 1)], v3[m < RAY ? m : 0]);
+      w[m] = e < NE ? x : double2{0.0, 0.0};
+      const double2 y = cmul(ax.ipre1[min(e, NE - 1)], v1[m < RAY ? m : 0]);
+      w1[m] = e < NE ? y : double2{0.0, 0.0};
+    } else {
+      w[m] = double2{0.0, 0.0};
+      w1[m] = double2{0.0, 0.0};
+    }
+  }
+  fft_regs_dual<NU, TL, true, false>(w, w1, t, fline, fline2, tw);   // ends with a barrier: both lines free
+  constexpr int DB = 18;   // dense rows per batch of matrix entries
+  if constexpr (!CH) {
+    // dm has LDS of its own: E3 part into u, then E1 and the dense modes
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int e = t + TL * m;
+      if (e < M) u[e] = cmul(ax.ipost3[e], w[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int e = t + TL * m;
+      if (e < M) {
+        double2 s = cadd(u[e], cmul(ax.ipost1[e], w1[m]));
+        for (int q0 = 0; q0 < ND; q0 += DB) {
+          double2 d[DB];
+#pragma unroll
+          for (int u8 = 0; u8 < DB; ++u8) d[u8] = ax.Dinv[(int64_t)min(q0 + u8, ND - 1) * M + e];
+#pragma unroll
+          for (int u8 = 0; u8 < DB; ++u8) {
+            if (q0 + u8 < ND) s = cadd(s, cmul(d[u8], dm[q0 + u8]));
+          }
+        }
+        u[e] = s;
+      }
+    }
+  } else {
+    // dm shares u's LDS.  Contract the C-modes onto the interpolation nodes
+    // (eq. (expintrpp) in the form of its values), split over (node, chunk)
+    // pairs and reduced through the second exchange line, which then holds
+    // the node values dv.
     const int P = ax.NP, NT = ax.NT, NC = ND - 2 * P;
-    double2* dv = dm + ND;
     const int C = TL / NR > 1 ? TL / NR : 1;
     const int L = (NC + C - 1) / C;
+    double2* dv = fline2 + NR * C;
     for (int i = t; i < NR * C; i += TL) {
       const int r = i / C, c = i - r * C;
       double2 acc = {0.0, 0.0};
@@ -205,59 +249,37 @@ __device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const doubl
       for (int c = 0; c < C; ++c) acc = cadd(acc, fline2[r * C + c]);
       dv[r] = acc;
     }
-    __syncthreads();
-    drow = dv;
-  }
-  double2 w[EPT], w1[EPT];
+    __syncthreads();   // dv complete, and every read of dm done: u may be written
 #pragma unroll
-  for (int m = 0; m < EPT; ++m) {
-    const int e = t + TL * m;
-    if (m < RAY) {
-      const double2 x = cmul(ax.ipre3[min(e, NE - 1)], v3[m < RAY ? m : 0]);
-      w[m] = e < NE ? x : double2{0.0, 0.0};
-      const double2 y = cmul(ax.ipre1[min(e, NE - 1)], v1[m < RAY ? m : 0]);
-      w1[m] = e < NE ? y : double2{0.0, 0.0};
-    } else {
-      w[m] = double2{0.0, 0.0};
-      w1[m] = double2{0.0, 0.0};
-    }
-  }
-  fft_regs_dual<NU, TL, true, false>(w, w1, t, fline, fline2, tw);
+    for (int m = 0; m < EPT; ++m) {
+      const int e = t + TL * m;
+      if (e < M) {
+        double2 s = cadd(cmul(ax.ipost3[e], w[m]), cmul(ax.ipost1[e], w1[m]));
+        for (int q0 = 0; q0 < NR; q0 += DB) {
+          double2 d[DB];
 #pragma unroll
-  for (int m = 0; m < EPT; ++m) {
-    const int e = t + TL * m;
-    if (e < M) u[e] = cmul(ax.ipost3[e], w[m]);
-  }
-  // E1 part, then the dense rows in batches of DB matrix entries
-  constexpr int DB = 18;
+          for (int u8 = 0; u8 < DB; ++u8) d[u8] = ax.Dinv[(int64_t)min(q0 + u8, NR - 1) * M + e];
 #pragma unroll
-  for (int m = 0; m < EPT; ++m) {
-    const int e = t + TL * m;
-    if (e < M) {
-      double2 s = cadd(u[e], cmul(ax.ipost1[e], w1[m]));
-      for (int q0 = 0; q0 < NR; q0 += DB) {
-        double2 d[DB];
-#pragma unroll
-        for (int u8 = 0; u8 < DB; ++u8) d[u8] = ax.Dinv[(int64_t)min(q0 + u8, NR - 1) * M + e];
-#pragma unroll
-        for (int u8 = 0; u8 < DB; ++u8) {
-          if (q0 + u8 < NR) s = cadd(s, cmul(d[u8], drow[q0 + u8]));
+          for (int u8 = 0; u8 < DB; ++u8) {
+            if (q0 + u8 < NR) s = cadd(s, cmul(d[u8], dv[q0 + u8]));
+          }
         }
+        u[e] = s;
       }
-      u[e] = s;
     }
   }
 }
 
-// LDS of a line kernel: dynamic f[M] | first FFT exchange line | dense
-// block (dm[ND], then the node values dr[NR] with the interpolant) |
+// LDS of a line kernel: dynamic f[M] | dm[ND] | first FFT exchange line |
 // twiddles, and a static second exchange line that also holds the dense
-// partials.  At nu = 2048 with M = 256 and direct sums that is 79.9 KB, two
-// workgroups per CU.
+// partials and, with the interpolant, the node values.  With the
+// interpolant, f and dm share max(M, ND) entries.  At nu = 2048 with M = 256
+// that is 79.9 KB with N_D = 36 direct rows and 79.4 KB with N_D <= 256
+// through the interpolant: two workgroups per CU.
 template <int NU>
-size_t fs_lds_bytes(int M, int ndense) {
-  return sizeof(double2) *
-         (size_t)(M + lds_line_len(NU) + ndense + fs_tw<NU>::NC + fs_tw<NU>::NF);
+size_t fs_lds_bytes(int M, int ND, bool ch) {
+  const int line = ch ? (M > ND ? M : ND) : M + ND;
+  return sizeof(double2) * (size_t)(line + lds_line_len(NU) + fs_tw<NU>::NC + fs_tw<NU>::NF);
 }
 
 // The per-mode step of the row pass for mode g = row_m + k; W is the mode of
@@ -319,10 +341,10 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   double2* part = fline2;
   const CFAxis& ax = a.ax2;
   const int M2 = ax.M, N2 = ax.N, NE = ax.NE, ND = ax.ND;
-  double2* fin = fs_lds;
-  double2* fline = fin + M2;
-  double2* dm = fline + lds_line_len(NU);
-  double2* tws = dm + cf_dense_lds(ax);
+  double2* fin = fs_lds;                           // the row, then u (CH: the dense modes in between)
+  double2* dm = CH ? fin : fin + M2;
+  double2* fline = CH ? fin + (M2 > ND ? M2 : ND) : dm + ND;
+  double2* tws = fline + lds_line_len(NU);
   const int t = threadIdx.x;
   const int k1 = blockIdx.x;
   const auto tw = stage_twiddles<NU>(ax, tws, t);   // read after the first barrier below
@@ -503,10 +525,10 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
   const CFAxis& ax = a.ax1;
   const int M1 = ax.M, N1 = ax.N, NE = ax.NE, ND = ax.ND;
   const int M2 = a.ax2.M;
-  double2* fin = fs_lds;
-  double2* fline = fin + M1;
-  double2* dm = fline + lds_line_len(NU);
-  double2* tws = dm + cf_dense_lds(ax);
+  double2* fin = fs_lds;                           // u, then the forward input (CH: the dense modes first)
+  double2* dm = CH ? fin : fin + M1;
+  double2* fline = CH ? fin + (M1 > ND ? M1 : ND) : dm + ND;
+  double2* tws = fline + lds_line_len(NU);
   const int t = threadIdx.x;
   const int y = fs_col_of(blockIdx.x, gridDim.x);   // physical column (axis 1)
   const auto tw = stage_twiddles<NU>(ax, tws, t);   // read after the first barrier below
@@ -629,9 +651,9 @@ bool fs_nu_supported(int nu) {
   }
 }
 
-size_t fs_line_lds_bytes(int nu, int M, int ndense) {
+size_t fs_line_lds_bytes(int nu, int M, int ND, bool ch) {
   switch (nu) {
-#define X(n) case n: return fs_lds_bytes<n>(M, ndense);
+#define X(n) case n: return fs_lds_bytes<n>(M, ND, ch);
     TDSE_FS_NU(X)
 #undef X
     default:
@@ -644,9 +666,9 @@ hipError_t launch_fs_row(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0, 
 #define X(n)                                                                              \
   case n:                                                                                 \
     if (a.ax2.NT)                                                                         \
-      TDSE_FS_LAUNCH_SH((k_fs_row<n, true>), dim3(a.N1), dim3(n / 8), fs_lds_bytes<n>(a.ax2.M, cf_dense_lds(a.ax2)), s, e0, e1, a); \
+      TDSE_FS_LAUNCH_SH((k_fs_row<n, true>), dim3(a.N1), dim3(n / 8), fs_lds_bytes<n>(a.ax2.M, a.ax2.ND, a.ax2.NT != 0), s, e0, e1, a); \
     else                                                                                  \
-      TDSE_FS_LAUNCH_SH((k_fs_row<n, false>), dim3(a.N1), dim3(n / 8), fs_lds_bytes<n>(a.ax2.M, cf_dense_lds(a.ax2)), s, e0, e1, a); \
+      TDSE_FS_LAUNCH_SH((k_fs_row<n, false>), dim3(a.N1), dim3(n / 8), fs_lds_bytes<n>(a.ax2.M, a.ax2.ND, a.ax2.NT != 0), s, e0, e1, a); \
     break;
     TDSE_FS_NU(X)
 #undef X
@@ -667,9 +689,9 @@ hipError_t launch_fs_col(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0, 
 #define X(n)                                                                              \
   case n:                                                                                 \
     if (a.ax1.NT)                                                                         \
-      TDSE_FS_LAUNCH_SH((k_fs_col<n, true>), dim3(a.ax2.M), dim3(n / 8), fs_lds_bytes<n>(a.ax1.M, cf_dense_lds(a.ax1)), s, e0, e1, a); \
+      TDSE_FS_LAUNCH_SH((k_fs_col<n, true>), dim3(a.ax2.M), dim3(n / 8), fs_lds_bytes<n>(a.ax1.M, a.ax1.ND, a.ax1.NT != 0), s, e0, e1, a); \
     else                                                                                  \
-      TDSE_FS_LAUNCH_SH((k_fs_col<n, false>), dim3(a.ax2.M), dim3(n / 8), fs_lds_bytes<n>(a.ax1.M, cf_dense_lds(a.ax1)), s, e0, e1, a); \
+      TDSE_FS_LAUNCH_SH((k_fs_col<n, false>), dim3(a.ax2.M), dim3(n / 8), fs_lds_bytes<n>(a.ax1.M, a.ax1.ND, a.ax1.NT != 0), s, e0, e1, a); \
     break;
     TDSE_FS_NU(X)
 #undef X

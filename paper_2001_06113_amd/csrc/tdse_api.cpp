@@ -1326,11 +1326,7 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
     // the dense rows' partial sums share the second FFT exchange line
     if (p->fx[a].NR > nu / 2)
       return fail(TDSE_EINVAL, "more than nu/2 dense rows (2p + 2 q panels direct sums, or 2p + NT); use the interpolant or a larger nu");
-    tdse::CFAxis probe{};
-    probe.ND = p->fx[a].ND;
-    probe.NR = p->fx[a].NR;
-    probe.NT = p->fx[a].NT;
-    if (fs_line_lds_bytes(nu, M, tdse::cf_dense_lds(probe)) > 65536)
+    if (fs_line_lds_bytes(nu, M, p->fx[a].ND, p->fx[a].NT != 0) > 65536)
       return fail(TDSE_EINVAL, "free-space line needs more than 64 KiB of LDS (M too large for this nu)");
   }
   p->NM = (int64_t)p->fx[0].N * p->fx[1].N;

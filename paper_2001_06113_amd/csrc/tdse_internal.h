@@ -106,9 +106,7 @@ struct CFAxis {
   const double* Pf;             // [N_C][NT] interpolation from the nodes to the C-modes
   const double2* Pi;            // [NT][N_C] its transpose times w_k / 2pi
 };
-// LDS entries of a line's dense block: the modes, and the node values when
-// the interpolant is on
-__host__ __device__ inline int cf_dense_lds(const CFAxis& ax) { return ax.ND + (ax.NT ? ax.NR : 0); }
+
 
 struct FSArgs {
   int mode;
@@ -219,7 +217,7 @@ hipError_t launch_fs_row(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0 =
 hipError_t launch_fs_col(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_fs_phase(const FSArgs& a, hipStream_t s);
 bool fs_nu_supported(int nu);
-size_t fs_line_lds_bytes(int nu, int M, int ndense);   // dynamic LDS of a line workgroup (ndense: cf_dense_lds)
+size_t fs_line_lds_bytes(int nu, int M, int ND, bool ch);   // dynamic LDS of a line workgroup (ch: interpolant on)
 
 // Evaluation of a free-space representation at arbitrary points (far_kernels.hip).
 // far_scratch: device address, on the current GPU, of the library-owned array

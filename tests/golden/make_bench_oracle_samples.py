@@ -15,6 +15,10 @@ Cases (one file each, tests/golden/<case>_oracle_sample.txt):
                      to T = 2 pi / 15, every 8th point per axis
   batch_64           the 64 uneven periodic instances (seeds 4000 + i), 500 steps to T = 2,
                      stepwise field; 1D every (M/64)-th point, 2D every (M/16)-th point per axis
+  example2_long_time_nr5
+                     Section 6, Example 2's long-time wave packet: 1D free space, M = 128,
+                     nu = 1024, q = 16, n_r = 5, 1000 steps to T = 1000, the C-type block
+                     through the interpolant (automatic choice); every point
 
 File format: "# key value" header lines (the case, the full-grid 2-norm of the
 oracle's u(T) per instance, the sampling strides, free space: H per axis), then
@@ -33,8 +37,9 @@ sys.path.insert(0, ROOT)
 
 from oracle.freespace import FreeSpaceOracle  # noqa: E402
 from oracle.periodic import PeriodicOracle  # noqa: E402
-from workloads import (batch_64_problems, free_2d_256_problem, moving_well_problem,  # noqa: E402
-                       periodic_1d_256_problem, periodic_2d_512_problem, periodic_2d_1024_problem)
+from workloads import (batch_64_problems, example2_long_time_problem, free_2d_256_problem,  # noqa: E402
+                       moving_well_problem, periodic_1d_256_problem, periodic_2d_512_problem,
+                       periodic_2d_1024_problem)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -61,6 +66,7 @@ def cases():
                                         8, 8)],
         "batch_64": lambda: [("periodic", p, p.M[0] // 16, p.M[0] // 64)
                              for p in batch_64_problems(precision="fp64")],
+        "example2_long_time_nr5": lambda: [("free", example2_long_time_problem(5), 1, 1)],
     }
 
 

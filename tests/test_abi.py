@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def _problem(dim=2, M=(32, 64), T=1.0, nsteps=100, order=8, A=None, nV=1, f=None, domain=0, precision=0,
-             nu=(256, 256), fs_p=8, q=10, panels=1, eps=1e-10, H=0.0):
+             nu=(256, 256), fs_p=8, q=10, panels=1, eps=1e-10, H=0.0, cheb=0):
     from paper_2001_06113_amd import _lib
 
     p = _lib.Problem()
@@ -44,6 +44,7 @@ def _problem(dim=2, M=(32, 64), T=1.0, nsteps=100, order=8, A=None, nV=1, f=None
     p.domain = domain
     p.nu[0], p.nu[1] = nu
     p.p, p.q, p.panels, p.eps, p.H = fs_p, q, panels, eps, H
+    p.cheb = cheb
     p.M[0], p.M[1] = M[0], (M[1] if len(M) > 1 else 0)
     p.T = T
     p.nsteps = nsteps
@@ -97,7 +98,10 @@ def _plan(lib, p):
     (dict(domain=1, eps=0.0), -1),              # no tolerance and no H
     (dict(domain=1, q=1), -1),
     (dict(domain=1, panels=0), -1),
-    (dict(domain=1, q=32, panels=8, nu=(256, 256)), -1),   # more Gauss nodes than the kernels hold
+    (dict(domain=1, q=32, panels=8, nu=(256, 256), cheb=-1), -1),   # more direct-sum rows than nu/2
+    (dict(domain=1, cheb=1), -1),
+    (dict(domain=1, cheb=65), -1),
+    (dict(domain=1, cheb=-2), -1),
 ])
 def test_plan_rejects(lib, kw, status):
     st, h = _plan(lib, _problem(**kw))
@@ -269,6 +273,25 @@ def test_free_space_planner_contour_matches_oracle(lib, dim, M, nu):
     if dim == 1:
         assert lib.tdse_query(h, 82, C.byref(v)) == -1   # no second axis
     lib.tdse_destroy(h)
+
+
+@pytest.mark.parametrize("H", [0.3, 0.95, 1.7, 2.4, 3.0, 4.5, 7.0])
+def test_free_space_planner_chebyshev_terms_match_oracle(lib, H):
+    # NT of the C-type interpolant (Section 4.1): the planner's Bessel-series
+    # rule gives the oracle's count; the automatic choice takes the
+    # interpolant only when NT < N_C; -1 and a forced count are honoured
+    from oracle.chebyshev import choose_NT
+
+    nt = choose_NT(H)
+    v = C.c_double()
+    for q, panels, cheb, want in [(16, 4, 0, nt if 0 < nt < 128 else 0), (8, 1, 0, nt if 0 < nt < 16 else 0),
+                                  (16, 4, -1, 0), (16, 4, 20, 20)]:
+        st, h = _plan(lib, _problem(domain=1, dim=1, M=(64,), nu=(512, 0), q=q, panels=panels, H=H, cheb=cheb))
+        assert st == 0, lib.tdse_last_error()
+        assert lib.tdse_query(h, 134, C.byref(v)) == 0
+        assert v.value == want, (H, q, panels, cheb, v.value, want)
+        assert lib.tdse_query(h, 135, C.byref(v)) == -1   # no second axis
+        lib.tdse_destroy(h)
 
 
 def test_periodic_plan_has_no_contour(lib):

@@ -175,7 +175,8 @@ def test_emulated_example2_long_time(emu):
     # Section 6, Example 2's long-time run (T = 1000, q = 16, n_r = 5) through
     # the interpolant: the oracle's u(T) and the exact wave packet
     from emu.emu_plan import EmuPlan
-    from test_oracle_chebyshev import _wavepacket, example2_long_time_problem
+    from workloads import example2_long_time_problem
+    from workloads import wavepacket as _wavepacket
 
     prob = example2_long_time_problem(5, cheb=0, nsteps=40)
     orc = FreeSpaceOracle(prob)

@@ -10,7 +10,8 @@ import pytest
 
 from workloads.golden import GOLDEN, load_samples, sampled_error
 
-CASES = ["periodic_1d_256", "periodic_2d_512", "periodic_2d_1024", "free_2d_256_default_h", "moving_well_2d_512", "batch_64"]
+CASES = ["periodic_1d_256", "periodic_2d_512", "periodic_2d_1024", "free_2d_256_default_h", "moving_well_2d_512", "batch_64",
+         "example2_long_time_nr5"]
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -41,11 +42,16 @@ def _rerun(case, inst):
     from oracle.periodic import PeriodicOracle
 
     kind, prob, s2, s1 = mk.cases()[case]()[inst]
+    if kind == "free":
+        from oracle.freespace import FreeSpaceOracle
+
+        return FreeSpaceOracle(prob).run()[0]
     u, _ = PeriodicOracle(prob).run()
     return u
 
 
-@pytest.mark.parametrize("case,inst", [("periodic_1d_256", 0), ("batch_64", 0), ("batch_64", 1)])
+@pytest.mark.parametrize("case,inst", [("periodic_1d_256", 0), ("batch_64", 0), ("batch_64", 1),
+                                       ("example2_long_time_nr5", 0)])
 def test_cheap_cases_reproduce_exactly(case, inst):
     u = _rerun(case, inst)
     e = sampled_error(u, load_samples(case)[inst])

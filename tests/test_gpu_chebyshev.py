@@ -12,8 +12,8 @@ import numpy as np
 import pytest
 
 from oracle.freespace import FreeSpaceOracle
-from test_oracle_chebyshev import _wavepacket, example2_long_time_problem
-from workloads import free_problem_from_seed
+from workloads import example2_long_time_problem, free_problem_from_seed
+from workloads import wavepacket as _wavepacket
 
 pytestmark = pytest.mark.gpu
 

@@ -9,7 +9,7 @@ from scipy.special import iv
 from oracle.chebyshev import c_forward, c_inverse, cheb_T, choose_NT, interp_coeffs, lambda_matrix, rho_matrix
 from oracle.freespace import FreeSpaceOracle, free_grid
 from oracle.quadrature import gamma_rule
-from workloads.synth import Problem, free_problem_from_seed
+from workloads.synth import example2_long_time_problem, free_problem_from_seed, wavepacket
 
 
 def test_coefficients_of_a_chebyshev_polynomial():
@@ -107,19 +107,7 @@ def test_2d_ce_and_cc_blocks_match_the_2d_dft():
 
 
 def _wavepacket(x, t, sig):
-    # eq. (wavepacket) with k0 = 0, divided by sigma so that ||u0|| = 1
-    s = sig ** 2 + 2j * t
-    return sig ** 1.5 / np.pi ** 0.25 / np.sqrt(s) * np.exp(-(x / np.sqrt(2)) ** 2 / s) / sig
-
-
-def example2_long_time_problem(panels, cheb=0, M=128, nu=1024, nsteps=100, T=1000.0):
-    """Section 6, Example 2, long-time run: V = 0, sigma = 0.1, A of eq.
-    (apulse) with A0 = omega = 1 over [0, T], eps = 1e-14, p = 8, q = 16."""
-    x = free_grid(M)
-    return Problem(name="ex2_long", dim=1, domain="free", M=(M,), T=T, nsteps=nsteps, order=8,
-                   u0=_wavepacket(x, 0, 0.1).astype(complex), V_fields=[np.zeros(M)], f_kind=["const"],
-                   f_params=[(0, 0)], A_kind="pulse_cos2", A_params=(1.0, 1.0, T, 1.0),
-                   eps=1e-14, q=16, panels=panels, nu=(nu,), cheb=cheb)
+    return wavepacket(x, t, sig)
 
 
 @pytest.mark.parametrize("cheb", [-1, 0])
@@ -129,7 +117,7 @@ def test_example2_long_time_refinement(cheb):
     # n_r = O(log T) keeps the accuracy uniform)
     errs = []
     for nr in range(1, 6):
-        orc = FreeSpaceOracle(example2_long_time_problem(nr, cheb))
+        orc = FreeSpaceOracle(example2_long_time_problem(nr, cheb, nsteps=100))
         if cheb == 0:
             assert orc.NT[0] > 0 and orc.NT[0] < 32 * nr
         u, _ = orc.run()

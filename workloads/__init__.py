@@ -21,4 +21,6 @@ from .synth import (  # noqa: F401
     gaussian_well_ground_state_2d,
     periodic_well_ground_state,
     ionization_2d_problem,
+    wavepacket,
+    example2_long_time_problem,
 )

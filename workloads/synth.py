@@ -309,6 +309,28 @@ def free_2d_256_problem(seed: int = 2, M: int = 256, T: float = 1.0, nsteps: int
     return free_problem_from_seed(seed, 2, (M, M), T, nsteps, order, nu=(nu, nu), name="free-2d-256")
 
 
+def wavepacket(x, t: float, sigma: float):
+    """The Gaussian wave packet of Section 6, Example 2 (eq. (wavepacket),
+    k0 = 0), divided by sigma so that its L^2(R) norm is 1: the exact solution
+    for V = 0, A = 0; with a field A the exact solution is u(x + phi(t), t)."""
+    s = sigma ** 2 + 2j * t
+    return sigma ** 1.5 / np.pi ** 0.25 / np.sqrt(s) * np.exp(-(np.asarray(x) / np.sqrt(2)) ** 2 / s) / sigma
+
+
+def example2_long_time_problem(panels: int, cheb: int = 0, M: int = 128, nu: int = 1024, nsteps: int = 1000,
+                               T: float = 1000.0) -> Problem:
+    """Section 6, Example 2, long-time run: 1D free space, V = 0, u0 the wave
+    packet with sigma = 0.1, A of eq. (apulse) with A0 = omega = 1 over
+    [0, T], eps = 1e-14, p = 8, q = 16 and `panels` dyadic panels (n_r) per
+    side of Gamma_2.  M and nu are this implementation's choice (the paper
+    converges each parameter to about fifteen digits)."""
+    x = free_grid(M)
+    return Problem(name=f"ex2-long-nr{panels}", dim=1, domain="free", M=(M,), T=T, nsteps=nsteps, order=8,
+                   u0=wavepacket(x, 0.0, 0.1).astype(complex), V_fields=[np.zeros(M)], f_kind=["const"],
+                   f_params=[(0.0, 0.0)], A_kind="pulse_cos2", A_params=(1.0, 1.0, T, 1.0),
+                   eps=1e-14, q=16, panels=panels, nu=(nu,), cheb=cheb)
+
+
 def gaussian_well_ground_state(V0: float, beta: float, L: float = 2.0, n: int = 512):
     """Ground state of -u'' + V u = E u for the well V(x) = -V0 exp(-x^2/(2 beta^2))
     of Section 6, Examples 3 and 4 (1D), which the paper computes with
