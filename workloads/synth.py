@@ -146,8 +146,9 @@ def periodic_1d_256_problem(seed: int = 0, M: int = 256, T: float = 1.0, nsteps:
 def periodic_problem_from_seed(seed: int, dim: int, M: Sequence[int], T: float, nsteps: int,
                                order: int = 8, precision: str = "fp64", name: str = "",
                                A_kind: str = "pulse_sin2") -> Problem:
-    """The 2D (or 1D analogue) periodic recipe: four Gaussian wells with a
-    sinusoidal modulation, a sin^2-enveloped pulse along e1 and a Gaussian u0.
+    """The 2D (or 1D and 3D analogue) periodic recipe: four Gaussian wells
+    with a sinusoidal modulation, a sin^2-enveloped pulse along e1 and a
+    Gaussian u0.
 
     Draw order: c_j ~ U[2,8] (4), p_j ~ U[-2,2]^d (4), s_j ~ U[0.3,0.8] (4),
     E0 ~ U[0.5,2], omega ~ U[5,15], x0 ~ U[-1,1]^d, sigma ~ U[0.3,0.6].
@@ -163,13 +164,13 @@ def periodic_problem_from_seed(seed: int, dim: int, M: Sequence[int], T: float, 
     M = tuple(int(m) for m in M)
     axes = [periodic_grid(m) for m in M]
     X = list(np.meshgrid(*axes, indexing="ij"))
-    images = 1 if dim == 2 else 2
+    images = 1 if dim >= 2 else 2
     V0 = np.zeros(M)
     for j in range(4):
         V0 -= cj[j] * _periodized_gauss(X, pj[j], sj[j], images)
     u0 = _periodized_gauss(X, x0, sig, images).astype(np.complex128)
     u0 = _normalize(u0, (TWO_PI) ** dim / np.prod(M))
-    direction = (1.0, 0.0)
+    direction = (1.0, 0.0) if dim < 3 else (1.0, 0.0, 0.0)
     prob = Problem(name=name or f"periodic{dim}d_seed{seed}", dim=dim, domain="periodic", M=M, T=T,
                    nsteps=nsteps, order=order, u0=u0, V_fields=[V0], f_kind=["sin"],
                    f_params=[(0.1, om)], A_kind="pulse_sin2", A_params=(E0, om, T) + direction,
