@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-well", action="store_true", help="skip the moving-well (potential on the fly) leg")
     ap.add_argument("--no-ionization", action="store_true", help="skip the 1D ionization (Example 3) leg")
     ap.add_argument("--no-1d", action="store_true", help="skip the 1D periodic M = 256 leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D periodic 128^3 leg")
+    ap.add_argument("--runs-3d", type=int, default=3)
     ap.add_argument("--no-long-time", action="store_true",
                     help="skip the long-time free-space leg (Chebyshev-interpolated C-type block)")
     ap.add_argument("--batch-runs", type=int, default=3)
@@ -473,6 +475,57 @@ def periodic_1d_leg(runs: int = 20) -> dict:
             "us_per_time_step": wall * 1e6 / prob.nsteps, "one_workgroup_run_kernel_us": k_us, "error": err}
 
 
+def periodic_3d_leg(runs: int, copies: dict) -> dict:
+    """3D periodic FP64 on the 128^3 workload (seed 50, 500 steps to T = 0.5):
+    graph-replayed whole runs, the error against the stored oracle values,
+    and the per-pass durations of one eager run (dispatch-recorded HIP
+    events): row pass (last axis, recurrence), column pass (axis 0, solve)
+    and the two middle-axis FFT passes."""
+    import torch
+
+    from paper_2001_06113_amd.tdse import (Q_BYTES_COL, Q_BYTES_MID, Q_BYTES_PER_STEP, Q_BYTES_ROW, Q_PROF_MS_COL,
+                                           Q_PROF_MS_MID, Q_PROF_MS_ROW, Q_PROF_N_COL, Q_PROF_N_MID, Q_PROF_N_ROW,
+                                           Plan)
+    from workloads import periodic_3d_128_problem
+
+    dev = torch.device("cuda:0")
+    prob = periodic_3d_128_problem()
+    plan = Plan.from_problem(prob, device=dev)
+    u0 = torch.as_tensor(prob.u0).to(dev)
+    out = torch.empty_like(u0)
+    plan.use_graph(True)
+    plan.run(u0, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        plan.run(u0, out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / runs
+    err = oracle_error("periodic_3d_128", out)
+    plan.use_graph(False)
+    plan.profile(True)
+    plan.run(u0, out)
+    row = plan.query(Q_PROF_MS_ROW) * 1e3 / max(plan.query(Q_PROF_N_ROW), 1)
+    col = plan.query(Q_PROF_MS_COL) * 1e3 / max(plan.query(Q_PROF_N_COL), 1)
+    mid = plan.query(Q_PROF_MS_MID) * 1e3 / max(plan.query(Q_PROF_N_MID), 1)
+    plan.profile(False)
+    row_b, col_b, mid_b = plan.query(Q_BYTES_ROW), plan.query(Q_BYTES_COL), plan.query(Q_BYTES_MID)
+    step_b = plan.query(Q_BYTES_PER_STEP)
+    plan.close()
+    modes = u0.numel()
+
+    def rf(b, us):
+        a = b / (us * 1e-6) / 1e9
+        return {"us": us, "bytes_per_launch": b, "GBps": a, "frac": a / HBM_PEAK_GBS}
+
+    return {"workload": "3D periodic TDSE 128^3, T=0.5, 500 steps AM8, FP64",
+            "value": modes * prob.nsteps / wall, "unit": "mode-updates/s", "ms_per_run": wall * 1e3,
+            "us_per_time_step": wall * 1e6 / prob.nsteps, "error": err,
+            "end_to_end": end_to_end(step_b, prob.nsteps, wall, copies),
+            "row_pass": rf(row_b, row), "col_pass": rf(col_b, col), "mid_pass": rf(mid_b, mid),
+            "adams_step_us_eager": row + col + 2 * mid}
+
+
 def long_time_leg(runs: int = 5) -> dict:
     """The C-type block on Gamma_2 through the Chebyshev interpolant against
     direct sums (Section 4.1): Section 6, Example 2's long-time wave packet
@@ -751,6 +804,8 @@ def main():
         res["ionization"] = ionization_leg()
     if not args.no_long_time:
         res["long_time"] = long_time_leg()
+    if not args.no_3d:
+        res["periodic_3d"] = periodic_3d_leg(args.runs_3d, copies)
     if not args.no_batch:
         res["batch"] = batch_leg(args.batch_runs, copies)
     if not args.no_cpu:

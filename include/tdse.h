@@ -82,11 +82,15 @@ typedef double (*tdse_scalar_fn)(int32_t r, double t, void* ctx);
 typedef void (*tdse_vector_fn)(double t, double* A_out, void* ctx);
 
 /* Problem statement (Section 1: domain, u0 via tdse_set_state, V(x,t), A(t),
- * T, step size, order).  Unused fields may be zero. */
+ * T, step size, order).  Unused fields may be zero.
+ * d = 3 (Section 4.3's setting, periodic scheme of Section 2 in three
+ * dimensions): periodic domain, TDSE_FP64, stored fields (V_kind 0), at most
+ * 2^28 points; single plans (no batch, no adjoint).  Arrays are row-major over
+ * M[0] x M[1] x M[2] with the last axis fastest; A has d components. */
 typedef struct {
-  int32_t dim;             /* 1 or 2                                         */
+  int32_t dim;             /* 1, 2 or 3                                      */
   int32_t domain;          /* TDSE_PERIODIC | TDSE_FREE (FP64 only)          */
-  int32_t M[2];            /* grid points per axis: 2^a or 3*2^a, 8..3072    */
+  int32_t M[3];            /* grid points per axis: 2^a or 3*2^a, 8..3072    */
   double  T;               /* final time > 0                                 */
   int32_t nsteps;          /* number of steps, dt = T / nsteps               */
   int32_t order;           /* implicit Adams order n in {2,4,6,8}            */
@@ -205,6 +209,9 @@ int tdse_far_eval_noalloc(tdse_plan_t plan, const double* xs, int32_t nx, const 
 #define TDSE_Q_STEPS_DONE     1   /* steps taken since set_state               */
 #define TDSE_Q_DT             2
 #define TDSE_Q_BYTES_PER_STEP 3   /* algorithmic HBM bytes of one Adams step   */
+#define TDSE_Q_PROF_MS_MID    5   /* profiling (3D): summed ms of the middle-axis FFT passes */
+#define TDSE_Q_PROF_N_MID     6   /* profiling (3D): number of timed middle-axis passes      */
+#define TDSE_Q_BYTES_MID      7   /* 3D: algorithmic HBM bytes of one middle-axis pass        */
 #define TDSE_Q_PROF_MS_COL    8   /* profiling: summed ms of Adams column passes */
 #define TDSE_Q_PROF_MS_ROW    9   /* profiling: summed ms of Adams row passes  */
 #define TDSE_Q_PROF_N_COL    10   /* profiling: number of timed column passes  */

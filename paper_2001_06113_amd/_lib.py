@@ -12,7 +12,7 @@ VECTOR_FN = C.CFUNCTYPE(None, C.c_double, C.POINTER(C.c_double), C.c_void_p)
 
 class Problem(C.Structure):
     _fields_ = [
-        ("dim", C.c_int32), ("domain", C.c_int32), ("M", C.c_int32 * 2),
+        ("dim", C.c_int32), ("domain", C.c_int32), ("M", C.c_int32 * 3),
         ("T", C.c_double), ("nsteps", C.c_int32), ("order", C.c_int32),
         ("n_start", C.c_int32), ("precision", C.c_int32), ("nV", C.c_int32),
         ("V_fields", C.POINTER(C.c_double)),

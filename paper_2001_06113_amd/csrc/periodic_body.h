@@ -80,15 +80,18 @@ __device__ __forceinline__ void build_phase_table(const LineArgs& a, int nthread
   for (int idx = blk * nthreads + threadIdx.x; idx < total; idx += nblk * nthreads) {
     const int j = idx / per;
     const int kk = idx - j * per;
-    double k, dphi;
-    if (kk < a.M1) {
-      k = (double)signed_mode(kk, a.M1);
-      dphi = a.req.dphi1[j];
-    } else {
-      k = (double)signed_mode(kk - a.M1, a.M2);
-      dphi = a.req.dphi2[j];
+    double th;
+    if (kk >= a.M1) {
+      const double k = (double)signed_mode(kk - a.M1, a.M2);
+      th = -(k * k) * a.req.tau[j] + k * a.req.dphi2[j];
+    } else if (a.Mmid == 0) {
+      const double k = (double)signed_mode(kk, a.M1);
+      th = -(k * k) * a.req.tau[j] + k * a.req.dphi1[j];
+    } else {   // 3D row (k0, k1)
+      const int i0 = kk / a.Mmid;
+      const double k0 = (double)signed_mode(i0, a.M0), k1 = (double)signed_mode(kk - i0 * a.Mmid, a.Mmid);
+      th = -(k0 * k0 + k1 * k1) * a.req.tau[j] + k0 * a.req.dphi0[j] + k1 * a.req.dphi1[j];
     }
-    const double th = -(k * k) * a.req.tau[j] + k * dphi;
     double s, c;
     sincos(th, &s, &c);
     a.ph[idx] = double2{c, s};
@@ -274,6 +277,56 @@ __device__ __forceinline__ void col_body(const LineArgs& a, int line0, int blk, 
   }
   // last, so that its loads and waits delay none of the pass's own
   if (a.req.nj > 0) build_phase_table(a, NT, blk, nblk);
+}
+
+
+// Middle-axis pass of a 3D grid: FFT along axis 1 only (inverse before the
+// column pass, forward after it), in place.  Lines (i0, i2) of N elements at
+// stride elem_stride = M2, grouped in slabs of slab_lines = M2 lines per i0
+// (line l starts at (l / M2) slab_stride + l mod M2); lanes run across
+// consecutive lines as in the column pass.
+template <typename C, int N, int LPW, int TL, bool INV>
+__device__ __forceinline__ void mid_body(const LineArgs& a, int line0, C* lds) {
+  constexpr int NT = LPW * TL;
+  constexpr int EPT = N / TL;
+  constexpr int PITCH = col_lds<C, N, LPW>::PITCH;
+  constexpr bool TWL = col_lds<C, N, LPW>::TWL;
+  C* twl = lds + LPW * PITCH;
+  const int tid = threadIdx.x;
+  const int i = tid % LPW, t = tid / LPW;
+  const int line = line0 + i;
+  const bool active = line < a.nlines;
+  const int64_t base = (int64_t)(line / a.slab_lines) * a.slab_stride + (int64_t)(line % a.slab_lines) * a.line_stride;
+  constexpr int TWN = TWL ? (N + NT - 1) / NT : 1;
+  C twr[TWN];
+  if constexpr (TWL) {
+#pragma unroll
+    for (int k = 0; k < TWN; ++k) {
+      const int q = tid + k * NT;
+      if (N % NT == 0 || q < N) twr[k] = ((const C*)a.tw)[q];
+    }
+  }
+  C v[EPT];
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) v[m] = C{0, 0};
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) v[m] = ((const C*)a.src)[base + (int64_t)(t + TL * m) * a.elem_stride];
+  }
+  if constexpr (TWL) {
+#pragma unroll
+    for (int k = 0; k < TWN; ++k) {
+      const int q = tid + k * NT;
+      if (N % NT == 0 || q < N) twl[q] = twr[k];
+    }
+    __syncthreads();
+  }
+  const C* tw = TWL ? twl : (const C*)a.tw;
+  fft_regs<N, TL, INV>(v, t, &lds[i * PITCH], tw);
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) ((C*)a.dst)[base + (int64_t)(t + TL * m) * a.elem_stride] = v[m];
+  }
 }
 
 

@@ -1,6 +1,7 @@
 // HIP kernels of the periodic marching scheme, gfx950: the per-instance
-// column and row passes (bodies in periodic_body.h), their dispatch over
-// line lengths, and the complex128 -> complex64 narrowing.
+// column and row passes (bodies in periodic_body.h), the middle-axis FFT
+// passes of 3D grids, their dispatch over line lengths, and the
+// complex128 -> complex64 narrowing.
 #include <hip/hip_ext.h>
 
 #include "periodic_body.h"
@@ -15,6 +16,14 @@ __global__ __launch_bounds__(LPW * TL) void k_col(LineArgs a) {
   // tiles sharing a 128-byte line of the potential share an XCD
   const int tile = xcd_tile<(16 / LPW > 1 ? 16 / LPW : 1)>(blockIdx.x, gridDim.x);
   col_body<C, N, LPW, TL>(a, tile * LPW, blockIdx.x, gridDim.x, lds);
+}
+
+// FFT-only pass over the middle axis of a 3D grid (FP64)
+template <int N, int LPW, int TL, bool INV>
+__global__ __launch_bounds__(LPW * TL) void k_mid(LineArgs a) {
+  __shared__ double2 lds[col_lds<double2, N, LPW>::elems];
+  const int tile = xcd_tile<(16 / LPW > 1 ? 16 / LPW : 1)>(blockIdx.x, gridDim.x);
+  mid_body<double2, N, LPW, TL, INV>(a, tile * LPW, lds);
 }
 
 // ---------------------------------------------------------------- row pass
@@ -95,6 +104,26 @@ hipError_t col_pass(int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipE
   return hipGetLastError();
 }
 
+// middle-axis pass: the column pass's schedules (the lines are strided the same way)
+hipError_t mid_pass(int N, bool inverse, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (a.slab_lines < 1) return hipErrorInvalidValue;
+  switch (N) {
+#define X(n)                                                                                          \
+  case n: {                                                                                           \
+    constexpr int L = col_lpw(n), T = col_tl(n);                                                      \
+    const dim3 g((unsigned)((a.nlines + L - 1) / L));                                                 \
+    if (inverse) TDSE_LAUNCH((k_mid<n, L, T, true>), g, dim3(L * T), s, e0, e1, a);                  \
+    else TDSE_LAUNCH((k_mid<n, L, T, false>), g, dim3(L * T), s, e0, e1, a);                         \
+    break;                                                                                            \
+  }
+    TDSE_LINE_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename C>
 hipError_t row_pass(int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (N) {
@@ -126,6 +155,9 @@ hipError_t launch_narrow(const double2* src, float2* dst, int64_t n, hipStream_t
 
 hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   return prec == P_SPLIT ? col_pass<float2>(N, a, s, e0, e1) : col_pass<double2>(N, a, s, e0, e1);
+}
+hipError_t launch_mid_pass(int N, bool inverse, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return mid_pass(N, inverse, a, s, e0, e1);
 }
 hipError_t launch_row_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   return prec == P_SPLIT ? row_pass<float2>(N, a, s, e0, e1) : row_pass<double2>(N, a, s, e0, e1);

@@ -200,7 +200,7 @@ struct TimeFns {
   }
 
   void gl_piece(double a, double b, double* out) const {
-    double tmp[2];
+    double tmp[3];
     for (int c = 0; c < dim; ++c) out[c] = 0.0;
     for (size_t i = 0; i < glx.size(); ++i) {
       const double s = 0.5 * (a + b) + 0.5 * (b - a) * glx[i];
@@ -213,7 +213,7 @@ struct TimeFns {
     if (A_kind == TDSE_A_STEPWISE || A_kind == TDSE_A_CALLBACK) {
       if (A_kind == TDSE_A_CALLBACK) gauss_legendre(24, glx, glw);
       cum.assign((size_t)(nsteps + 1) * dim, 0.0);
-      double piece[2];
+      double piece[3];
       for (int m = 0; m < nsteps; ++m) {
         if (A_kind == TDSE_A_STEPWISE) {
           for (int c = 0; c < dim; ++c) piece[c] = A_steps[(size_t)m * dim + c] * dt;
@@ -226,7 +226,7 @@ struct TimeFns {
   }
 
   void phi(double t, double* out) const {
-    for (int a = 0; a < 2; ++a) out[a] = 0.0;
+    for (int a = 0; a < 3; ++a) out[a] = 0.0;
     switch (A_kind) {
       case TDSE_A_PULSE_SIN2:
       case TDSE_A_PULSE_COS2: {
@@ -244,7 +244,7 @@ struct TimeFns {
           for (int a = 0; a < dim; ++a)
             out[a] = cum[(size_t)ms * dim + a] + A_steps[(size_t)ms * dim + a] * (t - ms * dt);
         } else {
-          double piece[2] = {0, 0};
+          double piece[3] = {0, 0, 0};
           if (std::fabs(t - m * dt) > 1e-15 * std::max(1.0, std::fabs(t))) gl_piece(m * dt, t, piece);
           for (int a = 0; a < dim; ++a) out[a] = cum[(size_t)m * dim + a] + piece[a];
         }
@@ -274,7 +274,12 @@ struct RecLaunch {
 };
 
 struct tdse_plan_s {
+  // grid: M1 x M2 (1D: M1 = 1).  A 3D grid M0 x Mmid x M2 is held as M1 =
+  // M0 Mmid rows of M2: the row pass runs over the last axis, the column pass
+  // over axis 0 (lines of stride Mmid M2), and the middle axis has FFT-only
+  // passes of its own around every column pass.
   int dim = 1, M1 = 1, M2 = 1;
+  int M0 = 1, Mmid = 0;
   int64_t P = 1;
   int order = 8, ns = 6, L = 4, nsteps = 1, nV = 1, precision = TDSE_FP64;
   double T = 1.0, dt = 1.0;
@@ -286,8 +291,8 @@ struct tdse_plan_s {
   struct Stage {
     int prec = P_FP64;
     size_t cplx = 16, real = 8;          // bytes of a complex / real element
-    size_t o_ring = 0, o_tmp = 0, o_V = 0, o_tw1 = 0, o_tw2 = 0;
-    std::vector<char> Vhost, tw1, tw2;   // host copies uploaded at bind
+    size_t o_ring = 0, o_tmp = 0, o_V = 0, o_tw1 = 0, o_tw2 = 0, o_tw3 = 0;
+    std::vector<char> Vhost, tw1, tw2, tw3;   // host copies uploaded at bind (tw3: 3D middle axis)
   } st[2];
   // workspace layout
   size_t o_B = 0, o_u[2] = {0, 0}, o_ph = 0, o_ph32 = 0, total = 0;
@@ -426,7 +431,10 @@ struct tdse_plan_s {
   const void* V(int g) const { return ws + st[g].o_V; }
   double2* ph() const { return (double2*)(ws + o_ph); }
   float2* ph32() const { return o_ph32 ? (float2*)(ws + o_ph32) : nullptr; }
-  const void* tw(int g, int axis) const { return ws + (axis == 0 ? st[g].o_tw1 : st[g].o_tw2); }
+  const void* tw(int g, int axis) const {
+    return ws + (axis == 0 ? st[g].o_tw1 : axis == 1 ? st[g].o_tw2 : st[g].o_tw3);
+  }
+  int col_len() const { return Mmid ? M0 : M1; }   // line length of the column pass
   bool force_fp64 = false;   // run the Adams passes of a split plan in FP64 (adjoint recomputation)
   bool split() const { return precision == TDSE_FP32_SPLIT && !force_fp64; }
 
@@ -469,6 +477,8 @@ LineArgs base_args(const tdse_plan_s* p, int g) {
   std::memset(&a, 0, sizeof(a));
   a.M1 = p->M1;
   a.M2 = p->M2;
+  a.M0 = p->M0;
+  a.Mmid = p->Mmid;
   a.V = p->V(g);
   a.nV = p->nV;
   a.vkind = p->vkind;
@@ -483,11 +493,13 @@ LineArgs base_args(const tdse_plan_s* p, int g) {
   return a;
 }
 
-// column-pass geometry: lines are the M2 columns, elements step by M2
+// column-pass geometry: lines are the M2 columns, elements step by M2 (3D:
+// the Mmid M2 lines along axis 0)
 void col_geom(const tdse_plan_s* p, int g, LineArgs& a) {
+  const int64_t w = p->Mmid ? (int64_t)p->Mmid * p->M2 : p->M2;
   a.line_stride = 1;
-  a.elem_stride = p->M2;
-  a.nlines = p->M2;
+  a.elem_stride = w;
+  a.nlines = (int)w;
   a.tw = p->tw(g, 0);
 }
 void row_geom(const tdse_plan_s* p, int g, LineArgs& a) {
@@ -500,14 +512,18 @@ void row_geom(const tdse_plan_s* p, int g, LineArgs& a) {
 // phase request for E^(j) at t_b, j = 1..nj, over intervals of length j*tau
 void phase_req(const tdse_plan_s* p, LineArgs& a, int nj, double t_b, double tau, bool stepgrid, int m_b) {
   a.req.nj = nj;
-  double pb[2], pa[2];
+  double pb[3], pa[3];
   if (stepgrid) p->tf.phi(p->t_at(m_b), pb);
   else p->tf.phi(t_b, pb);
   for (int j = 1; j <= nj; ++j) {
     if (stepgrid) p->tf.phi(p->t_at(m_b - j), pa);
     else p->tf.phi(t_b - j * tau, pa);
     a.req.tau[j - 1] = j * tau;
-    if (p->dim == 2) {
+    if (p->dim == 3) {
+      a.req.dphi0[j - 1] = pb[0] - pa[0];
+      a.req.dphi1[j - 1] = pb[1] - pa[1];
+      a.req.dphi2[j - 1] = pb[2] - pa[2];
+    } else if (p->dim == 2) {
       a.req.dphi1[j - 1] = pb[0] - pa[0];
       a.req.dphi2[j - 1] = pb[1] - pa[1];
     } else {
@@ -517,6 +533,43 @@ void phase_req(const tdse_plan_s* p, LineArgs& a, int nj, double t_b, double tau
   }
 }
 
+// FFT-only pass along the middle axis of a 3D grid, in place on buf: lines
+// (i0, i2) of Mmid elements at stride M2, slabs of M2 lines per i0
+int launch_mid(const tdse_plan_s* p, int g, void* buf, bool inverse, hipEvent_t e0, hipEvent_t e1) {
+  LineArgs m;
+  std::memset(&m, 0, sizeof(m));
+  m.M1 = p->M1;
+  m.M2 = p->M2;
+  m.M0 = p->M0;
+  m.Mmid = p->Mmid;
+  m.src = buf;
+  m.dst = buf;
+  m.line_stride = 1;
+  m.elem_stride = p->M2;
+  m.nlines = p->M0 * p->M2;
+  m.slab_lines = p->M2;
+  m.slab_stride = (int64_t)p->Mmid * p->M2;
+  m.tw = p->tw(g, 2);
+  const hipError_t e = launch_mid_pass(p->Mmid, inverse, m, p->stream, e0, e1);
+  if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return TDSE_OK;
+}
+
+hipEvent_t next_event(tdse_plan_s* p);
+
+// 3D: the middle-axis pass, timed (kind 5) when profiling
+int launch_mid_timed(const tdse_plan_s* p, int g, void* buf, bool inverse) {
+  tdse_plan_s* q = const_cast<tdse_plan_s*>(p);
+  if (!q->prof) return launch_mid(p, g, buf, inverse, nullptr, nullptr);
+  const size_t first = q->ev_used;
+  hipEvent_t e0 = next_event(q), e1 = next_event(q);
+  if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
+  const int s = launch_mid(p, g, buf, inverse, e0, e1);
+  if (s) return s;
+  q->prof_marks.push_back({first, 5});
+  return TDSE_OK;
+}
+
 int launch(const tdse_plan_s* p, int g, bool col, const LineArgs& a, hipEvent_t e0 = nullptr,
            hipEvent_t e1 = nullptr) {
   if (p->rec) {
@@ -524,9 +577,16 @@ int launch(const tdse_plan_s* p, int g, bool col, const LineArgs& a, hipEvent_t 
     return TDSE_OK;
   }
   const int prec = p->st[g].prec;
-  hipError_t e = col ? launch_col_pass(prec, p->M1, a, p->stream, e0, e1)
+  // 3D: the column pass sees the tile transformed along axis 0 only, so the
+  // middle axis is inverted before a solve and transformed forward after it
+  if (col && p->Mmid && a.mode == C_SOLVE) {
+    const int s = launch_mid_timed(p, g, const_cast<void*>(a.src), true);
+    if (s) return s;
+  }
+  hipError_t e = col ? launch_col_pass(prec, p->col_len(), a, p->stream, e0, e1)
                      : launch_row_pass(prec, p->M2, a, p->stream, e0, e1);
   if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  if (col && p->Mmid) return launch_mid_timed(p, g, a.dst, false);
   return TDSE_OK;
 }
 
@@ -1296,7 +1356,7 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
         s2 += v * v;
       }
       normV = std::max(normV, std::sqrt(s2 * cell));
-      double ph[2];
+      double ph[3];
       p->tf.phi(t, ph);
       for (int a = 0; a < p->dim; ++a) phimax[a] = std::max(phimax[a], std::fabs(ph[a]));
     }
@@ -1368,7 +1428,7 @@ void build_run1d(tdse_plan_s* p) {
     T.insert(T.end(), f, f + MAXV);
   }
   p->r1_oR = (int64_t)T.size();
-  double pb[2], pa[2];
+  double pb[3], pa[3];
   for (int m = 1; m <= ns; ++m) {
     const double t = p->t_at(m - 1);
     for (int l = 0; l < L; ++l) {
@@ -1476,7 +1536,7 @@ void build_persist2d(tdse_plan_s* p) {
   const int N = p->nsteps, ns = p->ns, M = p->M2, nh = p->order - 1;
   std::vector<double>& T = p->p2tab;
   T.clear();
-  double f[MAXV], pb[2], pa[2];
+  double f[MAXV], pb[3], pa[3];
   for (int m = ns + 1; m <= N; ++m) {
     p->fV_at(p->t_at(m), f);
     T.insert(T.end(), f, f + MAXV);
@@ -1893,6 +1953,7 @@ int plan_batch(const tdse_problem_t* probs, int count, tdse_plan_s** out) {
   int64_t elem = 0;
   for (int i = 0; i < count; ++i) {
     if (probs[i].domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "batches hold periodic instances");
+    if (probs[i].dim == 3) return fail(TDSE_EUNSUPPORTED, "batches take 1D and 2D instances");
     tdse_plan_s* q = nullptr;
     const int s = tdse_plan(&probs[i], &q);
     if (s) return s;
@@ -2230,7 +2291,7 @@ struct AdjPh {
     q.ph = ph;
   }
   void set(const tdse_plan_s* p, int e, double tb, double tau) {
-    double pb[2], pa[2];
+    double pb[3], pa[3];
     p->tf.phi(tb, pb);
     p->tf.phi(tb - tau, pa);
     q.tau[e] = tau;
@@ -2255,6 +2316,7 @@ int adj_workers(const tdse_plan_s* p) { return std::max(1, std::min(p->adj_strea
 int adjoint_single(tdse_plan_s* p, char* w, size_t wbytes, int K, const void* u0, const void* lam, int on_device,
                    double* dF_dA, void* dF_du0) {
   if (p->free_space) return fail(TDSE_EUNSUPPORTED, "the adjoint covers the periodic scheme");
+  if (p->dim == 3) return fail(TDSE_EUNSUPPORTED, "the adjoint covers 1D and 2D plans");
   if (p->vkind != TDSE_V_FIELDS) return fail(TDSE_EUNSUPPORTED, "the adjoint takes potentials from stored fields");
   if (p->tf.A_kind != TDSE_A_STEPWISE) return fail(TDSE_EUNSUPPORTED, "the adjoint differentiates stepwise field samples");
   AdjRun R;
@@ -2563,7 +2625,14 @@ const char* tdse_last_error(void) { return g_last_error.c_str(); }
 int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   if (!prob || !out) return fail(TDSE_EINVAL, "NULL argument");
   *out = nullptr;
-  if (prob->dim != 1 && prob->dim != 2) return fail(prob->dim == 3 ? TDSE_EUNSUPPORTED : TDSE_EINVAL, "dim must be 1 or 2");
+  if (prob->dim < 1 || prob->dim > 3) return fail(TDSE_EINVAL, "dim must be 1, 2 or 3");
+  if (prob->dim == 3) {
+    if (prob->domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "3D runs the periodic scheme");
+    if (prob->precision != TDSE_FP64) return fail(TDSE_EUNSUPPORTED, "3D runs in FP64");
+    if (prob->V_kind != TDSE_V_FIELDS) return fail(TDSE_EUNSUPPORTED, "3D takes potentials from stored fields");
+    if ((int64_t)prob->M[0] * prob->M[1] * prob->M[2] > ((int64_t)1 << 28))
+      return fail(TDSE_EINVAL, "3D grid larger than 2^28 points");
+  }
   if (prob->domain != TDSE_PERIODIC && prob->domain != TDSE_FREE) return fail(TDSE_EINVAL, "unknown domain");
   if (prob->precision != TDSE_FP64 && prob->precision != TDSE_FP32_SPLIT) return fail(TDSE_EINVAL, "unknown precision");
   const bool free_dom = prob->domain == TDSE_FREE;
@@ -2595,8 +2664,15 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   tdse_plan_s* p = new (std::nothrow) tdse_plan_s();
   if (!p) return fail(TDSE_ENOMEM, "host allocation failed");
   p->dim = prob->dim;
-  p->M1 = prob->dim == 2 ? prob->M[0] : 1;
-  p->M2 = prob->dim == 2 ? prob->M[1] : prob->M[0];
+  if (prob->dim == 3) {
+    p->M0 = prob->M[0];
+    p->Mmid = prob->M[1];
+    p->M1 = prob->M[0] * prob->M[1];
+    p->M2 = prob->M[2];
+  } else {
+    p->M1 = prob->dim == 2 ? prob->M[0] : 1;
+    p->M2 = prob->dim == 2 ? prob->M[1] : prob->M[0];
+  }
   p->P = (int64_t)p->M1 * p->M2;
   p->order = prob->order;
   p->ns = prob->n_start < 0 ? prob->order - 2 : prob->n_start;
@@ -2667,8 +2743,9 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   }
 
   for (int g = 0; g < 2; ++g) {
-    p->st[g].tw1 = twiddles(p->M1, p->st[g].prec == P_SPLIT);
+    p->st[g].tw1 = twiddles(p->col_len(), p->st[g].prec == P_SPLIT);
     p->st[g].tw2 = twiddles(p->M2, p->st[g].prec == P_SPLIT);
+    if (p->Mmid) p->st[g].tw3 = twiddles(p->Mmid, p->st[g].prec == P_SPLIT);
   }
 
   size_t off = 0;
@@ -2689,12 +2766,14 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
     }
     S.o_tw1 = off; off = align256(off + S.tw1.size());
     S.o_tw2 = off; off = align256(off + S.tw2.size());
+    S.o_tw3 = off; off = align256(off + S.tw3.size());
   }
   if (!split) {
     p->st[1] = p->st[0];
     p->st[1].Vhost.clear();   // no second upload
     p->st[1].tw1.clear();
     p->st[1].tw2.clear();
+    p->st[1].tw3.clear();
   }
   p->o_ph = off; off = align256(off + (size_t)(p->order - 1) * (p->M1 + p->M2) * sizeof(double2));
   if (split) {   // the same table rounded to complex64, read by the split row pass
@@ -2756,6 +2835,8 @@ int tdse_bind(tdse_plan_t p, void* ws, size_t bytes, void* stream) {
       HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw1, S.tw1.data(), S.tw1.size(), hipMemcpyHostToDevice, p->stream));
     if (!S.tw2.empty())
       HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw2, S.tw2.data(), S.tw2.size(), hipMemcpyHostToDevice, p->stream));
+    if (!S.tw3.empty())
+      HIP_TRY(hipMemcpyAsync(p->ws + S.o_tw3, S.tw3.data(), S.tw3.size(), hipMemcpyHostToDevice, p->stream));
   }
   if (p->run1d) {
     const int s = upload_run1d(p);
@@ -3162,19 +3243,21 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     // per mode: B in/out (32), history ring n-2 reads + 1 write (16 (n-1)),
     // two tile round trips (64), the potential fields (8 nV)
     const double c = (double)p->st[1].cplx, r = (double)p->st[1].real;
-    const double per = 32.0 + c * (p->order - 1) + (p->dim == 2 ? 4 * c : 2 * c) + r * p->nV;
+    const double per = 32.0 + c * (p->order - 1) + (p->dim == 3 ? 8 * c : p->dim == 2 ? 4 * c : 2 * c) + r * p->nV;
     *value = per * (double)p->P;
     return TDSE_OK;
   }
   if ((key >= TDSE_Q_PROF_MS_COL && key <= TDSE_Q_PROF_N_ROW) || key == TDSE_Q_PROF_MS_FAR ||
       key == TDSE_Q_PROF_N_FAR || key == TDSE_Q_PROF_MS_RUN1D || key == TDSE_Q_PROF_N_RUN1D ||
-      key == TDSE_Q_PROF_MS_PERSIST || key == TDSE_Q_PROF_N_PERSIST) {
+      key == TDSE_Q_PROF_MS_PERSIST || key == TDSE_Q_PROF_N_PERSIST || key == TDSE_Q_PROF_MS_MID ||
+      key == TDSE_Q_PROF_N_MID) {
     const int kind = (key == TDSE_Q_PROF_MS_FAR || key == TDSE_Q_PROF_N_FAR)        ? 2
                      : (key == TDSE_Q_PROF_MS_RUN1D || key == TDSE_Q_PROF_N_RUN1D) ? 3
                      : (key == TDSE_Q_PROF_MS_PERSIST || key == TDSE_Q_PROF_N_PERSIST) ? 4
+                     : (key == TDSE_Q_PROF_MS_MID || key == TDSE_Q_PROF_N_MID) ? 5
                      : ((key == TDSE_Q_PROF_MS_COL || key == TDSE_Q_PROF_N_COL) ? 0 : 1);
     const bool count = key == TDSE_Q_PROF_N_COL || key == TDSE_Q_PROF_N_ROW || key == TDSE_Q_PROF_N_FAR ||
-                       key == TDSE_Q_PROF_N_RUN1D || key == TDSE_Q_PROF_N_PERSIST;
+                       key == TDSE_Q_PROF_N_RUN1D || key == TDSE_Q_PROF_N_PERSIST || key == TDSE_Q_PROF_N_MID;
     if (!p->prof_marks.empty()) HIP_TRY(hipStreamSynchronize(p->stream));
     double ms = 0.0, nk = 0.0;
     for (auto& mk : p->prof_marks) {
@@ -3185,6 +3268,11 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
       nk += 1.0;
     }
     *value = count ? nk : ms;
+    return TDSE_OK;
+  }
+  if (key == TDSE_Q_BYTES_MID) {   // 3D middle-axis pass: tile in and out
+    if (!p->Mmid) return fail(TDSE_EINVAL, "no middle axis (3D plans only)");
+    *value = 2.0 * (double)p->st[1].cplx * (double)p->P;
     return TDSE_OK;
   }
   if (key == TDSE_Q_BYTES_COL || key == TDSE_Q_BYTES_ROW) {
@@ -3199,7 +3287,7 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
   if (key >= TDSE_Q_MU && key < TDSE_Q_MU + p->order) { *value = p->mu[key - TDSE_Q_MU]; return TDSE_OK; }
   if (key >= TDSE_Q_RICHARDSON && key < TDSE_Q_RICHARDSON + p->L) { *value = p->rich[key - TDSE_Q_RICHARDSON]; return TDSE_OK; }
   if (key >= TDSE_Q_PHI && key < TDSE_Q_PHI + p->dim) {
-    double ph[2];
+    double ph[3];
     p->tf.phi(p->T, ph);
     *value = ph[key - TDSE_Q_PHI];
     return TDSE_OK;

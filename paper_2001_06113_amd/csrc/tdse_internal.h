@@ -29,9 +29,12 @@ enum Precision : int { P_FP64 = 0, P_SPLIT = 1 };
 
 // Phase entries a column pass precomputes for the next row pass:
 // theta_a(k) = -k^2 tau_j + k dphi_a[j], table ph[(j-1)(M1+M2) + kidx].
+// In 3D the row index combines axes 0 and 1 (k0, k1): its entry is
+// -(k0^2 + k1^2) tau_j + k0 dphi0[j] + k1 dphi1[j].
 struct PhaseReq {
   int nj;
   double tau[MAXH];
+  double dphi0[MAXH];
   double dphi1[MAXH];
   double dphi2[MAXH];
 };
@@ -45,7 +48,12 @@ struct LineArgs {
   void* dst;           // tile destination (transform precision)
   int64_t line_stride, elem_stride;
   int nlines;
-  int M1, M2;          // grid (M1 = 1 for a 1D problem)
+  int M1, M2;          // grid (M1 = 1 for a 1D problem); 3D: M1 = M0 Mmid rows of M2
+  int M0, Mmid;        // 3D: the two leading axes (Mmid = 0 in 1D and 2D)
+  // lines in slabs (the middle axis of a 3D grid): line l starts at
+  // (l / slab_lines) slab_stride + (l % slab_lines) line_stride; 0: no slabs
+  int slab_lines;
+  int64_t slab_stride;
   const void* tw;      // twiddles of this line length (transform precision)
   int mode;
   // potential V = sum_r fV[r] V_r (vkind 0), or for vkind 1 the moving
@@ -312,6 +320,8 @@ hipError_t launch_diffnorm(const float2* a32, const double2* a64, const double2*
 // the kernel's own start and end.  Return a hipError_t.
 hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
+hipError_t launch_mid_pass(int N, bool inverse, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);   // 3D middle axis, FP64, in place (a.src == a.dst)
 hipError_t launch_row_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
 bool line_length_supported(int N);

@@ -18,6 +18,7 @@ A_KINDS = {"none": 0, "pulse_sin2": 1, "callback": 2, "stepwise": 3, "pulse_cos2
 Q_MODES, Q_STEPS_DONE, Q_DT, Q_BYTES_PER_STEP = 0, 1, 2, 3
 Q_PROF_MS_COL, Q_PROF_MS_ROW, Q_PROF_N_COL, Q_PROF_N_ROW = 8, 9, 10, 11
 Q_BYTES_COL, Q_BYTES_ROW = 12, 13
+Q_PROF_MS_MID, Q_PROF_N_MID, Q_BYTES_MID = 5, 6, 7
 Q_PROF_MS_FAR, Q_PROF_N_FAR = 14, 15
 Q_MU, Q_RICHARDSON, Q_PHI = 16, 32, 64
 Q_INSTANCES, Q_INST_OFFSET, Q_INST_EPT_COL, Q_INST_EPT_ROW = 4, 4096, 8192, 12288

@@ -15,6 +15,7 @@ Cases (one file each, tests/golden/<case>_oracle_sample.txt):
                      to T = 2 pi / 15, every 8th point per axis
   batch_64           the 64 uneven periodic instances (seeds 4000 + i), 500 steps to T = 2,
                      stepwise field; 1D every (M/64)-th point, 2D every (M/16)-th point per axis
+  periodic_3d_128    3D periodic, 128^3, 500 steps to T = 0.5 (seed 50), every 8th point per axis
   example2_long_time_nr5
                      Section 6, Example 2's long-time wave packet: 1D free space, M = 128,
                      nu = 1024, q = 16, n_r = 5, 1000 steps to T = 1000, the C-type block
@@ -22,7 +23,8 @@ Cases (one file each, tests/golden/<case>_oracle_sample.txt):
 
 File format: "# key value" header lines (the case, the full-grid 2-norm of the
 oracle's u(T) per instance, the sampling strides, free space: H per axis), then
-one line per sample "inst i j Re(u) Im(u)" (1D: j = 0 and i the grid index).
+one line per sample "inst i j Re(u) Im(u)" (1D: j = 0 and i the grid index;
+3D: "inst i j k Re(u) Im(u)").
 
     python tests/golden/make_bench_oracle_samples.py CASE [CASE ...]
 """
@@ -39,7 +41,7 @@ from oracle.freespace import FreeSpaceOracle  # noqa: E402
 from oracle.periodic import PeriodicOracle  # noqa: E402
 from workloads import (batch_64_problems, example2_long_time_problem, free_2d_256_problem,  # noqa: E402
                        moving_well_problem, periodic_1d_256_problem, periodic_2d_512_problem,
-                       periodic_2d_1024_problem)
+                       periodic_2d_1024_problem, periodic_3d_128_problem)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -49,6 +51,12 @@ def _sample_lines(inst, u, stride):
     if u.ndim == 1:
         for i in range(0, u.shape[0], stride):
             out.append(f"{inst} {i} 0 {float(u[i].real)!r} {float(u[i].imag)!r}")
+    elif u.ndim == 3:
+        for i in range(0, u.shape[0], stride):
+            for j in range(0, u.shape[1], stride):
+                for k in range(0, u.shape[2], stride):
+                    v = u[i, j, k]
+                    out.append(f"{inst} {i} {j} {k} {float(v.real)!r} {float(v.imag)!r}")
     else:
         for i in range(0, u.shape[0], stride):
             for j in range(0, u.shape[1], stride):
@@ -67,6 +75,7 @@ def cases():
         "batch_64": lambda: [("periodic", p, p.M[0] // 16, p.M[0] // 64)
                              for p in batch_64_problems(precision="fp64")],
         "example2_long_time_nr5": lambda: [("free", example2_long_time_problem(5), 1, 1)],
+        "periodic_3d_128": lambda: [("periodic", periodic_3d_128_problem(), 8, 8)],
     }
 
 

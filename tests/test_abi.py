@@ -46,6 +46,7 @@ def _problem(dim=2, M=(32, 64), T=1.0, nsteps=100, order=8, A=None, nV=1, f=None
     p.p, p.q, p.panels, p.eps, p.H = fs_p, q, panels, eps, H
     p.cheb = cheb
     p.M[0], p.M[1] = M[0], (M[1] if len(M) > 1 else 0)
+    p.M[2] = M[2] if len(M) > 2 else 0
     p.T = T
     p.nsteps = nsteps
     p.order = order
@@ -53,7 +54,7 @@ def _problem(dim=2, M=(32, 64), T=1.0, nsteps=100, order=8, A=None, nV=1, f=None
     p.precision = precision
     p.nV = nV
     size = int(np.prod(M[:dim]))
-    V = np.zeros(nV * size)
+    V = np.zeros(nV * size if size <= (1 << 24) else 1)   # oversized grids are refused before V is read
     p._keep = [V]
     p.V_fields = V.ctypes.data_as(C.POINTER(C.c_double))
     if f is not None:
@@ -76,7 +77,12 @@ def _plan(lib, p):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(dim=3), -2),
+    (dict(dim=4), -1),
+    (dict(dim=3), -1),                               # third axis of size 0
+    (dict(dim=3, M=(32, 64, 16), domain=1), -2),     # 3D runs the periodic scheme
+    (dict(dim=3, M=(32, 64, 16), precision=1), -2),  # 3D runs in FP64
+    (dict(dim=3, M=(32, 64, 30)), -1),
+    (dict(dim=3, M=(1024, 1024, 512)), -1),          # more than 2^28 points
     (dict(dim=0), -1),
     (dict(M=(30, 64)), -1),          # not 2^a 3^b
     (dict(M=(6, 64)), -1),           # too small

@@ -18,7 +18,7 @@ GOLDEN = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 
 def load_samples(case: str) -> Dict[int, dict]:
-    """{instance: {"idx": int [n, 2], "val": complex [n], "norm": float,
+    """{instance: {"idx": int [n, 2] (3D: [n, 3]), "val": complex [n], "norm": float,
     "stride": int, "shape": tuple, "H": list (free space)}} of one case file."""
     path = os.path.join(GOLDEN, f"{case}_oracle_sample.txt")
     inst: Dict[int, dict] = {}
@@ -45,8 +45,9 @@ def load_samples(case: str) -> Dict[int, dict]:
             rows.setdefault(int(parts[0]), []).append(parts[1:])
     for i, r in rows.items():
         arr = np.array(r, dtype=object)
-        inst[i]["idx"] = arr[:, :2].astype(np.int64)
-        inst[i]["val"] = arr[:, 2].astype(np.float64) + 1j * arr[:, 3].astype(np.float64)
+        nd = arr.shape[1] - 2   # 1D and 2D files carry two indices, 3D files three
+        inst[i]["idx"] = arr[:, :nd].astype(np.int64)
+        inst[i]["val"] = arr[:, nd].astype(np.float64) + 1j * arr[:, nd + 1].astype(np.float64)
     return inst
 
 
@@ -55,7 +56,7 @@ def sampled_error(u: np.ndarray, ref: dict) -> dict:
     the stored points, and the relative deviation of the full-grid norm."""
     u = np.asarray(u)
     idx = ref["idx"]
-    got = u[idx[:, 0]] if u.ndim == 1 else u[idx[:, 0], idx[:, 1]]
+    got = u[idx[:, 0]] if u.ndim == 1 else u[tuple(idx[:, a] for a in range(u.ndim))]
     want = ref["val"]
     return {"rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
             "max_abs_rel": float(np.max(np.abs(got - want)) / np.max(np.abs(want))),

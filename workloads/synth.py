@@ -303,6 +303,14 @@ def free_problem_from_seed(seed: int, dim: int, M: Sequence[int], T: float, nste
     return prob
 
 
+def periodic_3d_128_problem(seed: int = 50, M: int = 128, T: float = 0.5, nsteps: int = 500,
+                            order: int = 8) -> Problem:
+    """3D periodic, M^3 = 128^3 points (2,097,152 modes), the periodic recipe
+    in three dimensions (seed 50): four modulated Gaussian wells, a sin^2
+    pulse along e1, a Gaussian u0; 500 steps to T = 0.5, FP64."""
+    return periodic_problem_from_seed(seed, 3, (M, M, M), T, nsteps, order, name="periodic-3d-128")
+
+
 def free_2d_256_problem(seed: int = 2, M: int = 256, T: float = 1.0, nsteps: int = 1000, order: int = 8,
                nu: int = 2048) -> Problem:
     """2D free space, 256 x 256 physical points, eps = 1e-10, p = 8, q = 10,
