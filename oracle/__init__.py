@@ -19,6 +19,7 @@ Modules
   quadrature Gauss-Legendre and Alpert end-corrected trapezoid rules on the
              contour Gamma (Section 3.4)
   chebyshev  C-type transforms through the Chebyshev interpolant (Section 4.1)
+  potential  potentials given as samples at the step times, interpolated in time
   freespace  the complex-frequency scheme by dense transforms (Sections 3.3-3.4),
              and its representation evaluated at arbitrary points (Remark on
              evaluation outside [-1,1])

@@ -29,6 +29,7 @@ import numpy as np
 
 from .adams import adams_coefficients, richardson_extrapolate
 from .chebyshev import c_forward, c_inverse, choose_NT
+from .potential import sampled_V
 from .periodic import make_phi
 from .quadrature import choose_H, gamma_rule
 
@@ -151,6 +152,8 @@ class FreeSpaceOracle:
     # --- problem data ----------------------------------------------------------
     def V(self, t: float) -> np.ndarray:
         p = self.prob
+        if getattr(p, "V_kind", "fields") == "sampled":
+            return sampled_V(p.V_samples, t, p.dt)
         out = np.zeros(self.shape)
         for r, Vr in enumerate(p.V_fields):
             out = out + p.f(r, t) * Vr

@@ -29,6 +29,7 @@ from typing import Callable, List, Optional
 import numpy as np
 
 from .adams import adams_coefficients, richardson_extrapolate
+from .potential import sampled_V
 
 
 def make_phi(prob) -> Callable[[float], np.ndarray]:
@@ -115,6 +116,8 @@ class PeriodicOracle:
         p = self.prob
         if getattr(p, "V_kind", "fields") == "moving_well":
             return self.moving_well(t)
+        if getattr(p, "V_kind", "fields") == "sampled":
+            return sampled_V(p.V_samples, t, p.dt)
         out = np.zeros(self.shape)
         for r, Vr in enumerate(p.V_fields):
             out = out + p.f(r, t) * Vr

@@ -11,7 +11,7 @@ import pytest
 from workloads.golden import GOLDEN, load_samples, sampled_error
 
 CASES = ["periodic_1d_256", "periodic_2d_512", "periodic_2d_1024", "free_2d_256_default_h", "moving_well_2d_512", "batch_64",
-         "example2_long_time_nr5"]
+         "example2_long_time_nr5", "periodic_3d_128"]
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -20,10 +20,9 @@ def test_sample_file_is_well_formed(case):
     assert len(inst) == (64 if case == "batch_64" else 1)
     for i, d in inst.items():
         s, shape = d["stride"], d["shape"]
-        grid = [range(0, m, s) for m in shape]
-        want = len(grid[0]) * (len(grid[1]) if len(shape) == 2 else 1)
+        want = int(np.prod([len(range(0, m, s)) for m in shape]))
         assert len(d["val"]) == want, (i, len(d["val"]), want)
-        assert np.all(d["idx"][:, 0] % s == 0) and np.all(d["idx"][:, 1] % s == 0)
+        assert np.all(d["idx"] % s == 0)
         assert np.isfinite(d["norm"]) and d["norm"] > 0
         assert np.all(np.isfinite(d["val"]))
         # the samples' norm is consistent with the full-grid norm

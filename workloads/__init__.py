@@ -13,6 +13,7 @@ from .synth import (  # noqa: F401
     free_2d_256_problem,
     periodic_2d_1024_problem,
     periodic_3d_128_problem,
+    sampled_potential_problem,
     batch_64_problems,
     periodic_problem_from_seed,
     free_problem_from_seed,

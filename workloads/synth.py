@@ -62,6 +62,8 @@ class Problem:
     # with V_well = (V0, beta, c_0[, c_1]) (Example 1 of Section 6)
     V_kind: str = "fields"
     V_well: Tuple[float, ...] = ()
+    # V_kind "sampled": V(x, t_n) at the step times t_n = n dt, [nsteps + 1, *M]
+    V_samples: Optional[np.ndarray] = None
     meta: dict = field(default_factory=dict)
 
     @property
@@ -300,6 +302,52 @@ def free_problem_from_seed(seed: int, dim: int, M: Sequence[int], T: float, nste
     if A_kind == "none":
         prob.A_kind = "none"
         prob.A_params = ()
+    return prob
+
+
+def sampled_potential_problem(base: Problem, depth: float = 6.0, width: float = 0.35, radius: float = 1.0,
+                              omega: float = 20.0) -> Problem:
+    """The problem `base` (periodic or free recipe) with its potential replaced
+    by a general, non-separable V(x, t) given as samples at the step times
+    t_n = n dt (V_kind "sampled"): the base fields with their time factors
+    plus a well of varying depth and width circling the origin,
+        W(x, t) = -depth (1 + 0.3 sin(omega t)) exp(-|x - c(t)|^2 / (2 b(t)^2)),
+        c(t) = radius (cos(omega t / 2), sin(omega t / 2), 0)[:d],
+        b(t) = width (1 + 0.2 cos(omega t)).
+    In free space the geometry is scaled by 0.3 into [-1, 1]^d and the well is
+    windowed by the recipe's bump; on the periodic box it is periodized."""
+    import copy
+
+    prob = copy.copy(base)
+    dim, M = base.dim, base.M
+    free = base.domain == "free"
+    scale = 0.3 if free else 1.0
+    g = free_grid if free else periodic_grid
+    X = list(np.meshgrid(*[g(m) for m in M], indexing="ij"))
+    win = np.ones(M)
+    if free:
+        for a in range(dim):
+            win = win * _bump(X[a])
+    samples = np.zeros((base.nsteps + 1,) + tuple(M))
+    for n in range(base.nsteps + 1):
+        t = n * base.dt
+        v = np.zeros(M)
+        for r, Vr in enumerate(base.V_fields):
+            v = v + base.f(r, t) * Vr
+        c = scale * radius * np.array([np.cos(0.5 * omega * t), np.sin(0.5 * omega * t), 0.0])[:dim]
+        b = scale * width * (1.0 + 0.2 * np.cos(omega * t))
+        d = depth * (1.0 + 0.3 * np.sin(omega * t))
+        if free:
+            w = np.exp(-sum((X[a] - c[a]) ** 2 for a in range(dim)) / (2.0 * b * b)) * win
+        else:
+            w = _periodized_gauss(X, c, np.sqrt(2.0) * b, images=1)
+        samples[n] = v - d * w
+    prob.V_kind = "sampled"
+    prob.V_samples = samples
+    prob.V_fields = []
+    prob.f_kind = []
+    prob.f_params = []
+    prob.name = base.name + "-sampled"
     return prob
 
 
