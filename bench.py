@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-ionization", action="store_true", help="skip the 1D ionization (Example 3) leg")
     ap.add_argument("--no-1d", action="store_true", help="skip the 1D periodic M = 256 leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D periodic 128^3 leg")
+    ap.add_argument("--no-sampled", action="store_true", help="skip the sampled-potential 512^2 leg")
     ap.add_argument("--runs-3d", type=int, default=3)
     ap.add_argument("--no-long-time", action="store_true",
                     help="skip the long-time free-space leg (Chebyshev-interpolated C-type block)")
@@ -526,6 +527,49 @@ def periodic_3d_leg(runs: int, copies: dict) -> dict:
             "adams_step_us_eager": row + col + 2 * mid}
 
 
+def sampled_leg(runs: int, copies: dict) -> dict:
+    """A general non-separable potential given as samples at the step times
+    (TDSE_V_SAMPLED) on the 512^2 grid (seed 1, 500 steps, dt = 1e-3):
+    graph-replayed whole runs (two passes per step: the persistent launch
+    takes stored fields only), the error against the stored oracle values,
+    and the per-pass durations of one eager run."""
+    import torch
+
+    from paper_2001_06113_amd.tdse import (Q_BYTES_COL, Q_BYTES_PER_STEP, Q_BYTES_ROW, Q_PROF_MS_COL, Q_PROF_MS_ROW,
+                                           Q_PROF_N_COL, Q_PROF_N_ROW, Plan)
+    from workloads import sampled_2d_512_problem
+
+    dev = torch.device("cuda:0")
+    prob = sampled_2d_512_problem()
+    plan = Plan.from_problem(prob, device=dev)
+    u0 = torch.as_tensor(prob.u0).to(dev)
+    out = torch.empty_like(u0)
+    plan.use_graph(True)
+    plan.run(u0, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        plan.run(u0, out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / runs
+    err = oracle_error("sampled_2d_512", out)
+    plan.use_graph(False)
+    plan.profile(True)
+    plan.run(u0, out)
+    row = plan.query(Q_PROF_MS_ROW) * 1e3 / max(plan.query(Q_PROF_N_ROW), 1)
+    col = plan.query(Q_PROF_MS_COL) * 1e3 / max(plan.query(Q_PROF_N_COL), 1)
+    plan.profile(False)
+    step_b, row_b, col_b = plan.query(Q_BYTES_PER_STEP), plan.query(Q_BYTES_ROW), plan.query(Q_BYTES_COL)
+    plan.close()
+    samples_gb = prob.V_samples.nbytes / 1e9
+    return {"workload": "2D periodic 512x512, general non-separable V(x,t) given by 501 samples in time "
+                        "(4 Gaussian wells modulated + a breathing well circling the origin), 500 steps, FP64",
+            "value": u0.numel() * prob.nsteps / wall, "unit": "mode-updates/s", "ms_per_run": wall * 1e3,
+            "us_per_time_step": wall * 1e6 / prob.nsteps, "samples_GB_in_HBM": samples_gb, "error": err,
+            "end_to_end": end_to_end(step_b, prob.nsteps, wall, copies),
+            "row_pass_us": row, "col_pass_us": col, "row_bytes_per_launch": row_b, "col_bytes_per_launch": col_b}
+
+
 def long_time_leg(runs: int = 5) -> dict:
     """The C-type block on Gamma_2 through the Chebyshev interpolant against
     direct sums (Section 4.1): Section 6, Example 2's long-time wave packet
@@ -806,6 +850,8 @@ def main():
         res["long_time"] = long_time_leg()
     if not args.no_3d:
         res["periodic_3d"] = periodic_3d_leg(args.runs_3d, copies)
+    if not args.no_sampled:
+        res["sampled"] = sampled_leg(3, copies)
     if not args.no_batch:
         res["batch"] = batch_leg(args.batch_runs, copies)
     if not args.no_cpu:

@@ -71,6 +71,14 @@ extern "C" {
                                   V_params = {V0, beta, c[0], c[1]} (c[a] along axis a; 0 < beta <= 1, so at most
                                   three images per axis lie within 9.2 beta of a point);
                                   periodic plans; no fields (nV = 0, V_fields NULL) */
+#define TDSE_V_SAMPLED   2     /* a general V(x, t) given by its samples at the step times t_n = n dt:
+                                  V_fields = [nsteps + 1][prod M] (nV ignored).  At a step time the sample;
+                                  between step times (the Richardson start-up's sub-steps) the degree-7
+                                  Lagrange interpolant through the eight nearest samples
+                                  t_n0..t_n0+7, n0 = clamp(floor(t/dt) - 3, 0, nsteps - 7) (every sample
+                                  when nsteps < 7), whose O(dt^8) error matches the scheme's order.
+                                  Periodic and free-space single plans, 1D to 3D; at most 64 GiB of
+                                  samples; no batch, no adjoint */
 
 #define TDSE_A_NONE      0     /* A = 0                                        */
 #define TDSE_A_PULSE_SIN2 1    /* A = E0 sin^2(pi t/Tp) sin(w t) dir; A_params = {E0, w, Tp, dir[0..d-1]} */
@@ -96,7 +104,7 @@ typedef struct {
   int32_t order;           /* implicit Adams order n in {2,4,6,8}            */
   int32_t n_start;         /* Richardson start-up steps; < 0 means n - 2     */
   int32_t precision;       /* TDSE_FP64 | TDSE_FP32_SPLIT                    */
-  int32_t nV;              /* number of spatial fields, 1..8 (0: V_kind well) */
+  int32_t nV;              /* number of spatial fields, 1..8 (0: V_kind well; ignored: sampled) */
   const double* V_fields;  /* host [nV][prod M] real, last axis fastest      */
   int32_t f_kind;          /* TDSE_F_*                                       */
   const double* f_params;  /* TDSE_F_SIN: [nV][2] = (amp, omega)             */

@@ -443,6 +443,39 @@ struct tdse_plan_s {
   int vkind = TDSE_V_FIELDS;
   double well[4] = {0.0, 0.0, 0.0, 0.0};
   double well_k = 0.0;
+  int64_t nsamp = 0;   // TDSE_V_SAMPLED: samples V(., t_n), n = 0..nsteps
+  // V(., t) as a weighted sum of stored fields: weights f[0..k) (k returned)
+  // of the fields starting at field *first.  Sampled V: the sample at a step
+  // time; elsewhere the degree-7 Lagrange interpolant through the eight
+  // samples n0..n0+7, n0 = clamp(floor(t/dt) - 3, 0, nsteps - 7) (every
+  // sample when nsteps < 7); a time within 1e-9 dt of a step time is that
+  // step time.
+  int V_window(double t, double* f, int64_t* first) const {
+    if (vkind != TDSE_V_SAMPLED) {
+      fV_at(t, f);
+      *first = 0;
+      return nV;
+    }
+    for (int r = 0; r < MAXV; ++r) f[r] = 0.0;
+    const double sv = t / dt;
+    const double nr = std::nearbyint(sv);
+    if (std::fabs(sv - nr) < 1e-9 && nr >= 0.0 && nr <= (double)nsteps) {
+      f[0] = 1.0;
+      *first = (int64_t)nr;
+      return 1;
+    }
+    const int count = std::min(MAXV, nsteps + 1);
+    int64_t n0 = (int64_t)std::floor(sv) - (count / 2 - 1);
+    n0 = std::min<int64_t>(std::max<int64_t>(n0, 0), (int64_t)nsteps + 1 - count);
+    for (int i = 0; i < count; ++i) {
+      double w = 1.0;
+      for (int j = 0; j < count; ++j)
+        if (j != i) w *= (sv - (double)(n0 + j)) / (double)(i - j);
+      f[i] = w;
+    }
+    *first = n0;
+    return count;
+  }
   void fV_at(double t, double* f) const {
     for (int r = 0; r < MAXV; ++r) f[r] = r < nV ? tf.f(r, t) : 0.0;
     if (vkind == TDSE_V_MOVING_WELL) {
@@ -491,6 +524,17 @@ LineArgs base_args(const tdse_plan_s* p, int g) {
   a.ph32 = p->ph32();
   a.slot_w = -1;
   return a;
+}
+
+// the potential of a pass at time t: weights, and for a sampled V the window
+// of samples (a.V moved to its first sample, a.nV its length)
+void set_V(const tdse_plan_s* p, int g, LineArgs& a, double t) {
+  int64_t first = 0;
+  const int k = p->V_window(t, a.fV, &first);
+  if (p->vkind == TDSE_V_SAMPLED) {
+    a.V = (const char*)p->V(g) + first * p->P * (int64_t)sizeof(double);
+    a.nV = k;
+  }
 }
 
 // column-pass geometry: lines are the M2 columns, elements step by M2 (3D:
@@ -624,7 +668,7 @@ int op_history(tdse_plan_s* p, int m) {
   a.mode = C_FWD;
   a.src = p->u(p->ucur);
   a.dst = p->tmp(g);
-  p->fV_at(p->t_at(m), a.fV);
+  set_V(p, g, a, p->t_at(m));
   a.alpha_re = 0.0; a.alpha_im = 0.0; a.beta_re = 1.0; a.beta_im = 0.0;
   int s = launch(p, g, true, a);
   if (s) return s;
@@ -650,7 +694,7 @@ int op_richardson(tdse_plan_s* p, int m) {
     a.mode = C_FWD;
     a.src = p->u(src);
     a.dst = p->tmp(g);
-    p->fV_at(t, a.fV);
+    set_V(p, g, a, t);
     a.alpha_re = 1.0; a.alpha_im = 0.0; a.beta_re = 0.0; a.beta_im = -0.5 * delta;
     phase_req(p, a, 1, t + delta, delta, false, 0);
     int s = launch(p, g, true, a);
@@ -671,7 +715,7 @@ int op_richardson(tdse_plan_s* p, int m) {
       c.mode = C_SOLVE;
       c.src = p->tmp(g);
       c.dst = p->tmp(g);
-      p->fV_at(ts1, c.fV);
+      set_V(p, g, c, ts1);
       c.csolve = 0.5 * delta;
       if (last) {
         c.uacc = p->u(acc);
@@ -752,7 +796,7 @@ int op_fp64_output(tdse_plan_s* p, int m) {
   c.mode = C_SOLVE;
   c.src = p->tmp(g);
   c.dst = p->tmp(g);
-  p->fV_at(p->t_at(m), c.fV);
+  set_V(p, g, c, p->t_at(m));
   c.csolve = p->mu[0] * p->dt;
   c.uout = p->u(p->ucur);
   return launch(p, g, true, c);
@@ -772,7 +816,7 @@ int op_am_step(tdse_plan_s* p, int m, bool write_u) {
   c.mode = C_SOLVE;
   c.src = p->tmp(g);
   c.dst = p->tmp(g);
-  p->fV_at(p->t_at(m), c.fV);
+  set_V(p, g, c, p->t_at(m));
   c.csolve = p->mu[0] * p->dt;
   if (write_u) c.uout = p->u(p->ucur);
   if (m < p->nsteps) phase_req(p, c, n - 1, 0.0, p->dt, true, m + 1);
@@ -1165,6 +1209,16 @@ FSArgs fs_args(const tdse_plan_s* p) {
   return a;
 }
 
+// the potential of a free-space pass at time t (see the periodic set_V)
+void set_V(const tdse_plan_s* p, int, FSArgs& a, double t) {
+  int64_t first = 0;
+  const int k = p->V_window(t, a.fV, &first);
+  if (p->vkind == TDSE_V_SAMPLED) {
+    a.V = (const double*)(p->ws + p->o_Vf) + first * p->P;
+    a.nV = k;
+  }
+}
+
 int fs_launch(tdse_plan_s* p, bool col, const FSArgs& a, bool timed = false) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const size_t first = p->ev_used;
@@ -1198,7 +1252,7 @@ int fs_forward(tdse_plan_s* p, double t, double ar, double ai, double br, double
   FSArgs a = fs_args(p);
   a.mode = C_FWD;
   a.usrc = p->u(p->ucur);
-  p->fV_at(t, a.fV);
+  set_V(p, 0, a, t);
   a.alpha_re = ar; a.alpha_im = ai; a.beta_re = br; a.beta_im = bi;
   int s = fs_launch(p, true, a);
   if (s) return s;
@@ -1238,7 +1292,7 @@ int fs_richardson(tdse_plan_s* p, int m) {
       const bool last = (k == nsub - 1);
       FSArgs c = fs_args(p);
       c.mode = C_SOLVE;
-      p->fV_at(ts1, c.fV);
+      set_V(p, 0, c, ts1);
       c.csolve = 0.5 * delta;
       if (last) {
         c.uacc = p->u(acc);
@@ -1290,7 +1344,7 @@ int fs_am_step(tdse_plan_s* p, int m, bool write_u) {
   const int n = p->order;
   FSArgs c = fs_args(p);
   c.mode = C_SOLVE;
-  p->fV_at(p->t_at(m), c.fV);
+  set_V(p, 0, c, p->t_at(m));
   c.csolve = p->mu[0] * p->dt;
   if (write_u) c.uout = p->u(p->ucur);
   if (m < p->nsteps) fs_phase_req(p, c, n - 1, 0.0, p->dt, true, m + 1);
@@ -1348,11 +1402,12 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
     std::vector<double> f(MAXV);
     for (int n = 0; n <= p->nsteps; ++n) {
       const double t = p->t_at(n);
-      p->fV_at(t, f.data());
+      int64_t first = 0;
+      const int k = p->V_window(t, f.data(), &first);
       double s2 = 0.0;
       for (int64_t g = 0; g < p->P; ++g) {
         double v = 0.0;
-        for (int r = 0; r < p->nV; ++r) v += f[r] * p->Vsrc[(size_t)r * p->P + g];
+        for (int r = 0; r < k; ++r) v += f[r] * p->Vsrc[(size_t)(first + r) * p->P + g];
         s2 += v * v;
       }
       normV = std::max(normV, std::sqrt(s2 * cell));
@@ -1399,7 +1454,7 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
   p->o_tmpf = off; off = align256(off + (size_t)p->fx[0].N * p->fx[1].M * sizeof(double2));
   p->o_u[0] = off; off = align256(off + (size_t)p->P * sizeof(double2));
   p->o_u[1] = off; off = align256(off + (size_t)p->P * sizeof(double2));
-  p->o_Vf = off; off = align256(off + (size_t)p->nV * p->P * sizeof(double));
+  p->o_Vf = off; off = align256(off + p->Vsrc.size() * sizeof(double));
   p->o_ph = off; off = align256(off + (size_t)(p->order - 1) * (p->fx[0].N + p->fx[1].N) * sizeof(double2));
   for (int a = 0; a < 2; ++a) {
     p->fx[a].o_tab = off;
@@ -1689,7 +1744,7 @@ int history_residual(tdse_plan_s* p, double* value) {
   a.mode = C_FWD;
   a.src = p->u(p->ucur);
   a.dst = X;
-  p->fV_at(p->t_at(n), a.fV);
+  set_V(p, 0, a, p->t_at(n));
   a.alpha_re = 0.0; a.alpha_im = 0.0; a.beta_re = 1.0; a.beta_im = 0.0;
   int s = launch(p, 0, true, a);
   if (s) return s;
@@ -1954,6 +2009,7 @@ int plan_batch(const tdse_problem_t* probs, int count, tdse_plan_s** out) {
   for (int i = 0; i < count; ++i) {
     if (probs[i].domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "batches hold periodic instances");
     if (probs[i].dim == 3) return fail(TDSE_EUNSUPPORTED, "batches take 1D and 2D instances");
+    if (probs[i].V_kind == TDSE_V_SAMPLED) return fail(TDSE_EUNSUPPORTED, "batches take stored fields or the moving well");
     tdse_plan_s* q = nullptr;
     const int s = tdse_plan(&probs[i], &q);
     if (s) return s;
@@ -2629,7 +2685,7 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   if (prob->dim == 3) {
     if (prob->domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "3D runs the periodic scheme");
     if (prob->precision != TDSE_FP64) return fail(TDSE_EUNSUPPORTED, "3D runs in FP64");
-    if (prob->V_kind != TDSE_V_FIELDS) return fail(TDSE_EUNSUPPORTED, "3D takes potentials from stored fields");
+    if (prob->V_kind == TDSE_V_MOVING_WELL) return fail(TDSE_EUNSUPPORTED, "3D takes stored or sampled potentials");
     if ((int64_t)prob->M[0] * prob->M[1] * prob->M[2] > ((int64_t)1 << 28))
       return fail(TDSE_EINVAL, "3D grid larger than 2^28 points");
   }
@@ -2642,14 +2698,22 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   if (!(prob->T > 0.0) || prob->nsteps < 1) return fail(TDSE_EINVAL, "need T > 0 and nsteps >= 1");
   if (prob->order < 2 || prob->order > 8 || prob->order % 2) return fail(TDSE_EINVAL, "order must be 2, 4, 6 or 8");
   const bool well = prob->V_kind == TDSE_V_MOVING_WELL;
-  if (prob->V_kind != TDSE_V_FIELDS && !well) return fail(TDSE_EINVAL, "bad V_kind");
+  const bool sampled = prob->V_kind == TDSE_V_SAMPLED;
+  if (prob->V_kind != TDSE_V_FIELDS && !well && !sampled) return fail(TDSE_EINVAL, "bad V_kind");
+  if (sampled) {
+    if (!prob->V_fields) return fail(TDSE_EINVAL, "sampled V: V_fields missing");
+    int64_t pts = 1;
+    for (int a = 0; a < std::max(1, std::min(3, (int)prob->dim)); ++a) pts *= std::max(1, (int)prob->M[a]);
+    if (prob->nsteps < 1 || (double)(prob->nsteps + 1) * (double)pts * 8.0 > (double)((int64_t)64 << 30))
+      return fail(TDSE_EINVAL, "sampled V: (nsteps + 1) samples must fit 64 GiB");
+  }
   if (well) {
     if (prob->domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "the moving well is a periodic potential");
     if (!(prob->V_params[1] > 0.0 && prob->V_params[1] <= 1.0))
       return fail(TDSE_EINVAL, "moving well: need 0 < beta <= 1 (at most three periodic images per axis)");
     for (int k = 0; k < 4; ++k)
       if (!std::isfinite(prob->V_params[k])) return fail(TDSE_EINVAL, "moving well: non-finite parameter");
-  } else if (prob->nV < 1 || prob->nV > MAXV || !prob->V_fields) {
+  } else if (!sampled && (prob->nV < 1 || prob->nV > MAXV || !prob->V_fields)) {
     return fail(TDSE_EINVAL, "need 1..8 potential fields");
   }
   if (prob->f_kind == TDSE_F_SIN && !prob->f_params) return fail(TDSE_EINVAL, "f_params missing");
@@ -2684,7 +2748,11 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   p->nsteps = prob->nsteps;
   p->T = prob->T;
   p->dt = prob->T / prob->nsteps;
-  p->nV = well ? 0 : prob->nV;
+  p->nV = well ? 0 : (sampled ? 1 : prob->nV);
+  if (sampled) {
+    p->vkind = TDSE_V_SAMPLED;
+    p->nsamp = (int64_t)prob->nsteps + 1;
+  }
   if (well) {
     p->vkind = TDSE_V_MOVING_WELL;
     p->well[0] = prob->V_params[0];
@@ -2706,8 +2774,9 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
     // the potential stays FP64 in both forms: rounded to FP32 it would be a
     // fixed perturbation of the Hamiltonian whose error grows linearly in time
     S.real = 8;
-    if (g == 0 && p->nV > 0)
-      S.Vhost.assign((const char*)prob->V_fields, (const char*)(prob->V_fields + (size_t)p->nV * p->P));
+    const int64_t nfields = sampled ? p->nsamp : p->nV;
+    if (g == 0 && nfields > 0)
+      S.Vhost.assign((const char*)prob->V_fields, (const char*)(prob->V_fields + (size_t)nfields * p->P));
   }
 
   TimeFns& tf = p->tf;
@@ -2728,7 +2797,7 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   tf.prepare();
 
   if (free_dom) {
-    p->Vsrc.assign(prob->V_fields, prob->V_fields + (size_t)p->nV * p->P);
+    p->Vsrc.assign(prob->V_fields, prob->V_fields + (size_t)(sampled ? p->nsamp : p->nV) * p->P);
     p->st[0].Vhost.clear();
     p->st[1].Vhost.clear();
     const int s = plan_free(p, prob);
@@ -2794,7 +2863,7 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
     p->o_p2S2 = off; off = align256(off + p->p2S2.size() * sizeof(double2));
     p->o_p2bar = off; off = align256(off + P2_BAR_WORDS * sizeof(unsigned));
   }
-  if (p->dim == 1 && !split && run1d_supported(p->M2)) {
+  if (p->dim == 1 && !split && run1d_supported(p->M2) && p->vkind != TDSE_V_SAMPLED) {
     p->run1d = true;
     build_run1d(p);
     p->o_r1tab = off; off = align256(off + p->r1tab.size() * sizeof(double));

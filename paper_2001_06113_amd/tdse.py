@@ -50,10 +50,11 @@ def problem_struct(*, dim: int, M: Sequence[int], T: float, nsteps: int, V_field
                    eps: float = 1e-10, p: int = 8, q: int = 10, panels: int = 1, nu: Sequence[int] = (),
                    H: float = 0.0, V_kind: str = "fields", V_params: Sequence[float] = (), cheb: int = 0):
     """Fill a tdse_problem_t; returns it with the arrays it points into (keep them alive).
-    V_kind "moving_well" takes V_params = (V0, beta, c_0[, c_1]) and no fields."""
+    V_kind "moving_well" takes V_params = (V0, beta, c_0[, c_1]) and no fields;
+    V_kind "sampled" takes V_fields = the samples V(x, t_n), n = 0..nsteps."""
     M = tuple(int(m) for m in M)
     well = V_kind == "moving_well"
-    if V_kind not in ("fields", "moving_well"):
+    if V_kind not in ("fields", "moving_well", "sampled"):
         raise ValueError(f"unknown V_kind {V_kind!r}")
     V = None if well else np.ascontiguousarray(np.asarray(V_fields, dtype=np.float64).reshape(-1, *M))
     prob = _lib.Problem()
@@ -73,7 +74,13 @@ def problem_struct(*, dim: int, M: Sequence[int], T: float, nsteps: int, V_field
         for k, v in enumerate(tuple(V_params) + (0.0,) * (4 - len(V_params))):
             prob.V_params[k] = float(v)
     else:
-        prob.nV = V.shape[0]
+        if V_kind == "sampled":
+            if V.shape[0] != int(nsteps) + 1:
+                raise ValueError("sampled V needs nsteps + 1 samples")
+            prob.nV = 0
+            prob.V_kind = 2
+        else:
+            prob.nV = V.shape[0]
         keep.append(V)
         prob.V_fields = _dptr(V)
     prob.f_kind = F_KINDS[f_kind]
@@ -110,10 +117,14 @@ def problem_kwargs(prob) -> dict:
     f_params = None
     if sin:
         f_params = [tuple(fp) if k == "sin" else (0.0, 0.0) for fp, k in zip(prob.f_params, prob.f_kind)]
-    well = getattr(prob, "V_kind", "fields") == "moving_well"
+    kind = getattr(prob, "V_kind", "fields")
+    well = kind == "moving_well"
+    if kind == "sampled":
+        fields = np.asarray(prob.V_samples)
+    else:
+        fields = None if well else np.stack(prob.V_fields)
     return dict(dim=prob.dim, M=prob.M, T=prob.T, nsteps=prob.nsteps,
-                V_fields=None if well else np.stack(prob.V_fields),
-                V_kind="moving_well" if well else "fields", V_params=tuple(prob.V_well) if well else (),
+                V_fields=fields, V_kind=kind, V_params=tuple(prob.V_well) if well else (),
                 order=prob.order, n_start=-1 if prob.n_start is None else prob.n_start,
                 precision=prob.precision, f_kind="sin" if sin else "const", f_params=f_params,
                 A_kind=prob.A_kind, A_params=prob.A_params if prob.A_kind in ("pulse_sin2", "pulse_cos2") else None,

@@ -46,6 +46,12 @@ class EmuPlan:
             p.V_kind = 1
             for k, v in enumerate(tuple(prob.V_well) + (0.0,) * (4 - len(prob.V_well))):
                 p.V_params[k] = v
+        elif getattr(prob, "V_kind", "fields") == "sampled":
+            V = np.ascontiguousarray(np.asarray(prob.V_samples, dtype=np.float64))
+            self._keep.append(V)
+            p.nV = 0
+            p.V_kind = 2
+            p.V_fields = V.ctypes.data_as(C.POINTER(C.c_double))
         else:
             V = np.ascontiguousarray(np.stack(prob.V_fields).astype(np.float64))
             self._keep.append(V)

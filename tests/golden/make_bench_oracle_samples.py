@@ -16,6 +16,8 @@ Cases (one file each, tests/golden/<case>_oracle_sample.txt):
   batch_64           the 64 uneven periodic instances (seeds 4000 + i), 500 steps to T = 2,
                      stepwise field; 1D every (M/64)-th point, 2D every (M/16)-th point per axis
   periodic_3d_128    3D periodic, 128^3, 500 steps to T = 0.5 (seed 50), every 8th point per axis
+  sampled_2d_512     2D periodic, 512^2 (seed 1), the potential replaced by the general sampled
+                     V(x, t) of sampled_potential_problem, 500 steps to T = 0.5, every 8th point
   example2_long_time_nr5
                      Section 6, Example 2's long-time wave packet: 1D free space, M = 128,
                      nu = 1024, q = 16, n_r = 5, 1000 steps to T = 1000, the C-type block
@@ -41,7 +43,7 @@ from oracle.freespace import FreeSpaceOracle  # noqa: E402
 from oracle.periodic import PeriodicOracle  # noqa: E402
 from workloads import (batch_64_problems, example2_long_time_problem, free_2d_256_problem,  # noqa: E402
                        moving_well_problem, periodic_1d_256_problem, periodic_2d_512_problem,
-                       periodic_2d_1024_problem, periodic_3d_128_problem)
+                       periodic_2d_1024_problem, periodic_3d_128_problem, sampled_2d_512_problem)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -76,6 +78,7 @@ def cases():
                              for p in batch_64_problems(precision="fp64")],
         "example2_long_time_nr5": lambda: [("free", example2_long_time_problem(5), 1, 1)],
         "periodic_3d_128": lambda: [("periodic", periodic_3d_128_problem(), 8, 8)],
+        "sampled_2d_512": lambda: [("periodic", sampled_2d_512_problem(), 8, 8)],
     }
 
 

@@ -300,6 +300,24 @@ def test_free_space_planner_chebyshev_terms_match_oracle(lib, H):
         lib.tdse_destroy(h)
 
 
+def test_sampled_potential_planning(lib):
+    # TDSE_V_SAMPLED: nsteps + 1 samples in V_fields, nV ignored; no batch
+    p = _problem(nsteps=10, nV=11)
+    p.V_kind = 2
+    p.nV = 0
+    st, h = _plan(lib, p)
+    assert st == 0, lib.tdse_last_error()
+    lib.tdse_destroy(h)
+    p.V_fields = None
+    st, h = _plan(lib, p)
+    assert st == -1
+    q = _problem(nsteps=10, nV=11)
+    q.V_kind = 2
+    arr = (type(q) * 1)(q)
+    h = C.c_void_p()
+    assert lib.tdse_plan_batch(arr, 1, C.byref(h)) == -2
+
+
 def test_periodic_plan_has_no_contour(lib):
     st, h = _plan(lib, _problem())
     v = C.c_double()

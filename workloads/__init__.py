@@ -14,6 +14,7 @@ from .synth import (  # noqa: F401
     periodic_2d_1024_problem,
     periodic_3d_128_problem,
     sampled_potential_problem,
+    sampled_2d_512_problem,
     batch_64_problems,
     periodic_problem_from_seed,
     free_problem_from_seed,

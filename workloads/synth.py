@@ -351,6 +351,13 @@ def sampled_potential_problem(base: Problem, depth: float = 6.0, width: float = 
     return prob
 
 
+def sampled_2d_512_problem(nsteps: int = 500, T: float = 0.5) -> Problem:
+    """The 512^2 periodic workload (seed 1) with a general, non-separable
+    potential given as samples at the step times (sampled_potential_problem),
+    500 steps to T = 0.5 (dt = 1e-3, as in the 2000-step run), FP64."""
+    return sampled_potential_problem(periodic_problem_from_seed(1, 2, (512, 512), T, nsteps, name="sampled-2d-512"))
+
+
 def periodic_3d_128_problem(seed: int = 50, M: int = 128, T: float = 0.5, nsteps: int = 500,
                             order: int = 8) -> Problem:
     """3D periodic, M^3 = 128^3 points (2,097,152 modes), the periodic recipe
