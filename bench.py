@@ -686,6 +686,11 @@ def batch_leg(runs: int, copies: dict) -> dict:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gAs, _ = b.adjoint(u0, lams)
+    torch.cuda.synchronize()
+    adj_first_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gAs, _ = b.adjoint(u0, lams)
+    torch.cuda.synchronize()
     adj_s = time.perf_counter() - t0
     b.close()
     return {"workload": "64 periodic instances (32 1D M=256..2048, 32 2D M=128^2..512^2), T=2, 500 steps AM8, "
@@ -696,7 +701,8 @@ def batch_leg(runs: int, copies: dict) -> dict:
                       "all_pass": all(e["pass"] for e in errs)},
             "one_plan_at_a_time_value": b.total * nsteps / seq, "speedup_vs_one_plan_at_a_time": seq / wall,
             "autotune_s": tune_s, "schedules_col_row": sorted(set(chosen)),
-            "adjoint_s_all_instances": adj_s, "adjoint_samples": int(sum(g.size for g in gAs))}
+            "adjoint_s_all_instances": adj_s, "adjoint_first_call_s": adj_first_s,
+            "adjoint_vs_forward_run": adj_s / wall, "adjoint_samples": int(sum(g.size for g in gAs))}
 
 
 def main():
