@@ -2641,7 +2641,10 @@ int adjoint_single(tdse_plan_s* p, char* w, size_t wbytes, int K, const void* u0
   if (b_wt) std::memcpy(csr.data() + o_wt, wt.data(), b_wt);
   s = adj_err(launch_adj_reduce((double*)(w + L.o_part), (double*)(w + L.o_red), (int)row, L.nblk, st), "adjoint reduce");
   if (!s) s = adj_err(hipStreamSynchronize(st), "adjoint sync");
-  if (!s) s = adj_err(hipMemcpy(w + L.o_csr, csr.data(), csr.size(), hipMemcpyHostToDevice), "adjoint map upload");
+  // on the plan's own stream: a synchronous copy on the null stream would
+  // order against every other stream's work (and serialize concurrent adjoints)
+  if (!s) s = adj_err(hipMemcpyAsync(w + L.o_csr, csr.data(), csr.size(), hipMemcpyHostToDevice, st), "adjoint map upload");
+  if (!s) s = adj_err(hipStreamSynchronize(st), "adjoint sync");   // csr is host memory of this call
   if (!s) {
     char* cb = w + L.o_csr;
     s = adj_err(launch_adj_to_A((double*)(w + L.o_red), (const int*)cb, (const int*)(cb + o_src),
