@@ -355,6 +355,23 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 
   double2 v3[RAY], v1[RAY];
   const bool need_fwd = (mode == R_AM || mode == R_FWD || mode == R_UHACC);
+  // Adams step with the full history: B of the thread's ray modes and the
+  // first history batch (term j = 2 on the E3 ray) are loaded before the
+  // forward transform, so their latency overlaps it
+  const bool pre = mode == R_AM && a.nh == MAXH - 1;
+  double2 Bp3[RAY], Bp1[RAY], w0[RAY], pf0[RAY];
+  if (pre) {
+    const double2* __restrict__ r2 = a.ring + a.slot_r[2] * a.ring_stride + row_m;
+    const double2* __restrict__ p2 = a.ph + (a.N1 + a.N2) + a.N1;
+#pragma unroll
+    for (int m = 0; m < RAY; ++m) {
+      const int ec = min(t + TL * m, NE - 1);
+      Bp3[m] = a.Bm[row_m + N2 - NE + ec];
+      Bp1[m] = a.Bm[row_m + NE - 1 - ec];
+      w0[m] = r2[N2 - NE + ec];
+      pf0[m] = p2[N2 - NE + ec];
+    }
+  }
   if (need_fwd) {
     for (int j = t; j < M2; j += TL) fin[j] = a.src[row_p + j];
     __syncthreads();
@@ -398,7 +415,7 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       const int ec = min(t + TL * m, NE - 1);
       k3[m] = N2 - NE + ec;
       k1r[m] = NE - 1 - ec;
-      const double2 B3 = a.Bm[row_m + k3[m]], B1 = a.Bm[row_m + k1r[m]];
+      const double2 B3 = pre ? Bp3[m] : a.Bm[row_m + k3[m]], B1 = pre ? Bp1[m] : a.Bm[row_m + k1r[m]];
       const double2 E3 = cmul(T1[0], ph[N1 + k3[m]]), E1 = cmul(T1[0], ph[N1 + k1r[m]]);
       // E^(1) (uhat - i dt mu_1 W),  uhat = B - i dt mu_0 W
       acc3[m] = cmul(E3, cadd(cadd(B3, fs_mul_mi(a.c0, v3[m])), fs_mul_mi(a.ch[1], v3[m])));
@@ -433,7 +450,11 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     };
     if (nh == MAXH - 1) {   // the full order-8 history: straight-line, software-pipelined
       constexpr int NB = 2 * (MAXH - 2);
-      load(0);
+#pragma unroll
+      for (int m = 0; m < RAY; ++m) {   // batch 0, loaded before the forward transform
+        w[0][m] = w0[m];
+        pf[0][m] = pf0[m];
+      }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         if (b + 1 < NB) load(b + 1);
