@@ -92,8 +92,9 @@ typedef void (*tdse_vector_fn)(double t, double* A_out, void* ctx);
 /* Problem statement (Section 1: domain, u0 via tdse_set_state, V(x,t), A(t),
  * T, step size, order).  Unused fields may be zero.
  * d = 3 (Section 4.3's setting, periodic scheme of Section 2 in three
- * dimensions): periodic domain, TDSE_FP64, stored fields (V_kind 0), at most
- * 2^28 points; single plans (no batch, no adjoint).  Arrays are row-major over
+ * dimensions): periodic domain, TDSE_FP64 or TDSE_FP32_SPLIT, stored or
+ * sampled potentials (V_kind 0 or 2), at most 2^28 points; single plans (no
+ * batch, no adjoint).  Arrays are row-major over
  * M[0] x M[1] x M[2] with the last axis fastest; A has d components. */
 typedef struct {
   int32_t dim;             /* 1, 2 or 3                                      */

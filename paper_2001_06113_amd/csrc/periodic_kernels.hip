@@ -18,12 +18,12 @@ __global__ __launch_bounds__(LPW * TL) void k_col(LineArgs a) {
   col_body<C, N, LPW, TL>(a, tile * LPW, blockIdx.x, gridDim.x, lds);
 }
 
-// FFT-only pass over the middle axis of a 3D grid (FP64)
-template <int N, int LPW, int TL, bool INV>
+// FFT-only pass over the middle axis of a 3D grid, in the transform precision
+template <typename C, int N, int LPW, int TL, bool INV>
 __global__ __launch_bounds__(LPW * TL) void k_mid(LineArgs a) {
-  __shared__ double2 lds[col_lds<double2, N, LPW>::elems];
+  __shared__ C lds[col_lds<C, N, LPW>::elems];
   const int tile = xcd_tile<(16 / LPW > 1 ? 16 / LPW : 1)>(blockIdx.x, gridDim.x);
-  mid_body<double2, N, LPW, TL, INV>(a, tile * LPW, lds);
+  mid_body<C, N, LPW, TL, INV>(a, tile * LPW, lds);
 }
 
 // ---------------------------------------------------------------- row pass
@@ -105,6 +105,7 @@ hipError_t col_pass(int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipE
 }
 
 // middle-axis pass: the column pass's schedules (the lines are strided the same way)
+template <typename C>
 hipError_t mid_pass(int N, bool inverse, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (a.slab_lines < 1) return hipErrorInvalidValue;
   switch (N) {
@@ -112,8 +113,8 @@ hipError_t mid_pass(int N, bool inverse, const LineArgs& a, hipStream_t s, hipEv
   case n: {                                                                                           \
     constexpr int L = col_lpw(n), T = col_tl(n);                                                      \
     const dim3 g((unsigned)((a.nlines + L - 1) / L));                                                 \
-    if (inverse) TDSE_LAUNCH((k_mid<n, L, T, true>), g, dim3(L * T), s, e0, e1, a);                  \
-    else TDSE_LAUNCH((k_mid<n, L, T, false>), g, dim3(L * T), s, e0, e1, a);                         \
+    if (inverse) TDSE_LAUNCH((k_mid<C, n, L, T, true>), g, dim3(L * T), s, e0, e1, a);               \
+    else TDSE_LAUNCH((k_mid<C, n, L, T, false>), g, dim3(L * T), s, e0, e1, a);                      \
     break;                                                                                            \
   }
     TDSE_LINE_SIZES(X)
@@ -156,8 +157,9 @@ hipError_t launch_narrow(const double2* src, float2* dst, int64_t n, hipStream_t
 hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   return prec == P_SPLIT ? col_pass<float2>(N, a, s, e0, e1) : col_pass<double2>(N, a, s, e0, e1);
 }
-hipError_t launch_mid_pass(int N, bool inverse, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  return mid_pass(N, inverse, a, s, e0, e1);
+hipError_t launch_mid_pass(int prec, int N, bool inverse, const LineArgs& a, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1) {
+  return prec == P_SPLIT ? mid_pass<float2>(N, inverse, a, s, e0, e1) : mid_pass<double2>(N, inverse, a, s, e0, e1);
 }
 hipError_t launch_row_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   return prec == P_SPLIT ? row_pass<float2>(N, a, s, e0, e1) : row_pass<double2>(N, a, s, e0, e1);

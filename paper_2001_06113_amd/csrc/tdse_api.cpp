@@ -594,7 +594,7 @@ int launch_mid(const tdse_plan_s* p, int g, void* buf, bool inverse, hipEvent_t 
   m.slab_lines = p->M2;
   m.slab_stride = (int64_t)p->Mmid * p->M2;
   m.tw = p->tw(g, 2);
-  const hipError_t e = launch_mid_pass(p->Mmid, inverse, m, p->stream, e0, e1);
+  const hipError_t e = launch_mid_pass(p->st[g].prec, p->Mmid, inverse, m, p->stream, e0, e1);
   if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
   return TDSE_OK;
 }
@@ -2687,7 +2687,6 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   if (prob->dim < 1 || prob->dim > 3) return fail(TDSE_EINVAL, "dim must be 1, 2 or 3");
   if (prob->dim == 3) {
     if (prob->domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "3D runs the periodic scheme");
-    if (prob->precision != TDSE_FP64) return fail(TDSE_EUNSUPPORTED, "3D runs in FP64");
     if (prob->V_kind == TDSE_V_MOVING_WELL) return fail(TDSE_EUNSUPPORTED, "3D takes stored or sampled potentials");
     if ((int64_t)prob->M[0] * prob->M[1] * prob->M[2] > ((int64_t)1 << 28))
       return fail(TDSE_EINVAL, "3D grid larger than 2^28 points");

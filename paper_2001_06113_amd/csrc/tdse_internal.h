@@ -320,8 +320,8 @@ hipError_t launch_diffnorm(const float2* a32, const double2* a64, const double2*
 // the kernel's own start and end.  Return a hipError_t.
 hipError_t launch_col_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
-hipError_t launch_mid_pass(int N, bool inverse, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
-                           hipEvent_t e1 = nullptr);   // 3D middle axis, FP64, in place (a.src == a.dst)
+hipError_t launch_mid_pass(int prec, int N, bool inverse, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);   // 3D middle axis, in place (a.src == a.dst)
 hipError_t launch_row_pass(int prec, int N, const LineArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
 bool line_length_supported(int N);

@@ -80,7 +80,6 @@ def _plan(lib, p):
     (dict(dim=4), -1),
     (dict(dim=3), -1),                               # third axis of size 0
     (dict(dim=3, M=(32, 64, 16), domain=1), -2),     # 3D runs the periodic scheme
-    (dict(dim=3, M=(32, 64, 16), precision=1), -2),  # 3D runs in FP64
     (dict(dim=3, M=(32, 64, 30)), -1),
     (dict(dim=3, M=(1024, 1024, 512)), -1),          # more than 2^28 points
     (dict(dim=0), -1),

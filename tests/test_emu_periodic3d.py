@@ -61,10 +61,23 @@ def test_emulated_3d_steps_in_pieces(emu):
     assert np.array_equal(out, full)
 
 
-def test_3d_plan_limits(emu):
+SPLIT_CASES = [
+    dict(seed=46, M=(8, 8, 8), T=0.05, N=12),
+    dict(seed=51, M=(16, 24, 8), T=0.06, N=14, stepwise=True),
+    dict(seed=52, M=(8, 16, 32), T=0.05, N=9),                   # two split steps after the start-up
+]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=[f"split-{c['M']}-{c['N']}" for c in SPLIT_CASES])
+def test_emulated_3d_split_matches_oracle(emu, case):
+    # FP32 transforms along all three axes, FP64 carried state: the split bar
     from emu.emu_plan import EmuPlan
 
-    prob = periodic_problem_from_seed(46, 3, (8, 8, 8), 0.05, 4)
-    prob.precision = "fp32split"
-    with pytest.raises(RuntimeError):
-        EmuPlan(emu, prob)
+    prob = periodic_problem_from_seed(case["seed"], 3, case["M"], case["T"], case["N"], precision="fp32split")
+    if case.get("stepwise"):
+        _stepwise3(prob, case["seed"])
+    u = EmuPlan(emu, prob).run(prob.u0)
+    ref, _ = PeriodicOracle(prob).run()
+    r = _rel(u, ref)
+    assert r < 1e-6, r
+    assert r > 1e-12   # really ran in reduced precision

@@ -109,3 +109,43 @@ def test_3d_128_full_run_against_stored_oracle_samples():
     e = sampled_error(u, load_samples("periodic_3d_128")[0])
     print(f"  sampled rel-L2 = {e['rel_l2']:.3e}, max-abs {e['max_abs_rel']:.3e}, norm {e['norm_rel']:.3e}", flush=True)
     assert e["rel_l2"] < TOL and e["max_abs_rel"] < TOL and e["norm_rel"] < TOL
+
+
+SPLIT_CASES = [
+    dict(seed=46, M=(8, 8, 8), T=0.05, N=12),
+    dict(seed=51, M=(16, 24, 8), T=0.06, N=14, stepwise=True),
+    dict(seed=52, M=(8, 16, 32), T=0.05, N=9),
+    dict(seed=53, M=(64, 64, 64), T=0.05, N=20, stepwise=True),
+    dict(seed=54, M=(128, 32, 48), T=0.04, N=16),
+]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=[f"split-{c['M']}-{c['N']}" for c in SPLIT_CASES])
+def test_3d_split_matches_oracle(case):
+    # FP32 transforms along all three axes, FP64 carried state: rel-L2 <= 1e-6
+    print(f"case 3d split {case}", flush=True)
+    prob = periodic_problem_from_seed(case["seed"], 3, case["M"], case["T"], case["N"], precision="fp32split")
+    if case.get("stepwise"):
+        _stepwise3(prob, case["seed"])
+    plan = _plan(prob)
+    u = plan.run(prob.u0).cpu().numpy()
+    plan.close()
+    ref, _ = PeriodicOracle(prob).run()
+    e = _rel(u, ref)
+    print(f"  rel-L2 = {e:.3e}", flush=True)
+    assert 1e-12 < e < 1e-6
+
+
+def test_3d_128_split_full_run_against_stored_oracle_samples():
+    # the 128^3, 500-step workload with FP32 transforms, against the same
+    # FP64 oracle samples, at the split bar
+    prob = periodic_3d_128_problem()
+    prob.precision = "fp32split"
+    print("case 3d 128^3 split 500 steps", flush=True)
+    plan = _plan(prob)
+    plan.use_graph(True)
+    u = plan.run(prob.u0).cpu().numpy()
+    plan.close()
+    e = sampled_error(u, load_samples("periodic_3d_128")[0])
+    print(f"  sampled rel-L2 = {e['rel_l2']:.3e}, max-abs {e['max_abs_rel']:.3e}, norm {e['norm_rel']:.3e}", flush=True)
+    assert e["rel_l2"] < 1e-6 and e["norm_rel"] < 1e-6
