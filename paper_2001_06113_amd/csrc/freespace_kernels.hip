@@ -20,6 +20,10 @@
 // column-pass output, the implicit Adams recurrence on the row's N2 modes,
 // inverse transform into the tile buffer.  Column pass (axis 0, one physical
 // column per workgroup): inverse transform, diagonal solve, forward transform.
+// Two thread layouts: nu/8 threads that carry both rays (the 2D row pass,
+// with many rows and two workgroups per CU), and nu/4 threads with a ray per
+// half (the column pass and the single row of a 1D problem, where one
+// workgroup's latency is the pass's).
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
@@ -266,6 +270,189 @@ __device__ __forceinline__ void cf_inverse(const double2 (&v3)[RAY], const doubl
         }
         u[e] = s;
       }
+    }
+  }
+}
+
+// Ray-split line transforms: 2 TL threads per line.  Threads [0, TL) carry
+// the E3 ray and threads [TL, 2 TL) the E1 ray, each thread one FFT line of
+// its own ray (v[m] = that ray's mode at e = t + TL m, as above).  Both
+// halves run the same forward FFT (the ray whose transform is an inverse FFT
+// conjugates before and after it), so every barrier is reached from the same
+// code; the two lines' exchanges share them.
+template <int NU>
+__device__ __forceinline__ typename fs_tw<NU>::type stage_twiddles_n(const CFAxis& ax, double2* tws, int tid,
+                                                                     int nth) {
+  constexpr int NC = fs_tw<NU>::NC, NF = fs_tw<NU>::NF, LF = fs_tw<NU>::LF;
+  for (int i = tid; i < NC + NF; i += nth) tws[i] = i < NC ? ax.tw[i << LF] : ax.tw[i - NC];
+  return typename fs_tw<NU>::type{tws, tws + NC};
+}
+
+__device__ __forceinline__ double2 conj_if(bool c, double2 z) { return c ? double2{z.x, -z.y} : z; }
+
+// forward transform of f[0..M) (LDS) on the thread's ray; ends with dm
+// complete (a barrier).  dm may share f's LDS (CH), as in cf_forward.
+template <int NU, bool CH>
+__device__ __forceinline__ void rs_forward(const double2* f, double2 (&v)[RAY], double2* dm, double2* part,
+                                           double2* fline, double2* fline2, const CFAxis& ax,
+                                           const typename fs_tw<NU>::type& tw, int tid) {
+  constexpr int TL = NU / 8, NTH = 2 * TL;
+  constexpr int EPT = 8;
+  const int M = ax.M, NE = ax.NE, ND = ax.ND;
+  const bool ray = tid >= TL;   // false: E3 (forward FFT), true: E1 (inverse FFT)
+  const int t = ray ? tid - TL : tid;
+  const double2* __restrict__ pre = ray ? ax.pre1 : ax.pre3;
+  const double2* __restrict__ post = ray ? ax.post1 : ax.post3;
+  double2 w[EPT];
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) {
+    const int e = t + TL * m, ec = min(e, M - 1);
+    const double2 x = conj_if(ray, cmul(pre[ec], f[ec]));
+    w[m] = e < M ? x : double2{0.0, 0.0};
+  }
+  fft_regs<NU, TL, false>(w, t, ray ? fline2 : fline, tw);
+#pragma unroll
+  for (int m = 0; m < RAY; ++m) {
+    const int e = t + TL * m;
+    const double2 x = cmul(post[min(e, NE - 1)], conj_if(ray, w[m]));
+    v[m] = e < NE ? x : double2{0.0, 0.0};
+  }
+  // dense rows as in cf_forward, over all 2 TL threads
+  const int NR = CH ? ax.NR : ND;
+  const int C = NTH / NR > 1 ? NTH / NR : 1;
+  double2* dr = CH ? part + NR * C : dm;
+  const int L = (M + C - 1) / C;
+  for (int i = tid; i < NR * C; i += NTH) {
+    const int q = i / C, c = i - q * C;
+    const int j0 = c * L, j1 = min(j0 + L, M);
+    double2 acc = {0.0, 0.0};
+    if (j0 < M) {
+      const double2 r = ax.rfwd[q];
+      const double2 d0 = ax.Dfwd[(int64_t)q * M + j0];
+      for (int j = j1 - 1; j >= j0; --j) acc = cadd(cmul(acc, r), f[j]);
+      acc = cmul(d0, acc);
+    }
+    part[i] = acc;
+  }
+  __syncthreads();
+  for (int q = tid; q < NR; q += NTH) {
+    double2 acc = {0.0, 0.0};
+    for (int c = 0; c < C; ++c) acc = cadd(acc, part[q * C + c]);
+    dr[q] = acc;
+  }
+  __syncthreads();
+  if (CH) {
+    const int P = ax.NP, NT = ax.NT, NC = ND - 2 * P;
+    for (int q = tid; q < ND; q += NTH) {
+      double2 x;
+      if (q < P) {
+        x = dr[q];
+      } else if (q >= P + NC) {
+        x = dr[q - NC + NT];
+      } else {
+        const double* __restrict__ pr = ax.Pf + (int64_t)(q - P) * NT;
+        x = double2{0.0, 0.0};
+        for (int m = 0; m < NT; ++m) {
+          const double wt = pr[m];
+          const double2 y = dr[P + m];
+          x.x += wt * y.x;
+          x.y += wt * y.y;
+        }
+      }
+      dm[q] = x;
+    }
+    __syncthreads();
+  }
+}
+
+// inverse transform of the modes (v: the thread's ray, dm: LDS) into
+// u[0..M) (LDS).  The E3 half writes u[t + TL m] last (after a barrier that
+// follows the E1 half's writes of the same entries), so an E3 thread may read
+// its own entries back without a barrier.  The dense rows are split between
+// the halves.  With the interpolant (CH) dm shares u's LDS: u is written only
+// after every read of dm.
+template <int NU, bool CH>
+__device__ __forceinline__ void rs_inverse(const double2 (&v)[RAY], const double2* dm, double2* fline,
+                                           double2* fline2, const CFAxis& ax, const typename fs_tw<NU>::type& tw,
+                                           int tid, double2* u) {
+  constexpr int TL = NU / 8, NTH = 2 * TL;
+  constexpr int EPT = 8;
+  const int M = ax.M, NE = ax.NE, ND = ax.ND, NR = CH ? ax.NR : ND;
+  const bool ray = tid >= TL;   // false: E3 (inverse FFT), true: E1 (forward FFT)
+  const int t = ray ? tid - TL : tid;
+  const double2* __restrict__ ipre = ray ? ax.ipre1 : ax.ipre3;
+  const double2* __restrict__ ipost = ray ? ax.ipost1 : ax.ipost3;
+  double2 w[EPT];
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) {
+    const int e = t + TL * m;
+    if (m < RAY) {
+      const double2 x = conj_if(!ray, cmul(ipre[min(e, NE - 1)], v[m < RAY ? m : 0]));
+      w[m] = e < NE ? x : double2{0.0, 0.0};
+    } else {
+      w[m] = double2{0.0, 0.0};
+    }
+  }
+  fft_regs<NU, TL, false>(w, t, ray ? fline2 : fline, tw);   // ends with a barrier: both lines free
+  const double2* drow = dm;   // the rows' values: the dense modes, or (CH) the node values
+  if constexpr (CH) {
+    const int P = ax.NP, NT = ax.NT, NC = ND - 2 * P;
+    const int C = NTH / NR > 1 ? NTH / NR : 1;
+    const int L = (NC + C - 1) / C;
+    double2* dv = fline2 + NR * C;
+    for (int i = tid; i < NR * C; i += NTH) {
+      const int r = i / C, c = i - r * C;
+      double2 acc = {0.0, 0.0};
+      if (r < P || r >= P + NT) {
+        if (c == 0) acc = dm[r < P ? r : r - NT + NC];
+      } else {
+        const double2* __restrict__ pr = ax.Pi + (int64_t)(r - P) * NC;
+        const int k1 = min(c * L + L, NC);
+        for (int k = c * L; k < k1; ++k) acc = cadd(acc, cmul(pr[k], dm[P + k]));
+      }
+      fline2[i] = acc;
+    }
+    __syncthreads();
+    for (int r = tid; r < NR; r += NTH) {
+      double2 acc = {0.0, 0.0};
+      for (int c = 0; c < C; ++c) acc = cadd(acc, fline2[r * C + c]);
+      dv[r] = acc;
+    }
+    __syncthreads();   // dv complete, and every read of dm done: u may be written
+    drow = dv;
+  }
+  // rows [0, h) summed by the E3 half, [h, NR) by the E1 half; the E1 half
+  // writes its sums to u, the E3 half to the first exchange line (free once
+  // the FFT is done; u shares no LDS with it or with drow, and with the
+  // interpolant every read of dm is behind the barrier above), then the E3
+  // half adds the two
+  constexpr int DB = 8;
+  const int h = NR / 2;
+  const int q0 = ray ? h : 0, q1 = ray ? NR : h;
+  double2* dst = ray ? u : fline;
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) {
+    const int e = t + TL * m;
+    if (e < M) {
+      double2 acc = cmul(ipost[e], conj_if(!ray, w[m]));
+      for (int qb = q0; qb < q1; qb += DB) {
+        double2 d[DB];
+#pragma unroll
+        for (int k = 0; k < DB; ++k) d[k] = ax.Dinv[(int64_t)min(qb + k, q1 - 1) * M + e];
+#pragma unroll
+        for (int k = 0; k < DB; ++k) {
+          if (qb + k < q1) acc = cadd(acc, cmul(d[k], drow[qb + k]));
+        }
+      }
+      dst[e] = acc;
+    }
+  }
+  __syncthreads();
+  if (!ray) {
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int e = t + TL * m;
+      if (e < M) u[e] = cadd(u[e], fline[e]);
     }
   }
 }
@@ -536,60 +723,202 @@ __device__ __forceinline__ int fs_col_of(int b, int nb) {
   return 8 * ((s / 8) * 8 + x) + (s % 8);
 }
 
+// ------------------------------------------------ ray-split row and column passes
+
+// The row pass with 2 TL threads per row: each thread carries RAY modes of
+// one ray (E3 for threads [0, TL), E1 for [TL, 2 TL)) through the forward
+// transform, the recurrence and the inverse transform.
 template <int NU, bool CH>
-__global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
-  constexpr int TL = NU / 8;
-  constexpr int EPT = 8;
+__global__ __launch_bounds__(NU / 4) void k_fs_row_rs(FSArgs a) {
+  constexpr int TL = NU / 8, NTH = 2 * TL;
+  HIP_DYNAMIC_SHARED(double2, fs_lds)
+  __shared__ double2 fline2[lds_line_len(NU)];
+  double2* part = fline2;
+  const CFAxis& ax = a.ax2;
+  const int M2 = ax.M, N2 = ax.N, NE = ax.NE, ND = ax.ND;
+  double2* fin = fs_lds;
+  double2* dm = CH ? fin : fin + M2;
+  double2* fline = CH ? fin + (M2 > ND ? M2 : ND) : dm + ND;
+  double2* tws = fline + lds_line_len(NU);
+  const int tid = threadIdx.x;
+  const bool ray = tid >= TL;
+  const int t = ray ? tid - TL : tid;
+  const int k1 = blockIdx.x;
+  const auto tw = stage_twiddles_n<NU>(ax, tws, tid, NTH);   // read after the first barrier below
+  const int mode = a.mode;
+  const int per = a.N1 + a.N2;
+  const int64_t row_m = (int64_t)k1 * N2;
+  const int64_t row_p = (int64_t)k1 * M2;
+  // the thread's modes: E3 mode N2 - N_E + e, E1 mode N_E - 1 - e (lanes past
+  // the end of the ray take its last mode and store nothing)
+  int kk[RAY];
+#pragma unroll
+  for (int m = 0; m < RAY; ++m) {
+    const int ec = min(t + TL * m, NE - 1);
+    kk[m] = ray ? NE - 1 - ec : N2 - NE + ec;
+  }
+
+  double2 v[RAY];
+  const bool need_fwd = (mode == R_AM || mode == R_FWD || mode == R_UHACC);
+  if (need_fwd) {
+    for (int j = tid; j < M2; j += NTH) fin[j] = a.src[row_p + j];
+    __syncthreads();
+    rs_forward<NU, CH>(fin, v, dm, part, fline, fline2, ax, tw, tid);
+  } else {
+#pragma unroll
+    for (int m = 0; m < RAY; ++m) v[m] = double2{0.0, 0.0};
+  }
+  if (mode == R_FWD) {
+#pragma unroll
+    for (int m = 0; m < RAY; ++m)
+      if (t + TL * m < NE) a.fdst[row_m + kk[m]] = v[m];
+    for (int q = tid; q < ND; q += NTH) a.fdst[row_m + NE + q] = dm[q];
+    return;
+  }
+  double2 T1[MAXH];
+  const int nj = (mode == R_AM || mode == R_FORM) ? a.nh : (mode == R_BINIT ? 1 : 0);
+#pragma unroll
+  for (int j = 1; j <= MAXH; ++j) T1[j - 1] = j <= nj ? a.ph[(j - 1) * per + k1] : double2{0.0, 0.0};
+  if (mode == R_AM) {
+    const double2* __restrict__ ph = a.ph;
+    const double2* __restrict__ ring = a.ring;
+    const int64_t rs = a.ring_stride;
+    const int nh = a.nh;
+    const int N1 = a.N1;
+    double2 acc[RAY];
+#pragma unroll
+    for (int m = 0; m < RAY; ++m) {
+      const double2 B = a.Bm[row_m + kk[m]];
+      const double2 E = cmul(T1[0], ph[N1 + kk[m]]);
+      acc[m] = cmul(E, cadd(cadd(B, fs_mul_mi(a.c0, v[m])), fs_mul_mi(a.ch[1], v[m])));
+      if (a.slot_w >= 0 && t + TL * m < NE) a.ring[a.slot_w * rs + row_m + kk[m]] = v[m];
+    }
+    // history terms j >= 2, one term at a time (the occupancy of four waves
+    // per SIMD hides the loads' latency)
+#pragma unroll
+    for (int j = 2; j < MAXH; ++j) {
+      if (j <= nh) {
+        const double2* __restrict__ rj = ring + a.slot_r[j] * rs + row_m;
+        const double2* __restrict__ pj = ph + (j - 1) * per + N1;
+        double2 w[RAY], pf[RAY];
+#pragma unroll
+        for (int m = 0; m < RAY; ++m) {
+          w[m] = rj[kk[m]];
+          pf[m] = pj[kk[m]];
+        }
+#pragma unroll
+        for (int m = 0; m < RAY; ++m) acc[m] = cadd(acc[m], fs_mul_mi(a.ch[j], cmul(cmul(T1[j - 1], pf[m]), w[m])));
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < RAY; ++m) {
+      const bool live = t + TL * m < NE;
+      if (live) a.Bm[row_m + kk[m]] = acc[m];
+      v[m] = live ? acc[m] : double2{0.0, 0.0};
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < RAY; ++m) {
+      if (t + TL * m < NE) v[m] = fs_mode_update(a, T1, per, kk[m], row_m + kk[m], v[m]);
+    }
+  }
+  if (mode == R_AM && a.nh == MAXH - 1) {
+    const double2* __restrict__ ph = a.ph;
+    const double2* __restrict__ ring = a.ring;
+    const int64_t rs = a.ring_stride;
+    const int N1 = a.N1;
+    for (int q = tid; q < ND; q += NTH) {
+      const int k = NE + q;
+      const int64_t g = row_m + k;
+      const double2 W = dm[q];
+      double2 pfq[MAXH - 1], wh[MAXH - 2];
+      const double2 B = a.Bm[g];
+#pragma unroll
+      for (int j = 1; j < MAXH; ++j) pfq[j - 1] = ph[(j - 1) * per + N1 + k];
+#pragma unroll
+      for (int j = 2; j < MAXH; ++j) wh[j - 2] = ring[a.slot_r[j] * rs + g];
+      __builtin_amdgcn_sched_barrier(0);
+      double2 acc = cmul(cmul(T1[0], pfq[0]), cadd(cadd(B, fs_mul_mi(a.c0, W)), fs_mul_mi(a.ch[1], W)));
+#pragma unroll
+      for (int j = 2; j < MAXH; ++j) acc = cadd(acc, fs_mul_mi(a.ch[j], cmul(cmul(T1[j - 1], pfq[j - 1]), wh[j - 2])));
+      if (a.slot_w >= 0) a.ring[a.slot_w * rs + g] = W;
+      a.Bm[g] = acc;
+      dm[q] = acc;
+    }
+  } else {
+    for (int q = tid; q < ND; q += NTH)
+      dm[q] = fs_mode_update(a, T1, per, NE + q, row_m + NE + q, need_fwd ? dm[q] : double2{0.0, 0.0});
+  }
+  if (mode == R_UHACC) return;
+  __syncthreads();
+  rs_inverse<NU, CH>(v, dm, fline, fline2, ax, tw, tid, fin);
+  if (!ray) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = t + TL * m;
+      if (e < M2) a.dst[row_p + e] = fin[e];
+    }
+  }
+}
+
+// The column pass with 2 TL threads per column (ray halves as in the row pass).
+template <int NU, bool CH>
+__global__ __launch_bounds__(NU / 4) void k_fs_col_rs(FSArgs a) {
+  constexpr int TL = NU / 8, NTH = 2 * TL;
   HIP_DYNAMIC_SHARED(double2, fs_lds)
   __shared__ double2 fline2[lds_line_len(NU)];
   double2* part = fline2;
   const CFAxis& ax = a.ax1;
   const int M1 = ax.M, N1 = ax.N, NE = ax.NE, ND = ax.ND;
   const int M2 = a.ax2.M;
-  double2* fin = fs_lds;                           // u, then the forward input (CH: the dense modes first)
+  double2* fin = fs_lds;
   double2* dm = CH ? fin : fin + M1;
   double2* fline = CH ? fin + (M1 > ND ? M1 : ND) : dm + ND;
   double2* tws = fline + lds_line_len(NU);
-  const int t = threadIdx.x;
-  const int y = fs_col_of(blockIdx.x, gridDim.x);   // physical column (axis 1)
-  const auto tw = stage_twiddles<NU>(ax, tws, t);   // read after the first barrier below
+  const int tid = threadIdx.x;
+  const bool ray = tid >= TL;
+  const int t = ray ? tid - TL : tid;
+  const int y = fs_col_of(blockIdx.x, gridDim.x);
+  const auto tw = stage_twiddles_n<NU>(ax, tws, tid, NTH);
   const int mode = a.mode;
 
-  if (a.req.nj > 0) build_phase_table_fs(a, TL);
-  double2 v3[RAY], v1[RAY];
+  if (a.req.nj > 0) build_phase_table_fs(a, NTH);
+  double2 v[RAY];
   if (mode == C_SOLVE) {
 #pragma unroll
     for (int m = 0; m < RAY; ++m) {
       const int e = t + TL * m;
-      v3[m] = e < NE ? a.src[(int64_t)(N1 - NE + e) * M2 + y] : double2{0.0, 0.0};
-      v1[m] = e < NE ? a.src[(int64_t)(NE - 1 - e) * M2 + y] : double2{0.0, 0.0};
+      const int k = ray ? NE - 1 - e : N1 - NE + e;
+      v[m] = e < NE ? a.src[(int64_t)k * M2 + y] : double2{0.0, 0.0};
     }
-    for (int q = t; q < ND; q += TL) dm[q] = a.src[(int64_t)(NE + q) * M2 + y];
+    for (int q = tid; q < ND; q += NTH) dm[q] = a.src[(int64_t)(NE + q) * M2 + y];
     __syncthreads();
-    cf_inverse<NU, CH>(v3, v1, dm, fline, fline2, ax, tw, t, fin);   // w = F^-1 B on the column, in place of the forward input
+    rs_inverse<NU, CH>(v, dm, fline, fline2, ax, tw, tid, fin);
+    if (!ray) {
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) {
-      const int e = t + TL * m;
-      if (e < M1) {
-        const double2 wv = fin[e];
-        const int64_t g = (int64_t)e * M2 + y;
-        double Vs = 0.0;
-        for (int r = 0; r < a.nV; ++r) Vs += a.fV[r] * a.V[r * a.vstride + g];
-        const double q = a.csolve * Vs;
-        const double inv = 1.0 / (1.0 + q * q);
-        const double2 u = double2{(wv.x + q * wv.y) * inv, (wv.y - q * wv.x) * inv};
-        if (a.uout) a.uout[g] = u;
-        if (a.uacc) {
-          double2 s = a.acc_first ? double2{0.0, 0.0} : a.uacc[g];
-          s.x += a.wacc * u.x;
-          s.y += a.wacc * u.y;
-          a.uacc[g] = s;
+      for (int m = 0; m < 8; ++m) {
+        const int e = t + TL * m;
+        if (e < M1) {
+          const double2 wv = fin[e];
+          const int64_t g = (int64_t)e * M2 + y;
+          double Vs = 0.0;
+          for (int r = 0; r < a.nV; ++r) Vs += a.fV[r] * a.V[r * a.vstride + g];
+          const double q = a.csolve * Vs;
+          const double inv = 1.0 / (1.0 + q * q);
+          const double2 u = double2{(wv.x + q * wv.y) * inv, (wv.y - q * wv.x) * inv};
+          if (a.uout) a.uout[g] = u;
+          if (a.uacc) {
+            double2 s = a.acc_first ? double2{0.0, 0.0} : a.uacc[g];
+            s.x += a.wacc * u.x;
+            s.y += a.wacc * u.y;
+            a.uacc[g] = s;
+          }
+          fin[e] = double2{Vs * u.x, Vs * u.y};
         }
-        fin[e] = double2{Vs * u.x, Vs * u.y};
       }
     }
-  } else {  // C_FWD: (alpha + beta V) u from the physical solution
-    for (int e = t; e < M1; e += TL) {
+  } else {  // C_FWD
+    for (int e = tid; e < M1; e += NTH) {
       const int64_t g = (int64_t)e * M2 + y;
       double Vs = 0.0;
       for (int r = 0; r < a.nV; ++r) Vs += a.fV[r] * a.V[r * a.vstride + g];
@@ -599,16 +928,13 @@ __global__ __launch_bounds__(NU / 8) void k_fs_col(FSArgs a) {
     }
   }
   __syncthreads();
-  cf_forward<NU, CH>(fin, v3, v1, dm, part, fline, fline2, ax, tw, t);
+  rs_forward<NU, CH>(fin, v, dm, part, fline, fline2, ax, tw, tid);
 #pragma unroll
   for (int m = 0; m < RAY; ++m) {
     const int e = t + TL * m;
-    if (e < NE) {
-      a.dst[(int64_t)(N1 - NE + e) * M2 + y] = v3[m];
-      a.dst[(int64_t)(NE - 1 - e) * M2 + y] = v1[m];
-    }
+    if (e < NE) a.dst[(int64_t)(ray ? NE - 1 - e : N1 - NE + e) * M2 + y] = v[m];
   }
-  for (int q = t; q < ND; q += TL) a.dst[(int64_t)(NE + q) * M2 + y] = dm[q];
+  for (int q = tid; q < ND; q += NTH) a.dst[(int64_t)(NE + q) * M2 + y] = dm[q];
 }
 
 // --------------------------------------------------- pointwise column pass (1D)
@@ -682,7 +1008,26 @@ size_t fs_line_lds_bytes(int nu, int M, int ND, bool ch) {
   }
 }
 
+// The row pass of a 1D problem is a single workgroup: it takes the ray-split
+// kernel (twice the threads on the one line).  A 2D row pass has N1 rows, and
+// two workgroups of the two-line kernel per CU keep more loads in flight.
 hipError_t launch_fs_row(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (a.N1 == 1) {
+    switch (nu) {
+#define X(n)                                                                              \
+  case n:                                                                                 \
+    if (a.ax2.NT)                                                                         \
+      TDSE_FS_LAUNCH_SH((k_fs_row_rs<n, true>), dim3(a.N1), dim3(n / 4), fs_lds_bytes<n>(a.ax2.M, a.ax2.ND, a.ax2.NT != 0), s, e0, e1, a); \
+    else                                                                                  \
+      TDSE_FS_LAUNCH_SH((k_fs_row_rs<n, false>), dim3(a.N1), dim3(n / 4), fs_lds_bytes<n>(a.ax2.M, a.ax2.ND, a.ax2.NT != 0), s, e0, e1, a); \
+    break;
+      TDSE_FS_NU(X)
+#undef X
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (nu) {
 #define X(n)                                                                              \
   case n:                                                                                 \
@@ -710,9 +1055,9 @@ hipError_t launch_fs_col(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0, 
 #define X(n)                                                                              \
   case n:                                                                                 \
     if (a.ax1.NT)                                                                         \
-      TDSE_FS_LAUNCH_SH((k_fs_col<n, true>), dim3(a.ax2.M), dim3(n / 8), fs_lds_bytes<n>(a.ax1.M, a.ax1.ND, a.ax1.NT != 0), s, e0, e1, a); \
+      TDSE_FS_LAUNCH_SH((k_fs_col_rs<n, true>), dim3(a.ax2.M), dim3(n / 4), fs_lds_bytes<n>(a.ax1.M, a.ax1.ND, a.ax1.NT != 0), s, e0, e1, a); \
     else                                                                                  \
-      TDSE_FS_LAUNCH_SH((k_fs_col<n, false>), dim3(a.ax2.M), dim3(n / 8), fs_lds_bytes<n>(a.ax1.M, a.ax1.ND, a.ax1.NT != 0), s, e0, e1, a); \
+      TDSE_FS_LAUNCH_SH((k_fs_col_rs<n, false>), dim3(a.ax2.M), dim3(n / 4), fs_lds_bytes<n>(a.ax1.M, a.ax1.ND, a.ax1.NT != 0), s, e0, e1, a); \
     break;
     TDSE_FS_NU(X)
 #undef X
