@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-1d", action="store_true", help="skip the 1D periodic M = 256 leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D periodic 128^3 leg")
     ap.add_argument("--no-sampled", action="store_true", help="skip the sampled-potential 512^2 leg")
+    ap.add_argument("--no-free-3d", action="store_true", help="skip the 3D free-space 32^3 leg")
     ap.add_argument("--runs-3d", type=int, default=3)
     ap.add_argument("--no-long-time", action="store_true",
                     help="skip the long-time free-space leg (Chebyshev-interpolated C-type block)")
@@ -535,6 +536,60 @@ def _periodic_3d_run(runs: int, copies: dict, precision: str) -> dict:
             "adams_step_us_eager": row + col + 2 * mid}
 
 
+def free_space_3d_leg(runs: int, copies: dict) -> dict:
+    """3D free space on the 32^3 workload (seed 62, nu = 256 per axis, eps =
+    1e-8, q = 8, 100 order-8 steps to T = 0.1, the plan's default H per axis):
+    graph-replayed whole runs, the error against the stored oracle values,
+    and the per-pass durations of one eager run: row pass (last axis,
+    recurrence), column pass (axis 0, solve) and the middle-axis transforms."""
+    import torch
+
+    from paper_2001_06113_amd.tdse import (Q_BYTES_COL, Q_BYTES_MID, Q_BYTES_PER_STEP, Q_BYTES_ROW, Q_FS_AXIS2,
+                                           Q_FS_MODES, Q_PROF_MS_COL, Q_PROF_MS_MID, Q_PROF_MS_ROW, Q_PROF_N_COL,
+                                           Q_PROF_N_MID, Q_PROF_N_ROW, Plan)
+    from workloads import free_3d_32_problem
+
+    dev = torch.device("cuda:0")
+    prob = free_3d_32_problem()
+    plan = Plan.from_problem(prob, device=dev)
+    modes = 1
+    for a in range(3):
+        modes *= int(plan.query(Q_FS_MODES + a if a < 2 else Q_FS_AXIS2))
+    u0 = torch.as_tensor(prob.u0).to(dev)
+    out = torch.empty_like(u0)
+    plan.use_graph(True)
+    plan.run(u0, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        plan.run(u0, out)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / runs
+    err = oracle_error("free_3d_32", out)
+    plan.use_graph(False)
+    plan.profile(True)
+    plan.run(u0, out)
+    row = plan.query(Q_PROF_MS_ROW) * 1e3 / max(plan.query(Q_PROF_N_ROW), 1)
+    col = plan.query(Q_PROF_MS_COL) * 1e3 / max(plan.query(Q_PROF_N_COL), 1)
+    mid = plan.query(Q_PROF_MS_MID) * 1e3 / max(plan.query(Q_PROF_N_MID), 1)
+    plan.profile(False)
+    row_b, col_b, mid_b = plan.query(Q_BYTES_ROW), plan.query(Q_BYTES_COL), plan.query(Q_BYTES_MID)
+    step_b = plan.query(Q_BYTES_PER_STEP)
+    plan.close()
+
+    def rf(b, us):
+        a = b / (us * 1e-6) / 1e9
+        return {"us": us, "bytes_per_launch": b, "GBps": a, "frac": a / HBM_PEAK_GBS}
+
+    return {"workload": "3D free-space TDSE 32^3, nu=256 per axis, eps=1e-8, q=8, T=0.1, 100 steps AM8, FP64",
+            "value": modes * prob.nsteps / wall, "unit": "mode-updates/s", "modes": modes,
+            "grid_point_updates_per_s": u0.numel() * prob.nsteps / wall, "ms_per_run": wall * 1e3,
+            "us_per_time_step": wall * 1e6 / prob.nsteps, "error": err,
+            "end_to_end": end_to_end(step_b, prob.nsteps, wall, copies),
+            "row_pass": rf(row_b, row), "col_pass": rf(col_b, col), "mid_pass": rf(mid_b, mid),
+            "adams_step_us_eager": row + col + 2 * mid}
+
+
 def sampled_leg(runs: int, copies: dict) -> dict:
     """A general non-separable potential given as samples at the step times
     (TDSE_V_SAMPLED) on the 512^2 grid (seed 1, 500 steps, dt = 1e-3):
@@ -871,6 +926,8 @@ def main():
         res["periodic_3d"] = periodic_3d_leg(args.runs_3d, copies)
     if not args.no_sampled:
         res["sampled"] = sampled_leg(3, copies)
+    if not args.no_free_3d:
+        res["free_space_3d"] = free_space_3d_leg(3, copies)
     if batch is not None:
         res["batch"] = batch
     if not args.no_cpu:

@@ -91,10 +91,13 @@ typedef void (*tdse_vector_fn)(double t, double* A_out, void* ctx);
 
 /* Problem statement (Section 1: domain, u0 via tdse_set_state, V(x,t), A(t),
  * T, step size, order).  Unused fields may be zero.
- * d = 3 (Section 4.3's setting, periodic scheme of Section 2 in three
- * dimensions): periodic domain, TDSE_FP64 or TDSE_FP32_SPLIT, stored or
- * sampled potentials (V_kind 0 or 2), at most 2^28 points; single plans (no
- * batch, no adjoint).  Arrays are row-major over
+ * d = 3 (Section 4.3): the periodic scheme of Section 2 in three dimensions
+ * (TDSE_FP64 or TDSE_FP32_SPLIT) or the free-space scheme with the line
+ * transforms of Section 4.1 along each of the three axes (TDSE_FP64; the 125
+ * node-type subsets of Section 4.3 in tensor order); stored or sampled
+ * potentials (V_kind 0 or 2), at most 2^28 grid points; single plans (no
+ * batch, no adjoint, no evaluation at arbitrary points).  Arrays are
+ * row-major over
  * M[0] x M[1] x M[2] with the last axis fastest; A has d components. */
 typedef struct {
   int32_t dim;             /* 1, 2 or 3                                      */
@@ -122,7 +125,7 @@ typedef struct {
    * h = pi M / nu); H > 0 overrides the rule for H. */
   double  eps;
   int32_t p, q, panels;
-  int32_t nu[2];
+  int32_t nu[3];
   double  H;
   /* potential kind (TDSE_V_*; 0 = stored fields) and its parameters */
   int32_t V_kind;
@@ -253,6 +256,8 @@ int tdse_far_eval_noalloc(tdse_plan_t plan, const double* xs, int32_t nx, const 
 #define TDSE_Q_FS_NU         130  /* + axis: FFT size nu                          */
 #define TDSE_Q_FS_K          132  /* + axis: truncation K of Gamma_K (the last equispaced node is K - kappa h) */
 #define TDSE_Q_FS_CHEB       134  /* + axis: terms NT of the C-type Chebyshev interpolant (0: direct sums) */
+#define TDSE_Q_FS_AXIS2      136  /* + f: axis 2 of a 3D free-space plan (the keys above take axes 0 and 1):
+                                     f = 0 modes, 1 N_E, 2 H, 3 h, 4 nu, 5 K, 6 NT */
 #define TDSE_Q_ALPERT_X       96  /* + k: Alpert node x_k (units of h), k < p   */
 #define TDSE_Q_ALPERT_W      112  /* + k: Alpert weight w_k, k < p              */
 #define TDSE_Q_INSTANCES       4  /* batch: number of instances                 */

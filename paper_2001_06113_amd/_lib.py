@@ -22,7 +22,7 @@ class Problem(C.Structure):
         ("A_steps", C.POINTER(C.c_double)),
         ("A_fn", VECTOR_FN), ("A_ctx", C.c_void_p),
         ("eps", C.c_double), ("p", C.c_int32), ("q", C.c_int32), ("panels", C.c_int32),
-        ("nu", C.c_int32 * 2), ("H", C.c_double),
+        ("nu", C.c_int32 * 3), ("H", C.c_double),
         ("V_kind", C.c_int32), ("V_params", C.c_double * 4),
         ("cheb", C.c_int32),
     ]

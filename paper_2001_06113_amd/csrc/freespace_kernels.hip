@@ -35,26 +35,33 @@ namespace tdse {
 __device__ __forceinline__ double2 fs_mul_mi(double c, double2 z) { return double2{c * z.y, -c * z.x}; }
 
 // Per-axis phase factors exp(i(-zeta^2 tau_j + zeta dphi_j)) for complex
-// nodes zeta (|.| != 1 off the real axis), table ph[(j-1)(N1+N2) + k].
+// nodes zeta (|.| != 1 off the real axis), table ph[(j-1)(N1+N2) + k]; in
+// 3D the first N1 = N0 Nm entries are the products of the axis-0 and
+// middle-axis factors of the row (k0, k1).
 __device__ __forceinline__ void build_phase_table_fs(const FSArgs& a, int nthreads) {
   const int per = a.N1 + a.N2;
   const int total = a.req.nj * per;
   for (int idx = blockIdx.x * nthreads + threadIdx.x; idx < total; idx += gridDim.x * nthreads) {
     const int j = idx / per;
     const int kk = idx - j * per;
-    double2 z;
-    double dphi;
-    if (kk < a.N1) {
-      z = a.ax1.zeta ? a.ax1.zeta[kk] : double2{0.0, 0.0};
-      dphi = a.req.dphi1[j];
-    } else {
-      z = a.ax2.zeta[kk - a.N1];
-      dphi = a.req.dphi2[j];
+    // theta = -(z . z) tau + z . dphi (complex); exp(i theta)
+    double tr, ti;
+    auto add = [&](double2 z, double dphi) {
+      const double2 z2 = cmul(z, z);
+      tr += -z2.x * a.req.tau[j] + z.x * dphi;
+      ti += -z2.y * a.req.tau[j] + z.y * dphi;
+    };
+    tr = 0.0;
+    ti = 0.0;
+    if (kk >= a.N1) {
+      add(a.ax2.zeta[kk - a.N1], a.req.dphi2[j]);
+    } else if (a.Nm == 0) {
+      add(a.ax1.zeta ? a.ax1.zeta[kk] : double2{0.0, 0.0}, a.req.dphi1[j]);
+    } else {   // 3D row (k0, k1): axis 0 and the middle axis
+      const int k0 = kk / a.Nm;
+      add(a.ax1.zeta[k0], a.req.dphi0[j]);
+      add(a.axm.zeta[kk - k0 * a.Nm], a.req.dphi1[j]);
     }
-    const double2 z2 = cmul(z, z);
-    // theta = -z^2 tau + z dphi (complex); exp(i theta)
-    const double tr = -z2.x * a.req.tau[j] + z.x * dphi;
-    const double ti = -z2.y * a.req.tau[j] + z.y * dphi;
     const double mag = exp(-ti);
     double s, c;
     sincos(tr, &s, &c);
@@ -861,7 +868,8 @@ __global__ __launch_bounds__(NU / 4) void k_fs_row_rs(FSArgs a) {
   }
 }
 
-// The column pass with 2 TL threads per column (ray halves as in the row pass).
+// The column pass with 2 TL threads per column (ray halves as in the row pass);
+// the columns are the ncol points of the other axes (x2, or (x1, x2) in 3D).
 template <int NU, bool CH>
 __global__ __launch_bounds__(NU / 4) void k_fs_col_rs(FSArgs a) {
   constexpr int TL = NU / 8, NTH = 2 * TL;
@@ -870,7 +878,7 @@ __global__ __launch_bounds__(NU / 4) void k_fs_col_rs(FSArgs a) {
   double2* part = fline2;
   const CFAxis& ax = a.ax1;
   const int M1 = ax.M, N1 = ax.N, NE = ax.NE, ND = ax.ND;
-  const int M2 = a.ax2.M;
+  const int64_t M2 = a.ncol;   // columns; the stride along axis 0
   double2* fin = fs_lds;
   double2* dm = CH ? fin : fin + M1;
   double2* fline = CH ? fin + (M1 > ND ? M1 : ND) : dm + ND;
@@ -935,6 +943,61 @@ __global__ __launch_bounds__(NU / 4) void k_fs_col_rs(FSArgs a) {
     if (e < NE) a.dst[(int64_t)(ray ? NE - 1 - e : N1 - NE + e) * M2 + y] = v[m];
   }
   for (int q = tid; q < ND; q += NTH) a.dst[(int64_t)(NE + q) * M2 + y] = dm[q];
+}
+
+// Middle-axis line transform of a 3D problem (ray halves as above): line
+// (k0, x2) of the N0 x Nm x M2 mode array and of the N0 x Mm x M2 grid array,
+// stride M2.  INV: modes to grid points (before the column pass), else grid
+// points to modes (after it).
+template <int NU, bool CH, bool INV>
+__global__ __launch_bounds__(NU / 4) void k_fs_mid_rs(FSArgs a) {
+  constexpr int TL = NU / 8, NTH = 2 * TL;
+  HIP_DYNAMIC_SHARED(double2, fs_lds)
+  __shared__ double2 fline2[lds_line_len(NU)];
+  double2* part = fline2;
+  const CFAxis& ax = a.axm;
+  const int Mm = ax.M, Nm = ax.N, NE = ax.NE, ND = ax.ND;
+  const int M2 = a.ax2.M;
+  double2* fin = fs_lds;
+  double2* dm = CH ? fin : fin + Mm;
+  double2* fline = CH ? fin + (Mm > ND ? Mm : ND) : dm + ND;
+  double2* tws = fline + lds_line_len(NU);
+  const int tid = threadIdx.x;
+  const bool ray = tid >= TL;
+  const int t = ray ? tid - TL : tid;
+  const int k0 = blockIdx.x / M2, x2 = blockIdx.x - k0 * M2;
+  const int64_t mbase = (int64_t)k0 * Nm * M2 + x2;   // mode k of the line at mbase + k M2
+  const int64_t gbase = (int64_t)k0 * Mm * M2 + x2;   // point e of the line at gbase + e M2
+  const auto tw = stage_twiddles_n<NU>(ax, tws, tid, NTH);
+  double2 v[RAY];
+  if constexpr (INV) {
+#pragma unroll
+    for (int m = 0; m < RAY; ++m) {
+      const int e = t + TL * m;
+      const int k = ray ? NE - 1 - e : Nm - NE + e;
+      v[m] = e < NE ? a.src[mbase + (int64_t)k * M2] : double2{0.0, 0.0};
+    }
+    for (int q = tid; q < ND; q += NTH) dm[q] = a.src[mbase + (int64_t)(NE + q) * M2];
+    __syncthreads();
+    rs_inverse<NU, CH>(v, dm, fline, fline2, ax, tw, tid, fin);
+    if (!ray) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int e = t + TL * m;
+        if (e < Mm) a.dst[gbase + (int64_t)e * M2] = fin[e];
+      }
+    }
+  } else {
+    for (int e = tid; e < Mm; e += NTH) fin[e] = a.src[gbase + (int64_t)e * M2];
+    __syncthreads();
+    rs_forward<NU, CH>(fin, v, dm, part, fline, fline2, ax, tw, tid);
+#pragma unroll
+    for (int m = 0; m < RAY; ++m) {
+      const int e = t + TL * m;
+      if (e < NE) a.dst[mbase + (int64_t)(ray ? NE - 1 - e : Nm - NE + e) * M2] = v[m];
+    }
+    for (int q = tid; q < ND; q += NTH) a.dst[mbase + (int64_t)(NE + q) * M2] = dm[q];
+  }
 }
 
 // --------------------------------------------------- pointwise column pass (1D)
@@ -1055,9 +1118,31 @@ hipError_t launch_fs_col(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0, 
 #define X(n)                                                                              \
   case n:                                                                                 \
     if (a.ax1.NT)                                                                         \
-      TDSE_FS_LAUNCH_SH((k_fs_col_rs<n, true>), dim3(a.ax2.M), dim3(n / 4), fs_lds_bytes<n>(a.ax1.M, a.ax1.ND, a.ax1.NT != 0), s, e0, e1, a); \
+      TDSE_FS_LAUNCH_SH((k_fs_col_rs<n, true>), dim3((unsigned)a.ncol), dim3(n / 4), fs_lds_bytes<n>(a.ax1.M, a.ax1.ND, a.ax1.NT != 0), s, e0, e1, a); \
     else                                                                                  \
-      TDSE_FS_LAUNCH_SH((k_fs_col_rs<n, false>), dim3(a.ax2.M), dim3(n / 4), fs_lds_bytes<n>(a.ax1.M, a.ax1.ND, a.ax1.NT != 0), s, e0, e1, a); \
+      TDSE_FS_LAUNCH_SH((k_fs_col_rs<n, false>), dim3((unsigned)a.ncol), dim3(n / 4), fs_lds_bytes<n>(a.ax1.M, a.ax1.ND, a.ax1.NT != 0), s, e0, e1, a); \
+    break;
+    TDSE_FS_NU(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fs_mid(int nu, bool inverse, const FSArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 g((unsigned)((int64_t)a.ax1.N * a.ax2.M));
+  const size_t lds_b = fs_line_lds_bytes(nu, a.axm.M, a.axm.ND, a.axm.NT != 0);
+  switch (nu) {
+#define X(n)                                                                                                  \
+  case n:                                                                                                     \
+    if (a.axm.NT) {                                                                                           \
+      if (inverse) TDSE_FS_LAUNCH_SH((k_fs_mid_rs<n, true, true>), g, dim3(n / 4), lds_b, s, e0, e1, a);       \
+      else TDSE_FS_LAUNCH_SH((k_fs_mid_rs<n, true, false>), g, dim3(n / 4), lds_b, s, e0, e1, a);              \
+    } else {                                                                                                  \
+      if (inverse) TDSE_FS_LAUNCH_SH((k_fs_mid_rs<n, false, true>), g, dim3(n / 4), lds_b, s, e0, e1, a);      \
+      else TDSE_FS_LAUNCH_SH((k_fs_mid_rs<n, false, false>), g, dim3(n / 4), lds_b, s, e0, e1, a);             \
+    }                                                                                                         \
     break;
     TDSE_FS_NU(X)
 #undef X

@@ -300,7 +300,7 @@ struct tdse_plan_s {
   // ---- free space (Sections 3.4 and 4)
   bool free_space = false;
   double H = 0.0;              // contour parameter of physical axis 0
-  double Hfx[2] = {0.0, 0.0};  // per transform axis fx[a] (1D: fx[1])
+  double Hfx[3] = {0.0, 0.0, 0.0};  // per transform axis fx[a] (see fx_of)
   std::vector<double> alp_x, alp_w;   // Alpert end correction, units of h
   struct FAxis {
     int M = 1, N = 1, NE = 0, ND = 0, nu = 0;
@@ -311,10 +311,11 @@ struct tdse_plan_s {
                                        // Dfwd [NR][M], Dinv [NR][M], tw [nu], zeta [N], rfwd [NR],
                                        // w [N], Pf [N_C][NT], Pi [NT][N_C]
     size_t o_tab = 0;                  // workspace offset of the tables
-  } fx[2];
-  int64_t NM = 1;                      // modes N1 N2
+  } fx[3];                            // fx[0]: axis 0 (column pass), fx[1]: the last axis (row
+                                       // pass), fx[2]: the middle axis of a 3D problem
+  int64_t NM = 1;                      // modes N1 N2 (3D: N0 N2 Nm)
   std::vector<double> Vsrc;            // potential fields (host copy, FP64)
-  size_t o_UH[2] = {0, 0}, o_tmpf = 0, o_ringf = 0, o_Vf = 0;
+  size_t o_UH[2] = {0, 0}, o_tmpf = 0, o_ringf = 0, o_Vf = 0, o_midf = 0;
   int uh_cur = 0;
   // binding and clock
   char* ws = nullptr;
@@ -982,6 +983,14 @@ int cheb_terms(double H) {
 // Nodes, weights and transform tables of one axis (Sections 3.4 and 4.1).
 // cheb: 0 automatic (the interpolant when it has fewer terms than Gamma_2 has
 // nodes), -1 direct C sums, n > 0 the interpolant with n terms.
+// transform axis fx[] of physical axis a: 1D: the row axis fx[1]; 2D: fx[a];
+// 3D: axis 0 -> fx[0], the middle axis -> fx[2], the last axis -> fx[1]
+int fx_of(int dim, int a) {
+  if (dim == 1) return 1;
+  if (dim == 2) return a;
+  return a == 0 ? 0 : (a == 1 ? 2 : 1);
+}
+
 void plan_free_axis(tdse_plan_s* p, int axis, int M, int nu, int q, int panels, int cheb) {
   typedef long double LD;
   tdse_plan_s::FAxis& F = p->fx[axis];
@@ -1190,10 +1199,14 @@ CFAxis cf_axis(const tdse_plan_s* p, int axis) {
 FSArgs fs_args(const tdse_plan_s* p) {
   FSArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.N1 = p->fx[0].N;
+  const bool d3 = p->dim == 3;
+  a.N1 = p->fx[0].N * (d3 ? p->fx[2].N : 1);
   a.N2 = p->fx[1].N;
   a.ax1 = cf_axis(p, 0);
   a.ax2 = cf_axis(p, 1);
+  a.Nm = d3 ? p->fx[2].N : 0;
+  a.ncol = (int64_t)p->fx[1].M * (d3 ? p->fx[2].M : 1);
+  if (d3) a.axm = cf_axis(p, 2);
   a.Bm = p->B();
   a.ring = (double2*)(p->ws + p->o_ringf);
   a.ring_stride = p->NM;
@@ -1219,7 +1232,12 @@ void set_V(const tdse_plan_s* p, int, FSArgs& a, double t) {
   }
 }
 
-int fs_launch(tdse_plan_s* p, bool col, const FSArgs& a, bool timed = false) {
+// 3D: a middle-axis transform between the (k0, k1, x2) mode tile and the
+// (k0, x1, x2) grid array, timed (kind 5) like the other passes
+int fs_mid(tdse_plan_s* p, const FSArgs& a, bool inverse, bool timed) {
+  FSArgs m = a;
+  m.src = inverse ? (const double2*)(p->ws + p->o_tmpf) : (const double2*)(p->ws + p->o_midf);
+  m.dst = inverse ? (double2*)(p->ws + p->o_midf) : (double2*)(p->ws + p->o_tmpf);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const size_t first = p->ev_used;
   if (timed && p->prof) {
@@ -1227,10 +1245,37 @@ int fs_launch(tdse_plan_s* p, bool col, const FSArgs& a, bool timed = false) {
     e1 = next_event(p);
     if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
   }
-  hipError_t e = col ? launch_fs_col(p->dim == 2 ? p->fx[0].nu : 0, a, p->stream, e0, e1)
-                     : launch_fs_row(p->fx[1].nu, a, p->stream, e0, e1);
+  const hipError_t e = launch_fs_mid(p->fx[2].nu, inverse, m, p->stream, e0, e1);
+  if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  if (e0) p->prof_marks.push_back({first, 5});
+  return TDSE_OK;
+}
+
+int fs_launch(tdse_plan_s* p, bool col, const FSArgs& a, bool timed = false) {
+  const bool d3 = p->dim == 3;
+  FSArgs c = a;
+  if (col && d3) {
+    // the column pass works on the (k0, x1, x2) array: the modes' middle axis
+    // is inverted first for a solve, and transformed back after the pass
+    if (a.mode == C_SOLVE) {
+      const int s = fs_mid(p, a, true, timed);
+      if (s) return s;
+    }
+    c.src = (const double2*)(p->ws + p->o_midf);
+    c.dst = (double2*)(p->ws + p->o_midf);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const size_t first = p->ev_used;
+  if (timed && p->prof) {
+    e0 = next_event(p);
+    e1 = next_event(p);
+    if (!e0 || !e1) return fail(TDSE_EDEVICE, "hipEventCreate failed");
+  }
+  hipError_t e = col ? launch_fs_col(p->dim >= 2 ? p->fx[0].nu : 0, c, p->stream, e0, e1)
+                     : launch_fs_row(p->fx[1].nu, c, p->stream, e0, e1);
   if (e != hipSuccess) return fail(TDSE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
   if (e0) p->prof_marks.push_back({first, col ? 0 : 1});
+  if (col && d3) return fs_mid(p, a, false, timed);
   return TDSE_OK;
 }
 
@@ -1395,10 +1440,10 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
   // representation bounds it, with that axis' quiver radius max_t |phi_a(t)|;
   // maxima over the step times
   if (prob->H > 0.0) {
-    p->Hfx[0] = p->Hfx[1] = prob->H;
+    p->Hfx[0] = p->Hfx[1] = p->Hfx[2] = prob->H;
   } else {
-    const double cell = (p->dim == 2 ? 4.0 / ((double)p->M1 * p->M2) : 2.0 / p->M2);
-    double normV = 0.0, phimax[2] = {0.0, 0.0};
+    const double cell = std::ldexp(1.0, p->dim) / (double)p->P;
+    double normV = 0.0, phimax[3] = {0.0, 0.0, 0.0};
     std::vector<double> f(MAXV);
     for (int n = 0; n <= p->nsteps; ++n) {
       const double t = p->t_at(n);
@@ -1416,15 +1461,17 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
       for (int a = 0; a < p->dim; ++a) phimax[a] = std::max(phimax[a], std::fabs(ph[a]));
     }
     const double num = std::log(prob->eps / ((1.0 + normV) * std::ldexp(1.0, -52)));
-    // physical axis a is transform axis fx[a] in 2D and fx[1] in 1D
-    for (int a = 0; a < p->dim; ++a) p->Hfx[p->dim == 2 ? a : 1] = num / (2.0 * p->dim * (1.0 + phimax[a]));
+    for (int a = 0; a < p->dim; ++a) p->Hfx[fx_of(p->dim, a)] = num / (2.0 * p->dim * (1.0 + phimax[a]));
   }
-  p->H = p->Hfx[p->dim == 2 ? 0 : 1];
+  p->H = p->Hfx[fx_of(p->dim, 0)];
   for (int a = 0; a < p->dim; ++a)
-    if (!(p->Hfx[p->dim == 2 ? a : 1] > 0.0)) return fail(TDSE_EINVAL, "the rule for H gives H <= 0 (eps too small)");
-  const int axes[2] = {p->dim == 2 ? prob->M[0] : 1, p->dim == 2 ? prob->M[1] : prob->M[0]};
-  const int nus[2] = {p->dim == 2 ? prob->nu[0] : 0, p->dim == 2 ? prob->nu[1] : prob->nu[0]};
-  for (int a = 0; a < 2; ++a) {
+    if (!(p->Hfx[fx_of(p->dim, a)] > 0.0)) return fail(TDSE_EINVAL, "the rule for H gives H <= 0 (eps too small)");
+  int axes[3] = {1, 1, 1}, nus[3] = {0, 0, 0};
+  for (int a = 0; a < p->dim; ++a) {
+    axes[fx_of(p->dim, a)] = prob->M[a];
+    nus[fx_of(p->dim, a)] = prob->nu[a];
+  }
+  for (int a = 0; a < (p->dim == 3 ? 3 : 2); ++a) {
     if (a == 0 && p->dim == 1) {
       tdse_plan_s::FAxis& F = p->fx[0];
       F = tdse_plan_s::FAxis();
@@ -1444,19 +1491,27 @@ int plan_free(tdse_plan_s* p, const tdse_problem_t* prob) {
     if (fs_line_lds_bytes(nu, M, p->fx[a].ND, p->fx[a].NT != 0) > 65536)
       return fail(TDSE_EINVAL, "free-space line needs more than 64 KiB of LDS (M too large for this nu)");
   }
-  p->NM = (int64_t)p->fx[0].N * p->fx[1].N;
+  const bool d3 = p->dim == 3;
+  const int64_t Nm = d3 ? p->fx[2].N : 1, Mm = d3 ? p->fx[2].M : 1;
+  p->NM = (int64_t)p->fx[0].N * Nm * p->fx[1].N;
+  if ((double)p->NM * sizeof(double2) * (p->order + 3) > (double)((int64_t)200 << 30))
+    return fail(TDSE_EINVAL, "free space: the mode arrays would pass 200 GiB");
   size_t off = 0;
   const size_t mb = (size_t)p->NM * sizeof(double2);
   p->o_B = off; off = align256(off + mb);
   p->o_ringf = off; off = align256(off + (size_t)(p->order - 1) * mb);
   p->o_UH[0] = off; off = align256(off + mb);
   p->o_UH[1] = off; off = align256(off + mb);
-  p->o_tmpf = off; off = align256(off + (size_t)p->fx[0].N * p->fx[1].M * sizeof(double2));
+  p->o_tmpf = off; off = align256(off + (size_t)p->fx[0].N * Nm * p->fx[1].M * sizeof(double2));
+  if (d3) {   // the (k0, x1, x2) array between the middle-axis passes and the column pass
+    p->o_midf = off;
+    off = align256(off + (size_t)p->fx[0].N * Mm * p->fx[1].M * sizeof(double2));
+  }
   p->o_u[0] = off; off = align256(off + (size_t)p->P * sizeof(double2));
   p->o_u[1] = off; off = align256(off + (size_t)p->P * sizeof(double2));
   p->o_Vf = off; off = align256(off + p->Vsrc.size() * sizeof(double));
-  p->o_ph = off; off = align256(off + (size_t)(p->order - 1) * (p->fx[0].N + p->fx[1].N) * sizeof(double2));
-  for (int a = 0; a < 2; ++a) {
+  p->o_ph = off; off = align256(off + (size_t)(p->order - 1) * (p->fx[0].N * Nm + p->fx[1].N) * sizeof(double2));
+  for (int a = 0; a < (d3 ? 3 : 2); ++a) {
     p->fx[a].o_tab = off;
     off = align256(off + p->fx[a].tables.size());
   }
@@ -2686,7 +2741,6 @@ int tdse_plan(const tdse_problem_t* prob, tdse_plan_t* out) {
   *out = nullptr;
   if (prob->dim < 1 || prob->dim > 3) return fail(TDSE_EINVAL, "dim must be 1, 2 or 3");
   if (prob->dim == 3) {
-    if (prob->domain != TDSE_PERIODIC) return fail(TDSE_EUNSUPPORTED, "3D runs the periodic scheme");
     if (prob->V_kind == TDSE_V_MOVING_WELL) return fail(TDSE_EUNSUPPORTED, "3D takes stored or sampled potentials");
     if ((int64_t)prob->M[0] * prob->M[1] * prob->M[2] > ((int64_t)1 << 28))
       return fail(TDSE_EINVAL, "3D grid larger than 2^28 points");
@@ -2920,7 +2974,7 @@ int tdse_bind(tdse_plan_t p, void* ws, size_t bytes, void* stream) {
   if (p->free_space) {
     HIP_TRY(hipMemcpyAsync(p->ws + p->o_Vf, p->Vsrc.data(), p->Vsrc.size() * sizeof(double), hipMemcpyHostToDevice,
                            p->stream));
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < (p->dim == 3 ? 3 : 2); ++a)
       HIP_TRY(hipMemcpyAsync(p->ws + p->fx[a].o_tab, p->fx[a].tables.data(), p->fx[a].tables.size(),
                              hipMemcpyHostToDevice, p->stream));
   }
@@ -3043,6 +3097,7 @@ FarLayout far_layout(const tdse_plan_s* p, int nx, int ny) {
 }
 int far_check(const tdse_plan_s* p, int nx, int ny) {
   if (p->is_batch() || !p->free_space) return fail(TDSE_EUNSUPPORTED, "evaluation at arbitrary points is for free-space plans");
+  if (p->dim == 3) return fail(TDSE_EUNSUPPORTED, "evaluation at arbitrary points covers 1D and 2D plans");
   if (ny < 1 || nx < 1 || ny > (1 << 24) || nx > (1 << 24)) return fail(TDSE_EINVAL, "need 1 <= nx, ny <= 2^24");
   if (p->dim == 1 && nx != 1) return fail(TDSE_EINVAL, "a 1D plan takes nx = 1");
   // every table and product launch must fit a one-dimensional grid
@@ -3254,14 +3309,23 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     *value = p->run1d ? 1.0 : (p->persist && p->persist_on) ? 2.0 : 0.0;
     return TDSE_OK;
   }
+  if (p->free_space && p->dim == 3 && key == TDSE_Q_BYTES_MID) {
+    *value = 16.0 * (double)p->fx[0].N * p->fx[1].M * ((double)p->fx[2].N + p->fx[2].M);
+    return TDSE_OK;
+  }
   if (p->free_space && (key == TDSE_Q_BYTES_PER_STEP || key == TDSE_Q_BYTES_COL || key == TDSE_Q_BYTES_ROW)) {
     // column pass: tile (N1 x M2) in and out (32 per element) and the
     // potential fields (8 nV per grid point); row pass: tile in and out,
     // B in and out (32 per mode), n-2 history reads and one write (16 (n-1))
-    const double tile = (double)p->fx[0].N * p->fx[1].M;
-    const double col = 32.0 * tile + 8.0 * p->nV * (double)p->P;
+    // 3D: the row tile is N0 Nm M2, the column pass moves the N0 Mm M2 grid
+    // array, and each middle-axis pass moves both (16 per element each)
+    const bool d3 = p->dim == 3;
+    const double Nm = d3 ? p->fx[2].N : 1.0, Mm = d3 ? p->fx[2].M : 1.0;
+    const double tile = (double)p->fx[0].N * Nm * p->fx[1].M, grid = (double)p->fx[0].N * Mm * p->fx[1].M;
+    const double col = 32.0 * grid + 8.0 * p->nV * (double)p->P;
     const double row = 32.0 * tile + (32.0 + 16.0 * (p->order - 1)) * (double)p->NM;
-    *value = key == TDSE_Q_BYTES_COL ? col : key == TDSE_Q_BYTES_ROW ? row : col + row;
+    const double mid = d3 ? 16.0 * (tile + grid) : 0.0;
+    *value = key == TDSE_Q_BYTES_COL ? col : key == TDSE_Q_BYTES_ROW ? row : col + row + 2.0 * mid;
     return TDSE_OK;
   }
   if (key == TDSE_Q_FS_H) {
@@ -3269,38 +3333,33 @@ int tdse_query(tdse_plan_t p, int32_t key, double* value) {
     *value = p->H;
     return TDSE_OK;
   }
-  if (key >= TDSE_Q_FS_H_AXIS && key < TDSE_Q_FS_H_AXIS + 2) {
-    if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");
-    const int axis = key - TDSE_Q_FS_H_AXIS;
-    if (axis >= p->dim) return fail(TDSE_EINVAL, "axis out of range");
-    *value = p->Hfx[p->dim == 2 ? axis : 1];
-    return TDSE_OK;
-  }
-  if ((key >= TDSE_Q_FS_HSTEP && key < TDSE_Q_FS_HSTEP + 2) || (key >= TDSE_Q_FS_NU && key < TDSE_Q_FS_NU + 2) ||
-      (key >= TDSE_Q_FS_K && key < TDSE_Q_FS_K + 2) || (key >= TDSE_Q_FS_CHEB && key < TDSE_Q_FS_CHEB + 2)) {
-    if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");
-    const int base = key < TDSE_Q_FS_NU ? TDSE_Q_FS_HSTEP
-                     : key < TDSE_Q_FS_K ? TDSE_Q_FS_NU
-                     : key < TDSE_Q_FS_CHEB ? TDSE_Q_FS_K
-                                            : TDSE_Q_FS_CHEB;
-    const int axis = key - base;
-    if (axis >= p->dim) return fail(TDSE_EINVAL, "axis out of range");
-    const int fa = p->dim == 2 ? axis : 1;
-    const tdse_plan_s::FAxis& F = p->fx[fa];
-    if (base == TDSE_Q_FS_HSTEP) *value = F.h;
-    else if (base == TDSE_Q_FS_NU) *value = F.nu;
-    else if (base == TDSE_Q_FS_CHEB) *value = F.NT;
-    else *value = p->Hfx[fa] + (2.0 * 7 + F.NE - 1) * F.h;   // the last equispaced node is K - kappa h (kappa = 7)
-    return TDSE_OK;
-  }
-  if ((key >= TDSE_Q_FS_MODES && key < TDSE_Q_FS_MODES + 2) || (key >= TDSE_Q_FS_NE && key < TDSE_Q_FS_NE + 2)) {
-    if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");
-    const bool modes = key < TDSE_Q_FS_NE;
-    const int axis = key - (modes ? TDSE_Q_FS_MODES : TDSE_Q_FS_NE);
-    if (axis >= p->dim) return fail(TDSE_EINVAL, "axis out of range");
-    const tdse_plan_s::FAxis& F = p->fx[p->dim == 2 ? axis : 1];
-    *value = modes ? (double)F.N : (double)F.NE;
-    return TDSE_OK;
+  {
+    // per-axis contour keys: (field, physical axis)
+    int field = -1, axis = 0;
+    if (key >= TDSE_Q_FS_MODES && key < TDSE_Q_FS_MODES + 2) field = 0, axis = key - TDSE_Q_FS_MODES;
+    else if (key >= TDSE_Q_FS_NE && key < TDSE_Q_FS_NE + 2) field = 1, axis = key - TDSE_Q_FS_NE;
+    else if (key >= TDSE_Q_FS_H_AXIS && key < TDSE_Q_FS_H_AXIS + 2) field = 2, axis = key - TDSE_Q_FS_H_AXIS;
+    else if (key >= TDSE_Q_FS_HSTEP && key < TDSE_Q_FS_HSTEP + 2) field = 3, axis = key - TDSE_Q_FS_HSTEP;
+    else if (key >= TDSE_Q_FS_NU && key < TDSE_Q_FS_NU + 2) field = 4, axis = key - TDSE_Q_FS_NU;
+    else if (key >= TDSE_Q_FS_K && key < TDSE_Q_FS_K + 2) field = 5, axis = key - TDSE_Q_FS_K;
+    else if (key >= TDSE_Q_FS_CHEB && key < TDSE_Q_FS_CHEB + 2) field = 6, axis = key - TDSE_Q_FS_CHEB;
+    else if (key >= TDSE_Q_FS_AXIS2 && key < TDSE_Q_FS_AXIS2 + 7) field = key - TDSE_Q_FS_AXIS2, axis = 2;
+    if (field >= 0) {
+      if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");
+      if (axis >= p->dim) return fail(TDSE_EINVAL, "axis out of range");
+      const int fa = fx_of(p->dim, axis);
+      const tdse_plan_s::FAxis& F = p->fx[fa];
+      switch (field) {
+        case 0: *value = (double)F.N; break;
+        case 1: *value = (double)F.NE; break;
+        case 2: *value = p->Hfx[fa]; break;
+        case 3: *value = F.h; break;
+        case 4: *value = F.nu; break;
+        case 5: *value = p->Hfx[fa] + (2.0 * 7 + F.NE - 1) * F.h; break;   // the last equispaced node is K - kappa h
+        default: *value = F.NT; break;
+      }
+      return TDSE_OK;
+    }
   }
   if ((key >= TDSE_Q_ALPERT_X && key < TDSE_Q_ALPERT_X + 16) || (key >= TDSE_Q_ALPERT_W && key < TDSE_Q_ALPERT_W + 16)) {
     if (!p->free_space) return fail(TDSE_EINVAL, "not a free-space plan");

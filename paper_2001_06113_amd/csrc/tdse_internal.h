@@ -145,6 +145,12 @@ struct FSArgs {
   double2* ph;
   PhaseReq req;
   CFAxis ax1, ax2;
+  // 3D: the row pass runs over N1 = N0 Nm rows (k0, k1), the column pass
+  // over ncol = Mm M2 columns (x1, x2) of the (k0, x1, x2) array, and the
+  // middle-axis passes transform along axis 1 (axm) between the two
+  int Nm;                       // middle-axis modes (0: 1D or 2D)
+  int64_t ncol;                 // columns of the column pass (M2 in 2D)
+  CFAxis axm;
 };
 
 // Batched passes (batch_fp64.hip, batch_split.hip): one launch per schedule
@@ -224,6 +230,11 @@ hipError_t launch_fs_row(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0 =
 // nu = 0: the pointwise pass of a 1D problem
 hipError_t launch_fs_col(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_fs_phase(const FSArgs& a, hipStream_t s);
+// 3D: the line transform along the middle axis (a.axm) of the N0 x Nm x M2
+// mode array src into the N0 x Mm x M2 grid array dst (inverse), or back
+// (forward); lines (k0, x2), one per workgroup
+hipError_t launch_fs_mid(int nu, bool inverse, const FSArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 bool fs_nu_supported(int nu);
 size_t fs_line_lds_bytes(int nu, int M, int ND, bool ch);   // dynamic LDS of a line workgroup (ch: interpolant on)
 

@@ -24,7 +24,8 @@ Q_MU, Q_RICHARDSON, Q_PHI = 16, 32, 64
 Q_INSTANCES, Q_INST_OFFSET, Q_INST_EPT_COL, Q_INST_EPT_ROW = 4, 4096, 8192, 12288
 Q_PROF_MS_RUN1D, Q_PROF_N_RUN1D, Q_PROF_MS_PERSIST, Q_PROF_N_PERSIST, Q_PATH = 24, 25, 26, 27, 28
 Q_RESIDUAL, Q_STATE_NORM = 29, 30
-Q_FS_H_AXIS, Q_FS_HSTEP, Q_FS_NU, Q_FS_K, Q_FS_CHEB = 86, 128, 130, 132, 134
+Q_FS_H, Q_FS_MODES, Q_FS_NE = 80, 81, 83
+Q_FS_H_AXIS, Q_FS_HSTEP, Q_FS_NU, Q_FS_K, Q_FS_CHEB, Q_FS_AXIS2 = 86, 128, 130, 132, 134, 136
 CFG_PERSISTENT, CFG_GUARD = 0, 1
 
 

@@ -18,6 +18,8 @@ Cases (one file each, tests/golden/<case>_oracle_sample.txt):
   periodic_3d_128    3D periodic, 128^3, 500 steps to T = 0.5 (seed 50), every 8th point per axis
   sampled_2d_512     2D periodic, 512^2 (seed 1), the potential replaced by the general sampled
                      V(x, t) of sampled_potential_problem, 500 steps to T = 0.5, every 8th point
+  free_3d_32         3D free space, 32^3, nu = 256 per axis, eps = 1e-8, q = 8, 100 steps to
+                     T = 0.1 (seed 62), the plan's default H per axis, every 4th point per axis
   example2_long_time_nr5
                      Section 6, Example 2's long-time wave packet: 1D free space, M = 128,
                      nu = 1024, q = 16, n_r = 5, 1000 steps to T = 1000, the C-type block
@@ -42,6 +44,7 @@ sys.path.insert(0, ROOT)
 from oracle.freespace import FreeSpaceOracle  # noqa: E402
 from oracle.periodic import PeriodicOracle  # noqa: E402
 from workloads import (batch_64_problems, example2_long_time_problem, free_2d_256_problem,  # noqa: E402
+                       free_3d_32_problem,
                        moving_well_problem, periodic_1d_256_problem, periodic_2d_512_problem,
                        periodic_2d_1024_problem, periodic_3d_128_problem, sampled_2d_512_problem)
 
@@ -79,6 +82,7 @@ def cases():
         "example2_long_time_nr5": lambda: [("free", example2_long_time_problem(5), 1, 1)],
         "periodic_3d_128": lambda: [("periodic", periodic_3d_128_problem(), 8, 8)],
         "sampled_2d_512": lambda: [("periodic", sampled_2d_512_problem(), 8, 8)],
+        "free_3d_32": lambda: [("free", free_3d_32_problem(), 4, 4)],
     }
 
 

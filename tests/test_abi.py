@@ -42,7 +42,8 @@ def _problem(dim=2, M=(32, 64), T=1.0, nsteps=100, order=8, A=None, nV=1, f=None
     p = _lib.Problem()
     p.dim = dim
     p.domain = domain
-    p.nu[0], p.nu[1] = nu
+    for a, n in enumerate(nu):
+        p.nu[a] = n
     p.p, p.q, p.panels, p.eps, p.H = fs_p, q, panels, eps, H
     p.cheb = cheb
     p.M[0], p.M[1] = M[0], (M[1] if len(M) > 1 else 0)
@@ -79,7 +80,8 @@ def _plan(lib, p):
 @pytest.mark.parametrize("kw,status", [
     (dict(dim=4), -1),
     (dict(dim=3), -1),                               # third axis of size 0
-    (dict(dim=3, M=(32, 64, 16), domain=1), -2),     # 3D runs the periodic scheme
+    (dict(dim=3, M=(32, 64, 16), domain=1), -1),     # 3D free space: no FFT size for the third axis
+    (dict(dim=3, M=(32, 64, 16), domain=1, nu=(256, 256, 256), precision=1), -2),   # free space: FP64 only
     (dict(dim=3, M=(32, 64, 30)), -1),
     (dict(dim=3, M=(1024, 1024, 512)), -1),          # more than 2^28 points
     (dict(dim=0), -1),
@@ -234,7 +236,14 @@ def test_free_space_planner_alpert_rule_matches_oracle(lib):
     lib.tdse_destroy(h)
 
 
-@pytest.mark.parametrize("dim,M,nu", [(1, (64,), (512,)), (2, (48, 32), (256, 512))])
+def _fs_key(field, axis):
+    # per-axis contour keys: axes 0 and 1 in their own blocks, axis 2 in TDSE_Q_FS_AXIS2
+    if axis == 2:
+        return 136 + field
+    return {0: 81, 1: 83, 2: 86}[field] + axis
+
+
+@pytest.mark.parametrize("dim,M,nu", [(1, (64,), (512,)), (2, (48, 32), (256, 512)), (3, (16, 24, 32), (256, 256, 256))])
 def test_free_space_planner_contour_matches_oracle(lib, dim, M, nu):
     # H from the rule of Section 3.2 with ||V|| and phi over the step times,
     # mode counts N = 2 N_E + 2p + N_C of Section 3.4
@@ -263,20 +272,23 @@ def test_free_space_planner_contour_matches_oracle(lib, dim, M, nu):
     assert lib.tdse_query(h, 80, C.byref(v)) == 0
     assert abs(v.value - orc.H) < 1e-12 * orc.H
     for a in range(dim):
-        # per-axis H: the field lies along axis 0, so a field-free axis 1 gets
+        # per-axis H: the field lies along axis 0, so a field-free axis gets
         # the rule's value at phi_max = 0, larger than axis 0's
-        assert lib.tdse_query(h, 86 + a, C.byref(v)) == 0
+        assert lib.tdse_query(h, _fs_key(2, a), C.byref(v)) == 0
         assert abs(v.value - orc.Hs[a]) < 1e-12 * orc.Hs[a]
-    if dim == 2:
+    if dim >= 2:
         assert orc.Hs[1] > orc.Hs[0]
-    assert lib.tdse_query(h, 86 + dim, C.byref(v)) == -1
+    if dim < 3:
+        assert lib.tdse_query(h, 86 + dim, C.byref(v)) == -1
     for a in range(dim):
-        assert lib.tdse_query(h, 81 + a, C.byref(v)) == 0
+        assert lib.tdse_query(h, _fs_key(0, a), C.byref(v)) == 0
         assert v.value == orc.nodes[a][2]["N"]
-        assert lib.tdse_query(h, 83 + a, C.byref(v)) == 0
+        assert lib.tdse_query(h, _fs_key(1, a), C.byref(v)) == 0
         assert v.value == orc.nodes[a][2]["NE"]
     if dim == 1:
         assert lib.tdse_query(h, 82, C.byref(v)) == -1   # no second axis
+    if dim < 3:
+        assert lib.tdse_query(h, 136, C.byref(v)) == -1   # no third axis
     lib.tdse_destroy(h)
 
 

@@ -11,6 +11,7 @@ from .synth import (  # noqa: F401
     periodic_1d_256_problem,
     periodic_2d_512_problem,
     free_2d_256_problem,
+    free_3d_32_problem,
     periodic_2d_1024_problem,
     periodic_3d_128_problem,
     sampled_potential_problem,

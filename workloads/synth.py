@@ -296,7 +296,7 @@ def free_problem_from_seed(seed: int, dim: int, M: Sequence[int], T: float, nste
         nu = tuple(4 * m for m in M)
     prob = Problem(name=name or f"free{dim}d_seed{seed}", dim=dim, domain="free", M=M, T=T, nsteps=nsteps,
                    order=order, u0=u0, V_fields=[V0], f_kind=["sin"], f_params=[(0.1, om)],
-                   A_kind="pulse_sin2", A_params=(E0, om, T, 1.0, 0.0), eps=eps, q=q, panels=panels,
+                   A_kind="pulse_sin2", A_params=(E0, om, T, 1.0, 0.0) + (0.0,) * (dim - 2), eps=eps, q=q, panels=panels,
                    nu=tuple(int(v) for v in nu),
                    meta=dict(c=cj, p=pj, s=sj, E0=E0, omega=om, x0=x0, sigma=sig))
     if A_kind == "none":
@@ -371,6 +371,15 @@ def free_2d_256_problem(seed: int = 2, M: int = 256, T: float = 1.0, nsteps: int
     """2D free space, 256 x 256 physical points, eps = 1e-10, p = 8, q = 10,
     one Gauss panel per side, FFT size nu = 2048 per axis (seed 2)."""
     return free_problem_from_seed(seed, 2, (M, M), T, nsteps, order, nu=(nu, nu), name="free-2d-256")
+
+
+def free_3d_32_problem(seed: int = 62, M: int = 32, T: float = 0.1, nsteps: int = 100, order: int = 8,
+                       nu: int = 256) -> Problem:
+    """3D free space, 32^3 physical points, eps = 1e-8, p = 8, q = 8, one
+    Gauss panel per side, FFT size nu = 256 per axis (seed 62): the free-space
+    recipe in three dimensions, about 1.8e7 complex-frequency modes."""
+    return free_problem_from_seed(seed, 3, (M, M, M), T, nsteps, order, eps=1e-8, q=8, nu=(nu, nu, nu),
+                                  name="free-3d-32")
 
 
 def wavepacket(x, t: float, sigma: float):
