@@ -20,10 +20,11 @@
 // column-pass output, the implicit Adams recurrence on the row's N2 modes,
 // inverse transform into the tile buffer.  Column pass (axis 0, one physical
 // column per workgroup): inverse transform, diagonal solve, forward transform.
-// Two thread layouts: nu/8 threads that carry both rays (the 2D row pass,
-// with many rows and two workgroups per CU), and nu/4 threads with a ray per
-// half (the column pass and the single row of a 1D problem, where one
-// workgroup's latency is the pass's).
+// Two thread layouts: nu/8 threads that carry both rays (the row pass at
+// nu >= 1024 in 2D and 3D, with many rows and two workgroups per CU), and
+// nu/4 threads with a ray per half (the column and middle-axis passes, the
+// single row of a 1D problem, where one workgroup's latency is the pass's,
+// and the short rows of nu <= 512).
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
@@ -1072,10 +1073,12 @@ size_t fs_line_lds_bytes(int nu, int M, int ND, bool ch) {
 }
 
 // The row pass of a 1D problem is a single workgroup: it takes the ray-split
-// kernel (twice the threads on the one line).  A 2D row pass has N1 rows, and
-// two workgroups of the two-line kernel per CU keep more loads in flight.
+// kernel (twice the threads on the one line).  So do the many short rows of
+// nu <= 512, whose workgroups are small enough that LDS does not cap the
+// occupancy.  The rows of nu >= 1024 keep the two-ray kernel: at 80 KB of LDS
+// per workgroup, two of them per CU keep more loads in flight.
 hipError_t launch_fs_row(int nu, const FSArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (a.N1 == 1) {
+  if (a.N1 == 1 || nu <= 512) {
     switch (nu) {
 #define X(n)                                                                              \
   case n:                                                                                 \
