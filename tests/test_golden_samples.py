@@ -11,7 +11,7 @@ import pytest
 from workloads.golden import GOLDEN, load_samples, sampled_error
 
 CASES = ["periodic_1d_256", "periodic_2d_512", "periodic_2d_1024", "free_2d_256_default_h", "moving_well_2d_512", "batch_64",
-         "example2_long_time_nr5", "periodic_3d_128"]
+         "example2_long_time_nr5", "periodic_3d_128", "free_3d_32"]
 
 
 @pytest.mark.parametrize("case", CASES)
