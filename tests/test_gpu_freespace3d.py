@@ -47,21 +47,42 @@ CASES = [
     dict(seed=61, M=(8, 10, 8), nu=(256, 256, 256), N=2, order=2, q=4),
     dict(seed=64, M=(16, 12, 20), nu=(256, 512, 256), N=3, order=2, q=6),
     dict(seed=65, M=(12, 16, 8), nu=(256, 256, 256), N=4, order=4, q=4),   # start-up and one Adams step
+    # N_C = 32 > NT = 24 on every axis: the C-type block through the interpolant
+    dict(seed=67, M=(8, 8, 10), nu=(256, 256, 256), N=2, order=2, q=8, panels=2, nt=24),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[f"{c['M']}-{c['nu']}-o{c['order']}" for c in CASES])
 def test_3d_free_space_matches_oracle(case):
     print(f"case 3d free {case}", flush=True)
+    from paper_2001_06113_amd.tdse import Q_FS_AXIS2, Q_FS_CHEB
+
     prob = free_problem_from_seed(case["seed"], 3, case["M"], 0.02, case["N"], order=case["order"], nu=case["nu"],
-                                  eps=1e-8, q=case["q"], panels=1)
+                                  eps=1e-8, q=case["q"], panels=case.get("panels", 1))
+    plan = _plan(prob)
+    nt = [int(plan.query(Q_FS_CHEB + a if a < 2 else Q_FS_AXIS2 + 6)) for a in range(3)]
+    u = plan.run(prob.u0).cpu().numpy()
+    plan.close()
+    orc = FreeSpaceOracle(prob)
+    assert nt == orc.NT == [case.get("nt", 0)] * 3
+    ref, _ = orc.run()
+    e = _rel(u, ref)
+    print(f"  rel-L2 = {e:.3e}", flush=True)
+    assert e < TOL
+
+
+def test_3d_free_space_sampled_potential_matches_oracle():
+    # a general V(x, t) given by samples at the step times (the free-space
+    # moving well of sampled_potential_problem) on a 3D plan
+    from workloads import sampled_potential_problem
+
+    base = free_problem_from_seed(68, 3, (10, 8, 8), 0.02, 3, order=2, nu=(256, 256, 256), eps=1e-8, q=4, panels=1)
+    prob = sampled_potential_problem(base)
     plan = _plan(prob)
     u = plan.run(prob.u0).cpu().numpy()
     plan.close()
     ref, _ = FreeSpaceOracle(prob).run()
-    e = _rel(u, ref)
-    print(f"  rel-L2 = {e:.3e}", flush=True)
-    assert e < TOL
+    assert _rel(u, ref) < TOL
 
 
 def test_3d_free_space_pieces_and_graph_replay_bitwise():
