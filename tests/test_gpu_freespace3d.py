@@ -71,6 +71,24 @@ def test_3d_free_space_matches_oracle(case):
     assert e < TOL
 
 
+def test_3d_free_space_field_on_every_axis_matches_oracle():
+    # a stepwise field with components on all three axes: every axis' phase
+    # increment (the row factor's axis-0 and middle-axis parts, the last axis)
+    prob = free_problem_from_seed(69, 3, (8, 10, 12), 0.03, 5, order=4, nu=(256, 256, 256), eps=1e-8, q=4, panels=1)
+    rng = np.random.default_rng(69)
+    t = (np.arange(prob.nsteps) + 0.5) / prob.nsteps
+    prob.A_kind = "stepwise"
+    prob.A_steps = rng.uniform(-8.0, 8.0, size=3)[None, :] * np.sin(2 * np.pi * t)[:, None]
+    prob.A_params = ()
+    plan = _plan(prob)
+    u = plan.run(prob.u0).cpu().numpy()
+    plan.close()
+    orc = FreeSpaceOracle(prob)
+    assert all(abs(x) > 1e-4 for x in orc.phi(0.5 * prob.T))
+    ref, _ = orc.run()
+    assert _rel(u, ref) < TOL
+
+
 def test_3d_free_space_sampled_potential_matches_oracle():
     # a general V(x, t) given by samples at the step times (the free-space
     # moving well of sampled_potential_problem) on a 3D plan
