@@ -966,7 +966,9 @@ __global__ __launch_bounds__(NU / 4) void k_fs_mid_rs(FSArgs a) {
   const int tid = threadIdx.x;
   const bool ray = tid >= TL;
   const int t = ray ? tid - TL : tid;
-  const int k0 = blockIdx.x / M2, x2 = blockIdx.x - k0 * M2;
+  // lines sharing 128-byte lines of memory (consecutive x2) on one XCD
+  const int line = fs_col_of(blockIdx.x, gridDim.x);
+  const int k0 = line / M2, x2 = line - k0 * M2;
   const int64_t mbase = (int64_t)k0 * Nm * M2 + x2;   // mode k of the line at mbase + k M2
   const int64_t gbase = (int64_t)k0 * Mm * M2 + x2;   // point e of the line at gbase + e M2
   const auto tw = stage_twiddles_n<NU>(ax, tws, tid, NTH);
