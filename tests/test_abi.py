@@ -423,3 +423,8 @@ def test_far_evaluation_sizing_and_checks(lib):
     assert st == 0
     assert lib.tdse_far_workspace_size(h, 4, 4, C.byref(sz)) == -2
     lib.tdse_destroy(h)
+    # a 3D free-space plan: evaluation at arbitrary points is not offered
+    st, h = _plan(lib, _problem(dim=3, M=(8, 8, 8), domain=1, nu=(256, 256, 256), q=4, panels=1))
+    assert st == 0, lib.tdse_last_error()
+    assert lib.tdse_far_workspace_size(h, 4, 4, C.byref(sz)) == -2
+    lib.tdse_destroy(h)
