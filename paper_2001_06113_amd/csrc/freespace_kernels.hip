@@ -554,6 +554,7 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   // first history batch (term j = 2 on the E3 ray) are loaded before the
   // forward transform, so their latency overlaps it
   const bool pre = mode == R_AM && a.nh == MAXH - 1;
+  const bool pw = pre && a.pf_pow;
   double2 Bp3[RAY], Bp1[RAY], w0[RAY], pf0[RAY];
   if (pre) {
     const double2* __restrict__ r2 = a.ring + a.slot_r[2] * a.ring_stride + row_m;
@@ -564,7 +565,7 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       Bp3[m] = a.Bm[row_m + N2 - NE + ec];
       Bp1[m] = a.Bm[row_m + NE - 1 - ec];
       w0[m] = r2[N2 - NE + ec];
-      pf0[m] = p2[N2 - NE + ec];
+      if (!pw) pf0[m] = p2[N2 - NE + ec];
     }
   }
   if (need_fwd) {
@@ -605,13 +606,16 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     const int N1 = a.N1;
     int k3[RAY], k1r[RAY];
     double2 acc3[RAY], acc1[RAY];
+    double2 P3[RAY], P1[RAY];   // the last axis' factors of E^(1)
 #pragma unroll
     for (int m = 0; m < RAY; ++m) {
       const int ec = min(t + TL * m, NE - 1);
       k3[m] = N2 - NE + ec;
       k1r[m] = NE - 1 - ec;
       const double2 B3 = pre ? Bp3[m] : a.Bm[row_m + k3[m]], B1 = pre ? Bp1[m] : a.Bm[row_m + k1r[m]];
-      const double2 E3 = cmul(T1[0], ph[N1 + k3[m]]), E1 = cmul(T1[0], ph[N1 + k1r[m]]);
+      P3[m] = ph[N1 + k3[m]];
+      P1[m] = ph[N1 + k1r[m]];
+      const double2 E3 = cmul(T1[0], P3[m]), E1 = cmul(T1[0], P1[m]);
       // E^(1) (uhat - i dt mu_1 W),  uhat = B - i dt mu_0 W
       acc3[m] = cmul(E3, cadd(cadd(B3, fs_mul_mi(a.c0, v3[m])), fs_mul_mi(a.ch[1], v3[m])));
       acc1[m] = cmul(E1, cadd(cadd(B1, fs_mul_mi(a.c0, v1[m])), fs_mul_mi(a.ch[1], v1[m])));
@@ -643,7 +647,41 @@ __global__ __launch_bounds__(NU / 8) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         else acc3[m] = cadd(acc3[m], x);
       }
     };
-    if (nh == MAXH - 1) {   // the full order-8 history: straight-line, software-pipelined
+    if (pw) {
+      // the full history with the last axis' factors as powers of E^(1)'s
+      // (exp(-i zeta^2 j tau) = exp(-i zeta^2 tau)^j): only the history
+      // modes are loaded, batch b + 1 while batch b is summed
+      constexpr int NB = 2 * (MAXH - 2);
+      double2 R3[RAY], R1[RAY];
+#pragma unroll
+      for (int m = 0; m < RAY; ++m) {
+        w[0][m] = w0[m];
+        R3[m] = P3[m];
+        R1[m] = P1[m];
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        if (b + 1 < NB) {
+          const int jn = 2 + ((b + 1) >> 1);
+          const double2* __restrict__ rj = ring + a.slot_r[jn] * rs + row_m;
+#pragma unroll
+          for (int m = 0; m < RAY; ++m) w[(b + 1) & 1][m] = rj[((b + 1) & 1) ? k1r[m] : k3[m]];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const int j = 2 + (b >> 1);
+#pragma unroll
+        for (int m = 0; m < RAY; ++m) {
+          if (b & 1) {
+            R1[m] = cmul(R1[m], P1[m]);
+            acc1[m] = cadd(acc1[m], fs_mul_mi(a.ch[j], cmul(cmul(T1[j - 1], R1[m]), w[1][m])));
+          } else {
+            R3[m] = cmul(R3[m], P3[m]);
+            acc3[m] = cadd(acc3[m], fs_mul_mi(a.ch[j], cmul(cmul(T1[j - 1], R3[m]), w[0][m])));
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else if (nh == MAXH - 1) {   // the full order-8 history: straight-line, software-pipelined
       constexpr int NB = 2 * (MAXH - 2);
 #pragma unroll
       for (int m = 0; m < RAY; ++m) {   // batch 0, loaded before the forward transform
@@ -793,16 +831,19 @@ __global__ __launch_bounds__(NU / 4) void k_fs_row_rs(FSArgs a) {
     const int64_t rs = a.ring_stride;
     const int nh = a.nh;
     const int N1 = a.N1;
-    double2 acc[RAY];
+    const bool pw = a.pf_pow != 0;   // the last axis' factors as powers of E^(1)'s
+    double2 acc[RAY], P[RAY], R[RAY];
 #pragma unroll
     for (int m = 0; m < RAY; ++m) {
       const double2 B = a.Bm[row_m + kk[m]];
-      const double2 E = cmul(T1[0], ph[N1 + kk[m]]);
+      P[m] = ph[N1 + kk[m]];
+      R[m] = P[m];
+      const double2 E = cmul(T1[0], P[m]);
       acc[m] = cmul(E, cadd(cadd(B, fs_mul_mi(a.c0, v[m])), fs_mul_mi(a.ch[1], v[m])));
       if (a.slot_w >= 0 && t + TL * m < NE) a.ring[a.slot_w * rs + row_m + kk[m]] = v[m];
     }
-    // history terms j >= 2, one term at a time (the occupancy of four waves
-    // per SIMD hides the loads' latency)
+    // history terms j >= 2, one term at a time (the occupancy hides the
+    // loads' latency)
 #pragma unroll
     for (int j = 2; j < MAXH; ++j) {
       if (j <= nh) {
@@ -812,7 +853,12 @@ __global__ __launch_bounds__(NU / 4) void k_fs_row_rs(FSArgs a) {
 #pragma unroll
         for (int m = 0; m < RAY; ++m) {
           w[m] = rj[kk[m]];
-          pf[m] = pj[kk[m]];
+          if (pw) {
+            R[m] = cmul(R[m], P[m]);
+            pf[m] = R[m];
+          } else {
+            pf[m] = pj[kk[m]];
+          }
         }
 #pragma unroll
         for (int m = 0; m < RAY; ++m) acc[m] = cadd(acc[m], fs_mul_mi(a.ch[j], cmul(cmul(T1[j - 1], pf[m]), w[m])));

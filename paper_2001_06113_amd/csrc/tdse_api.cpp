@@ -1401,6 +1401,11 @@ int fs_am_step(tdse_plan_s* p, int m, bool write_u) {
   r.nh = n - 1;
   r.c0 = p->mu[0] * p->dt;
   r.slot_w = m % (n - 1);
+  // no field component along the last axis: its factors of E^(j) are the
+  // j-th powers of E^(1)'s, formed in the row pass instead of loaded
+  r.pf_pow = 1;
+  for (int j = 0; j < n - 1; ++j)
+    if (c.req.dphi2[j] != 0.0) r.pf_pow = 0;
   for (int j = 1; j <= n - 1; ++j) {
     r.ch[j] = p->dt * p->mu[j];
     r.slot_r[j] = ((m + 1 - j) % (n - 1) + (n - 1)) % (n - 1);

@@ -148,6 +148,8 @@ struct FSArgs {
   // 3D: the row pass runs over N1 = N0 Nm rows (k0, k1), the column pass
   // over ncol = Mm M2 columns (x1, x2) of the (k0, x1, x2) array, and the
   // middle-axis passes transform along axis 1 (axm) between the two
+  int pf_pow;                   // the last axis' phase factors of E^(j) are the j-th powers of E^(1)'s
+                                // (no field component along it): the row pass forms them by products
   int Nm;                       // middle-axis modes (0: 1D or 2D)
   int64_t ncol;                 // columns of the column pass (M2 in 2D)
   CFAxis axm;
