@@ -51,6 +51,10 @@ CASES = [
     dict(seed=9, dim=2, M=(24, 32), nu=(256, 256), T=0.04, N=9, q=6, panels=2),
     dict(seed=23, dim=2, M=(48, 96), nu=(256, 1024), T=0.03, N=10, q=10, panels=1),
     dict(seed=24, dim=2, M=(128, 64), nu=(512, 512), T=0.02, N=8, q=10, panels=2, A_kind="none"),
+    # field-free 1D, and a 2D field with a component along the last axis at
+    # nu = 1024: the last axis' phase factors as powers, and from the table
+    dict(seed=25, dim=1, M=(64,), nu=(512,), T=0.04, N=12, q=8, panels=1, A_kind="none"),
+    dict(seed=26, dim=2, M=(32, 96), nu=(256, 1024), T=0.03, N=10, q=8, panels=1, Adir=(0.6, 0.8)),
 ]
 
 
@@ -59,6 +63,8 @@ def test_free_space_matches_oracle(case):
     prob = free_problem_from_seed(case["seed"], case["dim"], case["M"], case["T"], case["N"], nu=case["nu"],
                                   order=case.get("order", 8), eps=1e-11, q=case["q"], panels=case["panels"],
                                   A_kind=case.get("A_kind", "pulse_sin2"))
+    if "Adir" in case:
+        prob.A_params = tuple(prob.A_params[:3]) + tuple(case["Adir"])
     print(f"case free M={prob.M} nu={prob.nu} steps={prob.nsteps}", flush=True)
     plan = gpu_plan(prob)
     u = plan.run(prob.u0).cpu().numpy()
