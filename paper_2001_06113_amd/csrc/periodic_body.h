@@ -341,7 +341,7 @@ struct row_lds {
 
 // Row pass over rows k1 = line0 .. line0+LPW-1 of one instance; lds holds
 // row_lds<C,N,LPW>::elems elements.
-template <typename C, int N, int LPW, int TL>
+template <typename C, int N, int LPW, int TL, bool PW = false>
 __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
   constexpr int NT = LPW * TL;
   constexpr int EPT = N / TL;
@@ -374,7 +374,10 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
   // forward FFT: a product taken here would wait for its loads, and loads
   // complete in order, so for every load issued before them
   double2 P1[EPT];
-  C T2[PF ? NH - 1 : 1][EPT];    // axis-2 factors of E^(j), j >= 2, transform precision
+  // axis-2 factors of E^(j), j >= 2, transform precision; PW (FP64, no field
+  // along axis 2): exp(-i k^2 j dt) = P1^j, formed by products instead
+  static_assert(!PW || sizeof(C) == sizeof(double2), "phase powers are for the FP64 form");
+  C T2[PF && !PW ? NH - 1 : 1][EPT];
   double2 T1[NH];
   constexpr bool F64 = sizeof(C) == sizeof(double2);
   // Loads are issued in the order their values are first needed, since
@@ -436,7 +439,7 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
   if (phases) {
 #pragma unroll
     for (int m = 0; m < EPT; ++m) P1[m] = ph[M1 + (t + TL * m)];
-    if constexpr (PF) {
+    if constexpr (PF && !PW) {
       // the split form reads the complex64 copy: no conversion waits here
       const C* __restrict__ tpj = F64 ? (const C*)ph : (const C*)a.ph32;
 #pragma unroll
@@ -452,7 +455,7 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
   // registers (PF) or memory.  Only plain locals are captured: taking the
   // address of the by-value kernel argument would copy it to scratch.
   auto Ej = [&T1, &T2, ph, per, M1, t](int j, int m) -> C {
-    if constexpr (PF) return cmul(from_d<C>(T1[j - 1]), T2[j - 2][m]);
+    if constexpr (PF && !PW) return cmul(from_d<C>(T1[j - 1]), T2[j - 2][m]);
     else return from_d<C>(cmul(T1[j - 1], ph[(j - 1) * per + M1 + (t + TL * m)]));
   };
   auto Wh = [&Wr, &slot_r, ring, rstride, row0, t](int j, int m) -> C {
@@ -489,9 +492,20 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
       // products E^(j) What in the transform precision, weighted by dt mu_j
       // and summed in FP64
       double2 hist = double2{0.0, 0.0};
+      if constexpr (PW) {
+        double2 R = P1[m];
 #pragma unroll
-      for (int j = 2; j <= NH; ++j) {
-        if (j <= nh) hist = cadd(hist, mul_mi(a.ch[j], to_d(cmul(Ej(j, m), Wh(j, m)))));
+        for (int j = 2; j <= NH; ++j) {
+          if (j <= nh) {
+            R = cmul(R, P1[m]);
+            hist = cadd(hist, mul_mi(a.ch[j], cmul(cmul(T1[j - 1], R), to_d(Wh(j, m)))));
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 2; j <= NH; ++j) {
+          if (j <= nh) hist = cadd(hist, mul_mi(a.ch[j], to_d(cmul(Ej(j, m), Wh(j, m)))));
+        }
       }
       acc = cadd(acc, hist);
       const int64_t g = row0 + (t + TL * m);

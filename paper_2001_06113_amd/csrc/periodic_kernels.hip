@@ -28,10 +28,10 @@ __global__ __launch_bounds__(LPW * TL) void k_mid(LineArgs a) {
 
 // ---------------------------------------------------------------- row pass
 
-template <typename C, int N, int LPW, int TL>
+template <typename C, int N, int LPW, int TL, bool PW = false>
 __global__ __launch_bounds__(LPW * TL) void k_row(LineArgs a) {
   __shared__ C lds[row_lds<C, N, LPW>::elems];
-  row_body<C, N, LPW, TL>(a, blockIdx.x * LPW, lds);
+  row_body<C, N, LPW, TL, PW>(a, blockIdx.x * LPW, lds);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -131,6 +131,12 @@ hipError_t row_pass(int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipE
 #define X(n)                                                                                      \
   case n: {                                                                                       \
     constexpr int L = row_lpw(n), T = row_tl(n);                                                  \
+    if constexpr (sizeof(C) == sizeof(double2)) {                                                 \
+      if (a.pf_pow) {                                                                             \
+        TDSE_LAUNCH((k_row<C, n, L, T, true>), dim3((a.nlines + L - 1) / L), dim3(L * T), s, e0, e1, a); \
+        break;                                                                                    \
+      }                                                                                           \
+    }                                                                                             \
     TDSE_LAUNCH((k_row<C, n, L, T>), dim3((a.nlines + L - 1) / L), dim3(L * T), s, e0, e1, a);   \
     break;                                                                                        \
   }
