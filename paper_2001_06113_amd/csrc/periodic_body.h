@@ -374,9 +374,9 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
   // forward FFT: a product taken here would wait for its loads, and loads
   // complete in order, so for every load issued before them
   double2 P1[EPT];
-  // axis-2 factors of E^(j), j >= 2, transform precision; PW (FP64, no field
-  // along axis 2): exp(-i k^2 j dt) = P1^j, formed by products instead
-  static_assert(!PW || sizeof(C) == sizeof(double2), "phase powers are for the FP64 form");
+  // axis-2 factors of E^(j), j >= 2, transform precision; PW (no field along
+  // axis 2): exp(-i k^2 j dt) = P1^j, formed by FP64 products instead (the
+  // split form rounds E^(j) to complex64 once, as it rounds the table)
   C T2[PF && !PW ? NH - 1 : 1][EPT];
   double2 T1[NH];
   constexpr bool F64 = sizeof(C) == sizeof(double2);
@@ -498,7 +498,8 @@ __device__ __forceinline__ void row_body(const LineArgs& a, int line0, C* lds) {
         for (int j = 2; j <= NH; ++j) {
           if (j <= nh) {
             R = cmul(R, P1[m]);
-            hist = cadd(hist, mul_mi(a.ch[j], cmul(cmul(T1[j - 1], R), to_d(Wh(j, m)))));
+            if constexpr (F64) hist = cadd(hist, mul_mi(a.ch[j], cmul(cmul(T1[j - 1], R), to_d(Wh(j, m)))));
+            else hist = cadd(hist, mul_mi(a.ch[j], to_d(cmul(from_d<C>(cmul(T1[j - 1], R)), Wh(j, m)))));
           }
         }
       } else {

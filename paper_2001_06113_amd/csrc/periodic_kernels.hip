@@ -131,11 +131,9 @@ hipError_t row_pass(int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipE
 #define X(n)                                                                                      \
   case n: {                                                                                       \
     constexpr int L = row_lpw(n), T = row_tl(n);                                                  \
-    if constexpr (sizeof(C) == sizeof(double2)) {                                                 \
-      if (a.pf_pow) {                                                                             \
-        TDSE_LAUNCH((k_row<C, n, L, T, true>), dim3((a.nlines + L - 1) / L), dim3(L * T), s, e0, e1, a); \
-        break;                                                                                    \
-      }                                                                                           \
+    if (a.pf_pow) {                                                                               \
+      TDSE_LAUNCH((k_row<C, n, L, T, true>), dim3((a.nlines + L - 1) / L), dim3(L * T), s, e0, e1, a); \
+      break;                                                                                      \
     }                                                                                             \
     TDSE_LAUNCH((k_row<C, n, L, T>), dim3((a.nlines + L - 1) / L), dim3(L * T), s, e0, e1, a);   \
     break;                                                                                        \

@@ -836,9 +836,9 @@ int op_am_step(tdse_plan_s* p, int m, bool write_u) {
     r.ch[j] = p->dt * p->mu[j];
     r.slot_r[j] = ((m + 1 - j) % (n - 1) + (n - 1)) % (n - 1);
   }
-  // FP64, no field component along the last axis: its factors of E^(j) are
-  // the j-th powers of E^(1)'s (the split form keeps the complex64 table)
-  r.pf_pow = p->st[g].prec == P_FP64 ? 1 : 0;
+  // no field component along the last axis: its factors of E^(j) are the
+  // j-th powers of E^(1)'s
+  r.pf_pow = 1;
   for (int j = 0; j < n - 1; ++j)
     if (c.req.dphi2[j] != 0.0) r.pf_pow = 0;
   return launch_timed(p, g, false, r);

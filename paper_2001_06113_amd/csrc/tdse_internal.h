@@ -83,8 +83,8 @@ struct LineArgs {
   double c0;           // mu_0 dt  (uhat = B - i c0 W)
   double ch[MAXH + 1]; // dt mu_j
   void* fdst;          // R_FWD destination (transform precision)
-  int pf_pow;          // FP64 R_AM: no field along the last axis, its factors of E^(j) are
-                       // the j-th powers of E^(1)'s (formed by products, not loaded)
+  int pf_pow;          // R_AM: no field along the last axis, its factors of E^(j) are the
+                       // j-th powers of E^(1)'s (formed by products, not loaded)
   // phase table
   double2* ph;
   float2* ph32;        // split form: the table rounded to complex64 (null in FP64 plans)
