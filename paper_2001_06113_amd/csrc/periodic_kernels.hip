@@ -11,7 +11,7 @@ namespace tdse {
 // ------------------------------------------------------------- column pass
 
 template <typename C, int N, int LPW, int TL>
-__global__ __launch_bounds__(LPW * TL) void k_col(LineArgs a) {
+__global__ __launch_bounds__(LPW * TL, (sizeof(C) == sizeof(double2) && N >= 256 && N <= 1024 && (N & (N - 1)) == 0) ? 4 : 1) void k_col(LineArgs a) {
   __shared__ C lds[col_lds<C, N, LPW>::elems];
   // tiles sharing a 128-byte line of the potential share an XCD
   const int tile = xcd_tile<(16 / LPW > 1 ? 16 / LPW : 1)>(blockIdx.x, gridDim.x);
