@@ -49,7 +49,9 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_col_batch(const LineArgs* __r
 #undef X
 }
 
-template <typename C, int F>
+// PW: the row kernel of instances with no field component along their last
+// axis (that axis' factors of E^(j) formed as powers of E^(1)'s)
+template <typename C, int F, bool PW = false>
 __global__ __launch_bounds__(BATCH_THREADS) void k_row_batch(const LineArgs* __restrict__ args,
                                                              const BatchTile* __restrict__ tiles) {
   HIP_DYNAMIC_SHARED(double2, tdse_batch_lds)
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_row_batch(const LineArgs* __r
 #define X(n, e)                                                         \
   case n * 64 + e: {                                                    \
     constexpr int T = n / e, L = BATCH_THREADS / T;                     \
-    row_body<C, n, L, T>(a, tl.line0, lds);                             \
+    row_body<C, n, L, T, PW>(a, tl.line0, lds);                         \
     break;                                                              \
   }
   if constexpr (F == 0) {
@@ -72,16 +74,16 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_row_batch(const LineArgs* __r
 #undef X
 }
 
-template <typename C, int F>
+template <typename C, int F, bool PW>
 void launch_batch_f(bool col, const LineArgs* args, const BatchTile* tiles, int ntiles, size_t lds_bytes,
                     hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const dim3 grid(ntiles), block(BATCH_THREADS);
   if (e0) {
     if (col) hipExtLaunchKernelGGL((k_col_batch<C, F>), grid, block, lds_bytes, s, e0, e1, 0, args, tiles);
-    else hipExtLaunchKernelGGL((k_row_batch<C, F>), grid, block, lds_bytes, s, e0, e1, 0, args, tiles);
+    else hipExtLaunchKernelGGL((k_row_batch<C, F, PW>), grid, block, lds_bytes, s, e0, e1, 0, args, tiles);
   } else {
     if (col) hipLaunchKernelGGL((k_col_batch<C, F>), grid, block, lds_bytes, s, args, tiles);
-    else hipLaunchKernelGGL((k_row_batch<C, F>), grid, block, lds_bytes, s, args, tiles);
+    else hipLaunchKernelGGL((k_row_batch<C, F, PW>), grid, block, lds_bytes, s, args, tiles);
   }
 }
 
@@ -89,10 +91,16 @@ template <typename C>
 hipError_t launch_batch(bool col, int family, const LineArgs* args, const BatchTile* tiles, int ntiles,
                         size_t lds_bytes, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (ntiles <= 0) return hipSuccess;
+  // families 3..5: the row kernels of families 0..2 for instances whose last
+  // axis carries no field (column passes never take them)
+  if (col && family >= 3) return hipErrorInvalidValue;
   switch (family) {
-    case 0: launch_batch_f<C, 0>(col, args, tiles, ntiles, lds_bytes, s, e0, e1); break;
-    case 1: launch_batch_f<C, 1>(col, args, tiles, ntiles, lds_bytes, s, e0, e1); break;
-    case 2: launch_batch_f<C, 2>(col, args, tiles, ntiles, lds_bytes, s, e0, e1); break;
+    case 0: launch_batch_f<C, 0, false>(col, args, tiles, ntiles, lds_bytes, s, e0, e1); break;
+    case 1: launch_batch_f<C, 1, false>(col, args, tiles, ntiles, lds_bytes, s, e0, e1); break;
+    case 2: launch_batch_f<C, 2, false>(col, args, tiles, ntiles, lds_bytes, s, e0, e1); break;
+    case 3: launch_batch_f<C, 0, true>(col, args, tiles, ntiles, lds_bytes, s, e0, e1); break;
+    case 4: launch_batch_f<C, 1, true>(col, args, tiles, ntiles, lds_bytes, s, e0, e1); break;
+    case 5: launch_batch_f<C, 2, true>(col, args, tiles, ntiles, lds_bytes, s, e0, e1); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -273,6 +273,8 @@ struct RecLaunch {
   int64_t nn;
 };
 
+constexpr int NFAM = 6;   // batched pass families (schedule families 0..2, phase-power rows 3..5)
+
 struct tdse_plan_s {
   // grid: M1 x M2 (1D: M1 = 1).  A 3D grid M0 x Mmid x M2 is held as M1 =
   // M0 Mmid rows of M2: the row pass runs over the last axis, the column pass
@@ -357,8 +359,10 @@ struct tdse_plan_s {
   int64_t cap_tiles[2] = {0, 0};                // tile capacity per pass kind
   struct TileSet {
     int64_t off = 0;                            // element offset in the tile region
-    int first[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
-    size_t lds[3] = {0, 0, 0};
+    // schedule families 0..2, and for row passes 3..5: the same schedules
+    // for instances whose last axis carries no field (phase powers)
+    int first[NFAM] = {}, cnt[NFAM] = {};
+    size_t lds[NFAM] = {};
   };
   TileSet tiles[2][2];                          // [column/row][stage]
   std::vector<int> ept[2];                      // [column/row][instance]: schedule of the Adams stage
@@ -409,13 +413,13 @@ struct tdse_plan_s {
   }
   // batch: the schedule families of one pass run concurrently, families 1
   // and 2 on side streams forked from and joined back to the bound stream
-  hipStream_t fam_st[2] = {nullptr, nullptr};
-  hipEvent_t fam_fork = nullptr, fam_join[2] = {nullptr, nullptr};
+  hipStream_t fam_st[NFAM - 1] = {};
+  hipEvent_t fam_fork = nullptr, fam_join[NFAM - 1] = {};
 
   ~tdse_plan_s() {
     drop_graph();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NFAM - 1; ++i) {
       if (fam_join[i]) (void)hipEventDestroy(fam_join[i]);
       if (fam_st[i]) (void)hipStreamDestroy(fam_st[i]);
     }
@@ -1881,19 +1885,40 @@ int64_t tile_base(const tdse_plan_s* p, int kind, int g) {
   return kind == 0 ? g * p->cap_tiles[0] : 2 * p->cap_tiles[0] + g * p->cap_tiles[1];
 }
 
+// An instance whose field has no component along its last axis at any time
+// the scheme samples (step times and start-up sub-step times): its phase
+// increments along that axis are zero, and its row passes may form that
+// axis' factors of E^(j) as powers of E^(1)'s.
+bool last_axis_field_free(const tdse_plan_s* q) {
+  const int last = q->dim - 1;
+  double ph[3];
+  for (int m = 0; m <= q->nsteps; ++m) {
+    q->tf.phi(q->t_at(m), ph);
+    if (ph[last] != 0.0) return false;
+  }
+  for (int m = 1; m <= std::min(q->ns, q->nsteps); ++m)
+    for (int l = 0; l < q->L; ++l)
+      for (int k = 1; k < (1 << l); ++k) {
+        q->tf.phi(q->t_at(m - 1) + k * q->dt / (1 << l), ph);
+        if (ph[last] != 0.0) return false;
+      }
+  return true;
+}
+
 // Tile table of one pass kind and buffer stage from per-instance schedules,
 // ordered by schedule family; uploaded synchronously.
 int batch_tiles(tdse_plan_s* p, int kind, int g, const std::vector<int>& ept) {
   const int prec = p->sub[0]->st[g].prec;
-  std::vector<BatchTile> fam[3];
+  std::vector<BatchTile> fam[NFAM];
   tdse_plan_s::TileSet& ts = p->tiles[kind][g];
   ts.off = tile_base(p, kind, g);
-  for (int f = 0; f < 3; ++f) ts.lds[f] = 0;
+  for (int f = 0; f < NFAM; ++f) ts.lds[f] = 0;
   for (size_t i = 0; i < p->sub.size(); ++i) {
     const tdse_plan_s* q = p->sub[i];
     const int N = batch_len(q, kind), e = ept[i];
-    const int f = batch_family(N, e);
+    int f = batch_family(N, e);
     if (f < 0) return fail(TDSE_EINVAL, "no batched schedule for this line length");
+    if (kind == 1 && last_axis_field_free(q)) f += 3;
     const int LPW = BATCH_THREADS / (N / e);
     const int nl = batch_lines(q, kind);
     const int nt = (nl + LPW - 1) / LPW;
@@ -1901,7 +1926,7 @@ int batch_tiles(tdse_plan_s* p, int kind, int g, const std::vector<int>& ept) {
     ts.lds[f] = std::max(ts.lds[f], batch_lds_bytes(prec, kind == 0, N, e));
   }
   std::vector<BatchTile> all;
-  for (int f = 0; f < 3; ++f) {
+  for (int f = 0; f < NFAM; ++f) {
     ts.first[f] = (int)all.size();
     ts.cnt[f] = (int)fam[f].size();
     if (ts.lds[f] > p->lds_max) return fail(TDSE_EINVAL, "batched schedule exceeds the LDS of a workgroup");
@@ -1997,12 +2022,13 @@ int batch_exec(tdse_plan_s* p, const std::vector<tdse_plan_s::GLaunch>& L, const
     const bool timed = p->prof && gl.timed;
     // the families touch disjoint instances: with more than one, the later
     // ones go to side streams (not when each launch is being timed)
-    const int nfam = (ts.cnt[0] > 0) + (ts.cnt[1] > 0) + (ts.cnt[2] > 0);
+    int nfam = 0;
+    for (int f = 0; f < NFAM; ++f) nfam += ts.cnt[f] > 0;
     const bool fork = nfam > 1 && !timed && p->fam_fork;
     if (fork) HIP_TRY(hipEventRecord(p->fam_fork, p->stream));
     int side = 0;
     bool on_main = false;
-    for (int f = 0; f < 3; ++f) {
+    for (int f = 0; f < NFAM; ++f) {
       if (!ts.cnt[f]) continue;
       hipStream_t s = p->stream;
       if (fork && on_main) {
@@ -2153,7 +2179,7 @@ int bind_batch(tdse_plan_s* p) {
   HIP_TRY(hipGetDevice(&dev));
   if (!p->fam_fork) {   // default priority, non-blocking
     HIP_TRY(hipEventCreateWithFlags(&p->fam_fork, hipEventDisableTiming));
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NFAM - 1; ++i) {
       HIP_TRY(hipStreamCreateWithFlags(&p->fam_st[i], hipStreamNonBlocking));
       HIP_TRY(hipEventCreateWithFlags(&p->fam_join[i], hipEventDisableTiming));
     }
