@@ -91,7 +91,7 @@ hipError_t col_pass(int N, const LineArgs& a, hipStream_t s, hipEvent_t e0, hipE
   switch (N) {
 #define X(n)                                                                                      \
   case n: {                                                                                       \
-    constexpr int L = col_lpw(n), T = col_tl(n);                                                  \
+    constexpr int L = (sizeof(C) == sizeof(float2) && n == 128) ? 16 : col_lpw(n), T = col_tl(n);                                                \
     TDSE_LAUNCH((k_col<C, n, L, T>), dim3((unsigned)col_blocks(n, a, L, T)), dim3(L * T), s, e0, e1, a); \
     break;                                                                                        \
   }
@@ -111,7 +111,7 @@ hipError_t mid_pass(int N, bool inverse, const LineArgs& a, hipStream_t s, hipEv
   switch (N) {
 #define X(n)                                                                                          \
   case n: {                                                                                           \
-    constexpr int L = col_lpw(n), T = col_tl(n);                                                      \
+    constexpr int L = (sizeof(C) == sizeof(float2) && n == 128) ? 16 : col_lpw(n), T = col_tl(n);                                                    \
     const dim3 g((unsigned)((a.nlines + L - 1) / L));                                                 \
     if (inverse) TDSE_LAUNCH((k_mid<C, n, L, T, true>), g, dim3(L * T), s, e0, e1, a);               \
     else TDSE_LAUNCH((k_mid<C, n, L, T, false>), g, dim3(L * T), s, e0, e1, a);                      \
