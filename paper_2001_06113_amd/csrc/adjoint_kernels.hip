@@ -15,7 +15,7 @@
 //   k_adj_sub    the phase factor of an order-2 sub-step (forward, or adjoint
 //                with its dJ/d(dphi) partial sums);
 //   k_adj_point  diagonal factors (alpha + beta V) or 1/(alpha + beta V) on the grid;
-//   k_adj_axpy, k_adj_phase, k_adj_reduce, k_adj_to_A  (helpers).
+//   k_adj_axpy, k_adj_copy2, k_adj_phase, k_adj_reduce, k_adj_to_A  (helpers).
 #include <hip/hip_runtime.h>
 
 #include "periodic_body.h"
@@ -178,6 +178,17 @@ __global__ __launch_bounds__(256) void k_adj_axpy(int64_t P, const double2* x, c
   out[g] = cadd(x[g], cmul(double2{cr, ci}, y[g]));
 }
 
+// two copies of P entries in one launch: workgroups [0, nb) copy src0 into
+// dst0, the next nb copy src1 into dst1
+__global__ __launch_bounds__(256) void k_adj_copy2(int64_t P, int nblk, double2* dst0, const double2* src0,
+                                                   double2* dst1, const double2* src1) {
+  const bool second = (int)blockIdx.x >= nblk;
+  const int64_t g = (int64_t)(second ? blockIdx.x - nblk : blockIdx.x) * 256 + threadIdx.x;
+  if (g >= P) return;
+  if (second) dst1[g] = src1[g];
+  else dst0[g] = src0[g];
+}
+
 // red[r] = sum_b part[r * nblk + b], one workgroup per row
 __global__ __launch_bounds__(256) void k_adj_reduce(const double* part, double* red, int nblk) {
   __shared__ double buf[256];
@@ -224,6 +235,13 @@ hipError_t launch_adj_point(const AdjPoint& a, hipStream_t s) {
 hipError_t launch_adj_axpy(int64_t P, const double2* x, const double2* y, double cr, double ci, double2* out,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_adj_axpy, dim3(nb(P)), dim3(256), 0, s, P, x, y, cr, ci, out);
+  return hipGetLastError();
+}
+hipError_t launch_adj_copy2(int64_t P, double2* dst0, const double2* src0, double2* dst1, const double2* src1,
+                            hipStream_t s) {
+  if (P <= 0) return hipSuccess;
+  const int n = nb(P);
+  hipLaunchKernelGGL(k_adj_copy2, dim3(2 * n), dim3(256), 0, s, P, n, dst0, src0, dst1, src1);
   return hipGetLastError();
 }
 hipError_t launch_adj_reduce(const double* part, double* red, int nrows, int nblk, hipStream_t s) {

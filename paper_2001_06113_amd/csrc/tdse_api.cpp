@@ -2591,11 +2591,18 @@ int adjoint_single(tdse_plan_s* p, char* w, size_t wbytes, int K, const void* u0
         s = launch(p, 0, false, r);
       }
       for (int i = std::max(w0, 0); i < sc && !s; ++i) s = adj_copy(p, R.at(L.o_wwin, i - w0), (char*)p->ring(0) + (size_t)(i % H) * a, a);
+      // B_n into its segment slot before step n; What_{n-1}, which step n-1
+      // left in the ring, into the window in the same launch
+      auto ring_slot = [&](int m) { return (const double2*)((char*)p->ring(0) + (size_t)(m % H) * a); };
       for (int n = sc; n <= ec && !s; ++n) {
-        s = adj_copy(p, R.at(L.o_bseg, n - sc), p->B(), a);
+        if (n == sc) s = adj_copy(p, R.at(L.o_bseg, 0), p->B(), a);
+        else
+          s = adj_err(launch_adj_copy2(p->P, R.at(L.o_bseg, n - sc), p->B(), R.at(L.o_wwin, n - 1 - w0),
+                                       ring_slot(n - 1), p->stream),
+                      "adjoint copy");
         if (!s) s = op_am_step(p, n, false);
-        if (!s) s = adj_copy(p, R.at(L.o_wwin, n - w0), (char*)p->ring(0) + (size_t)(n % H) * a, a);
       }
+      if (!s && ec >= sc) s = adj_copy(p, R.at(L.o_wwin, ec - w0), ring_slot(ec), a);
       for (int n = ec; n >= sc && !s; --n) {
         // Z = G_n^H omega_n = F conj(S_n) V_n F^-1 omega_n
         s = adj_ifft2(p, R.at(L.o_omega), nullptr, -mu[0] * dt, n * dt, R.at(L.o_Z));

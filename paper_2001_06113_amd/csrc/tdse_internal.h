@@ -225,6 +225,8 @@ hipError_t launch_adj_sub(const AdjSub& a, hipStream_t s);
 hipError_t launch_adj_point(const AdjPoint& a, hipStream_t s);
 hipError_t launch_adj_axpy(int64_t P, const double2* x, const double2* y, double cr, double ci, double2* out,
                            hipStream_t s);
+hipError_t launch_adj_copy2(int64_t P, double2* dst0, const double2* src0, double2* dst1, const double2* src1,
+                            hipStream_t s);
 hipError_t launch_adj_reduce(const double* part, double* red, int nrows, int nblk, hipStream_t s);
 hipError_t launch_adj_to_A(const double* red, const int* rowptr, const int* src, const double* wt, double* out,
                            int nout, hipStream_t s);
