@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--split-steps", type=int, default=3)
     ap.add_argument("--no-free", action="store_true", help="skip the free-space 256x256 leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched leg")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="batched leg without its adjoint (which launches from several host threads)")
     ap.add_argument("--no-well", action="store_true", help="skip the moving-well (potential on the fly) leg")
     ap.add_argument("--no-ionization", action="store_true", help="skip the 1D ionization (Example 3) leg")
     ap.add_argument("--no-1d", action="store_true", help="skip the 1D periodic M = 256 leg")
@@ -695,7 +697,7 @@ def long_time_leg(runs: int = 5) -> dict:
     return res
 
 
-def batch_leg(runs: int, copies: dict) -> dict:
+def batch_leg(runs: int, copies: dict, adjoint: bool = True) -> dict:
     """Batched form on the 64-instance workload (seed 4000 + i; 32 1D with
     M in {256..2048}, 32 2D with M in {128..512}^2; 500 steps, FP32-split,
     stepwise field): autotuned schedules, graph-replayed whole runs, against
@@ -741,20 +743,24 @@ def batch_leg(runs: int, copies: dict) -> dict:
         seq += time.perf_counter() - t1
         pl.close()
     # adjoint of <x_1>(T) for every instance, seeded from the batch output
-    lams = []
-    for p, uT in zip(probs, b.unpack(out)):
-        x = torch.as_tensor(-np.pi + 2 * np.pi * np.arange(p.M[0]) / p.M[0], device=dev)
-        w = float(np.prod([2 * np.pi / m for m in p.M]))
-        lams.append(2.0 * w * (x.reshape(-1, *([1] * (p.dim - 1)))) * uT)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gAs, _ = b.adjoint(u0, lams)
-    torch.cuda.synchronize()
-    adj_first_s = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    gAs, _ = b.adjoint(u0, lams)
-    torch.cuda.synchronize()
-    adj_s = time.perf_counter() - t0
+    adj = {}
+    lams = [] if adjoint else None
+    if adjoint:
+        for p, uT in zip(probs, b.unpack(out)):
+            x = torch.as_tensor(-np.pi + 2 * np.pi * np.arange(p.M[0]) / p.M[0], device=dev)
+            w = float(np.prod([2 * np.pi / m for m in p.M]))
+            lams.append(2.0 * w * (x.reshape(-1, *([1] * (p.dim - 1)))) * uT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gAs, _ = b.adjoint(u0, lams)
+        torch.cuda.synchronize()
+        adj_first_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        gAs, _ = b.adjoint(u0, lams)
+        torch.cuda.synchronize()
+        adj_s = time.perf_counter() - t0
+        adj = {"adjoint_s_all_instances": adj_s, "adjoint_first_call_s": adj_first_s,
+               "adjoint_vs_forward_run": adj_s / wall, "adjoint_samples": int(sum(g.size for g in gAs))}
     b.close()
     return {"workload": "64 periodic instances (32 1D M=256..2048, 32 2D M=128^2..512^2), T=2, 500 steps AM8, "
                         "FP32-split, stepwise A",
@@ -763,9 +769,7 @@ def batch_leg(runs: int, copies: dict) -> dict:
             "error": {"worst_instance": errs.index(worst), **worst,
                       "all_pass": all(e["pass"] for e in errs)},
             "one_plan_at_a_time_value": b.total * nsteps / seq, "speedup_vs_one_plan_at_a_time": seq / wall,
-            "autotune_s": tune_s, "schedules_col_row": sorted(set(chosen)),
-            "adjoint_s_all_instances": adj_s, "adjoint_first_call_s": adj_first_s,
-            "adjoint_vs_forward_run": adj_s / wall, "adjoint_samples": int(sum(g.size for g in gAs))}
+            "autotune_s": tune_s, "schedules_col_row": sorted(set(chosen)), **adj}
 
 
 def main():
@@ -803,7 +807,7 @@ def main():
     # launch (the persistent 2D path below), kernels launched for the first
     # time afterwards from several streams at once run about 3x slower (the
     # eight-stream adjoint: 3.3 s instead of 1.06 s).
-    batch = batch_leg(args.batch_runs, copies) if not args.no_batch else None
+    batch = batch_leg(args.batch_runs, copies, not args.no_adjoint) if not args.no_batch else None
     plan = Plan.from_problem(prob, device=dev)
     u0 = torch.as_tensor(prob.u0).to(dev)
     out = torch.empty_like(u0)
