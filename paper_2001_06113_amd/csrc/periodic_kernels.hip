@@ -46,10 +46,15 @@ constexpr int col_tl(int N) { return N / col_ept(N); }
 constexpr int col_lpw(int N) {
   return N == 1 ? 256 : (N > 1536 ? 1 : (N >= 256 ? 2 : (64 / col_tl(N) > 2 ? 64 / col_tl(N) : 2)));
 }
-// Row pass: EPT 4 (12 with a factor 3, 8 from 2048), at least 128 threads.
+// Row pass: EPT 4 (12 with a factor 3, 8 from 2048). At least 128 threads
+// below length 256; from 256 on, one wave is enough, which keeps a 256- or
+// 384-row grid at one or two lines per workgroup (256 or 192 workgroups
+// instead of 128 or 96).
 constexpr int row_ept(int N) { return N % 3 == 0 ? (N < 12 ? N : 12) : (N >= 2048 ? 8 : (N < 4 ? N : 4)); }
 constexpr int row_tl(int N) { return N / row_ept(N); }
-constexpr int row_lpw(int N) { return 128 / row_tl(N) > 1 ? 128 / row_tl(N) : 1; }
+constexpr int row_lpw(int N) {
+  return (N >= 256 ? 64 : 128) / row_tl(N) > 1 ? (N >= 256 ? 64 : 128) / row_tl(N) : 1;
+}
 
 #define TDSE_LINE_SIZES(X) \
   X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) \
