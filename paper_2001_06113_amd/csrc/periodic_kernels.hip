@@ -37,20 +37,26 @@ __global__ __launch_bounds__(LPW * TL) void k_row(LineArgs a) {
 // ---------------------------------------------------------------- dispatch
 
 // Column pass: EPT elements per thread (4 for lengths 256..1024, 8 otherwise,
-// 12 with a factor 3), LPW columns per workgroup (2 from length 256: enough
-// workgroups to fill the chip at 512 columns), padded LDS lines.
+// 12 with a factor 3, 6 at 384), LPW columns per workgroup (2 from length
+// 256: enough workgroups to fill the chip at 512 columns), padded LDS lines.
 constexpr int col_ept(int N) {
-  return N == 1 ? 1 : (N % 3 == 0 ? (N < 12 ? N : 12) : (N < 8 ? N : (N >= 256 && N <= 1024 ? 4 : 8)));
+  return N == 1 ? 1
+                : (N % 3 == 0 ? (N < 12 ? N : (N == 384 ? 6 : 12))
+                              : (N < 8 ? N : (N >= 256 && N <= 1024 ? 4 : 8)));
 }
 constexpr int col_tl(int N) { return N / col_ept(N); }
 constexpr int col_lpw(int N) {
   return N == 1 ? 256 : (N > 1536 ? 1 : (N >= 256 ? 2 : (64 / col_tl(N) > 2 ? 64 / col_tl(N) : 2)));
 }
-// Row pass: EPT 4 (12 with a factor 3, 8 from 2048). At least 128 threads
-// below length 256; from 256 on, one wave is enough, which keeps a 256- or
-// 384-row grid at one or two lines per workgroup (256 or 192 workgroups
-// instead of 128 or 96).
-constexpr int row_ept(int N) { return N % 3 == 0 ? (N < 12 ? N : 12) : (N >= 2048 ? 8 : (N < 4 ? N : 4)); }
+// Row pass: EPT 4 (12 with a factor 3, 6 at 384 and 768: twice the threads
+// for the history loads of an Adams step, 13-17 % faster there than 12
+// despite three more radix-2 passes; 8 from 2048). At least 128 threads
+// below length 256; from 256 on, one wave is enough, so 256-, 384- and
+// 768-point rows take one line per workgroup (a 384-row grid: 384
+// workgroups, against 96 of four lines with EPT 12 and 128 threads).
+constexpr int row_ept(int N) {
+  return N % 3 == 0 ? (N < 12 ? N : (N == 384 || N == 768 ? 6 : 12)) : (N >= 2048 ? 8 : (N < 4 ? N : 4));
+}
 constexpr int row_tl(int N) { return N / row_ept(N); }
 constexpr int row_lpw(int N) {
   return (N >= 256 ? 64 : 128) / row_tl(N) > 1 ? (N >= 256 ? 64 : 128) / row_tl(N) : 1;
